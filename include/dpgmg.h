@@ -1,0 +1,199 @@
+/*
+ * libdpgmg -- DPG multigrid solver for ultraweak time-harmonic acoustics on
+ * uniform hexahedral meshes, for one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Badger, Henneking, Petrides, Demkowicz, "Scalable DPG multigrid
+ * solver for Helmholtz problems: a study on convergence" (arXiv 2304.01728).
+ *
+ *   Problem (Sec. 2, eq. helmholtz; rho = 1, wave speed c per element):
+ *       i w c^-2 p + div u = f,  i w u + grad p = 0  in the cube,
+ *       Z^-1 p - u.n = u0  on its boundary Gamma, Z = c.
+ *   Discretisation (Sec. 2): broken ultraweak form, adjoint graph test norm
+ *   (eq. Gnorm) with alpha = 1, test order raised by dp; element DPG
+ *   matrices B^H G^-1 B condensed onto the trace unknowns (Sec. 1.2).
+ *   Solver (Sec. 3): CG on the macro grid preconditioned by a V-cycle with
+ *   vertex-patch additive Schwarz smoothing, natural-inclusion prolongation
+ *   and coarse operators by Galerkin restriction P^T A P; a direct Cholesky
+ *   solve on the coarsest mesh; zero initial guess; stop at relative l2
+ *   residual <= tol (Sec. 4 parameters).
+ *
+ * Conventions
+ *   Complex numbers are interleaved (re, im) doubles.  Integers are int32
+ *   unless stated.  Arrays are column-major when two-dimensional.
+ *   Canonical trace numbering of an N^3 mesh of order p (the order of x in
+ *   dpg_solve): H1 pressure-trace lattice points (X,Y,Z) in [0,Np]^3 with a
+ *   coordinate divisible by p, X fastest; then flux families x, y, z, each
+ *   over interior planes s = 1..N-1 and in-plane (T1,T2) in [0,Np)^2, T1
+ *   fastest (x-family in-plane axes (y,z), y-family (x,z), z-family (x,y)).
+ *   Shape functions: hierarchical H1 (vertex hats and normalised integrated
+ *   Legendre bubbles) for the pressure trace, Legendre polynomials for fluxes
+ *   and fields.  Flux unknowns are u.e_d; none lives on Gamma.
+ *
+ * Ownership: the caller owns every array passed in or out; the library copies
+ * inputs during the call.  The context owns all device memory it allocates
+ * until dpg_destroy.  By default pointers are host pointers; with
+ * DPG_DEVICE_PTRS in dpg_options.flags, the rhs / x / fields arguments of
+ * dpg_solve and dpg_get_fields are device pointers (e.g. torch tensors).
+ *
+ * Errors: every call returns DPG_OK (0) or a negative code; dpg_last_error
+ * gives the message of the last failure on that context.  The call order
+ * setup -> assemble -> build_hierarchy -> solve is enforced (DPG_ESTATE).
+ * One context per host thread; distinct contexts may run concurrently.
+ */
+#ifndef DPGMG_H
+#define DPGMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DPG_OK = 0,
+  DPG_EINVAL = -1,     /* bad argument                                       */
+  DPG_ENOMEM = -2,     /* device allocation failed or over hbm_budget        */
+  DPG_ENOTPD = -3,     /* a Cholesky factorisation met a non-positive pivot  */
+  DPG_ENOCONV = -4,    /* maxit reached; x holds the last iterate            */
+  DPG_EBREAKDOWN = -5, /* CG breakdown (p^H M p <= 0 or not finite)          */
+  DPG_ESTATE = -6,     /* call out of order                                  */
+  DPG_EDEVICE = -7     /* HIP runtime error                                  */
+};
+
+enum { DPG_FP64 = 0, DPG_MIXED = 1 };       /* dpg_options.precision          */
+enum { DPG_DEVICE_PTRS = 1 };               /* dpg_options.flags              */
+
+/* Uniform mesh of the cube [origin, origin + side]^3 into n^3 equal boxes;
+ * element e = i + n (j + n k). */
+typedef struct {
+  int32_t n;
+  double origin[3];
+  double side;
+} dpg_mesh;
+
+/* Per-element wave speed c (length n^3); NULL means c = 1 everywhere. */
+typedef struct {
+  const double *c;
+} dpg_material;
+
+/* One right-hand side (Sec. 2 load l, eq. helmholtz data):
+ *  - impedance data of a plane wave p = A exp(-i w d.x), u = d p, i.e.
+ *    u0 = (Z^-1 - d.n) A exp(-i w d.x) on Gamma (A = amp; A = 0: u0 = 0);
+ *  - nsrc Gaussian point sources in the first equation,
+ *    f = sum a_s (2 pi s^2)^(-3/2) exp(-|x - x_s|^2 / (2 s^2)), given as
+ *    src[6*k .. 6*k+5] = (x, y, z, sigma, re a, im a). */
+typedef struct {
+  double dir[3];
+  double amp[2];
+  int32_t nsrc;
+  const double *src;
+} dpg_load;
+
+typedef struct {
+  int32_t precision;  /* DPG_FP64: everything FP64.  DPG_MIXED: V-cycle
+                         (matvecs, smoother, transfers) in complex FP32;
+                         setup, coarsest factor and outer CG in FP64.        */
+  int32_t nu_pre;     /* smoothing sweeps before / after the coarse solve    */
+  int32_t nu_post;
+  int32_t nlevels;    /* 0: halve while n is even and n > 2 (n = 2: once)    */
+  int32_t maxit;      /* outer CG iteration cap                              */
+  int32_t flags;      /* DPG_DEVICE_PTRS                                     */
+  double theta;       /* smoother damping; must be < 1/4                     */
+  int64_t hbm_budget; /* bytes the context may allocate; 0 = no limit        */
+  void *stream;       /* hipStream_t to launch on; NULL = default stream     */
+} dpg_options;
+
+typedef struct dpg_ctx dpg_ctx;
+
+/* Fills opt with the defaults: FP64, V(1,1), theta = 1/5, maxit = 500. */
+void dpg_default_options(dpg_options *opt);
+
+/* Builds the mesh topology (canonical numbering, element maps, macro sets,
+ * vertex patches, prolongation maps) for an n^3 mesh of order p >= 1 with
+ * test enrichment dp >= 1 and angular frequency omega > 0, and uploads it.
+ * loads[0..nrhs-1] are the right-hand sides assembled by dpg_assemble.
+ * mat may be NULL.  On success *out owns the context. */
+int dpg_setup(const dpg_mesh *mesh, int p, int dp, double omega, const dpg_material *mat,
+              const dpg_load *loads, int nrhs, const dpg_options *opt, dpg_ctx **out);
+
+/* Element DPG work on the GPU, all in FP64 (Sec. 2 and Sec. 1.2): Gram
+ * matrix G of the adjoint graph norm, B and loads l; Cholesky G = L L^H;
+ * W = L^-1 [B l]; K = W^H W; static condensation of the fields,
+ * S = K_tt - K_tf K_ff^-1 K_ft and s likewise.  Errors: DPG_ENOTPD names
+ * the element. */
+int dpg_assemble(dpg_ctx *ctx);
+
+/* Multigrid hierarchy on the GPU (Sec. 3), FP64: per level, macro
+ * condensation of the 8 children of every coarse element, Galerkin coarse
+ * element matrices P^T M P, vertex-patch blocks factored and inverted (the
+ * inverse kept in FP64, plus an FP32 copy in mixed mode); dense Cholesky of
+ * the coarsest operator. */
+int dpg_build_hierarchy(dpg_ctx *ctx);
+
+/* Replaces the assembled loads by new right-hand sides for the same operator
+ * (runs the load part of dpg_assemble).  Output: the condensed trace loads,
+ * n_trace x nrhs, if s_out is not NULL. */
+int dpg_load_rhs(dpg_ctx *ctx, const dpg_load *loads, int nrhs, double *s_out);
+
+/* Solves T x = rhs for nrhs right-hand sides (rhs: n_trace x nrhs trace
+ * vectors; NULL: the assembled loads).  PCG on the macro grid with one
+ * V(nu_pre, nu_post) cycle per iteration, x0 = 0, stop at
+ * ||r|| / ||b|| <= tol (macro-grid residual), then recovery of the
+ * condensed unknowns.  Outputs: x (n_trace x nrhs, canonical order),
+ * iteration counts and final relative residuals (nrhs each; any may be
+ * NULL).  Returns DPG_ENOCONV if some column hit maxit (its x is the last
+ * iterate). */
+int dpg_solve(dpg_ctx *ctx, const double *rhs, int nrhs, double tol, double *x_out,
+              int32_t *iters_out, double *relres_out);
+
+/* Field coefficients of the element-interior unknowns for trace solutions x
+ * (n_trace x nrhs): x_f = K_ff^-1 (b_f - K_ft x_t) per element, output
+ * [nrhs][n^3][4 p^3] in the order (p, u_x, u_y, u_z), each a Legendre
+ * tensor product with x-degree fastest.  Requires the assembled loads. */
+int dpg_get_fields(dpg_ctx *ctx, const double *x, int nrhs, double *fields_out);
+
+typedef struct {
+  int64_t n_trace;          /* trace unknowns of the finest mesh          */
+  int64_t n_macro;          /* macro-grid unknowns of the finest mesh     */
+  int32_t nlevels;          /* meshes in the hierarchy (finest included)  */
+  int32_t level_n[16];      /* mesh size per level, finest first          */
+  int64_t level_ntrace[16];
+  int64_t level_nmacro[16]; /* 0 for the coarsest                         */
+  int64_t resident_bytes;   /* device memory held by the context          */
+  int32_t n_test, n_field, n_tr;
+  double setup_ms[4];       /* topology, assemble, hierarchy, last solve  */
+} dpg_info_t;
+
+int dpg_info(const dpg_ctx *ctx, dpg_info_t *info);
+
+/* Export of internal arrays, for testing against an independent reference.
+ * Writes at most cap elements to out and returns the number of elements the
+ * full array has (or a negative error).  `level` indexes meshes finest = 0.
+ * Integer arrays are int64; matrices are complex (2 doubles per entry). */
+enum {
+  DPG_X_ELEM_DOFS = 1,   /* int64 [nel][n_tr], -1 = absent (Gamma flux)          */
+  DPG_X_MACRO_B = 2,     /* int64 canonical index of each macro unknown         */
+  DPG_X_BLOCK_B = 3,     /* int64 CSR: [nblk+1 offsets][macro indices, ascending]*/
+  DPG_X_BLOCK_I = 4,     /* int64 CSR: [nblk+1 offsets][canonical indices]      */
+  DPG_X_PATCHES = 5,     /* int64 CSR: [npatch+1 offsets][macro indices]        */
+  DPG_X_PROLONG = 6,     /* int64 CSR of P: [nM+1 offsets][coarse trace cols]   */
+  DPG_X_ELEM_S = 7,      /* complex [nel][n_tr][n_tr] condensed element matrix  */
+  DPG_X_ELEM_RHS = 8,    /* complex [nrhs][nel][n_tr] condensed element loads   */
+  DPG_X_MACRO_M = 9,     /* complex per block n_B x n_B (ascending macro order) */
+  DPG_X_COARSE_E = 10,   /* complex [nel][n_tr][n_tr] Galerkin element matrices */
+  DPG_X_PATCH_INV = 11,  /* complex per patch n x n inverse of the patch block  */
+  DPG_X_COARSEST = 12,   /* complex n0 x n0 coarsest operator T_0               */
+  DPG_X_PROLONG_VAL = 13,/* double values of P, in the order of DPG_X_PROLONG   */
+  DPG_X_ASM_RHS = 14     /* complex [nrhs][n_trace] assembled condensed loads   */
+};
+int64_t dpg_export(const dpg_ctx *ctx, int what, int level, void *out, int64_t cap);
+
+const char *dpg_last_error(const dpg_ctx *ctx);
+
+void dpg_destroy(dpg_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPGMG_H */

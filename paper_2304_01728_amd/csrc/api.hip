@@ -1,0 +1,988 @@
+// C ABI of libdpgmg (include/dpgmg.h): setup, element stage, hierarchy,
+// preconditioned CG with the DPG-MG V-cycle, exports.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "ctx.hpp"
+
+using namespace dpg;
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+double ms_since(clk::time_point t0) {
+  return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+
+template <class F> int guarded(dpg_ctx *c, F &&f) {
+  try {
+    return f();
+  } catch (const DpgError &e) {
+    if (c) c->err = e.what();
+    return e.code;
+  } catch (const std::exception &e) {
+    if (c) c->err = e.what();
+    return DPG_EINVAL;
+  }
+}
+
+// Mesh sizes from finest to coarsest: halve while N is even and N > 2; a
+// mesh with N = 2 is halved once.
+std::vector<int> level_sizes(int N, int nlevels) {
+  std::vector<int> s{N};
+  while (N % 2 == 0 && (N > 2 || s.size() == 1)) {
+    N /= 2;
+    s.push_back(N);
+  }
+  if (nlevels > 0 && (int)s.size() > nlevels) s.resize(nlevels);
+  return s;
+}
+
+void set_loads(dpg_ctx *c, const dpg_load *loads, int nrhs) {
+  c->nrhs = nrhs;
+  c->ld_h.assign(nrhs, LoadDesc{});
+  c->src_h.clear();
+  for (int r = 0; r < nrhs; ++r) {
+    LoadDesc &d = c->ld_h[r];
+    for (int k = 0; k < 3; ++k) d.dir[k] = loads[r].dir[k];
+    d.amp[0] = loads[r].amp[0];
+    d.amp[1] = loads[r].amp[1];
+    d.src0 = (int)(c->src_h.size() / 6);
+    d.nsrc = loads[r].nsrc;
+    if (d.nsrc < 0 || (d.nsrc > 0 && !loads[r].src)) throw DpgError(DPG_EINVAL, "bad source list");
+    for (int k = 0; k < 6 * d.nsrc; ++k) c->src_h.push_back(loads[r].src[k]);
+    for (int k = 0; k < d.nsrc; ++k)
+      if (!(loads[r].src[6 * k + 3] > 0.0)) throw DpgError(DPG_EINVAL, "source width must be > 0");
+  }
+  c->ld.upload(c->ld_h, &c->bud, c->stream);
+  if (c->src_h.empty()) c->src_h.push_back(0.0);
+  c->src.upload(c->src_h, &c->bud, c->stream);
+  HIP_OK(hipStreamSynchronize(c->stream));
+}
+
+template <class Item> void upload_items(DevBuf<Item> &d, const std::vector<Item> &h, dpg_ctx *c) {
+  d.upload(h, &c->bud, c->stream);
+}
+
+void check_info(DevBuf<int> &info, int count, dpg_ctx *c, const char *what, int base) {
+  std::vector<int> h(count);
+  HIP_OK(hipMemcpyAsync(h.data(), info.p, count * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < count; ++i)
+    if (h[i] != 0)
+      throw DpgError(DPG_ENOTPD, std::string(what) + " " + std::to_string(base + i) +
+                                     ": Cholesky pivot " + std::to_string(h[i] - 1) +
+                                     " is not positive");
+}
+
+// ---- element stage -----------------------------------------------------------------
+
+void element_stage(dpg_ctx *c, bool write_matrices) {
+  LevelData &f = c->lv[c->L];
+  const int nt = c->n_test, nf = c->n_field, ntr = c->n_tr, m = c->m, nr = c->nrhs;
+  const int mp = m + nr;
+  const int nel = f.nel;
+  const int64_t per = 16LL * ((int64_t)nt * nt + (int64_t)nt * mp + (int64_t)mp * mp);
+  int C = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nel, 2500000000LL / per, 65535}));
+  DevBuf<double2> G, BL, K;
+  G.alloc((int64_t)C * nt * nt, &c->bud);
+  BL.alloc((int64_t)C * nt * mp, &c->bud);
+  K.alloc((int64_t)C * mp * mp, &c->bud);
+  std::vector<PotrfItem> pG(C), pK(C);
+  std::vector<TrsmItem> tG(C), tK(C);
+  std::vector<GemmItem> gK(C), gS(C);
+  for (int i = 0; i < C; ++i) {
+    const int64_t oG = (int64_t)i * nt * nt, oB = (int64_t)i * nt * mp, oK = (int64_t)i * mp * mp;
+    pG[i] = {oG, nt, nt};
+    tG[i] = {oG, oB, nt, mp, nt, nt};
+    gK[i] = {oB, oB, oK, mp, mp, nt, nt, nt, mp};
+    pK[i] = {oK, nf, mp};
+    tK[i] = {oK, oK + (int64_t)nf * mp, nf, mp - nf, mp, mp};
+    gS[i] = {oK + (int64_t)nf * mp, oK + (int64_t)nf * mp, oK + nf + (int64_t)nf * mp,
+             mp - nf, mp - nf, nf, mp, mp, mp};
+  }
+  DevBuf<PotrfItem> dpG, dpK;
+  DevBuf<TrsmItem> dtG, dtK;
+  DevBuf<GemmItem> dgK, dgS;
+  upload_items(dpG, pG, c);
+  upload_items(dpK, pK, c);
+  upload_items(dtG, tG, c);
+  upload_items(dtK, tK, c);
+  upload_items(dgK, gK, c);
+  upload_items(dgS, gS, c);
+  DevBuf<int> info;
+  info.alloc(C, &c->bud);
+  ElemGeom g{c->N, c->side / c->N, c->omega, 1.0, {c->org[0], c->org[1], c->org[2]}};
+  const hipStream_t s = c->stream;
+  for (int e0 = 0; e0 < nel; e0 += C) {
+    const int cnt = std::min(C, nel - e0);
+    launch_gram(c->tables.p, c->testd.p, nt, g, c->kappa.p, e0, cnt, G.p, s);
+    launch_bmat(c->tables.p, c->testd.p, c->triald.p, nt, m, g, c->kappa.p, c->Zel.p, e0, cnt,
+                BL.p, (int64_t)nt * mp, s);
+    launch_load(c->tables.p, nt, m, g, c->Zel.p, c->ld.p, c->src.p, nr, e0, cnt, BL.p,
+                (int64_t)nt * mp, s);
+    potrf_batched(G.p, dpG.p, cnt, info.p, s);
+    check_info(info, cnt, c, "element Gram matrix", e0);
+    trsm_batched(G.p, BL.p, dtG.p, cnt, mp, s);
+    gemm_batched(OP_C, OP_N, mk(1, 0), BL.p, BL.p, mk(0, 0), K.p, dgK.p, cnt, mp, mp, s);
+    potrf_batched(K.p, dpK.p, cnt, info.p, s);
+    check_info(info, cnt, c, "element field block", e0);
+    trsm_batched(K.p, K.p, dtK.p, cnt, mp - nf, s);
+    gemm_batched(OP_C, OP_N, mk(-1, 0), K.p, K.p, mk(1, 0), K.p, dgS.p, cnt, mp - nf, mp - nf, s);
+    if (write_matrices)
+      launch_copy_sub(K.p, (int64_t)mp * mp, mp, nf, nf, ntr, ntr, f.E.p + (int64_t)e0 * ntr * ntr,
+                      (int64_t)ntr * ntr, ntr, cnt, s);
+    for (int r = 0; r < nr; ++r)
+      launch_copy_sub(K.p, (int64_t)mp * mp, mp, nf, m + r, ntr, 1,
+                      c->s_elem.p + ((int64_t)r * nel + e0) * ntr, ntr, ntr, cnt, s);
+    if (c->keep_recovery) {
+      launch_copy_sub(K.p, (int64_t)mp * mp, mp, 0, 0, nf, nf, c->rec_L.p + (int64_t)e0 * nf * nf,
+                      (int64_t)nf * nf, nf, cnt, s);
+      launch_copy_sub(K.p, (int64_t)mp * mp, mp, 0, nf, nf, mp - nf,
+                      c->rec_Y.p + (int64_t)e0 * nf * (mp - nf), (int64_t)nf * (mp - nf), nf, cnt,
+                      s);
+    }
+  }
+  // assembled loads
+  for (int r = 0; r < nr; ++r)
+    launch_assemble_vec(f.num.n, c->asm_ptr.p, c->asm_ent.p, c->s_elem.p + (int64_t)r * nel * ntr,
+                        0, c->s_asm.p + (int64_t)r * f.num.n, s);
+  HIP_OK(hipStreamSynchronize(s));
+}
+
+// ---- hierarchy -------------------------------------------------------------------------
+
+void build_macro_level(dpg_ctx *c, int l) {
+  LevelData &f = c->lv[l];
+  LevelData &cl = c->lv[l - 1];
+  const hipStream_t s = c->stream;
+  const int ntr = c->n_tr, nBf = f.nBf, nI = f.nI, nT = nBf + nI, nblk = f.nblk;
+  cl.E.alloc((int64_t)nblk * ntr * ntr, &c->bud);
+  f.Mfull.alloc((int64_t)nblk * nBf * nBf, &c->bud);
+  f.Tinv.alloc((int64_t)nblk * nI * nI, &c->bud);
+  f.WH.alloc((int64_t)nblk * nBf * nI, &c->bud);
+  std::vector<double2> ploc_h(f.P.local.size());
+  for (size_t i = 0; i < ploc_h.size(); ++i) ploc_h[i] = mk(f.P.local[i], 0.0);
+  DevBuf<double2> Ploc;
+  Ploc.upload(ploc_h, &c->bud, s);
+  const int64_t per = 16LL * ((int64_t)nT * nT + (int64_t)nI * nI + (int64_t)nBf * ntr);
+  const int CB = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nblk, 2500000000LL / per, 65535}));
+  DevBuf<double2> T, Linv, X;
+  T.alloc((int64_t)CB * nT * nT, &c->bud);
+  Linv.alloc((int64_t)CB * nI * nI, &c->bud);
+  X.alloc((int64_t)CB * nBf * ntr, &c->bud);
+  std::vector<PotrfItem> pII(CB);
+  std::vector<TrsmItem> tIB(CB), tLi(CB);
+  std::vector<GemmItem> gS(CB), gTi(CB), gWH(CB), gX(CB), gA(CB);
+  std::vector<int64_t> idoff(CB);
+  std::vector<int32_t> idn(CB, nI);
+  for (int i = 0; i < CB; ++i) {
+    const int64_t oT = (int64_t)i * nT * nT, oL = (int64_t)i * nI * nI;
+    const int64_t oII = oT + nBf + (int64_t)nBf * nT, oIB = oT + nBf;
+    pII[i] = {oII, nI, nT};
+    tIB[i] = {oII, oIB, nI, nBf, nT, nT};
+    gS[i] = {oIB, oIB, oT, nBf, nBf, nI, nT, nT, nT};
+    tLi[i] = {oII, oL, nI, nI, nT, nI};
+    gTi[i] = {oL, oL, oL, nI, nI, nI, nI, nI, nI};
+    gWH[i] = {oIB, oL, (int64_t)i * nBf * nI, nBf, nI, nI, nT, nI, nBf};
+    gX[i] = {oT, 0, (int64_t)i * nBf * ntr, nBf, ntr, nBf, nT, nBf, nBf};
+    gA[i] = {0, (int64_t)i * nBf * ntr, (int64_t)i * ntr * ntr, ntr, ntr, nBf, nBf, nBf, ntr};
+    idoff[i] = oL;
+  }
+  DevBuf<PotrfItem> dpII;
+  DevBuf<TrsmItem> dtIB, dtLi;
+  DevBuf<GemmItem> dgS, dgTi, dgWH, dgX, dgA;
+  DevBuf<int64_t> didoff;
+  DevBuf<int32_t> didn;
+  upload_items(dpII, pII, c);
+  upload_items(dtIB, tIB, c);
+  upload_items(dtLi, tLi, c);
+  upload_items(dgS, gS, c);
+  upload_items(dgTi, gTi, c);
+  upload_items(dgWH, gWH, c);
+  upload_items(dgX, gX, c);
+  upload_items(dgA, gA, c);
+  didoff.upload(idoff, &c->bud, s);
+  didn.upload(idn, &c->bud, s);
+  DevBuf<int32_t> cmap;
+  cmap.upload(f.mc.child_map, &c->bud, s);
+  DevBuf<int> info;
+  info.alloc(CB, &c->bud);
+  for (int b0 = 0; b0 < nblk; b0 += CB) {
+    const int cnt = std::min(CB, nblk - b0);
+    launch_macro_assemble(f.E.p, ntr, cmap.p, f.N, b0, cnt, nT, T.p, s);
+    potrf_batched(T.p, dpII.p, cnt, info.p, s);
+    check_info(info, cnt, c, "interior block of coarse element", b0);
+    trsm_batched(T.p, T.p, dtIB.p, cnt, nBf, s);
+    gemm_batched(OP_C, OP_N, mk(-1, 0), T.p, T.p, mk(1, 0), T.p, dgS.p, cnt, nBf, nBf, s);
+    launch_identity(didoff.p, didn.p, cnt, nI, Linv.p, s);
+    trsm_batched(T.p, Linv.p, dtLi.p, cnt, nI, s);
+    gemm_batched(OP_C, OP_N, mk(1, 0), Linv.p, Linv.p, mk(0, 0), f.Tinv.p + (int64_t)b0 * nI * nI,
+                 dgTi.p, cnt, nI, nI, s);
+    gemm_batched(OP_C, OP_N, mk(1, 0), T.p, Linv.p, mk(0, 0), f.WH.p + (int64_t)b0 * nBf * nI,
+                 dgWH.p, cnt, nBf, nI, s);
+    launch_copy_sub(T.p, (int64_t)nT * nT, nT, 0, 0, nBf, nBf, f.Mfull.p + (int64_t)b0 * nBf * nBf,
+                    (int64_t)nBf * nBf, nBf, cnt, s);
+    gemm_batched(OP_N, OP_N, mk(1, 0), T.p, Ploc.p, mk(0, 0), X.p, dgX.p, cnt, nBf, ntr, s);
+    gemm_batched(OP_T, OP_N, mk(1, 0), Ploc.p, X.p, mk(0, 0), cl.E.p + (int64_t)b0 * ntr * ntr,
+                 dgA.p, cnt, ntr, ntr, s);
+  }
+  HIP_OK(hipStreamSynchronize(s));
+  if (c->opt.precision == DPG_MIXED && l < c->L) {
+    f.Tinv32.alloc(f.Tinv.n, &c->bud);
+    f.WH32.alloc(f.WH.n, &c->bud);
+    launch_to32(f.Tinv.n, f.Tinv.p, f.Tinv32.p, s);
+    launch_to32(f.WH.n, f.WH.p, f.WH32.p, s);
+  }
+  // macro blocks -> packed tiles (present slots only)
+  std::vector<int64_t> soff(nblk), moff(nblk);
+  std::vector<int32_t> sld(nblk, nBf);
+  for (int b = 0; b < nblk; ++b) {
+    soff[b] = (int64_t)b * nBf * nBf;
+    moff[b] = f.mc.blkB_ptr[b];
+  }
+  DevBuf<int64_t> dsoff, dmoff;
+  DevBuf<int32_t> dsld, dmap;
+  dsoff.upload(soff, &c->bud, s);
+  dmoff.upload(moff, &c->bud, s);
+  dsld.upload(sld, &c->bud, s);
+  dmap.upload(f.mc.blkB_present, &c->bud, s);
+  f.Mset.pack(f.Mfull.p, dsoff.p, dsld.p, dmoff.p, dmap.p, s);
+  HIP_OK(hipStreamSynchronize(s));
+}
+
+void build_patches(dpg_ctx *c, int l) {
+  LevelData &f = c->lv[l];
+  const hipStream_t s = c->stream;
+  const int np = (int)f.mc.patch_ptr.size() - 1;
+  std::vector<int32_t> nv(np);
+  for (int v = 0; v < np; ++v) nv[v] = (int32_t)(f.mc.patch_ptr[v + 1] - f.mc.patch_ptr[v]);
+  const int64_t cap = 1500000000LL / 32;   // entries per workspace (S and X)
+  int64_t maxent = 0;
+  for (int v = 0; v < np; ++v) maxent = std::max<int64_t>(maxent, (int64_t)nv[v] * nv[v]);
+  const int64_t ws = std::max(cap, maxent);
+  DevBuf<double2> S, X;
+  S.alloc(ws, &c->bud);
+  X.alloc(ws, &c->bud);
+  DevBuf<int> info;
+  info.alloc(std::min(np, 65535), &c->bud);
+  std::vector<int64_t> soff_all(np, 0);
+  DevBuf<int64_t> dsoff_all;
+  DevBuf<int32_t> dld_all;
+  dsoff_all.alloc(np, &c->bud);
+  dld_all.upload(nv, &c->bud, s);
+  int v0 = 0;
+  while (v0 < np) {
+    int cnt = 0;
+    int64_t used = 0;
+    while (v0 + cnt < np && cnt < 65535 && (cnt == 0 || used + (int64_t)nv[v0 + cnt] * nv[v0 + cnt] <= ws)) {
+      used += (int64_t)nv[v0 + cnt] * nv[v0 + cnt];
+      ++cnt;
+    }
+    std::vector<int64_t> off(cnt);
+    std::vector<int32_t> nn(cnt);
+    std::vector<PotrfItem> pi(cnt);
+    std::vector<TrsmItem> ti(cnt);
+    std::vector<GemmItem> gi(cnt);
+    int64_t o = 0;
+    int nmax = 0;
+    for (int i = 0; i < cnt; ++i) {
+      const int n = nv[v0 + i];
+      off[i] = o;
+      nn[i] = n;
+      nmax = std::max(nmax, n);
+      pi[i] = {o, n, n};
+      ti[i] = {o, o, n, n, n, n};
+      gi[i] = {o, o, o, n, n, n, n, n, n};
+      soff_all[v0 + i] = o;
+      o += (int64_t)n * n;
+    }
+    DevBuf<int64_t> doff;
+    DevBuf<int32_t> dnn;
+    DevBuf<PotrfItem> dpi;
+    DevBuf<TrsmItem> dti;
+    DevBuf<GemmItem> dgi;
+    doff.upload(off, &c->bud, s);
+    dnn.upload(nn, &c->bud, s);
+    upload_items(dpi, pi, c);
+    upload_items(dti, ti, c);
+    upload_items(dgi, gi, c);
+    HIP_OK(hipMemcpyAsync(dsoff_all.p, soff_all.data(), np * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    launch_patch_gather(f.Mfull.p, f.nBf, f.mc.Nc, f.patch_ptr.p, f.patch_slot.p, v0, cnt, doff.p,
+                        S.p, s);
+    potrf_batched(S.p, dpi.p, cnt, info.p, s);
+    check_info(info, cnt, c, "vertex patch", v0);
+    launch_identity(doff.p, dnn.p, cnt, nmax, X.p, s);
+    trsm_batched(S.p, X.p, dti.p, cnt, nmax, s);
+    gemm_batched(OP_C, OP_N, mk(1, 0), X.p, X.p, mk(0, 0), S.p, dgi.p, cnt, nmax, nmax, s);
+    const int64_t t0 = f.Sset.tile_off_h[v0];
+    const int64_t t1 = (v0 + cnt < np) ? f.Sset.tile_off_h[v0 + cnt] : f.Sset.ntiles;
+    f.Sset.pack(S.p, dsoff_all.p, dld_all.p, nullptr, nullptr, s, t0, t1 - t0);
+    HIP_OK(hipStreamSynchronize(s));
+    v0 += cnt;
+  }
+}
+
+void build_coarsest(dpg_ctx *c) {
+  LevelData &z = c->lv[0];
+  const hipStream_t s = c->stream;
+  const int n0 = (int)z.num.n;
+  c->T0.alloc((int64_t)n0 * n0, &c->bud);
+  launch_assemble_dense(z.E.p, c->n_tr, z.edofs.p, z.nel, n0, c->T0.p, s);
+  DevBuf<double2> F, Li, Ti;
+  F.alloc((int64_t)n0 * n0, &c->bud);
+  Li.alloc((int64_t)n0 * n0, &c->bud);
+  Ti.alloc((int64_t)n0 * n0, &c->bud);
+  HIP_OK(hipMemcpyAsync(F.p, c->T0.p, (size_t)n0 * n0 * 16, hipMemcpyDeviceToDevice, s));
+  std::vector<PotrfItem> pi{{0, n0, n0}};
+  std::vector<TrsmItem> ti{{0, 0, n0, n0, n0, n0}};
+  std::vector<GemmItem> gi{{0, 0, 0, n0, n0, n0, n0, n0, n0}};
+  std::vector<int64_t> off{0};
+  std::vector<int32_t> nn{n0};
+  DevBuf<PotrfItem> dpi;
+  DevBuf<TrsmItem> dti;
+  DevBuf<GemmItem> dgi;
+  DevBuf<int64_t> doff;
+  DevBuf<int32_t> dnn;
+  upload_items(dpi, pi, c);
+  upload_items(dti, ti, c);
+  upload_items(dgi, gi, c);
+  doff.upload(off, &c->bud, s);
+  dnn.upload(nn, &c->bud, s);
+  DevBuf<int> info;
+  info.alloc(1, &c->bud);
+  potrf_batched(F.p, dpi.p, 1, info.p, s);
+  check_info(info, 1, c, "coarsest operator", 0);
+  launch_identity(doff.p, dnn.p, 1, n0, Li.p, s);
+  trsm_batched(F.p, Li.p, dti.p, 1, n0, s);
+  gemm_batched(OP_C, OP_N, mk(1, 0), Li.p, Li.p, mk(0, 0), Ti.p, dgi.p, 1, n0, n0, s);
+  std::vector<int32_t> ld{n0};
+  DevBuf<int32_t> dld;
+  dld.upload(ld, &c->bud, s);
+  c->T0set.pack(Ti.p, doff.p, dld.p, nullptr, nullptr, s);
+  HIP_OK(hipStreamSynchronize(s));
+}
+
+// ---- V-cycle -----------------------------------------------------------------------------
+
+template <typename T> struct LB;
+template <> struct LB<double> {
+  static double2 *r(LevelData &f) { return f.r64.p; }
+  static double2 *x(LevelData &f) { return f.x64.p; }
+  static double2 *res(LevelData &f) { return f.res64.p; }
+  static double2 *rc(LevelData &f) { return f.rc64.p; }
+  static double2 *ec(LevelData &f) { return f.ec64.p; }
+  static double2 *cc(LevelData &f) { return f.c64.p; }
+  static const double2 *WH(LevelData &f) { return f.WH.p; }
+  static const double2 *Ti(LevelData &f) { return f.Tinv.p; }
+  static const double *Pv(LevelData &f) { return f.Pval.p; }
+  static const double *Ptv(LevelData &f) { return f.Ptval.p; }
+};
+template <> struct LB<float> {
+  static float2 *r(LevelData &f) { return f.r32.p; }
+  static float2 *x(LevelData &f) { return f.x32.p; }
+  static float2 *res(LevelData &f) { return f.res32.p; }
+  static float2 *rc(LevelData &f) { return f.rc32.p; }
+  static float2 *ec(LevelData &f) { return f.ec32.p; }
+  static float2 *cc(LevelData &f) { return f.c32.p; }
+  static const float2 *WH(LevelData &f) { return f.WH32.p; }
+  static const float2 *Ti(LevelData &f) { return f.Tinv32.p; }
+  static const float *Pv(LevelData &f) { return f.Pval32.p; }
+  static const float *Ptv(LevelData &f) { return f.Ptval32.p; }
+};
+
+template <typename T> void vcycle(dpg_ctx *c, int l) {
+  using B = LB<T>;
+  LevelData &f = c->lv[l];
+  const hipStream_t s = c->stream;
+  const T th = (T)c->opt.theta;
+  auto r = B::r(f), x = B::x(f), res = B::res(f), rc = B::rc(f), ec = B::ec(f);
+  if (c->opt.nu_pre == 0) HIP_OK(hipMemsetAsync(x, 0, f.nM * sizeof(*x), s));
+  for (int k = 0; k < c->opt.nu_pre; ++k) {
+    if (k == 0) {
+      herm_apply<T>(f.Sset, r, x, nullptr, RED_SET_SCALED, th, s);
+    } else {
+      herm_apply<T>(f.Mset, x, res, r, RED_RESID, (T)0, s);
+      herm_apply<T>(f.Sset, res, x, nullptr, RED_AXPY, th, s);
+    }
+  }
+  herm_apply<T>(f.Mset, x, res, r, RED_RESID, (T)0, s);
+  LevelData &g = c->lv[l - 1];
+  launch_csr<T>(g.num.n, f.Ptptr.p, f.Ptcol.p, B::Ptv(f), res, rc, 0, s);
+  if (l - 1 == 0) {
+    herm_apply<T>(c->T0set, rc, ec, nullptr, RED_SET, (T)1, s);
+  } else {
+    launch_condense_local<T>(B::WH(g), g.nI, g.nBf, g.blkI.p, g.nblk, rc, B::cc(g), s);
+    launch_condense_reduce<T>(g.nM, g.macroB.p, g.cred_ptr.p, g.cred_ent.p, rc, B::cc(g), B::r(g), s);
+    vcycle<T>(c, l - 1);
+    launch_expand<T>(B::WH(g), B::Ti(g), g.nI, g.nBf, g.blkI.p, g.blkBm.p, g.nblk, rc, B::x(g),
+                     g.nM, g.macroB.p, ec, s);
+  }
+  launch_csr<T>(f.nM, f.Pptr.p, f.Pcol.p, B::Pv(f), ec, x, 1, s);
+  for (int k = 0; k < c->opt.nu_post; ++k) {
+    herm_apply<T>(f.Mset, x, res, r, RED_RESID, (T)0, s);
+    herm_apply<T>(f.Sset, res, x, nullptr, RED_AXPY, th, s);
+  }
+}
+
+// z = V(r) on the finest macro grid (FP64 vectors in and out).
+void precondition(dpg_ctx *c, const double2 *r, double2 *z) {
+  LevelData &top = c->lv[c->L];
+  const hipStream_t s = c->stream;
+  if (c->opt.precision == DPG_MIXED) {
+    launch_to32(top.nM, r, top.r32.p, s);
+    vcycle<float>(c, c->L);
+    launch_to64(top.nM, top.x32.p, z, s);
+  } else {
+    HIP_OK(hipMemcpyAsync(top.r64.p, r, top.nM * 16, hipMemcpyDeviceToDevice, s));
+    vcycle<double>(c, c->L);
+    HIP_OK(hipMemcpyAsync(z, top.x64.p, top.nM * 16, hipMemcpyDeviceToDevice, s));
+  }
+}
+
+void read_sc(dpg_ctx *c) {
+  HIP_OK(hipMemcpyAsync(c->host_sc, c->sc.p, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));
+}
+
+// PCG on the finest macro grid for one trace right-hand side s (device);
+// full trace solution into xout (device).  Returns DPG_OK / ENOCONV.
+int solve_one(dpg_ctx *c, const double2 *sv, double tol, double2 *xout, int32_t *iters,
+              double *relres) {
+  LevelData &top = c->lv[c->L];
+  const hipStream_t s = c->stream;
+  const int64_t nM = top.nM;
+  launch_condense_local<double>(top.WH.p, top.nI, top.nBf, top.blkI.p, top.nblk, sv, top.c64.p, s);
+  launch_condense_reduce<double>(nM, top.macroB.p, top.cred_ptr.p, top.cred_ent.p, sv, top.c64.p,
+                                 c->b.p, s);
+  HIP_OK(hipMemsetAsync(c->sc.p, 0, 8 * sizeof(double), s));
+  dot_re(nM, c->b.p, c->b.p, c->partial.p, c->sc.p + 5, s);
+  HIP_OK(hipMemsetAsync(c->x.p, 0, nM * 16, s));
+  HIP_OK(hipMemcpyAsync(c->r.p, c->b.p, nM * 16, hipMemcpyDeviceToDevice, s));
+  read_sc(c);
+  const double bb = c->host_sc[5];
+  int it = 0;
+  double rr = 0.0;
+  int status = DPG_OK;
+  if (!std::isfinite(bb)) throw DpgError(DPG_EINVAL, "right-hand side is not finite");
+  if (bb > 0.0) {
+    double2 *z = c->z.p, *zo = c->zo.p;
+    precondition(c, c->r.p, z);
+    dot_re(nM, c->r.p, z, c->partial.p, c->sc.p + 0, s);
+    HIP_OK(hipMemcpyAsync(c->pv.p, z, nM * 16, hipMemcpyDeviceToDevice, s));
+    rr = 1.0;
+    while (it < c->opt.maxit) {
+      herm_apply<double>(top.Mset, c->pv.p, c->q.p, nullptr, RED_SET, 1.0, s);
+      cg_alpha(nM, c->pv.p, c->q.p, c->partial.p, c->sc.p, s);
+      cg_update_xr(nM, c->x.p, c->r.p, c->pv.p, c->q.p, c->partial.p, c->sc.p, s);
+      ++it;
+      read_sc(c);
+      if (c->host_sc[6] != 0.0)
+        throw DpgError(DPG_EBREAKDOWN, "CG breakdown at iteration " + std::to_string(it) +
+                                           " (p^H M p = " + std::to_string(c->host_sc[1]) + ")");
+      rr = std::sqrt(c->host_sc[4] / bb);
+      if (!std::isfinite(rr)) throw DpgError(DPG_EBREAKDOWN, "residual is not finite");
+      if (rr <= tol) break;
+      std::swap(z, zo);
+      precondition(c, c->r.p, z);
+      cg_beta(nM, c->r.p, z, zo, c->partial.p, c->sc.p, s);
+      cg_update_p(nM, c->pv.p, z, c->sc.p, s);
+    }
+    if (rr > tol) status = DPG_ENOCONV;
+  }
+  launch_expand<double>(top.WH.p, top.Tinv.p, top.nI, top.nBf, top.blkI.p, top.blkBm.p, top.nblk,
+                        sv, c->x.p, nM, top.macroB.p, xout, s);
+  HIP_OK(hipStreamSynchronize(s));
+  if (iters) *iters = it;
+  if (relres) *relres = rr;
+  return status;
+}
+
+template <typename V> int64_t put(const std::vector<V> &v, void *out, int64_t cap) {
+  if (out && cap > 0) std::memcpy(out, v.data(), sizeof(V) * std::min<int64_t>(cap, (int64_t)v.size()));
+  return (int64_t)v.size();
+}
+template <typename V> std::vector<int64_t> widen(const std::vector<V> &v) {
+  return std::vector<int64_t>(v.begin(), v.end());
+}
+}  // namespace
+
+// ---- API ------------------------------------------------------------------------------------
+
+extern "C" {
+
+void dpg_default_options(dpg_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = DPG_FP64;
+  o->nu_pre = 1;
+  o->nu_post = 1;
+  o->nlevels = 0;
+  o->maxit = 500;
+  o->flags = 0;
+  o->theta = 0.2;
+  o->hbm_budget = 0;
+  o->stream = nullptr;
+}
+
+int dpg_setup(const dpg_mesh *mesh, int p, int dp, double omega, const dpg_material *mat,
+              const dpg_load *loads, int nrhs, const dpg_options *opt, dpg_ctx **out) {
+  if (!out) return DPG_EINVAL;
+  *out = nullptr;
+  if (!mesh || mesh->n < 1 || p < 1 || dp < 1 || !(omega > 0) || !(mesh->side > 0) || nrhs < 0 ||
+      (nrhs > 0 && !loads))
+    return DPG_EINVAL;
+  dpg_ctx *c = new dpg_ctx();
+  int rc = guarded(c, [&]() {
+    auto t0 = clk::now();
+    if (opt) c->opt = *opt;
+    else dpg_default_options(&c->opt);
+    if (!(c->opt.theta > 0.0 && c->opt.theta < 0.25))
+      throw DpgError(DPG_EINVAL, "smoother damping must lie in (0, 1/4)");
+    if (c->opt.nu_pre < 0 || c->opt.nu_post < 0 || c->opt.maxit < 1)
+      throw DpgError(DPG_EINVAL, "bad smoothing counts or maxit");
+    if (c->opt.precision != DPG_FP64 && c->opt.precision != DPG_MIXED)
+      throw DpgError(DPG_EINVAL, "unknown precision mode");
+    c->stream = (hipStream_t)c->opt.stream;
+    c->bud.limit = c->opt.hbm_budget;
+    c->N = mesh->n;
+    c->p = p;
+    c->dp = dp;
+    c->omega = omega;
+    c->side = mesh->side;
+    for (int k = 0; k < 3; ++k) c->org[k] = mesh->origin[k];
+    const int64_t nel = (int64_t)c->N * c->N * c->N;
+    c->c_h.assign(nel, 1.0);
+    if (mat && mat->c)
+      for (int64_t e = 0; e < nel; ++e) {
+        if (!(mat->c[e] > 0)) throw DpgError(DPG_EINVAL, "wave speed must be positive");
+        c->c_h[e] = mat->c[e];
+      }
+    std::vector<double> kap(nel), Z(nel);
+    for (int64_t e = 0; e < nel; ++e) {
+      kap[e] = 1.0 / (c->c_h[e] * c->c_h[e]);
+      Z[e] = c->c_h[e];
+    }
+    c->kappa.upload(kap, &c->bud, c->stream);
+    c->Zel.upload(Z, &c->bud, c->stream);
+    c->el.build(p);
+    build_elem_tables(p, dp, c->tables_h);
+    c->tables.upload(std::vector<ElemTables>{c->tables_h}, &c->bud, c->stream);
+    std::vector<int4> test, trial;
+    build_descriptors(p, dp, test, trial);
+    c->n_test = (int)test.size();
+    c->n_field = 4 * p * p * p;
+    c->n_tr = c->el.n_tr;
+    c->m = c->n_field + c->n_tr;
+    if ((int)trial.size() != c->m) throw DpgError(DPG_EINVAL, "descriptor size mismatch");
+    c->testd.upload(test, &c->bud, c->stream);
+    c->triald.upload(trial, &c->bud, c->stream);
+    set_loads(c, loads, nrhs);
+    std::vector<int> sizes = level_sizes(c->N, c->opt.nlevels);
+    if (sizes.size() < 2)
+      throw DpgError(DPG_EINVAL, "the mesh size must be even (at least one coarsening)");
+    c->L = (int)sizes.size() - 1;
+    c->lv.resize(c->L + 1);
+    const bool mixed = c->opt.precision == DPG_MIXED;
+    const hipStream_t s = c->stream;
+    for (int l = 0; l <= c->L; ++l) {
+      LevelData &f = c->lv[l];
+      f.N = sizes[c->L - l];
+      f.nel = f.N * f.N * f.N;
+      f.num.build(f.N, p);
+      f.edofs_h = element_dofs(f.num, c->el);
+      f.edofs.upload(f.edofs_h, &c->bud, s);
+    }
+    for (int l = 1; l <= c->L; ++l) {
+      LevelData &f = c->lv[l];
+      f.macro = true;
+      f.mc.build(f.num, c->el);
+      f.P.build(f.mc, f.num, c->lv[l - 1].num, c->el);
+      f.nblk = f.mc.Nc * f.mc.Nc * f.mc.Nc;
+      f.nBf = f.mc.nBf;
+      f.nI = f.mc.nI;
+      f.nM = f.mc.nM;
+      f.macroB.upload(f.mc.macro_B, &c->bud, s);
+      f.blkI.upload(f.mc.blkI, &c->bud, s);
+      std::vector<int32_t> bm(f.mc.blkB.size());
+      for (size_t k = 0; k < bm.size(); ++k) bm[k] = f.mc.blkB[k] >= 0 ? f.mc.macro_of[f.mc.blkB[k]] : -1;
+      f.blkBm.upload(bm, &c->bud, s);
+      // condensation reduction lists: (block, slot) holding each macro unknown
+      std::vector<int32_t> cnt(f.nM + 1, 0), ent;
+      for (size_t k = 0; k < bm.size(); ++k)
+        if (bm[k] >= 0) cnt[bm[k] + 1]++;
+      for (int64_t mm = 0; mm < f.nM; ++mm) cnt[mm + 1] += cnt[mm];
+      ent.assign(cnt[f.nM], 0);
+      std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+      for (size_t k = 0; k < bm.size(); ++k)
+        if (bm[k] >= 0) ent[fill[bm[k]]++] = (int32_t)k;
+      f.cred_ptr.upload(cnt, &c->bud, s);
+      f.cred_ent.upload(ent, &c->bud, s);
+      f.patch_ptr.upload(f.mc.patch_ptr, &c->bud, s);
+      f.patch_slot.upload(f.mc.patch_slot, &c->bud, s);
+      f.Pptr.upload(f.P.ptr, &c->bud, s);
+      f.Pcol.upload(f.P.col, &c->bud, s);
+      f.Pval.upload(f.P.val, &c->bud, s);
+      f.Ptptr.upload(f.P.tptr, &c->bud, s);
+      f.Ptcol.upload(f.P.tcol, &c->bud, s);
+      f.Ptval.upload(f.P.tval, &c->bud, s);
+      if (mixed) {
+        std::vector<float> pv(f.P.val.begin(), f.P.val.end()), ptv(f.P.tval.begin(), f.P.tval.end());
+        f.Pval32.upload(pv, &c->bud, s);
+        f.Ptval32.upload(ptv, &c->bud, s);
+      }
+      // block sets
+      std::vector<int32_t> msz(f.nblk), midx;
+      for (int b = 0; b < f.nblk; ++b) {
+        msz[b] = (int32_t)(f.mc.blkB_ptr[b + 1] - f.mc.blkB_ptr[b]);
+        for (int64_t k = f.mc.blkB_ptr[b]; k < f.mc.blkB_ptr[b + 1]; ++k)
+          midx.push_back(f.mc.macro_of[f.mc.blkB[(int64_t)b * f.nBf + f.mc.blkB_present[k]]]);
+      }
+      f.Mset.build(msz, midx, f.nM, !mixed || l == c->L, mixed, &c->bud, s);
+      const int np = (int)f.mc.patch_ptr.size() - 1;
+      std::vector<int32_t> psz(np);
+      for (int v = 0; v < np; ++v) psz[v] = (int32_t)(f.mc.patch_ptr[v + 1] - f.mc.patch_ptr[v]);
+      f.Sset.build(psz, f.mc.patch_idx, f.nM, !mixed, mixed, &c->bud, s);
+      // work vectors
+      const int64_t nc = c->lv[l - 1].num.n;
+      if (mixed) {
+        f.r32.alloc(f.nM, &c->bud);
+        f.x32.alloc(f.nM, &c->bud);
+        f.res32.alloc(f.nM, &c->bud);
+        f.rc32.alloc(nc, &c->bud);
+        f.ec32.alloc(nc, &c->bud);
+        f.c32.alloc((int64_t)f.nblk * f.nBf, &c->bud);
+      } else {
+        f.r64.alloc(f.nM, &c->bud);
+        f.x64.alloc(f.nM, &c->bud);
+        f.res64.alloc(f.nM, &c->bud);
+        f.rc64.alloc(nc, &c->bud);
+        f.ec64.alloc(nc, &c->bud);
+      }
+      if (!mixed || l == c->L) f.c64.alloc((int64_t)f.nblk * f.nBf, &c->bud);
+    }
+    {
+      const int64_t n0 = c->lv[0].num.n;
+      std::vector<int32_t> sz{(int32_t)n0}, id(n0);
+      for (int64_t i = 0; i < n0; ++i) id[i] = (int32_t)i;
+      c->T0set.build(sz, id, n0, !mixed, mixed, &c->bud, s);
+    }
+    // element load assembly lists of the finest mesh
+    LevelData &top = c->lv[c->L];
+    {
+      const int64_t n = top.num.n;
+      std::vector<int32_t> cnt(n + 1, 0), ent;
+      for (int32_t t : top.edofs_h)
+        if (t >= 0) cnt[t + 1]++;
+      for (int64_t t = 0; t < n; ++t) cnt[t + 1] += cnt[t];
+      ent.assign(cnt[n], 0);
+      std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+      for (size_t k = 0; k < top.edofs_h.size(); ++k)
+        if (top.edofs_h[k] >= 0) ent[fill[top.edofs_h[k]]++] = (int32_t)k;
+      c->asm_ptr.upload(cnt, &c->bud, s);
+      c->asm_ent.upload(ent, &c->bud, s);
+    }
+    const int64_t nM = top.nM, nT = top.num.n;
+    for (auto *v : {&c->b, &c->x, &c->r, &c->z, &c->zo, &c->pv, &c->q}) v->alloc(nM, &c->bud);
+    c->xfull.alloc(nT, &c->bud);
+    c->sB.alloc(nT, &c->bud);
+    c->partial.alloc(2 * kDotBlocks, &c->bud);
+    c->sc.alloc(8, &c->bud);
+    HIP_OK(hipHostMalloc((void **)&c->host_sc, 8 * sizeof(double), 0));
+    const int64_t rec_bytes = 16LL * top.nel * ((int64_t)c->n_field * c->n_field +
+                                                (int64_t)c->n_field * (c->n_tr + c->nrhs));
+    c->keep_recovery = rec_bytes <= 4000000000LL;
+    HIP_OK(hipStreamSynchronize(s));
+    c->ms[0] = ms_since(t0);
+    c->stage = 1;
+    return DPG_OK;
+  });
+  if (rc != DPG_OK) {
+    std::string m = c->err;
+    delete c;
+    // no context to hold the message: report through stderr-free path (code only)
+    (void)m;
+    return rc;
+  }
+  *out = c;
+  return DPG_OK;
+}
+
+int dpg_assemble(dpg_ctx *c) {
+  if (!c) return DPG_EINVAL;
+  return guarded(c, [&]() {
+    if (c->stage < 1) throw DpgError(DPG_ESTATE, "dpg_setup first");
+    auto t0 = clk::now();
+    LevelData &top = c->lv[c->L];
+    top.E.alloc((int64_t)top.nel * c->n_tr * c->n_tr, &c->bud);
+    c->s_elem.alloc(std::max<int64_t>(1, (int64_t)c->nrhs * top.nel * c->n_tr), &c->bud);
+    c->s_asm.alloc(std::max<int64_t>(1, (int64_t)c->nrhs * top.num.n), &c->bud);
+    if (c->keep_recovery) {
+      c->rec_L.alloc((int64_t)top.nel * c->n_field * c->n_field, &c->bud);
+      c->rec_Y.alloc((int64_t)top.nel * c->n_field * (c->n_tr + c->nrhs), &c->bud);
+    }
+    element_stage(c, true);
+    c->ms[1] = ms_since(t0);
+    c->stage = 2;
+    return DPG_OK;
+  });
+}
+
+int dpg_build_hierarchy(dpg_ctx *c) {
+  if (!c) return DPG_EINVAL;
+  return guarded(c, [&]() {
+    if (c->stage < 2) throw DpgError(DPG_ESTATE, "dpg_assemble first");
+    auto t0 = clk::now();
+    for (int l = c->L; l >= 1; --l) {
+      build_macro_level(c, l);
+      build_patches(c, l);
+    }
+    build_coarsest(c);
+    c->ms[2] = ms_since(t0);
+    c->stage = 3;
+    return DPG_OK;
+  });
+}
+
+int dpg_load_rhs(dpg_ctx *c, const dpg_load *loads, int nrhs, double *s_out) {
+  if (!c) return DPG_EINVAL;
+  return guarded(c, [&]() {
+    if (c->stage < 2) throw DpgError(DPG_ESTATE, "dpg_assemble first");
+    if (nrhs < 1 || !loads) throw DpgError(DPG_EINVAL, "need at least one load");
+    LevelData &top = c->lv[c->L];
+    set_loads(c, loads, nrhs);
+    c->s_elem.alloc((int64_t)nrhs * top.nel * c->n_tr, &c->bud);
+    c->s_asm.alloc((int64_t)nrhs * top.num.n, &c->bud);
+    if (c->keep_recovery) {
+      c->rec_L.alloc((int64_t)top.nel * c->n_field * c->n_field, &c->bud);
+      c->rec_Y.alloc((int64_t)top.nel * c->n_field * (c->n_tr + c->nrhs), &c->bud);
+    }
+    element_stage(c, false);
+    if (s_out) {
+      const bool dev = c->opt.flags & DPG_DEVICE_PTRS;
+      HIP_OK(hipMemcpyAsync(s_out, c->s_asm.p, (size_t)nrhs * top.num.n * 16,
+                            dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+      HIP_OK(hipStreamSynchronize(c->stream));
+    }
+    return DPG_OK;
+  });
+}
+
+int dpg_solve(dpg_ctx *c, const double *rhs, int nrhs, double tol, double *x_out,
+              int32_t *iters_out, double *relres_out) {
+  if (!c) return DPG_EINVAL;
+  return guarded(c, [&]() {
+    if (c->stage < 3) throw DpgError(DPG_ESTATE, "dpg_build_hierarchy first");
+    if (nrhs < 1 || !(tol >= 0.0)) throw DpgError(DPG_EINVAL, "bad nrhs or tol");
+    if (!rhs && nrhs > c->nrhs) throw DpgError(DPG_EINVAL, "more columns than assembled loads");
+    auto t0 = clk::now();
+    LevelData &top = c->lv[c->L];
+    const int64_t nT = top.num.n;
+    const bool dev = c->opt.flags & DPG_DEVICE_PTRS;
+    int status = DPG_OK;
+    for (int k = 0; k < nrhs; ++k) {
+      const double2 *sv;
+      if (rhs) {
+        HIP_OK(hipMemcpyAsync(c->sB.p, rhs + 2 * nT * k, nT * 16,
+                              dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+        sv = c->sB.p;
+      } else {
+        sv = c->s_asm.p + nT * k;
+      }
+      int32_t it = 0;
+      double rr = 0;
+      const int st = solve_one(c, sv, tol, c->xfull.p, &it, &rr);
+      if (st != DPG_OK) status = st;
+      if (iters_out) iters_out[k] = it;
+      if (relres_out) relres_out[k] = rr;
+      if (x_out) {
+        HIP_OK(hipMemcpyAsync(x_out + 2 * nT * k, c->xfull.p, nT * 16,
+                              dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));
+      }
+    }
+    c->ms[3] = ms_since(t0);
+    if (status == DPG_ENOCONV) c->err = "maximum number of iterations reached";
+    return status;
+  });
+}
+
+int dpg_get_fields(dpg_ctx *c, const double *x, int nrhs, double *fields_out) {
+  if (!c) return DPG_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (c->stage < 2) throw DpgError(DPG_ESTATE, "dpg_assemble first");
+    if (!c->keep_recovery) throw DpgError(DPG_ENOMEM, "recovery data was not kept (too large)");
+    if (!x || !fields_out || nrhs < 1 || nrhs > c->nrhs)
+      throw DpgError(DPG_EINVAL, "need x and fields_out, 1 <= nrhs <= assembled loads");
+    LevelData &top = c->lv[c->L];
+    const int64_t nT = top.num.n, nfe = (int64_t)top.nel * c->n_field;
+    const bool dev = c->opt.flags & DPG_DEVICE_PTRS;
+    DevBuf<double2> out;
+    out.alloc(nfe, &c->bud);
+    for (int k = 0; k < nrhs; ++k) {
+      HIP_OK(hipMemcpyAsync(c->sB.p, x + 2 * nT * k, nT * 16,
+                            dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+      launch_fields(c->rec_L.p, c->rec_Y.p, c->n_field, c->n_tr, c->nrhs, k, top.edofs.p,
+                    top.nel, c->sB.p, out.p, c->stream);
+      HIP_OK(hipMemcpyAsync(fields_out + 2 * nfe * k, out.p, nfe * 16,
+                            dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+      HIP_OK(hipStreamSynchronize(c->stream));
+    }
+    return DPG_OK;
+  });
+}
+
+int dpg_info(const dpg_ctx *c, dpg_info_t *info) {
+  if (!c || !info) return DPG_EINVAL;
+  std::memset(info, 0, sizeof(*info));
+  if (c->stage < 1) return DPG_ESTATE;
+  const auto &top = c->lv[c->L];
+  info->n_trace = top.num.n;
+  info->n_macro = top.nM;
+  info->nlevels = c->L + 1;
+  for (int k = 0; k <= c->L && k < 16; ++k) {
+    const auto &f = c->lv[c->L - k];
+    info->level_n[k] = f.N;
+    info->level_ntrace[k] = f.num.n;
+    info->level_nmacro[k] = f.nM;
+  }
+  info->resident_bytes = c->bud.used;
+  info->n_test = c->n_test;
+  info->n_field = c->n_field;
+  info->n_tr = c->n_tr;
+  for (int k = 0; k < 4; ++k) info->setup_ms[k] = c->ms[k];
+  return DPG_OK;
+}
+
+const char *dpg_last_error(const dpg_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+
+int64_t dpg_export(const dpg_ctx *cc, int what, int level, void *out, int64_t cap) {
+  dpg_ctx *c = const_cast<dpg_ctx *>(cc);
+  if (!c) return DPG_EINVAL;
+  if (c->stage < 1) return DPG_ESTATE;
+  if (level < 0 || level > c->L) return DPG_EINVAL;
+  int64_t rc = DPG_EINVAL;
+  int st = guarded(c, [&]() -> int {
+    LevelData &f = c->lv[c->L - level];
+    const hipStream_t s = c->stream;
+    auto need_macro = [&]() {
+      if (!f.macro) throw DpgError(DPG_EINVAL, "the coarsest mesh has no macro grid");
+    };
+    switch (what) {
+      case DPG_X_ELEM_DOFS: rc = put(widen(f.edofs_h), out, cap); break;
+      case DPG_X_MACRO_B: need_macro(); rc = put(f.mc.macro_B, out, cap); break;
+      case DPG_X_BLOCK_B:
+      case DPG_X_BLOCK_I: {
+        need_macro();
+        std::vector<int64_t> v(f.nblk + 1, 0), body;
+        for (int b = 0; b < f.nblk; ++b) {
+          if (what == DPG_X_BLOCK_B) {
+            for (int64_t k = f.mc.blkB_ptr[b]; k < f.mc.blkB_ptr[b + 1]; ++k)
+              body.push_back(f.mc.macro_of[f.mc.blkB[(int64_t)b * f.nBf + f.mc.blkB_present[k]]]);
+          } else {
+            for (int i = 0; i < f.nI; ++i) body.push_back(f.mc.blkI[(int64_t)b * f.nI + i]);
+          }
+          v[b + 1] = (int64_t)body.size();
+        }
+        v.insert(v.end(), body.begin(), body.end());
+        rc = put(v, out, cap);
+        break;
+      }
+      case DPG_X_PATCHES: {
+        need_macro();
+        std::vector<int64_t> v(f.mc.patch_ptr);
+        v.insert(v.end(), f.mc.patch_idx.begin(), f.mc.patch_idx.end());
+        rc = put(v, out, cap);
+        break;
+      }
+      case DPG_X_PROLONG: {
+        need_macro();
+        std::vector<int64_t> v(f.P.ptr);
+        v.insert(v.end(), f.P.col.begin(), f.P.col.end());
+        rc = put(v, out, cap);
+        break;
+      }
+      case DPG_X_PROLONG_VAL: need_macro(); rc = put(f.P.val, out, cap); break;
+      case DPG_X_ELEM_S:
+      case DPG_X_COARSE_E: {
+        if (!f.E.p) throw DpgError(DPG_ESTATE, "element matrices not computed yet");
+        rc = put(f.E.download(s), out, cap);
+        break;
+      }
+      case DPG_X_ELEM_RHS: {
+        if (c->stage < 2) throw DpgError(DPG_ESTATE, "dpg_assemble first");
+        rc = put(c->s_elem.download(s), out, cap);
+        break;
+      }
+      case DPG_X_ASM_RHS: {
+        if (c->stage < 2) throw DpgError(DPG_ESTATE, "dpg_assemble first");
+        rc = put(c->s_asm.download(s), out, cap);
+        break;
+      }
+      case DPG_X_MACRO_M: {
+        need_macro();
+        if (!f.Mfull.p) throw DpgError(DPG_ESTATE, "dpg_build_hierarchy first");
+        std::vector<double2> full = f.Mfull.download(s), v;
+        for (int b = 0; b < f.nblk; ++b) {
+          const int64_t k0 = f.mc.blkB_ptr[b], n = f.mc.blkB_ptr[b + 1] - k0;
+          const double2 *Mb = full.data() + (int64_t)b * f.nBf * f.nBf;
+          for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < n; ++i)
+              v.push_back(Mb[f.mc.blkB_present[k0 + i] + (int64_t)f.mc.blkB_present[k0 + j] * f.nBf]);
+        }
+        rc = put(v, out, cap);
+        break;
+      }
+      case DPG_X_PATCH_INV: {
+        need_macro();
+        if (c->stage < 3) throw DpgError(DPG_ESTATE, "dpg_build_hierarchy first");
+        HermSet &H = f.Sset;
+        std::vector<double2> t;
+        if (H.t64.p) t = H.t64.download(s);
+        else {
+          std::vector<float2> t32 = H.t32.download(s);
+          t.resize(t32.size());
+          for (size_t k = 0; k < t32.size(); ++k) t[k] = mk(t32[k].x, t32[k].y);
+        }
+        std::vector<double2> v;
+        for (int b = 0; b < H.nblk; ++b) {
+          const int n = H.n_h[b], nt = (n + 31) / 32;
+          std::vector<double2> A((size_t)n * n);
+          for (int J = 0; J < nt; ++J)
+            for (int I = 0; I <= J; ++I) {
+              const double2 *tp = t.data() + (H.tile_off_h[b] + (int64_t)J * (J + 1) / 2 + I) * 1024;
+              for (int e = 0; e < 1024; ++e) {
+                const int k = e >> 6, lane = e & 63;
+                const int row = 32 * I + 4 * (lane >> 3) + (k >> 2), col = 32 * J + 4 * (lane & 7) + (k & 3);
+                if (row < n && col < n) {
+                  A[row + (size_t)col * n] = tp[e];
+                  if (I < J) A[col + (size_t)row * n] = mk(tp[e].x, -tp[e].y);
+                }
+              }
+            }
+          v.insert(v.end(), A.begin(), A.end());
+        }
+        rc = put(v, out, cap);
+        break;
+      }
+      case DPG_X_COARSEST: {
+        if (c->stage < 3) throw DpgError(DPG_ESTATE, "dpg_build_hierarchy first");
+        rc = put(c->T0.download(s), out, cap);
+        break;
+      }
+      default: throw DpgError(DPG_EINVAL, "unknown export");
+    }
+    return DPG_OK;
+  });
+  return st == DPG_OK ? rc : st;
+}
+
+void dpg_destroy(dpg_ctx *c) {
+  if (!c) return;
+  if (c->host_sc) (void)hipHostFree(c->host_sc);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// Internal context of libdpgmg.
+#pragma once
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "../../include/dpgmg.h"
+#include "common.hpp"
+#include "dense.hpp"
+#include "element.hpp"
+#include "hblocks.hpp"
+#include "kernels.hpp"
+#include "topology.hpp"
+
+namespace dpg {
+
+// One mesh of the hierarchy.  Level 0 is the coarsest mesh, level L the finest.
+struct LevelData {
+  int N = 0, nel = 0;
+  Numbering num;
+  std::vector<int32_t> edofs_h;
+  DevBuf<int32_t> edofs;
+  DevBuf<double2> E;                 // element matrices [nel][n_tr^2]
+  // macro grid (levels >= 1)
+  bool macro = false;
+  MacroLevel mc;
+  Prolongation P;
+  int nblk = 0, nBf = 0, nI = 0;
+  int64_t nM = 0;
+  DevBuf<double2> Mfull;             // [nblk][nBf^2] condensed blocks, full local layout
+  DevBuf<double2> Tinv, WH;          // [nblk][nI^2], [nblk][nBf nI]
+  DevBuf<float2> Tinv32, WH32;
+  DevBuf<int32_t> blkI, blkBm;       // [nblk][nI] canonical, [nblk][nBf] macro index / -1
+  DevBuf<int64_t> macroB;            // [nM] canonical index of each macro unknown
+  DevBuf<int32_t> cred_ptr, cred_ent;
+  DevBuf<int64_t> patch_ptr;
+  DevBuf<int32_t> patch_slot;
+  HermSet Mset, Sset;
+  DevBuf<int64_t> Pptr, Ptptr;
+  DevBuf<int32_t> Pcol, Ptcol;
+  DevBuf<double> Pval, Ptval;
+  DevBuf<float> Pval32, Ptval32;
+  // V-cycle work vectors: r, x, res on this macro grid; rc, ec on the coarser
+  // mesh's traces; c = per-block condensation contributions of this level.
+  DevBuf<double2> r64, x64, res64, rc64, ec64, c64;
+  DevBuf<float2> r32, x32, res32, rc32, ec32, c32;
+};
+
+}  // namespace dpg
+
+struct dpg_ctx {
+  std::string err;
+  int stage = 0;                     // 1 set up, 2 assembled, 3 hierarchy built
+  int N = 0, p = 0, dp = 1, nrhs = 0;
+  double omega = 0, side = 1, org[3] = {0, 0, 0};
+  dpg_options opt{};
+  hipStream_t stream = nullptr;
+  dpg::Budget bud;
+  dpg::ElementLayout el;
+  int n_test = 0, n_field = 0, n_tr = 0, m = 0;
+  std::vector<double> c_h;
+  dpg::DevBuf<double> kappa, Zel;
+  dpg::ElemTables tables_h{};
+  dpg::DevBuf<dpg::ElemTables> tables;
+  dpg::DevBuf<int4> testd, triald;
+  std::vector<dpg::LoadDesc> ld_h;
+  std::vector<double> src_h;
+  dpg::DevBuf<dpg::LoadDesc> ld;
+  dpg::DevBuf<double> src;
+  std::vector<dpg::LevelData> lv;
+  int L = 0;
+  bool keep_recovery = false;
+  dpg::DevBuf<double2> s_elem;       // [nrhs][nel][n_tr] condensed element loads
+  dpg::DevBuf<double2> s_asm;        // [nrhs][n_trace] assembled loads
+  dpg::DevBuf<int32_t> asm_ptr, asm_ent;
+  dpg::DevBuf<double2> rec_L, rec_Y; // [nel][nf^2], [nel][nf (n_tr + nrhs)]
+  // coarsest mesh
+  dpg::DevBuf<double2> T0;
+  dpg::HermSet T0set;
+  // outer CG (FP64, finest macro grid)
+  dpg::DevBuf<double2> b, x, r, z, zo, pv, q, xfull, sB;
+  dpg::DevBuf<double> partial, sc;
+  double *host_sc = nullptr;         // pinned
+  double ms[4] = {0, 0, 0, 0};
+};

@@ -1,0 +1,525 @@
+// Hierarchy-setup and solve-phase kernels (see kernels.hpp).
+#include "kernels.hpp"
+
+namespace dpg {
+namespace {
+
+constexpr int kMaxB = 2048, kMaxI = 1024;
+
+// ---- setup -----------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_macro_assemble(const double2 *__restrict__ E, int n_tr,
+                                                        const int32_t *__restrict__ child_map,
+                                                        int N, int b0, int nT,
+                                                        double2 *__restrict__ T) {
+  const int Nc = N / 2, b = b0 + blockIdx.x;
+  const int ci = b % Nc, cj = (b / Nc) % Nc, ck = b / (Nc * Nc);
+  double2 *Tb = T + (int64_t)blockIdx.x * nT * nT;
+  for (int64_t k = threadIdx.x; k < (int64_t)nT * nT; k += 256) Tb[k] = mk(0.0, 0.0);
+  __syncthreads();
+  const int n2 = n_tr * n_tr;
+  for (int c = 0; c < 8; ++c) {
+    const int e = (2 * ci + (c & 1)) + N * ((2 * cj + ((c >> 1) & 1)) + N * (2 * ck + (c >> 2)));
+    const double2 *Ee = E + (int64_t)e * n2;
+    const int32_t *mp = child_map + c * n_tr;
+    for (int k = threadIdx.x; k < n2; k += 256) {
+      const int i = k % n_tr, j = k / n_tr;
+      double2 *dst = &Tb[mp[i] + (int64_t)mp[j] * nT];
+      *dst = cadd(*dst, Ee[k]);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_copy_sub(const double2 *__restrict__ src,
+                                                  int64_t src_stride, int lds, int r0, int c0,
+                                                  int rows, int cols, double2 *__restrict__ dst,
+                                                  int64_t dst_stride, int ldd) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= (int64_t)rows * cols) return;
+  const int i = (int)(k % rows), j = (int)(k / rows);
+  dst[blockIdx.y * dst_stride + i + (int64_t)j * ldd] =
+      src[blockIdx.y * src_stride + (r0 + i) + (int64_t)(c0 + j) * lds];
+}
+
+__global__ __launch_bounds__(256) void k_patch_gather(const double2 *__restrict__ Mfull, int nBf,
+                                                      int Nc, const int64_t *__restrict__ pptr,
+                                                      const int32_t *__restrict__ pslot, int v0,
+                                                      const int64_t *__restrict__ dst_off,
+                                                      double2 *__restrict__ S) {
+  __shared__ int blk[8];
+  const int v = v0 + blockIdx.x;
+  const int vx = v % (Nc + 1), vy = (v / (Nc + 1)) % (Nc + 1), vz = v / ((Nc + 1) * (Nc + 1));
+  if (threadIdx.x < 8) {
+    const int c = threadIdx.x;
+    const int ci = vx - 1 + (c & 1), cj = vy - 1 + ((c >> 1) & 1), ck = vz - 1 + (c >> 2);
+    blk[c] = (ci >= 0 && cj >= 0 && ck >= 0 && ci < Nc && cj < Nc && ck < Nc)
+                 ? ci + Nc * (cj + Nc * ck) : -1;
+  }
+  __syncthreads();
+  const int64_t p0 = pptr[v];
+  const int n = (int)(pptr[v + 1] - p0);
+  const int32_t *sl = pslot + p0 * 8;
+  double2 *Sv = S + dst_off[blockIdx.x];
+  const int64_t nb2 = (int64_t)nBf * nBf;
+  for (int64_t k = threadIdx.x; k < (int64_t)n * n; k += 256) {
+    const int i = (int)(k % n), j = (int)(k / n);
+    double2 acc = mk(0.0, 0.0);
+    for (int c = 0; c < 8; ++c) {
+      if (blk[c] < 0) continue;
+      const int si = sl[i * 8 + c], sj = sl[j * 8 + c];
+      if (si >= 0 && sj >= 0) acc = cadd(acc, Mfull[blk[c] * nb2 + si + (int64_t)sj * nBf]);
+    }
+    Sv[k] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_identity(const int64_t *__restrict__ off,
+                                                  const int32_t *__restrict__ nn,
+                                                  double2 *__restrict__ X) {
+  const int n = nn[blockIdx.y];
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= (int64_t)n * n) return;
+  X[off[blockIdx.y] + k] = mk((k % n) == (k / n) ? 1.0 : 0.0, 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_assemble_dense(const double2 *__restrict__ E, int n_tr,
+                                                        const int32_t *__restrict__ edofs,
+                                                        int nel, int n0,
+                                                        double2 *__restrict__ T0) {
+  for (int64_t k = threadIdx.x; k < (int64_t)n0 * n0; k += 256) T0[k] = mk(0.0, 0.0);
+  __syncthreads();
+  const int n2 = n_tr * n_tr;
+  for (int e = 0; e < nel; ++e) {
+    const int32_t *d = edofs + (int64_t)e * n_tr;
+    for (int k = threadIdx.x; k < n2; k += 256) {
+      const int gi = d[k % n_tr], gj = d[k / n_tr];
+      if (gi >= 0 && gj >= 0) {
+        double2 *dst = &T0[gi + (int64_t)gj * n0];
+        *dst = cadd(*dst, E[(int64_t)e * n2 + k]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- solve phase --------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_csr(int64_t nrows, const int64_t *__restrict__ ptr,
+                                             const int32_t *__restrict__ col,
+                                             const T *__restrict__ val,
+                                             const cplx_t<T> *__restrict__ x,
+                                             cplx_t<T> *__restrict__ y, int add) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nrows) return;
+  cplx_t<T> acc;
+  acc.x = 0;
+  acc.y = 0;
+  for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) acc = cadd(acc, cscale(x[col[k]], val[k]));
+  y[i] = add ? cadd(y[i], acc) : acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_condense_local(const cplx_t<T> *__restrict__ WH, int nI,
+                                                        int nBf, const int32_t *__restrict__ blkI,
+                                                        const cplx_t<T> *__restrict__ rc,
+                                                        cplx_t<T> *__restrict__ c) {
+  using C = cplx_t<T>;
+  __shared__ C rI[kMaxI];
+  const int b = blockIdx.x;
+  for (int i = threadIdx.x; i < nI; i += 256) rI[i] = rc[blkI[(int64_t)b * nI + i]];
+  __syncthreads();
+  const C *W = WH + (int64_t)b * nBf * nI;
+  for (int sl = threadIdx.x; sl < nBf; sl += 256) {
+    C acc;
+    acc.x = 0;
+    acc.y = 0;
+    for (int i = 0; i < nI; ++i) acc = cfma(W[sl + (int64_t)i * nBf], rI[i], acc);
+    c[(int64_t)b * nBf + sl] = acc;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_condense_reduce(int64_t nM,
+                                                         const int64_t *__restrict__ macro_B,
+                                                         const int32_t *__restrict__ red_ptr,
+                                                         const int32_t *__restrict__ red_ent,
+                                                         const cplx_t<T> *__restrict__ rc,
+                                                         const cplx_t<T> *__restrict__ c,
+                                                         cplx_t<T> *__restrict__ rB) {
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m >= nM) return;
+  cplx_t<T> acc = rc[macro_B[m]];
+  for (int32_t k = red_ptr[m]; k < red_ptr[m + 1]; ++k) acc = csub(acc, c[red_ent[k]]);
+  rB[m] = acc;
+}
+
+template <typename C> __device__ inline C wave_sum(C v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o, 64);
+    v.y += __shfl_xor(v.y, o, 64);
+  }
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_expand(const cplx_t<T> *__restrict__ WH,
+                                                const cplx_t<T> *__restrict__ Tinv, int nI,
+                                                int nBf, const int32_t *__restrict__ blkI,
+                                                const int32_t *__restrict__ blkBm,
+                                                const cplx_t<T> *__restrict__ rc,
+                                                const cplx_t<T> *__restrict__ eB,
+                                                cplx_t<T> *__restrict__ ec) {
+  using C = cplx_t<T>;
+  __shared__ C eBs[kMaxB];
+  __shared__ C rI[kMaxI];
+  const int b = blockIdx.x;
+  for (int sl = threadIdx.x; sl < nBf; sl += 256) {
+    const int m = blkBm[(int64_t)b * nBf + sl];
+    C v;
+    v.x = 0;
+    v.y = 0;
+    if (m >= 0) v = eB[m];
+    eBs[sl] = v;
+  }
+  for (int i = threadIdx.x; i < nI; i += 256) rI[i] = rc[blkI[(int64_t)b * nI + i]];
+  __syncthreads();
+  const C *W = WH + (int64_t)b * nBf * nI;
+  const C *Ti = Tinv + (int64_t)b * nI * nI;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < nI; i += 4) {
+    C u, v;
+    u.x = u.y = 0;
+    v.x = v.y = 0;
+    // u = (WH^H eB)_i = sum_sl conj(WH[sl, i]) eB[sl]; v = (Tinv rI)_i = sum_j conj(Tinv[j, i]) rI[j]
+    for (int sl = lane; sl < nBf; sl += 64) u = cfmaconj(W[sl + (int64_t)i * nBf], eBs[sl], u);
+    for (int j = lane; j < nI; j += 64) v = cfmaconj(Ti[j + (int64_t)i * nI], rI[j], v);
+    u = wave_sum(u);
+    v = wave_sum(v);
+    if (lane == 0) ec[blkI[(int64_t)b * nI + i]] = csub(v, u);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter_macro(int64_t nM, const int64_t *__restrict__ macro_B,
+                                                       const cplx_t<T> *__restrict__ eB,
+                                                       cplx_t<T> *__restrict__ ec) {
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m < nM) ec[macro_B[m]] = eB[m];
+}
+
+__global__ __launch_bounds__(256) void k_assemble_vec(int64_t n, const int32_t *__restrict__ ptr,
+                                                      const int32_t *__restrict__ ent,
+                                                      const double2 *__restrict__ se,
+                                                      int64_t se_stride,
+                                                      double2 *__restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  double2 acc = mk(0.0, 0.0);
+  for (int32_t k = ptr[t]; k < ptr[t + 1]; ++k) acc = cadd(acc, se[ent[k]]);
+  out[t] = acc;
+  (void)se_stride;
+}
+
+__global__ __launch_bounds__(256) void k_fields(const double2 *__restrict__ recL,
+                                                const double2 *__restrict__ recY, int nf, int ntr,
+                                                int nrhs, int col,
+                                                const int32_t *__restrict__ edofs,
+                                                const double2 *__restrict__ x,
+                                                double2 *__restrict__ out) {
+  __shared__ double2 v[kMaxI];
+  __shared__ double2 xt[kMaxB];
+  const int e = blockIdx.x;
+  for (int j = threadIdx.x; j < ntr; j += 256) {
+    const int32_t t = edofs[(int64_t)e * ntr + j];
+    xt[j] = t >= 0 ? x[t] : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  const double2 *Y = recY + (int64_t)e * nf * (ntr + nrhs);
+  const double2 *L = recL + (int64_t)e * nf * nf;
+  for (int i = threadIdx.x; i < nf; i += 256) {
+    double2 acc = Y[i + (int64_t)(ntr + col) * nf];
+    for (int j = 0; j < ntr; ++j) acc = csub(acc, cmul(Y[i + (int64_t)j * nf], xt[j]));
+    v[i] = acc;
+  }
+  __syncthreads();
+  // L^H u = v, column by column from the last unknown
+  for (int i = nf - 1; i >= 0; --i) {
+    if (threadIdx.x == 0) v[i] = cscale(v[i], 1.0 / L[i + (int64_t)i * nf].x);
+    __syncthreads();
+    for (int k = threadIdx.x; k < i; k += 256)
+      v[k] = csub(v[k], cmul(cconj(L[i + (int64_t)k * nf]), v[i]));
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < nf; i += 256) out[(int64_t)e * nf + i] = v[i];
+}
+
+__global__ void k_to32(int64_t n, const double2 *a, float2 *b) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) b[i] = mkf((float)a[i].x, (float)a[i].y);
+}
+__global__ void k_to64(int64_t n, const float2 *a, double2 *b) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) b[i] = mk((double)a[i].x, (double)a[i].y);
+}
+
+// ---- CG ---------------------------------------------------------------------------------
+
+__device__ inline double block_sum(double v) {
+  __shared__ double sh[4];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+// partial[blockIdx] = sum over a grid-stride slice of Re(conj(a) b)
+__global__ __launch_bounds__(256) void k_dot_partial(int64_t n, const double2 *__restrict__ a,
+                                                     const double2 *__restrict__ b,
+                                                     double *__restrict__ partial) {
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    s += a[i].x * b[i].x + a[i].y * b[i].y;
+  s = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_dot2_partial(int64_t n, const double2 *__restrict__ r,
+                                                      const double2 *__restrict__ z,
+                                                      const double2 *__restrict__ zo,
+                                                      double *__restrict__ partial) {
+  double s = 0.0, t = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    s += r[i].x * z[i].x + r[i].y * z[i].y;
+    t += r[i].x * zo[i].x + r[i].y * zo[i].y;
+  }
+  s = block_sum(s);
+  t = block_sum(t);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s;
+    partial[kDotBlocks + blockIdx.x] = t;
+  }
+}
+
+__device__ inline double sum_partials(const double *partial) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < kDotBlocks; i += 256) s += partial[i];
+  return block_sum(s);
+}
+
+// mode 0: dst = sum; 1: pq / alpha; 2: ||r||^2; 3: beta
+__global__ __launch_bounds__(256) void k_final(const double *__restrict__ partial, double *dst,
+                                               double *sc, int mode) {
+  const double s = sum_partials(partial);
+  double t = 0.0;
+  if (mode == 3) t = sum_partials(partial + kDotBlocks);
+  if (threadIdx.x != 0) return;
+  if (mode == 0) {
+    *dst = s;
+  } else if (mode == 1) {
+    sc[1] = s;
+    if (!(s > 0.0) || !isfinite(s)) sc[6] = 1.0;
+    sc[2] = sc[0] / s;
+  } else if (mode == 2) {
+    sc[4] = s;
+  } else {
+    // flexible (Polak-Ribiere) beta = Re(r^H (z - z_old)) / Re(r_old^H z_old)
+    sc[3] = (s - t) / sc[0];
+    sc[7] = t;
+    sc[0] = s;
+    if (!isfinite(sc[3])) sc[6] = 1.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_update_xr(int64_t n, double2 *__restrict__ x,
+                                                   double2 *__restrict__ r,
+                                                   const double2 *__restrict__ p,
+                                                   const double2 *__restrict__ q,
+                                                   double *__restrict__ partial,
+                                                   const double *__restrict__ sc) {
+  const double a = sc[2];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    x[i] = mk(x[i].x + a * p[i].x, x[i].y + a * p[i].y);
+    const double2 ri = mk(r[i].x - a * q[i].x, r[i].y - a * q[i].y);
+    r[i] = ri;
+    s += ri.x * ri.x + ri.y * ri.y;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_update_p(int64_t n, double2 *__restrict__ p,
+                                                  const double2 *__restrict__ z,
+                                                  const double *__restrict__ sc) {
+  const double b = sc[3];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = mk(z[i].x + b * p[i].x, z[i].y + b * p[i].y);
+}
+
+}  // namespace
+
+// ---- launchers --------------------------------------------------------------------------
+
+void launch_macro_assemble(const double2 *E, int n_tr, const int32_t *child_map, int N, int b0,
+                           int count, int nT, double2 *T, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_macro_assemble, dim3(count), dim3(256), 0, s, E, n_tr, child_map, N, b0,
+                     nT, T);
+  LAUNCH_OK();
+}
+
+void launch_copy_sub(const double2 *src, int64_t src_stride, int lds, int r0, int c0, int rows,
+                     int cols, double2 *dst, int64_t dst_stride, int ldd, int count,
+                     hipStream_t s) {
+  if (count <= 0 || rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(k_copy_sub, dim3(cdiv((int64_t)rows * cols, 256), count), dim3(256), 0, s,
+                     src, src_stride, lds, r0, c0, rows, cols, dst, dst_stride, ldd);
+  LAUNCH_OK();
+}
+
+void launch_patch_gather(const double2 *Mfull, int nBf, int Nc, const int64_t *patch_ptr,
+                         const int32_t *patch_slot, int v0, int count, const int64_t *dst_off,
+                         double2 *S, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_patch_gather, dim3(count), dim3(256), 0, s, Mfull, nBf, Nc, patch_ptr,
+                     patch_slot, v0, dst_off, S);
+  LAUNCH_OK();
+}
+
+void launch_identity(const int64_t *off, const int32_t *n, int count, int nmax, double2 *X,
+                     hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_identity, dim3(cdiv((int64_t)nmax * nmax, 256), count), dim3(256), 0, s,
+                     off, n, X);
+  LAUNCH_OK();
+}
+
+void launch_assemble_dense(const double2 *E, int n_tr, const int32_t *edofs, int nel, int n0,
+                           double2 *T0, hipStream_t s) {
+  hipLaunchKernelGGL(k_assemble_dense, dim3(1), dim3(256), 0, s, E, n_tr, edofs, nel, n0, T0);
+  LAUNCH_OK();
+}
+
+template <typename T>
+void launch_csr(int64_t nrows, const int64_t *ptr, const int32_t *col, const T *val,
+                const cplx_t<T> *x, cplx_t<T> *y, int add, hipStream_t s) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL((k_csr<T>), dim3(cdiv(nrows, 256)), dim3(256), 0, s, nrows, ptr, col, val, x,
+                     y, add);
+  LAUNCH_OK();
+}
+
+template <typename T>
+void launch_condense_local(const cplx_t<T> *WH, int nI, int nBf, const int32_t *blkI, int nblk,
+                           const cplx_t<T> *rc, cplx_t<T> *c, hipStream_t s) {
+  if (nI > kMaxI || nBf > kMaxB) throw DpgError(-1, "macro block too large");
+  hipLaunchKernelGGL((k_condense_local<T>), dim3(nblk), dim3(256), 0, s, WH, nI, nBf, blkI, rc, c);
+  LAUNCH_OK();
+}
+
+template <typename T>
+void launch_condense_reduce(int64_t nM, const int64_t *macro_B, const int32_t *red_ptr,
+                            const int32_t *red_ent, const cplx_t<T> *rc, const cplx_t<T> *c,
+                            cplx_t<T> *rB, hipStream_t s) {
+  hipLaunchKernelGGL((k_condense_reduce<T>), dim3(cdiv(nM, 256)), dim3(256), 0, s, nM, macro_B,
+                     red_ptr, red_ent, rc, c, rB);
+  LAUNCH_OK();
+}
+
+template <typename T>
+void launch_expand(const cplx_t<T> *WH, const cplx_t<T> *Tinv, int nI, int nBf,
+                   const int32_t *blkI, const int32_t *blkBm, int nblk, const cplx_t<T> *rc,
+                   const cplx_t<T> *eB, int64_t nM, const int64_t *macro_B, cplx_t<T> *ec,
+                   hipStream_t s) {
+  if (nI > kMaxI || nBf > kMaxB) throw DpgError(-1, "macro block too large");
+  hipLaunchKernelGGL((k_scatter_macro<T>), dim3(cdiv(nM, 256)), dim3(256), 0, s, nM, macro_B, eB,
+                     ec);
+  LAUNCH_OK();
+  hipLaunchKernelGGL((k_expand<T>), dim3(nblk), dim3(256), 0, s, WH, Tinv, nI, nBf, blkI, blkBm,
+                     rc, eB, ec);
+  LAUNCH_OK();
+}
+
+void launch_assemble_vec(int64_t n, const int32_t *ptr, const int32_t *ent, const double2 *se,
+                         int64_t se_stride, double2 *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_assemble_vec, dim3(cdiv(n, 256)), dim3(256), 0, s, n, ptr, ent, se,
+                     se_stride, out);
+  LAUNCH_OK();
+}
+
+void launch_fields(const double2 *recL, const double2 *recY, int nf, int ntr, int nrhs, int col,
+                   const int32_t *edofs, int nel, const double2 *x, double2 *out, hipStream_t s) {
+  if (nf > kMaxI || ntr > kMaxB) throw DpgError(-1, "element too large for field recovery");
+  hipLaunchKernelGGL(k_fields, dim3(nel), dim3(256), 0, s, recL, recY, nf, ntr, nrhs, col, edofs,
+                     x, out);
+  LAUNCH_OK();
+}
+
+void launch_to32(int64_t n, const double2 *a, float2 *b, hipStream_t s) {
+  hipLaunchKernelGGL(k_to32, dim3(cdiv(n, 256)), dim3(256), 0, s, n, a, b);
+  LAUNCH_OK();
+}
+void launch_to64(int64_t n, const float2 *a, double2 *b, hipStream_t s) {
+  hipLaunchKernelGGL(k_to64, dim3(cdiv(n, 256)), dim3(256), 0, s, n, a, b);
+  LAUNCH_OK();
+}
+
+void dot_re(int64_t n, const double2 *a, const double2 *b, double *partial, double *dst,
+            hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, n, a, b, partial);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, partial, dst, (double *)nullptr, 0);
+  LAUNCH_OK();
+}
+
+void cg_alpha(int64_t n, const double2 *p, const double2 *q, double *partial, double *sc,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, n, p, q, partial);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, partial, (double *)nullptr, sc, 1);
+  LAUNCH_OK();
+}
+
+void cg_update_xr(int64_t n, double2 *x, double2 *r, const double2 *p, const double2 *q,
+                  double *partial, double *sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_xr, dim3(kDotBlocks), dim3(256), 0, s, n, x, r, p, q, partial, sc);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, partial, (double *)nullptr, sc, 2);
+  LAUNCH_OK();
+}
+
+void cg_beta(int64_t n, const double2 *r, const double2 *z, const double2 *zold, double *partial,
+             double *sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot2_partial, dim3(kDotBlocks), dim3(256), 0, s, n, r, z, zold, partial);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, partial, (double *)nullptr, sc, 3);
+  LAUNCH_OK();
+}
+
+void cg_update_p(int64_t n, double2 *p, const double2 *z, const double *sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_p, dim3(cdiv(n, 256)), dim3(256), 0, s, n, p, z, sc);
+  LAUNCH_OK();
+}
+
+template void launch_csr<double>(int64_t, const int64_t *, const int32_t *, const double *,
+                                 const double2 *, double2 *, int, hipStream_t);
+template void launch_csr<float>(int64_t, const int64_t *, const int32_t *, const float *,
+                                const float2 *, float2 *, int, hipStream_t);
+template void launch_condense_local<double>(const double2 *, int, int, const int32_t *, int,
+                                            const double2 *, double2 *, hipStream_t);
+template void launch_condense_local<float>(const float2 *, int, int, const int32_t *, int,
+                                           const float2 *, float2 *, hipStream_t);
+template void launch_condense_reduce<double>(int64_t, const int64_t *, const int32_t *,
+                                             const int32_t *, const double2 *, const double2 *,
+                                             double2 *, hipStream_t);
+template void launch_condense_reduce<float>(int64_t, const int64_t *, const int32_t *,
+                                            const int32_t *, const float2 *, const float2 *,
+                                            float2 *, hipStream_t);
+template void launch_expand<double>(const double2 *, const double2 *, int, int, const int32_t *,
+                                    const int32_t *, int, const double2 *, const double2 *,
+                                    int64_t, const int64_t *, double2 *, hipStream_t);
+template void launch_expand<float>(const float2 *, const float2 *, int, int, const int32_t *,
+                                   const int32_t *, int, const float2 *, const float2 *, int64_t,
+                                   const int64_t *, float2 *, hipStream_t);
+
+}  // namespace dpg

@@ -1,0 +1,242 @@
+"""Python binding of libdpgmg (argument marshalling only).
+
+Mirrors include/dpgmg.h call for call.  Every step of the solver runs in the
+HIP library; this module only converts numpy arrays / torch tensors to
+pointers.  It fails loudly when the library has not been built.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libdpgmg.so")
+
+DPG_OK, DPG_EINVAL, DPG_ENOMEM, DPG_ENOTPD, DPG_ENOCONV, DPG_EBREAKDOWN, DPG_ESTATE, DPG_EDEVICE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+DPG_FP64, DPG_MIXED = 0, 1
+DPG_DEVICE_PTRS = 1
+(X_ELEM_DOFS, X_MACRO_B, X_BLOCK_B, X_BLOCK_I, X_PATCHES, X_PROLONG, X_ELEM_S, X_ELEM_RHS,
+ X_MACRO_M, X_COARSE_E, X_PATCH_INV, X_COARSEST, X_PROLONG_VAL, X_ASM_RHS) = range(1, 15)
+
+_INT64_EXPORTS = {X_ELEM_DOFS, X_MACRO_B, X_BLOCK_B, X_BLOCK_I, X_PATCHES, X_PROLONG}
+_DOUBLE_EXPORTS = {X_PROLONG_VAL}
+
+SYMBOLS = ["dpg_default_options", "dpg_setup", "dpg_assemble", "dpg_build_hierarchy",
+           "dpg_load_rhs", "dpg_solve", "dpg_get_fields", "dpg_info", "dpg_export",
+           "dpg_last_error", "dpg_destroy"]
+
+
+class dpg_mesh(C.Structure):
+    _fields_ = [("n", C.c_int32), ("origin", C.c_double * 3), ("side", C.c_double)]
+
+
+class dpg_material(C.Structure):
+    _fields_ = [("c", C.POINTER(C.c_double))]
+
+
+class dpg_load(C.Structure):
+    _fields_ = [("dir", C.c_double * 3), ("amp", C.c_double * 2), ("nsrc", C.c_int32),
+                ("src", C.POINTER(C.c_double))]
+
+
+class dpg_options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
+                ("nlevels", C.c_int32), ("maxit", C.c_int32), ("flags", C.c_int32),
+                ("theta", C.c_double), ("hbm_budget", C.c_int64), ("stream", C.c_void_p)]
+
+
+class dpg_info_t(C.Structure):
+    _fields_ = [("n_trace", C.c_int64), ("n_macro", C.c_int64), ("nlevels", C.c_int32),
+                ("level_n", C.c_int32 * 16), ("level_ntrace", C.c_int64 * 16),
+                ("level_nmacro", C.c_int64 * 16), ("resident_bytes", C.c_int64),
+                ("n_test", C.c_int32), ("n_field", C.c_int32), ("n_tr", C.c_int32),
+                ("setup_ms", C.c_double * 4)]
+
+
+class DPGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libdpgmg error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is missing: run python -m paper_2304_01728_amd.build")
+        L = C.CDLL(LIBPATH)
+        vp = C.c_void_p
+        L.dpg_default_options.argtypes = [C.POINTER(dpg_options)]
+        L.dpg_default_options.restype = None
+        L.dpg_setup.argtypes = [C.POINTER(dpg_mesh), C.c_int, C.c_int, C.c_double,
+                                C.POINTER(dpg_material), C.POINTER(dpg_load), C.c_int,
+                                C.POINTER(dpg_options), C.POINTER(vp)]
+        L.dpg_setup.restype = C.c_int
+        for name in ("dpg_assemble", "dpg_build_hierarchy"):
+            getattr(L, name).argtypes = [vp]
+            getattr(L, name).restype = C.c_int
+        L.dpg_load_rhs.argtypes = [vp, C.POINTER(dpg_load), C.c_int, vp]
+        L.dpg_load_rhs.restype = C.c_int
+        L.dpg_solve.argtypes = [vp, vp, C.c_int, C.c_double, vp, vp, vp]
+        L.dpg_solve.restype = C.c_int
+        L.dpg_get_fields.argtypes = [vp, vp, C.c_int, vp]
+        L.dpg_get_fields.restype = C.c_int
+        L.dpg_info.argtypes = [vp, C.POINTER(dpg_info_t)]
+        L.dpg_info.restype = C.c_int
+        L.dpg_export.argtypes = [vp, C.c_int, C.c_int, vp, C.c_int64]
+        L.dpg_export.restype = C.c_int64
+        L.dpg_last_error.argtypes = [vp]
+        L.dpg_last_error.restype = C.c_char_p
+        L.dpg_destroy.argtypes = [vp]
+        L.dpg_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(ctx, code, allow=()):
+    if code != DPG_OK and code not in allow:
+        msg = lib().dpg_last_error(ctx).decode() if ctx else "setup failed"
+        raise DPGError(code, msg)
+    return code
+
+
+def dpg_default_options(**kw):
+    o = dpg_options()
+    lib().dpg_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _loads(loads):
+    """list of dicts {dir, amp, sources: [[x,y,z,sigma,re,im], ...]} -> ctypes array."""
+    arr = (dpg_load * max(1, len(loads)))()
+    keep = []
+    for i, ld in enumerate(loads):
+        arr[i].dir[:] = list(np.asarray(ld.get("dir", (0.0, 0.0, 1.0)), dtype=float))
+        amp = complex(ld.get("amp", 0.0))
+        arr[i].amp[:] = [amp.real, amp.imag]
+        src = np.ascontiguousarray(np.asarray(ld.get("sources", np.zeros((0, 6))), dtype=float))
+        arr[i].nsrc = src.shape[0]
+        if src.size:
+            keep.append(src)
+            arr[i].src = src.ctypes.data_as(C.POINTER(C.c_double))
+    return arr, keep
+
+
+class Context:
+    """Owner of a dpg_ctx handle."""
+
+    def __init__(self, handle):
+        self.h = handle
+
+    def close(self):
+        if self.h:
+            lib().dpg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dpg_setup(n, p, omega, loads, dp=1, side=1.0, origin=(0.0, 0.0, 0.0), c=None, options=None):
+    mesh = dpg_mesh(n=n, side=side)
+    mesh.origin[:] = list(origin)
+    mat = None
+    keepc = None
+    if c is not None:
+        keepc = np.ascontiguousarray(np.asarray(c, dtype=float))
+        mat = dpg_material(c=keepc.ctypes.data_as(C.POINTER(C.c_double)))
+    arr, keep = _loads(loads)
+    opt = options if options is not None else dpg_default_options()
+    h = C.c_void_p()
+    code = lib().dpg_setup(C.byref(mesh), p, dp, omega, C.byref(mat) if mat else None, arr,
+                           len(loads), C.byref(opt), C.byref(h))
+    del keep, keepc
+    if code != DPG_OK:
+        raise DPGError(code, "dpg_setup failed")
+    return Context(h.value)
+
+
+def dpg_assemble(ctx):
+    _check(ctx.h, lib().dpg_assemble(ctx.h))
+
+
+def dpg_build_hierarchy(ctx):
+    _check(ctx.h, lib().dpg_build_hierarchy(ctx.h))
+
+
+def dpg_info(ctx):
+    info = dpg_info_t()
+    _check(ctx.h, lib().dpg_info(ctx.h, C.byref(info)))
+    return info
+
+
+def dpg_load_rhs(ctx, loads, want=True):
+    arr, keep = _loads(loads)
+    nT = dpg_info(ctx).n_trace
+    out = np.zeros((len(loads), nT), dtype=np.complex128) if want else None
+    _check(ctx.h, lib().dpg_load_rhs(ctx.h, arr, len(loads),
+                                     out.ctypes.data if want else None))
+    return out
+
+
+def dpg_solve(ctx, rhs=None, nrhs=1, tol=1e-8, x_out=None, device=False):
+    """Solve; rhs: [nrhs, n_trace] complex128 (host) or None for the assembled
+    loads.  With device=True, rhs / x_out are torch device tensors (complex128,
+    contiguous) and the context must have been set up with DPG_DEVICE_PTRS.
+    Returns (x, iters, relres, status)."""
+    nT = dpg_info(ctx).n_trace
+    iters = np.zeros(nrhs, dtype=np.int32)
+    rel = np.zeros(nrhs, dtype=np.float64)
+    if device:
+        rp = rhs.data_ptr() if rhs is not None else None
+        xp = x_out.data_ptr() if x_out is not None else None
+        x = x_out
+    else:
+        if rhs is not None:
+            rhs = np.ascontiguousarray(np.asarray(rhs, dtype=np.complex128).reshape(nrhs, nT))
+        x = np.zeros((nrhs, nT), dtype=np.complex128) if x_out is None else x_out
+        rp = rhs.ctypes.data if rhs is not None else None
+        xp = x.ctypes.data
+    code = lib().dpg_solve(ctx.h, rp, nrhs, tol, xp, iters.ctypes.data, rel.ctypes.data)
+    _check(ctx.h, code, allow=(DPG_ENOCONV,))
+    return x, iters, rel, code
+
+
+def dpg_get_fields(ctx, x):
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+    x = x.reshape(-1, x.shape[-1])
+    info = dpg_info(ctx)
+    nel = info.level_n[0] ** 3
+    out = np.zeros((x.shape[0], nel, info.n_field), dtype=np.complex128)
+    _check(ctx.h, lib().dpg_get_fields(ctx.h, x.ctypes.data, x.shape[0], out.ctypes.data))
+    return out
+
+
+def dpg_export(ctx, what, level=0):
+    n = lib().dpg_export(ctx.h, what, level, None, 0)
+    if n < 0:
+        _check(ctx.h, int(n))
+    if what in _INT64_EXPORTS:
+        out = np.zeros(n, dtype=np.int64)
+    elif what in _DOUBLE_EXPORTS:
+        out = np.zeros(n, dtype=np.float64)
+    else:
+        out = np.zeros(n, dtype=np.complex128)
+    m = lib().dpg_export(ctx.h, what, level, out.ctypes.data, n)
+    if m < 0:
+        _check(ctx.h, int(m))
+    return out
+
+
+def dpg_destroy(ctx):
+    ctx.close()
