@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Benchmark of the DPG multigrid hot path on one MI355X.
+
+One step = one pass of the whole GPU path over the workload: the element DPG
+stage (Gram Cholesky, B^H G^-1 B, static condensation), the multigrid
+hierarchy (macro condensation, Galerkin coarse operators, vertex-patch
+inverses, coarsest factorisation) and the preconditioned CG solve to the
+workload's tolerance.  The mesh topology (integer numbering, maps, patch lists)
+is built once per mesh by dpg_setup before the timed region, like the inputs.
+
+Prints one JSON line.  value = n_trace * PCG iterations / (seconds per step).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6      # 256 CU x 2.4 GHz x 128 FP64 flop/clk (vector = matrix peak)
+FP32_PEAK_TFLOPS = 157.3
+
+
+def make_options(D, w, torch_stream=None, device_ptrs=True):
+    return D.dpg_default_options(
+        nu_pre=w.nu_pre, nu_post=w.nu_post, theta=w.theta,
+        precision=D.DPG_MIXED if w.precision == "mixed" else D.DPG_FP64,
+        flags=D.DPG_DEVICE_PTRS if device_ptrs else 0,
+        stream=torch_stream)
+
+
+def loads_of(w):
+    if w.sources is not None:
+        return [dict(dir=(0.0, 0.0, 1.0), amp=0.0,
+                     sources=[[*c, w.sigma, 1.0, 0.0]]) for c in w.sources]
+    return [dict(dir=w.direction, amp=1.0)]
+
+
+def roofline_for(stats, precision):
+    """Roofline object for the kernel class with the largest total time."""
+    from paper_2304_01728_amd import dpgmg as D
+    cls, (n, ms, work) = max(stats.items(), key=lambda kv: kv[1][1])
+    avg_ms = ms / n
+    if cls in ("apply64", "apply32"):
+        achieved = work / n / (avg_ms * 1e-3) / 1e9
+        return {"kernel": D.KERNEL_SYMBOLS.get(cls, cls), "bound": "hbm", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": None, "launches": n, "avg_ms": avg_ms,
+                "work_per_launch": work / n}
+    if work > 0:
+        achieved = work / n / (avg_ms * 1e-3) / 1e12
+        return {"kernel": D.KERNEL_SYMBOLS.get(cls, cls), "bound": "alu", "achieved": achieved,
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                "traffic": None, "launches": n, "avg_ms": avg_ms,
+                "work_per_launch": work / n}
+    return {"kernel": D.KERNEL_SYMBOLS.get(cls, cls), "bound": "hbm", "achieved": None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None, "traffic": None,
+            "launches": n, "avg_ms": avg_ms}
+
+
+def cpu_baseline(w, iters):
+    """The oracle timed on a bounded sample of the same workload, extrapolated.
+
+    Sample: a 3x3x3 block of coarse cells at the centre of the mesh and their
+    fine elements.  Element stage on those elements; macro condensation and
+    Galerkin products of the cells; the inverses of the vertex patches inside
+    the block; one smoothing sweep restricted to one of them.  Each phase is scaled to the full finest
+    level by its work model (elements, cells, sum n^3 over patches, sum n^2
+    over patches and cells); coarser levels are not counted.
+    """
+    from oracle import dpg, multigrid, topology
+    from threadpoolctl import threadpool_info
+    threads = max([tp.get("num_threads", 1) for tp in threadpool_info()] + [1])
+    N, p = w.N, w.p
+    Nc = N // 2
+    t = {}
+    t0 = time.perf_counter()
+    loads = [dict(u0=dpg.plane_wave_u0(w.omega, w.direction))] if w.direction is not None else \
+        [dict(f=dpg.gaussian_sources(w.sources[:1], w.sigma, [1.0]))]
+    pr = dpg.Problem(N, p, w.omega, loads)
+    lv = multigrid.Level(N, p, None)
+    mc = topology.MacroLevel(lv.num)
+    cnum = topology.Numbering(Nc, p)
+    P = topology.prolongation(mc, cnum)
+    cedofs = topology.element_dofs(cnum)
+    t["topology"] = time.perf_counter() - t0
+    c0 = max(Nc // 2 - 1, 0)
+    span = min(3, Nc)
+    cells = [(c0 + a) + Nc * ((c0 + b) + Nc * (c0 + c))
+             for c in range(span) for b in range(span) for a in range(span)]
+    kids = sorted(e for kc in cells for e in mc.children[kc])
+    t0 = time.perf_counter()
+    S, s, _ = pr.condensed(elements=kids)
+    t["element"] = (time.perf_counter() - t0) * pr.nel / len(kids)
+    lv.E = S
+    t0 = time.perf_counter()
+    Mb = [multigrid.condense_block(lv, mc, kc)[0] for kc in cells]
+    t["macro"] = (time.perf_counter() - t0) * Nc ** 3 / len(cells)
+    t0 = time.perf_counter()
+    for kc, Mk in zip(cells, Mb):
+        multigrid.galerkin_block(mc, P, Mk, kc, cedofs)
+    t["galerkin"] = (time.perf_counter() - t0) * Nc ** 3 / len(cells)
+    M = multigrid.assemble_macro(mc, cells, Mb)
+    # vertices whose 8 surrounding cells all lie in the sampled block
+    verts = [(vx, vy, vz) for vz in range(c0 + 1, c0 + span) for vy in range(c0 + 1, c0 + span)
+             for vx in range(c0 + 1, c0 + span)]
+    pidx = [mc.patches[(vz * (Nc + 1) + vy) * (Nc + 1) + vx] for vx, vy, vz in verts]
+    sizes = np.array([len(x) for x in mc.patches], dtype=float)
+    t0 = time.perf_counter()
+    Sis = [multigrid.patch_inverse(M, idx) for idx in pidx]
+    t["patches"] = (time.perf_counter() - t0) * np.sum(sizes ** 3) / \
+        sum(float(idx.size) ** 3 for idx in pidx)
+    Si, idx = Sis[0], pidx[0]
+    # one sweep: the macro operator on the 8 cells and the patch product
+    x = np.random.default_rng(0).standard_normal(mc.nM) + 0j
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        M @ x
+    t_m = (time.perf_counter() - t0) / reps * Nc ** 3 / len(cells)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        Si @ x[idx]
+    t_s = (time.perf_counter() - t0) / reps * np.sum(sizes ** 2) / idx.size ** 2
+    nsw = w.nu_pre + w.nu_post
+    # per iteration: outer matvec + one residual + nsw smoothing sweeps (matvec + patches)
+    t["per_iteration"] = (1 + 1 + nsw) * t_m + nsw * t_s
+    total = t["topology"] + t["element"] + t["macro"] + t["galerkin"] + t["patches"] + \
+        iters * t["per_iteration"]
+    nT = topology.n_trace(N, p)
+    return {"value": nT * iters / total, "unit": "trace-DOF*PCG-iters/s", "cores": threads,
+            "kind": "oracle",
+            "sample": ("a 3x3x3 block of coarse cells at the mesh centre (%d elements), the "
+                       "%d vertex patches inside it and one smoothing sweep; each phase scaled "
+                       "to the finest level of the full mesh by its work model (elements, cells, "
+                       "sum n^3 / sum n^2 over patches); coarser levels not counted; %d PCG "
+                       "iterations" % (len(kids), len(pidx), iters)),
+            "phase_s": {k: round(v, 3) for k, v in t.items()},
+            "extrapolated_job_s": total}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="plane_wave_16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(how it would shard is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2304_01728_amd import dpgmg as D
+    from paper_2304_01728_amd import workloads as W
+
+    w = W.ALL[args.workload]()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    opt = make_options(D, w, torch_stream=stream.cuda_stream)
+    t0 = time.perf_counter()
+    ctx = D.dpg_setup(w.N, w.p, w.omega, loads_of(w), dp=w.dp, options=opt)
+    setup_s = time.perf_counter() - t0
+    info = D.dpg_info(ctx)
+    nT = info.n_trace
+    x = torch.zeros((w.nrhs, nT), dtype=torch.complex128, device=dev)
+
+    def step():
+        D.dpg_assemble(ctx)
+        D.dpg_build_hierarchy(ctx)
+        _, it, rr, code = D.dpg_solve(ctx, nrhs=w.nrhs, tol=w.tol, x_out=x, device=True)
+        return it, rr, code
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    D.dpg_profile(ctx, True)
+    iters_total = 0
+    phase = {"assemble": 0.0, "hierarchy": 0.0, "solve": 0.0}
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        ta = time.perf_counter()
+        D.dpg_assemble(ctx)
+        tb = time.perf_counter()
+        D.dpg_build_hierarchy(ctx)
+        tc = time.perf_counter()
+        _, it, rr, code = D.dpg_solve(ctx, nrhs=w.nrhs, tol=w.tol, x_out=x, device=True)
+        td = time.perf_counter()
+        phase["assemble"] += tb - ta
+        phase["hierarchy"] += tc - tb
+        phase["solve"] += td - tc
+        iters_total += int(np.sum(it))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    stats = D.dpg_kernel_stats(ctx)
+    D.dpg_profile(ctx, False)
+    iters_per_step = iters_total / args.steps
+    value = nT * iters_total / elapsed
+    solve_s = phase["solve"] / args.steps
+    out = {
+        "metric": "trace-DOF*PCG-iters/s",
+        "value": value,
+        "unit": "trace-DOF*PCG-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if w.precision == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "N": w.N, "p": w.p, "dp": w.dp, "omega": w.omega,
+                   "nu": [w.nu_pre, w.nu_post], "theta": w.theta, "tol": w.tol,
+                   "precision": w.precision, "nrhs": w.nrhs, "n_trace": nT,
+                   "n_macro": info.n_macro, "levels": list(info.level_n)[:info.nlevels]},
+        "iterations": iters_per_step,
+        "relres": float(np.max(rr)),
+        "time_to_tol_ms": 1e3 * solve_s,
+        "solve_only": {"value": nT * iters_per_step / solve_s, "unit": "trace-DOF*PCG-iters/s",
+                       "ms_per_iteration": 1e3 * solve_s / max(iters_per_step, 1)},
+        "phases_ms": {k: 1e3 * v / args.steps for k, v in phase.items()},
+        "setup_topology_ms": 1e3 * setup_s,
+        "resident_GB": info.resident_bytes / 1e9,
+        "roofline": roofline_for(stats, w.precision),
+        "kernels": {k: {"launches": n, "ms": ms, "work": wk} for k, (n, ms, wk) in stats.items()},
+    }
+    if "apply64" in stats or "apply32" in stats:
+        k = "apply64" if "apply64" in stats else "apply32"
+        n, ms, wk = stats[k]
+        out["roofline_apply"] = {"kernel": D.KERNEL_SYMBOLS[k], "bound": "hbm",
+                                 "achieved": wk / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": wk / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 "traffic": None}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, int(round(iters_per_step)))
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

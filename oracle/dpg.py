@@ -125,17 +125,18 @@ class Problem:
         G, B, _ = self._operator(e)
         return optimal_test_product(G, B, self.element_load(e))
 
-    def condensed(self):
+    def condensed(self, elements=None):
         """Per-element S [nel, n_tr, n_tr], s [nel, n_tr, nrhs], recovery data.
 
         K and S are memoised per element class like G and B; the loads are
-        computed for every element.
+        computed for every element.  `elements` restricts the work to a subset
+        (the other rows stay zero).
         """
         S = np.zeros((self.nel, self.n_tr, self.n_tr), dtype=np.complex128)
         s = np.zeros((self.nel, self.n_tr, len(self.loads)), dtype=np.complex128)
-        rec = []
+        rec = [None] * self.nel
         scache = {}
-        for e in range(self.nel):
+        for e in (range(self.nel) if elements is None else elements):
             G, B, cG = self._operator(e)
             key = id(cG)
             l = self.element_load(e)
@@ -147,7 +148,7 @@ class Problem:
             f = slice(0, self.n_field)
             S[e] = Se
             s[e] = b[self.n_field:] - Kft.conj().T @ sla.cho_solve(cK, b[f])
-            rec.append((cK, Kft, b[f]))
+            rec[e] = (cK, Kft, b[f])
         return S, s, rec
 
 

@@ -49,62 +49,80 @@ class Level:
         self.n = self.num.n
 
 
-def macro_condense(lv):
-    """Per coarse element: M_K = T_BB - T_BI T_II^-1 T_IB from its 8 children."""
-    mc = topology.MacroLevel(lv.num)
-    lv.macro = mc
-    lv.Mblocks, lv.TII, lv.TIB = [], [], []
-    for kc, kids in enumerate(mc.children):
-        Bd, Id = mc.blocks_B[kc], mc.blocks_I[kc]
-        dofs = np.concatenate([Bd, Id])
-        pos = {int(d): i for i, d in enumerate(dofs)}
-        T = np.zeros((dofs.size, dofs.size), dtype=np.complex128)
-        for e in kids:
-            d = lv.edofs[e]
-            ok = np.nonzero(d >= 0)[0]
-            loc = np.array([pos[int(d[i])] for i in ok])
-            T[np.ix_(loc, loc)] += lv.E[e][np.ix_(ok, ok)]
-        nb = Bd.size
-        TBB, TBI, TIB, TII = T[:nb, :nb], T[:nb, nb:], T[nb:, :nb], T[nb:, nb:]
-        c = sla.cho_factor(TII, lower=True)
-        M = TBB - TBI @ sla.cho_solve(c, TIB)
-        lv.Mblocks.append(0.5 * (M + M.conj().T))
-        lv.TII.append(c)
-        lv.TIB.append(TIB)
+def condense_block(lv, mc, kc):
+    """Coarse element kc: M_K = T_BB - T_BI T_II^-1 T_IB from its 8 children.
+
+    Returns (M_K, Cholesky factor of T_II, T_IB)."""
+    Bd, Id = mc.blocks_B[kc], mc.blocks_I[kc]
+    dofs = np.concatenate([Bd, Id])
+    pos = {int(d): i for i, d in enumerate(dofs)}
+    T = np.zeros((dofs.size, dofs.size), dtype=np.complex128)
+    for e in mc.children[kc]:
+        d = lv.edofs[e]
+        ok = np.nonzero(d >= 0)[0]
+        loc = np.array([pos[int(d[i])] for i in ok])
+        T[np.ix_(loc, loc)] += lv.E[e][np.ix_(ok, ok)]
+    nb = Bd.size
+    TBB, TBI, TIB, TII = T[:nb, :nb], T[:nb, nb:], T[nb:, :nb], T[nb:, nb:]
+    c = sla.cho_factor(TII, lower=True)
+    M = TBB - TBI @ sla.cho_solve(c, TIB)
+    return 0.5 * (M + M.conj().T), c, TIB
+
+
+def assemble_macro(mc, blocks, Mblocks):
+    """Sparse macro operator sum_K E_K^T M_K E_K over the given blocks."""
     rows, cols, vals = [], [], []
-    for kc, M in enumerate(lv.Mblocks):
+    for kc, M in zip(blocks, Mblocks):
         m = mc.macro_of[mc.blocks_B[kc]]
         rows.append(np.repeat(m, m.size))
         cols.append(np.tile(m, m.size))
         vals.append(M.ravel())
-    lv.M = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                          shape=(mc.nM, mc.nM)).tocsr()
 
 
-def galerkin(lv, coarse_num, coarse_edofs):
-    """A_Kc = P_Kc^T M_Kc P_Kc for every coarse element (coarse element matrices)."""
-    mc = lv.macro
-    P = lv.P
-    A = []
+def macro_condense(lv):
+    """Macro condensation of every coarse element of the level."""
+    mc = topology.MacroLevel(lv.num)
+    lv.macro = mc
+    lv.Mblocks, lv.TII, lv.TIB = [], [], []
     for kc in range(len(mc.children)):
-        rows = mc.macro_of[mc.blocks_B[kc]]
-        cd = coarse_edofs[kc]
-        Pk = np.zeros((rows.size, cd.size))
-        ok = cd >= 0
-        Pk[:, ok] = P[rows][:, cd[ok]].toarray()
-        Ak = Pk.T @ lv.Mblocks[kc] @ Pk
-        A.append(0.5 * (Ak + Ak.conj().T))
-    return np.array(A)
+        M, c, TIB = condense_block(lv, mc, kc)
+        lv.Mblocks.append(M)
+        lv.TII.append(c)
+        lv.TIB.append(TIB)
+    lv.M = assemble_macro(mc, range(len(mc.children)), lv.Mblocks)
+
+
+def galerkin_block(mc, P, Mk, kc, coarse_edofs):
+    """A_Kc = P_Kc^T M_Kc P_Kc of coarse element kc."""
+    rows = mc.macro_of[mc.blocks_B[kc]]
+    cd = coarse_edofs[kc]
+    Pk = np.zeros((rows.size, cd.size))
+    ok = cd >= 0
+    Pk[:, ok] = P[rows][:, cd[ok]].toarray()
+    Ak = Pk.T @ Mk @ Pk
+    return 0.5 * (Ak + Ak.conj().T)
+
+
+def galerkin(lv, coarse_num, coarse_edofs):
+    """Coarse element matrices of every coarse element."""
+    mc = lv.macro
+    return np.array([galerkin_block(mc, lv.P, lv.Mblocks[kc], kc, coarse_edofs)
+                     for kc in range(len(mc.children))])
+
+
+def patch_inverse(M, idx):
+    """Inverse of the principal submatrix of M on the patch unknowns idx."""
+    S = M[idx][:, idx].toarray()
+    c = sla.cho_factor(S, lower=True)
+    Si = sla.cho_solve(c, np.eye(idx.size, dtype=np.complex128))
+    return 0.5 * (Si + Si.conj().T)
 
 
 def build_patches(lv):
-    lv.Sinv = []
     Md = lv.M.tocsr()
-    for idx in lv.macro.patches:
-        S = Md[idx][:, idx].toarray()
-        c = sla.cho_factor(S, lower=True)
-        Si = sla.cho_solve(c, np.eye(idx.size, dtype=np.complex128))
-        lv.Sinv.append(0.5 * (Si + Si.conj().T))
+    lv.Sinv = [patch_inverse(Md, idx) for idx in lv.macro.patches]
 
 
 class Hierarchy:

@@ -15,6 +15,14 @@ double ms_since(clk::time_point t0) {
   return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
 }
 
+// LAPACK-style flop counts of complex double routines
+double f_potrf(double n) { return 4.0 / 3.0 * n * n * n; }
+double f_trsm(double n, double k) { return 4.0 * n * n * k; }
+double f_gemm(double m, double n, double k) { return 8.0 * m * n * k; }
+double f_herk(double n, double k) { return 4.0 * n * n * k; }   // Hermitian product, one triangle
+
+#define PROF(cls, work) ProfScope _prof_scope(&c->prof, (cls), (double)(work), c->stream)
+
 template <class F> int guarded(dpg_ctx *c, F &&f) {
   try {
     return f();
@@ -117,19 +125,46 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
   const hipStream_t s = c->stream;
   for (int e0 = 0; e0 < nel; e0 += C) {
     const int cnt = std::min(C, nel - e0);
-    launch_gram(c->tables.p, c->testd.p, nt, g, c->kappa.p, e0, cnt, G.p, s);
-    launch_bmat(c->tables.p, c->testd.p, c->triald.p, nt, m, g, c->kappa.p, c->Zel.p, e0, cnt,
-                BL.p, (int64_t)nt * mp, s);
-    launch_load(c->tables.p, nt, m, g, c->Zel.p, c->ld.p, c->src.p, nr, e0, cnt, BL.p,
-                (int64_t)nt * mp, s);
-    potrf_batched(G.p, dpG.p, cnt, info.p, s);
+    {
+      PROF(DPG_K_GRAM, 0);
+      launch_gram(c->tables.p, c->testd.p, nt, g, c->kappa.p, e0, cnt, G.p, s);
+    }
+    {
+      PROF(DPG_K_BMAT, 0);
+      launch_bmat(c->tables.p, c->testd.p, c->triald.p, nt, m, g, c->kappa.p, c->Zel.p, e0, cnt,
+                  BL.p, (int64_t)nt * mp, s);
+    }
+    {
+      PROF(DPG_K_LOAD, 0);
+      launch_load(c->tables.p, nt, m, g, c->Zel.p, c->ld.p, c->src.p, nr, e0, cnt, BL.p,
+                  (int64_t)nt * mp, s);
+    }
+    {
+      PROF(DPG_K_POTRF, cnt * f_potrf(nt));
+      potrf_batched(G.p, dpG.p, cnt, info.p, s);
+    }
     check_info(info, cnt, c, "element Gram matrix", e0);
-    trsm_batched(G.p, BL.p, dtG.p, cnt, mp, s);
-    gemm_batched(OP_C, OP_N, mk(1, 0), BL.p, BL.p, mk(0, 0), K.p, dgK.p, cnt, mp, mp, s);
-    potrf_batched(K.p, dpK.p, cnt, info.p, s);
+    {
+      PROF(DPG_K_TRSM, cnt * f_trsm(nt, mp));
+      trsm_batched(G.p, BL.p, dtG.p, cnt, mp, s);
+    }
+    {
+      PROF(DPG_K_GEMM, cnt * f_herk(mp, nt));
+      gemm_batched(OP_C, OP_N, mk(1, 0), BL.p, BL.p, mk(0, 0), K.p, dgK.p, cnt, mp, mp, s);
+    }
+    {
+      PROF(DPG_K_POTRF, cnt * f_potrf(nf));
+      potrf_batched(K.p, dpK.p, cnt, info.p, s);
+    }
     check_info(info, cnt, c, "element field block", e0);
-    trsm_batched(K.p, K.p, dtK.p, cnt, mp - nf, s);
-    gemm_batched(OP_C, OP_N, mk(-1, 0), K.p, K.p, mk(1, 0), K.p, dgS.p, cnt, mp - nf, mp - nf, s);
+    {
+      PROF(DPG_K_TRSM, cnt * f_trsm(nf, mp - nf));
+      trsm_batched(K.p, K.p, dtK.p, cnt, mp - nf, s);
+    }
+    {
+      PROF(DPG_K_GEMM, cnt * f_herk(mp - nf, nf));
+      gemm_batched(OP_C, OP_N, mk(-1, 0), K.p, K.p, mk(1, 0), K.p, dgS.p, cnt, mp - nf, mp - nf, s);
+    }
     if (write_matrices)
       launch_copy_sub(K.p, (int64_t)mp * mp, mp, nf, nf, ntr, ntr, f.E.p + (int64_t)e0 * ntr * ntr,
                       (int64_t)ntr * ntr, ntr, cnt, s);
@@ -211,22 +246,52 @@ void build_macro_level(dpg_ctx *c, int l) {
   info.alloc(CB, &c->bud);
   for (int b0 = 0; b0 < nblk; b0 += CB) {
     const int cnt = std::min(CB, nblk - b0);
-    launch_macro_assemble(f.E.p, ntr, cmap.p, f.N, b0, cnt, nT, T.p, s);
-    potrf_batched(T.p, dpII.p, cnt, info.p, s);
+    {
+      PROF(DPG_K_MACRO_ASM, 0);
+      launch_macro_assemble(f.E.p, ntr, cmap.p, f.N, b0, cnt, nT, T.p, s);
+    }
+    {
+      PROF(DPG_K_POTRF, cnt * f_potrf(nI));
+      potrf_batched(T.p, dpII.p, cnt, info.p, s);
+    }
     check_info(info, cnt, c, "interior block of coarse element", b0);
-    trsm_batched(T.p, T.p, dtIB.p, cnt, nBf, s);
-    gemm_batched(OP_C, OP_N, mk(-1, 0), T.p, T.p, mk(1, 0), T.p, dgS.p, cnt, nBf, nBf, s);
-    launch_identity(didoff.p, didn.p, cnt, nI, Linv.p, s);
-    trsm_batched(T.p, Linv.p, dtLi.p, cnt, nI, s);
-    gemm_batched(OP_C, OP_N, mk(1, 0), Linv.p, Linv.p, mk(0, 0), f.Tinv.p + (int64_t)b0 * nI * nI,
-                 dgTi.p, cnt, nI, nI, s);
-    gemm_batched(OP_C, OP_N, mk(1, 0), T.p, Linv.p, mk(0, 0), f.WH.p + (int64_t)b0 * nBf * nI,
-                 dgWH.p, cnt, nBf, nI, s);
-    launch_copy_sub(T.p, (int64_t)nT * nT, nT, 0, 0, nBf, nBf, f.Mfull.p + (int64_t)b0 * nBf * nBf,
-                    (int64_t)nBf * nBf, nBf, cnt, s);
-    gemm_batched(OP_N, OP_N, mk(1, 0), T.p, Ploc.p, mk(0, 0), X.p, dgX.p, cnt, nBf, ntr, s);
-    gemm_batched(OP_T, OP_N, mk(1, 0), Ploc.p, X.p, mk(0, 0), cl.E.p + (int64_t)b0 * ntr * ntr,
-                 dgA.p, cnt, ntr, ntr, s);
+    {
+      PROF(DPG_K_TRSM, cnt * f_trsm(nI, nBf));
+      trsm_batched(T.p, T.p, dtIB.p, cnt, nBf, s);
+    }
+    {
+      PROF(DPG_K_GEMM, cnt * f_herk(nBf, nI));
+      gemm_batched(OP_C, OP_N, mk(-1, 0), T.p, T.p, mk(1, 0), T.p, dgS.p, cnt, nBf, nBf, s);
+    }
+    {
+      PROF(DPG_K_OTHER, 0);
+      launch_identity(didoff.p, didn.p, cnt, nI, Linv.p, s);
+    }
+    {
+      PROF(DPG_K_TRSM, cnt * f_trsm(nI, nI));
+      trsm_batched(T.p, Linv.p, dtLi.p, cnt, nI, s);
+    }
+    {
+      PROF(DPG_K_GEMM, cnt * f_herk(nI, nI));
+      gemm_batched(OP_C, OP_N, mk(1, 0), Linv.p, Linv.p, mk(0, 0), f.Tinv.p + (int64_t)b0 * nI * nI,
+                   dgTi.p, cnt, nI, nI, s);
+    }
+    {
+      PROF(DPG_K_GEMM, cnt * f_gemm(nBf, nI, nI));
+      gemm_batched(OP_C, OP_N, mk(1, 0), T.p, Linv.p, mk(0, 0), f.WH.p + (int64_t)b0 * nBf * nI,
+                   dgWH.p, cnt, nBf, nI, s);
+    }
+    {
+      PROF(DPG_K_OTHER, 0);
+      launch_copy_sub(T.p, (int64_t)nT * nT, nT, 0, 0, nBf, nBf, f.Mfull.p + (int64_t)b0 * nBf * nBf,
+                      (int64_t)nBf * nBf, nBf, cnt, s);
+    }
+    {
+      PROF(DPG_K_GEMM, cnt * (f_gemm(nBf, ntr, nBf) + f_gemm(ntr, ntr, nBf)));
+      gemm_batched(OP_N, OP_N, mk(1, 0), T.p, Ploc.p, mk(0, 0), X.p, dgX.p, cnt, nBf, ntr, s);
+      gemm_batched(OP_T, OP_N, mk(1, 0), Ploc.p, X.p, mk(0, 0), cl.E.p + (int64_t)b0 * ntr * ntr,
+                   dgA.p, cnt, ntr, ntr, s);
+    }
   }
   HIP_OK(hipStreamSynchronize(s));
   if (c->opt.precision == DPG_MIXED && l < c->L) {
@@ -309,13 +374,34 @@ void build_patches(dpg_ctx *c, int l) {
     upload_items(dti, ti, c);
     upload_items(dgi, gi, c);
     HIP_OK(hipMemcpyAsync(dsoff_all.p, soff_all.data(), np * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    launch_patch_gather(f.Mfull.p, f.nBf, f.mc.Nc, f.patch_ptr.p, f.patch_slot.p, v0, cnt, doff.p,
-                        S.p, s);
-    potrf_batched(S.p, dpi.p, cnt, info.p, s);
+    double fp = 0, ft = 0, fg = 0;
+    for (int i = 0; i < cnt; ++i) {
+      fp += f_potrf(nn[i]);
+      ft += f_trsm(nn[i], nn[i]);
+      fg += f_herk(nn[i], nn[i]);
+    }
+    {
+      PROF(DPG_K_PATCH_GATHER, 0);
+      launch_patch_gather(f.Mfull.p, f.nBf, f.mc.Nc, f.patch_ptr.p, f.patch_slot.p, v0, cnt,
+                          doff.p, S.p, s);
+    }
+    {
+      PROF(DPG_K_POTRF, fp);
+      potrf_batched(S.p, dpi.p, cnt, info.p, s);
+    }
     check_info(info, cnt, c, "vertex patch", v0);
-    launch_identity(doff.p, dnn.p, cnt, nmax, X.p, s);
-    trsm_batched(S.p, X.p, dti.p, cnt, nmax, s);
-    gemm_batched(OP_C, OP_N, mk(1, 0), X.p, X.p, mk(0, 0), S.p, dgi.p, cnt, nmax, nmax, s);
+    {
+      PROF(DPG_K_OTHER, 0);
+      launch_identity(doff.p, dnn.p, cnt, nmax, X.p, s);
+    }
+    {
+      PROF(DPG_K_TRSM, ft);
+      trsm_batched(S.p, X.p, dti.p, cnt, nmax, s);
+    }
+    {
+      PROF(DPG_K_GEMM, fg);
+      gemm_batched(OP_C, OP_N, mk(1, 0), X.p, X.p, mk(0, 0), S.p, dgi.p, cnt, nmax, nmax, s);
+    }
     const int64_t t0 = f.Sset.tile_off_h[v0];
     const int64_t t1 = (v0 + cnt < np) ? f.Sset.tile_off_h[v0 + cnt] : f.Sset.ntiles;
     f.Sset.pack(S.p, dsoff_all.p, dld_all.p, nullptr, nullptr, s, t0, t1 - t0);
@@ -409,17 +495,28 @@ template <typename T> void vcycle(dpg_ctx *c, int l) {
   }
   herm_apply<T>(f.Mset, x, res, r, RED_RESID, (T)0, s);
   LevelData &g = c->lv[l - 1];
-  launch_csr<T>(g.num.n, f.Ptptr.p, f.Ptcol.p, B::Ptv(f), res, rc, 0, s);
+  {
+    PROF(DPG_K_TRANSFER, 0);
+    launch_csr<T>(g.num.n, f.Ptptr.p, f.Ptcol.p, B::Ptv(f), res, rc, 0, s);
+  }
   if (l - 1 == 0) {
     herm_apply<T>(c->T0set, rc, ec, nullptr, RED_SET, (T)1, s);
   } else {
-    launch_condense_local<T>(B::WH(g), g.nI, g.nBf, g.blkI.p, g.nblk, rc, B::cc(g), s);
-    launch_condense_reduce<T>(g.nM, g.macroB.p, g.cred_ptr.p, g.cred_ent.p, rc, B::cc(g), B::r(g), s);
+    {
+      PROF(DPG_K_CONDENSE, 0);
+      launch_condense_local<T>(B::WH(g), g.nI, g.nBf, g.blkI.p, g.nblk, rc, B::cc(g), s);
+      launch_condense_reduce<T>(g.nM, g.macroB.p, g.cred_ptr.p, g.cred_ent.p, rc, B::cc(g),
+                                B::r(g), s);
+    }
     vcycle<T>(c, l - 1);
+    PROF(DPG_K_EXPAND, 0);
     launch_expand<T>(B::WH(g), B::Ti(g), g.nI, g.nBf, g.blkI.p, g.blkBm.p, g.nblk, rc, B::x(g),
                      g.nM, g.macroB.p, ec, s);
   }
-  launch_csr<T>(f.nM, f.Pptr.p, f.Pcol.p, B::Pv(f), ec, x, 1, s);
+  {
+    PROF(DPG_K_TRANSFER, 0);
+    launch_csr<T>(f.nM, f.Pptr.p, f.Pcol.p, B::Pv(f), ec, x, 1, s);
+  }
   for (int k = 0; k < c->opt.nu_post; ++k) {
     herm_apply<T>(f.Mset, x, res, r, RED_RESID, (T)0, s);
     herm_apply<T>(f.Sset, res, x, nullptr, RED_AXPY, th, s);
@@ -474,8 +571,11 @@ int solve_one(dpg_ctx *c, const double2 *sv, double tol, double2 *xout, int32_t 
     rr = 1.0;
     while (it < c->opt.maxit) {
       herm_apply<double>(top.Mset, c->pv.p, c->q.p, nullptr, RED_SET, 1.0, s);
-      cg_alpha(nM, c->pv.p, c->q.p, c->partial.p, c->sc.p, s);
-      cg_update_xr(nM, c->x.p, c->r.p, c->pv.p, c->q.p, c->partial.p, c->sc.p, s);
+      {
+        PROF(DPG_K_CG, 0);
+        cg_alpha(nM, c->pv.p, c->q.p, c->partial.p, c->sc.p, s);
+        cg_update_xr(nM, c->x.p, c->r.p, c->pv.p, c->q.p, c->partial.p, c->sc.p, s);
+      }
       ++it;
       read_sc(c);
       if (c->host_sc[6] != 0.0)
@@ -486,6 +586,7 @@ int solve_one(dpg_ctx *c, const double2 *sv, double tol, double2 *xout, int32_t 
       if (rr <= tol) break;
       std::swap(z, zo);
       precondition(c, c->r.p, z);
+      PROF(DPG_K_CG, 0);
       cg_beta(nM, c->r.p, z, zo, c->partial.p, c->sc.p, s);
       cg_update_p(nM, c->pv.p, z, c->sc.p, s);
     }
@@ -644,6 +745,8 @@ int dpg_setup(const dpg_mesh *mesh, int p, int dp, double omega, const dpg_mater
       std::vector<int32_t> psz(np);
       for (int v = 0; v < np; ++v) psz[v] = (int32_t)(f.mc.patch_ptr[v + 1] - f.mc.patch_ptr[v]);
       f.Sset.build(psz, f.mc.patch_idx, f.nM, !mixed, mixed, &c->bud, s);
+      f.Mset.prof = &c->prof;
+      f.Sset.prof = &c->prof;
       // work vectors
       const int64_t nc = c->lv[l - 1].num.n;
       if (mixed) {
@@ -667,6 +770,7 @@ int dpg_setup(const dpg_mesh *mesh, int p, int dp, double omega, const dpg_mater
       std::vector<int32_t> sz{(int32_t)n0}, id(n0);
       for (int64_t i = 0; i < n0; ++i) id[i] = (int32_t)i;
       c->T0set.build(sz, id, n0, !mixed, mixed, &c->bud, s);
+      c->T0set.prof = &c->prof;
     }
     // element load assembly lists of the finest mesh
     LevelData &top = c->lv[c->L];
@@ -723,6 +827,7 @@ int dpg_assemble(dpg_ctx *c) {
       c->rec_Y.alloc((int64_t)top.nel * c->n_field * (c->n_tr + c->nrhs), &c->bud);
     }
     element_stage(c, true);
+    c->prof.flush();
     c->ms[1] = ms_since(t0);
     c->stage = 2;
     return DPG_OK;
@@ -739,6 +844,7 @@ int dpg_build_hierarchy(dpg_ctx *c) {
       build_patches(c, l);
     }
     build_coarsest(c);
+    c->prof.flush();
     c->ms[2] = ms_since(t0);
     c->stage = 3;
     return DPG_OK;
@@ -759,6 +865,7 @@ int dpg_load_rhs(dpg_ctx *c, const dpg_load *loads, int nrhs, double *s_out) {
       c->rec_Y.alloc((int64_t)top.nel * c->n_field * (c->n_tr + c->nrhs), &c->bud);
     }
     element_stage(c, false);
+    c->prof.flush();
     if (s_out) {
       const bool dev = c->opt.flags & DPG_DEVICE_PTRS;
       HIP_OK(hipMemcpyAsync(s_out, c->s_asm.p, (size_t)nrhs * top.num.n * 16,
@@ -802,6 +909,7 @@ int dpg_solve(dpg_ctx *c, const double *rhs, int nrhs, double tol, double *x_out
         HIP_OK(hipStreamSynchronize(c->stream));
       }
     }
+    c->prof.flush();
     c->ms[3] = ms_since(t0);
     if (status == DPG_ENOCONV) c->err = "maximum number of iterations reached";
     return status;
@@ -856,6 +964,27 @@ int dpg_info(const dpg_ctx *c, dpg_info_t *info) {
 }
 
 const char *dpg_last_error(const dpg_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+int dpg_profile(dpg_ctx *c, int enable) {
+  if (!c) return DPG_EINVAL;
+  return guarded(c, [&]() {
+    c->prof.reset();
+    c->prof.on = enable != 0;
+    return DPG_OK;
+  });
+}
+
+int dpg_kernel_stats(const dpg_ctx *cc, int cls, dpg_kstat *out) {
+  dpg_ctx *c = const_cast<dpg_ctx *>(cc);
+  if (!c || !out || cls < 0 || cls >= DPG_K_NCLASS) return DPG_EINVAL;
+  return guarded(c, [&]() {
+    c->prof.flush();
+    out->launches = c->prof.stat[cls].n;
+    out->total_ms = c->prof.stat[cls].ms;
+    out->work = c->prof.stat[cls].work;
+    return DPG_OK;
+  });
+}
 
 
 int64_t dpg_export(const dpg_ctx *cc, int what, int level, void *out, int64_t cap) {

@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include "../../include/dpgmg.h"
+
 namespace dpg {
 
 constexpr int kWave = 64;
@@ -116,5 +118,73 @@ template <typename T> struct DevBuf {
 };
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// ---- kernel timing with HIP events (optional, per context) -------------------------
+// Classes match the kernel symbols, so that averages can be compared with a
+// rocprofv3 kernel trace of the same run.  `work` is algorithmic bytes for the
+// HBM-bound apply kernels and algorithmic flops for the dense kernels.
+constexpr int kProfClasses = 32;
+struct Prof {
+  bool on = false;
+  struct Rec { int cls; hipEvent_t a, b; double work; };
+  struct Stat { int64_t n = 0; double ms = 0.0, work = 0.0; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  Stat stat[kProfClasses];
+  hipEvent_t ev() {
+    if (pool.empty()) {
+      hipEvent_t e;
+      HIP_OK(hipEventCreate(&e));
+      return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  void flush() {
+    for (Rec &r : pending) {
+      HIP_OK(hipEventSynchronize(r.b));
+      float ms = 0.0f;
+      HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+      stat[r.cls].n += 1;
+      stat[r.cls].ms += ms;
+      stat[r.cls].work += r.work;
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  void reset() {
+    flush();
+    for (auto &s : stat) s = Stat{};
+  }
+  ~Prof() {
+    for (Rec &r : pending) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+// Records one launch (or one batch call) of class cls between construction and
+// destruction.
+struct ProfScope {
+  Prof *p;
+  Prof::Rec rec{};
+  hipStream_t s;
+  ProfScope(Prof *p_, int cls, double work, hipStream_t s_) : p(p_), s(s_) {
+    if (!p || !p->on) return;
+    rec.cls = cls;
+    rec.work = work;
+    rec.a = p->ev();
+    rec.b = p->ev();
+    HIP_OK(hipEventRecord(rec.a, s));
+  }
+  ~ProfScope() {
+    if (!p || !p->on) return;
+    if (hipEventRecord(rec.b, s) == hipSuccess) p->pending.push_back(rec);
+  }
+};
 
 }  // namespace dpg

@@ -82,4 +82,5 @@ struct dpg_ctx {
   dpg::DevBuf<double> partial, sc;
   double *host_sc = nullptr;         // pinned
   double ms[4] = {0, 0, 0, 0};
+  dpg::Prof prof;
 };

@@ -238,9 +238,14 @@ void herm_apply(HermSet &H, const cplx_t<T> *x, cplx_t<T> *y, const cplx_t<T> *r
     part = H.p32.p;
   }
   if (!tiles || !part) throw DpgError(-6, "block set has no tiles of this precision");
-  hipLaunchKernelGGL((k_units<T>), dim3(cdiv(H.nunits, 4)), dim3(256), 0, s, tiles, H.units.p,
-                     H.nunits, H.bn.p, H.tile_off.p, H.part_off.p, H.idx_off.p, H.idx.p, x, part);
-  LAUNCH_OK();
+  {
+    ProfScope ps(H.prof, sizeof(T) == 8 ? DPG_K_APPLY64 : DPG_K_APPLY32,
+                 (double)H.packed_entries() * sizeof(cplx_t<T>), s);
+    hipLaunchKernelGGL((k_units<T>), dim3(cdiv(H.nunits, 4)), dim3(256), 0, s, tiles, H.units.p,
+                       H.nunits, H.bn.p, H.tile_off.p, H.part_off.p, H.idx_off.p, H.idx.p, x, part);
+    LAUNCH_OK();
+  }
+  ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
   const dim3 g(cdiv(H.nvec, 256));
   switch (mode) {
     case RED_SET:

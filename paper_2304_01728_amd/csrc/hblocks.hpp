@@ -38,6 +38,7 @@ struct HermSet {
   DevBuf<float2> t32;        // tiles, FP32 (mixed precision)
   DevBuf<double2> p64;       // partials
   DevBuf<float2> p32;
+  Prof *prof = nullptr;      // kernel timing of the owning context
   int64_t bytes_fp64() const { return ntiles * 1024 * 16; }
   int64_t bytes_fp32() const { return ntiles * 1024 * 8; }
   // algorithmic bytes: packed Hermitian n(n+1)/2 entries per block

@@ -24,7 +24,7 @@ _DOUBLE_EXPORTS = {X_PROLONG_VAL}
 
 SYMBOLS = ["dpg_default_options", "dpg_setup", "dpg_assemble", "dpg_build_hierarchy",
            "dpg_load_rhs", "dpg_solve", "dpg_get_fields", "dpg_info", "dpg_export",
-           "dpg_last_error", "dpg_destroy"]
+           "dpg_profile", "dpg_kernel_stats", "dpg_last_error", "dpg_destroy"]
 
 
 class dpg_mesh(C.Structure):
@@ -52,6 +52,19 @@ class dpg_info_t(C.Structure):
                 ("level_nmacro", C.c_int64 * 16), ("resident_bytes", C.c_int64),
                 ("n_test", C.c_int32), ("n_field", C.c_int32), ("n_tr", C.c_int32),
                 ("setup_ms", C.c_double * 4)]
+
+
+class dpg_kstat(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("work", C.c_double)]
+
+
+KERNEL_CLASSES = ["gram", "bmat", "load", "potrf", "trsm", "gemm", "macro_asm", "patch_gather",
+                  "apply64", "apply32", "reduce", "condense", "expand", "transfer", "cg", "other"]
+# kernel symbols behind each class (for matching a rocprofv3 trace)
+KERNEL_SYMBOLS = {"gram": "k_gram", "bmat": "k_bmat", "load": "k_load", "potrf": "k_potrf",
+                  "trsm": "k_trsm", "gemm": "k_gemm", "macro_asm": "k_macro_assemble",
+                  "patch_gather": "k_patch_gather", "apply64": "k_units<double>",
+                  "apply32": "k_units<float>", "reduce": "k_reduce"}
 
 
 class DPGError(RuntimeError):
@@ -90,6 +103,10 @@ def lib():
         L.dpg_info.restype = C.c_int
         L.dpg_export.argtypes = [vp, C.c_int, C.c_int, vp, C.c_int64]
         L.dpg_export.restype = C.c_int64
+        L.dpg_profile.argtypes = [vp, C.c_int]
+        L.dpg_profile.restype = C.c_int
+        L.dpg_kernel_stats.argtypes = [vp, C.c_int, C.POINTER(dpg_kstat)]
+        L.dpg_kernel_stats.restype = C.c_int
         L.dpg_last_error.argtypes = [vp]
         L.dpg_last_error.restype = C.c_char_p
         L.dpg_destroy.argtypes = [vp]
@@ -235,6 +252,21 @@ def dpg_export(ctx, what, level=0):
     m = lib().dpg_export(ctx.h, what, level, out.ctypes.data, n)
     if m < 0:
         _check(ctx.h, int(m))
+    return out
+
+
+def dpg_profile(ctx, enable=True):
+    _check(ctx.h, lib().dpg_profile(ctx.h, 1 if enable else 0))
+
+
+def dpg_kernel_stats(ctx):
+    """{class name: (launches, total_ms, work)} for every class with launches."""
+    out = {}
+    for k, name in enumerate(KERNEL_CLASSES):
+        st = dpg_kstat()
+        _check(ctx.h, lib().dpg_kernel_stats(ctx.h, k, C.byref(st)))
+        if st.launches:
+            out[name] = (st.launches, st.total_ms, st.work)
     return out
 
 
