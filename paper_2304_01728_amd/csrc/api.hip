@@ -141,12 +141,12 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
     }
     {
       PROF(DPG_K_POTRF, cnt * f_potrf(nt));
-      potrf_batched(G.p, dpG.p, cnt, info.p, s);
+      potrf_batched(G.p, dpG.p, cnt, info.p, nt, s);
     }
     check_info(info, cnt, c, "element Gram matrix", e0);
     {
       PROF(DPG_K_TRSM, cnt * f_trsm(nt, mp));
-      trsm_batched(G.p, BL.p, dtG.p, cnt, mp, s);
+      trsm_batched(G.p, BL.p, dtG.p, cnt, nt, mp, false, s);
     }
     {
       PROF(DPG_K_GEMM, cnt * f_herk(mp, nt));
@@ -154,12 +154,12 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
     }
     {
       PROF(DPG_K_POTRF, cnt * f_potrf(nf));
-      potrf_batched(K.p, dpK.p, cnt, info.p, s);
+      potrf_batched(K.p, dpK.p, cnt, info.p, nf, s);
     }
     check_info(info, cnt, c, "element field block", e0);
     {
       PROF(DPG_K_TRSM, cnt * f_trsm(nf, mp - nf));
-      trsm_batched(K.p, K.p, dtK.p, cnt, mp - nf, s);
+      trsm_batched(K.p, K.p, dtK.p, cnt, nf, mp - nf, false, s);
     }
     {
       PROF(DPG_K_GEMM, cnt * f_herk(mp - nf, nf));
@@ -252,12 +252,12 @@ void build_macro_level(dpg_ctx *c, int l) {
     }
     {
       PROF(DPG_K_POTRF, cnt * f_potrf(nI));
-      potrf_batched(T.p, dpII.p, cnt, info.p, s);
+      potrf_batched(T.p, dpII.p, cnt, info.p, nI, s);
     }
     check_info(info, cnt, c, "interior block of coarse element", b0);
     {
       PROF(DPG_K_TRSM, cnt * f_trsm(nI, nBf));
-      trsm_batched(T.p, T.p, dtIB.p, cnt, nBf, s);
+      trsm_batched(T.p, T.p, dtIB.p, cnt, nI, nBf, false, s);
     }
     {
       PROF(DPG_K_GEMM, cnt * f_herk(nBf, nI));
@@ -269,7 +269,7 @@ void build_macro_level(dpg_ctx *c, int l) {
     }
     {
       PROF(DPG_K_TRSM, cnt * f_trsm(nI, nI));
-      trsm_batched(T.p, Linv.p, dtLi.p, cnt, nI, s);
+      trsm_batched(T.p, Linv.p, dtLi.p, cnt, nI, nI, true, s);
     }
     {
       PROF(DPG_K_GEMM, cnt * f_herk(nI, nI));
@@ -323,7 +323,7 @@ void build_patches(dpg_ctx *c, int l) {
   const int np = (int)f.mc.patch_ptr.size() - 1;
   std::vector<int32_t> nv(np);
   for (int v = 0; v < np; ++v) nv[v] = (int32_t)(f.mc.patch_ptr[v + 1] - f.mc.patch_ptr[v]);
-  const int64_t cap = 1500000000LL / 32;   // entries per workspace (S and X)
+  const int64_t cap = 6000000000LL / 16;   // entries per workspace (S and X): 6 GB each
   int64_t maxent = 0;
   for (int v = 0; v < np; ++v) maxent = std::max<int64_t>(maxent, (int64_t)nv[v] * nv[v]);
   const int64_t ws = std::max(cap, maxent);
@@ -377,17 +377,17 @@ void build_patches(dpg_ctx *c, int l) {
     double fp = 0, ft = 0, fg = 0;
     for (int i = 0; i < cnt; ++i) {
       fp += f_potrf(nn[i]);
-      ft += f_trsm(nn[i], nn[i]);
-      fg += f_herk(nn[i], nn[i]);
+      ft += f_trsm(nn[i], nn[i]) / 3.0;   // identity right-hand side: L^-1 only
+      fg += f_herk(nn[i], nn[i]) / 3.0;   // X^H X with X triangular
     }
     {
       PROF(DPG_K_PATCH_GATHER, 0);
-      launch_patch_gather(f.Mfull.p, f.nBf, f.mc.Nc, f.patch_ptr.p, f.patch_slot.p, v0, cnt,
+      launch_patch_gather(f.Mfull.p, f.nBf, f.mc.Nc, f.patch_ptr.p, f.patch_slot.p, v0, cnt, nmax,
                           doff.p, S.p, s);
     }
     {
       PROF(DPG_K_POTRF, fp);
-      potrf_batched(S.p, dpi.p, cnt, info.p, s);
+      potrf_batched(S.p, dpi.p, cnt, info.p, nmax, s);
     }
     check_info(info, cnt, c, "vertex patch", v0);
     {
@@ -396,11 +396,12 @@ void build_patches(dpg_ctx *c, int l) {
     }
     {
       PROF(DPG_K_TRSM, ft);
-      trsm_batched(S.p, X.p, dti.p, cnt, nmax, s);
+      trsm_batched(S.p, X.p, dti.p, cnt, nmax, nmax, true, s);
     }
     {
       PROF(DPG_K_GEMM, fg);
-      gemm_batched(OP_C, OP_N, mk(1, 0), X.p, X.p, mk(0, 0), S.p, dgi.p, cnt, nmax, nmax, s);
+      gemm_batched(OP_C, OP_N, mk(1, 0), X.p, X.p, mk(0, 0), S.p, dgi.p, cnt, nmax, nmax, s,
+                   GEMM_UPPER_LOWTRI);
     }
     const int64_t t0 = f.Sset.tile_off_h[v0];
     const int64_t t1 = (v0 + cnt < np) ? f.Sset.tile_off_h[v0 + cnt] : f.Sset.ntiles;
@@ -438,11 +439,12 @@ void build_coarsest(dpg_ctx *c) {
   dnn.upload(nn, &c->bud, s);
   DevBuf<int> info;
   info.alloc(1, &c->bud);
-  potrf_batched(F.p, dpi.p, 1, info.p, s);
+  potrf_batched(F.p, dpi.p, 1, info.p, n0, s);
   check_info(info, 1, c, "coarsest operator", 0);
   launch_identity(doff.p, dnn.p, 1, n0, Li.p, s);
-  trsm_batched(F.p, Li.p, dti.p, 1, n0, s);
-  gemm_batched(OP_C, OP_N, mk(1, 0), Li.p, Li.p, mk(0, 0), Ti.p, dgi.p, 1, n0, n0, s);
+  trsm_batched(F.p, Li.p, dti.p, 1, n0, n0, true, s);
+  gemm_batched(OP_C, OP_N, mk(1, 0), Li.p, Li.p, mk(0, 0), Ti.p, dgi.p, 1, n0, n0, s,
+               GEMM_UPPER_LOWTRI);
   std::vector<int32_t> ld{n0};
   DevBuf<int32_t> dld;
   dld.upload(ld, &c->bud, s);

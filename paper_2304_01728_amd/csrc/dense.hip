@@ -1,18 +1,25 @@
 // Batched dense complex-FP64 kernels: Cholesky, forward solve, GEMM.
 //
-// One workgroup of 256 threads (4 waves) works on one item (Cholesky), one
-// 64-column panel of one item (triangular solve) or one 64x64 output tile of
-// one item (GEMM).  The rank-k updates share one register-blocked tile
-// routine: the workgroup stages 64x16 slices of op(A) and 16x64 slices of
-// op(B) in LDS and every thread accumulates a 4x4 block of the tile.  On
-// MI355X the FP64 vector and matrix-core peaks are equal (78.6 TFLOP/s), so
-// FP64 FMAs on the vector units are the plain choice here.
+// The rank-k updates share one tile routine: a workgroup of 256 threads
+// stages 64x16 slices of op(A) and 16x64 slices of op(B) in LDS and its four
+// waves accumulate the 64x64 complex output tile on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64).  The FP64 matrix and vector peaks of MI355X are
+// equal (78.6 TFLOP/s); the matrix cores win because they reuse each operand
+// sixteen times inside the instruction, where vector FMAs would need one LDS
+// read per two complex multiply-adds.
+//
+// Factorisations run panel by panel (width 32), with one launch per step for
+// the panel itself (one workgroup per item, or per 64 rows) and one for the
+// trailing update (one workgroup per 64x64 tile per item).
+#include <cmath>
+
 #include "dense.hpp"
 
 namespace dpg {
 namespace {
 
 constexpr int TM = 64, TN = 64, TK = 16, NT = 256, NB = 32;
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 struct GemmSmem {
   double2 As[TM][TK + 1];
@@ -28,20 +35,31 @@ template <int OP> __device__ inline double2 ld_op(const double2 *X, int ldx, int
 }
 
 // C[r0:r0+64, c0:c0+64] (clipped to m x n) <- alpha op(A) op(B) + beta C with
-// inner dimension k.  lower_only leaves entries above the diagonal alone.
-// Must be called by all 256 threads of the workgroup.
+// inner indices k_begin..k-1.  lower_only leaves entries above the diagonal
+// alone.  Must be called by all 256 threads of the workgroup.
 template <int OPA, int OPB>
-__device__ void gemm_tile(int m, int n, int k, int r0, int c0, double2 alpha, const double2 *A,
-                          int lda, const double2 *B, int ldb, double2 beta, double2 *C, int ldc,
-                          bool lower_only, GemmSmem &sm) {
+__device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int r0, int c0, double2 alpha,
+                          const double2 *A, int lda, const double2 *B, int ldb, double2 beta,
+                          double2 *C, int ldc, bool lower_only, GemmSmem &sm) {
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  double2 acc[4][4];
+  // FP64 matrix cores: v_mfma_f64_16x16x4f64 computes D(16x16) += A(16x4) B(4x16)
+  // with A[i][k] in lane i + 16k, B[k][j] in lane j + 16k and D[i][j] in
+  // lane j + 16 (i % 4), element i / 4.  Wave w owns the 32x32 sub-tile at
+  // (32 (w / 2), 32 (w % 2)) as 2x2 blocks; a complex product takes four real
+  // MFMAs (re*re - im*im, re*im + im*re).
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = 32 * (wave >> 1), wc = 32 * (wave & 1);
+  const int li = lane & 15, lk = lane >> 4;
+  v4d acc_re[2][2], acc_im[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = mk(0.0, 0.0);
-  for (int k0 = 0; k0 < k; k0 += TK) {
+    for (int j = 0; j < 2; ++j) {
+      acc_re[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      acc_im[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+#pragma unroll 1
+  for (int k0 = k_begin; k0 < k; k0 += TK) {
     for (int e = tid; e < TM * TK; e += NT) {
       int rr, kk;
       if (OPA == OP_N) { rr = e % TM; kk = e / TM; } else { kk = e % TK; rr = e / TK; }
@@ -55,212 +73,283 @@ __device__ void gemm_tile(int m, int n, int k, int r0, int c0, double2 alpha, co
       sm.Bs[kk][cc] = (c < n && kg < k) ? ld_op<OPB>(B, ldb, kg, c) : mk(0.0, 0.0);
     }
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < TK; ++kk) {
-      double2 a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = sm.As[ty + 16 * i][kk];
+    for (int ks = 0; ks < TK; ks += 4) {
+      double2 a[2], b[2];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = sm.Bs[kk][tx + 16 * j];
+      for (int i = 0; i < 2; ++i) a[i] = sm.As[wr + 16 * i + li][ks + lk];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 2; ++j) b[j] = sm.Bs[ks + lk][wc + 16 * j + li];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = cfma(a[i], b[j], acc[i][j]);
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc_re[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[i].y, b[j].y, acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].y, acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].x, acc_im[i][j], 0, 0, 0);
+        }
     }
     __syncthreads();
   }
   const bool use_beta = beta.x != 0.0 || beta.y != 0.0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
-      if (r < m && c < n && (!lower_only || c <= r)) {
-        double2 *p = &C[r + (int64_t)c * ldc];
-        double2 v = cmul(alpha, acc[i][j]);
-        if (use_beta) v = cfma(beta, *p, v);
-        *p = v;
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r0 + wr + 16 * i + lk + 4 * e, c = c0 + wc + 16 * j + li;
+        if (r < m && c < n && (!lower_only || c <= r)) {
+          double2 *p = &C[r + (int64_t)c * ldc];
+          double2 v = cmul(alpha, mk(acc_re[i][j][e], acc_im[i][j][e]));
+          if (use_beta) v = cfma(beta, *p, v);
+          *p = v;
+        }
       }
-    }
 }
 
-__global__ __launch_bounds__(NT) void k_potrf(double2 *base, const PotrfItem *items, int *info) {
-  __shared__ GemmSmem sm;
+// ---- Cholesky -------------------------------------------------------------------
+
+// Factor the diagonal block [k0, k0+32) of every item in LDS.
+__global__ __launch_bounds__(NT) void k_potrf_diag(double2 *base, const PotrfItem *items,
+                                                   int *info, int k0) {
   __shared__ double2 D[NB][NB + 1];
   __shared__ int fail;
   const PotrfItem it = items[blockIdx.x];
-  double2 *A = base + it.a;
   const int n = it.n, lda = it.lda, tid = threadIdx.x;
+  if (k0 >= n || info[blockIdx.x] != 0) return;
+  double2 *A = base + it.a;
+  const int kb = min(NB, n - k0);
   if (tid == 0) fail = 0;
+  for (int e = tid; e < kb * kb; e += NT) {
+    const int i = e % kb, j = e / kb;
+    if (j <= i) D[i][j] = A[(k0 + i) + (int64_t)(k0 + j) * lda];
+  }
   __syncthreads();
-  for (int k0 = 0; k0 < n; k0 += NB) {
-    const int kb = min(NB, n - k0);
-    for (int e = tid; e < kb * kb; e += NT) {
-      const int i = e % kb, j = e / kb;
-      if (j <= i) D[i][j] = A[(k0 + i) + (int64_t)(k0 + j) * lda];
+  for (int j = 0; j < kb; ++j) {
+    if (tid == 0) {
+      double d = D[j][j].x;
+      if (!(d > 0.0)) {
+        if (!fail) fail = k0 + j + 1;
+        d = 1.0;
+      }
+      D[j][j] = mk(sqrt(d), 0.0);
     }
     __syncthreads();
-    // unblocked factorisation of the diagonal block in LDS
-    for (int j = 0; j < kb; ++j) {
-      if (tid == 0) {
-        double d = D[j][j].x;
-        if (!(d > 0.0)) {
-          if (!fail) fail = k0 + j + 1;
-          d = 1.0;
-        }
-        D[j][j] = mk(sqrt(d), 0.0);
-      }
-      __syncthreads();
-      const double inv = 1.0 / D[j][j].x;
-      for (int i = j + 1 + tid; i < kb; i += NT) D[i][j] = cscale(D[i][j], inv);
-      __syncthreads();
-      const int rem = kb - j - 1;
-      for (int e = tid; e < rem * rem; e += NT) {
-        const int i = j + 1 + e % rem, jj = j + 1 + e / rem;
-        if (jj <= i) D[i][jj] = csub(D[i][jj], cmul(D[i][j], cconj(D[jj][j])));
-      }
-      __syncthreads();
-    }
-    if (fail) {
-      if (tid == 0) info[blockIdx.x] = fail;
-      return;
-    }
-    for (int e = tid; e < kb * kb; e += NT) {
-      const int i = e % kb, j = e / kb;
-      if (j <= i) A[(k0 + i) + (int64_t)(k0 + j) * lda] = D[i][j];
-    }
-    // panel below: X = A_panel L_kk^-H, one row per thread
-    for (int r = k0 + kb + tid; r < n; r += NT) {
-      double2 x[NB];
-#pragma unroll
-      for (int t = 0; t < NB; ++t)
-        if (t < kb) x[t] = A[r + (int64_t)(k0 + t) * lda];
-#pragma unroll
-      for (int t = 0; t < NB; ++t) {
-        if (t < kb) {
-          double2 v = x[t];
-#pragma unroll
-          for (int u = 0; u < NB; ++u)
-            if (u < t) v = csub(v, cmul(x[u], cconj(D[t][u])));
-          x[t] = cscale(v, 1.0 / D[t][t].x);
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < NB; ++t)
-        if (t < kb) A[r + (int64_t)(k0 + t) * lda] = x[t];
-    }
+    const double inv = 1.0 / D[j][j].x;
+    for (int i = j + 1 + tid; i < kb; i += NT) D[i][j] = cscale(D[i][j], inv);
     __syncthreads();
-    const int nt = n - k0 - kb;
-    if (nt > 0) {
-      const double2 *P = A + (k0 + kb) + (int64_t)k0 * lda;
-      double2 *Ct = A + (k0 + kb) + (int64_t)(k0 + kb) * lda;
-      const int tiles = (nt + TM - 1) / TM;
-      for (int ti = 0; ti < tiles; ++ti)
-        for (int tj = 0; tj <= ti; ++tj)
-          gemm_tile<OP_N, OP_C>(nt, nt, kb, ti * TM, tj * TN, mk(-1.0, 0.0), P, lda, P, lda,
-                                mk(1.0, 0.0), Ct, lda, ti == tj, sm);
+    const int rem = kb - j - 1;
+    for (int e = tid; e < rem * rem; e += NT) {
+      const int i = j + 1 + e % rem, jj = j + 1 + e / rem;
+      if (jj <= i) D[i][jj] = csub(D[i][jj], cmul(D[i][j], cconj(D[jj][j])));
     }
     __syncthreads();
   }
-  if (tid == 0) info[blockIdx.x] = 0;
+  if (fail) {
+    if (tid == 0) info[blockIdx.x] = fail;
+    return;
+  }
+  for (int e = tid; e < kb * kb; e += NT) {
+    const int i = e % kb, j = e / kb;
+    if (j <= i) A[(k0 + i) + (int64_t)(k0 + j) * lda] = D[i][j];
+  }
 }
 
-__global__ __launch_bounds__(NT) void k_trsm(const double2 *lbase, double2 *bbase,
-                                             const TrsmItem *items) {
+// Panel below the diagonal block: X = A_panel L_kk^-H, one row per thread.
+__global__ __launch_bounds__(64) void k_potrf_panel(double2 *base, const PotrfItem *items,
+                                                    const int *info, int k0) {
+  __shared__ double2 D[NB][NB + 1];
+  const PotrfItem it = items[blockIdx.y];
+  const int n = it.n, lda = it.lda, tid = threadIdx.x;
+  if (k0 + NB >= n || info[blockIdx.y] != 0) return;
+  const int r0 = k0 + NB + blockIdx.x * 64;
+  if (r0 >= n) return;
+  double2 *A = base + it.a;
+  for (int e = tid; e < NB * NB; e += 64) {
+    const int i = e % NB, j = e / NB;
+    if (j <= i) D[i][j] = A[(k0 + i) + (int64_t)(k0 + j) * lda];
+  }
+  __syncthreads();
+  const int r = r0 + tid;
+  if (r >= n) return;
+  double2 x[NB];
+#pragma unroll
+  for (int t = 0; t < NB; ++t) x[t] = A[r + (int64_t)(k0 + t) * lda];
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    double2 v = x[t];
+#pragma unroll
+    for (int u = 0; u < t; ++u) v = csub(v, cmul(x[u], cconj(D[t][u])));
+    x[t] = cscale(v, 1.0 / D[t][t].x);
+  }
+#pragma unroll
+  for (int t = 0; t < NB; ++t) A[r + (int64_t)(k0 + t) * lda] = x[t];
+}
+
+__device__ inline void tri_decode(int idx, int &ti, int &tj) {
+  // idx = ti (ti + 1) / 2 + tj, 0 <= tj <= ti
+  int t = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+  while ((t + 1) * (t + 2) / 2 <= idx) ++t;
+  while (t * (t + 1) / 2 > idx) --t;
+  ti = t;
+  tj = idx - t * (t + 1) / 2;
+}
+
+// Trailing update A22 -= X X^H (lower tiles) after panel k0.
+__global__ __launch_bounds__(NT) void k_potrf_update(double2 *base, const PotrfItem *items,
+                                                     const int *info, int k0) {
   __shared__ GemmSmem sm;
+  const PotrfItem it = items[blockIdx.y];
+  const int n = it.n, lda = it.lda;
+  const int m = n - k0 - NB;
+  if (m <= 0 || info[blockIdx.y] != 0) return;
+  int ti, tj;
+  tri_decode(blockIdx.x, ti, tj);
+  if (ti * TM >= m) return;
+  double2 *A = base + it.a;
+  const double2 *P = A + (k0 + NB) + (int64_t)k0 * lda;
+  double2 *C = A + (k0 + NB) + (int64_t)(k0 + NB) * lda;
+  gemm_tile<OP_N, OP_C>(m, m, NB, 0, ti * TM, tj * TN, mk(-1.0, 0.0), P, lda, P, lda,
+                        mk(1.0, 0.0), C, lda, ti == tj, sm);
+}
+
+// ---- triangular solve -------------------------------------------------------------
+
+// Rows [k0, k0+32) of B: solve L_kk X = B_k, one column per thread.
+__global__ __launch_bounds__(64) void k_trsm_diag(const double2 *lbase, double2 *bbase,
+                                                  const TrsmItem *items, int k0, int tri) {
   __shared__ double2 D[NB][NB + 1];
   const TrsmItem it = items[blockIdx.y];
-  const int c0 = blockIdx.x * TN;
-  if (c0 >= it.ncols) return;
-  const int nc = min(TN, it.ncols - c0);
+  const int n = it.n, tid = threadIdx.x;
+  if (k0 >= n) return;
+  const int kb = min(NB, n - k0);
+  const int ncols = tri ? min(it.ncols, k0 + kb) : it.ncols;
+  const int c = blockIdx.x * 64 + tid;
+  if (blockIdx.x * 64 >= ncols) return;
   const double2 *L = lbase + it.l;
-  double2 *B = bbase + it.b + (int64_t)c0 * it.ldb;
-  const int n = it.n, ldl = it.ldl, ldb = it.ldb, tid = threadIdx.x;
-  for (int k0 = 0; k0 < n; k0 += NB) {
-    const int kb = min(NB, n - k0);
-    for (int e = tid; e < kb * kb; e += NT) {
-      const int i = e % kb, j = e / kb;
-      if (j <= i) D[i][j] = L[(k0 + i) + (int64_t)(k0 + j) * ldl];
-    }
-    __syncthreads();
-    if (tid < nc) {
-      double2 x[NB];
-#pragma unroll
-      for (int t = 0; t < NB; ++t)
-        if (t < kb) x[t] = B[(k0 + t) + (int64_t)tid * ldb];
-#pragma unroll
-      for (int t = 0; t < NB; ++t) {
-        if (t < kb) {
-          double2 v = x[t];
-#pragma unroll
-          for (int u = 0; u < NB; ++u)
-            if (u < t) v = csub(v, cmul(D[t][u], x[u]));
-          x[t] = cscale(v, 1.0 / D[t][t].x);
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < NB; ++t)
-        if (t < kb) B[(k0 + t) + (int64_t)tid * ldb] = x[t];
-    }
-    __syncthreads();
-    const int nr = n - k0 - kb;
-    if (nr > 0) {
-      const int tiles = (nr + TM - 1) / TM;
-      for (int ti = 0; ti < tiles; ++ti)
-        gemm_tile<OP_N, OP_N>(nr, nc, kb, ti * TM, 0, mk(-1.0, 0.0),
-                              L + (k0 + kb) + (int64_t)k0 * ldl, ldl, B + k0, ldb, mk(1.0, 0.0),
-                              B + k0 + kb, ldb, false, sm);
-    }
-    __syncthreads();
+  double2 *B = bbase + it.b;
+  for (int e = tid; e < kb * kb; e += 64) {
+    const int i = e % kb, j = e / kb;
+    if (j <= i) D[i][j] = L[(k0 + i) + (int64_t)(k0 + j) * it.ldl];
   }
+  __syncthreads();
+  if (c >= ncols) return;
+  double2 x[NB];
+#pragma unroll
+  for (int t = 0; t < NB; ++t)
+    if (t < kb) x[t] = B[(k0 + t) + (int64_t)c * it.ldb];
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    if (t < kb) {
+      double2 v = x[t];
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+        if (u < t) v = csub(v, cmul(D[t][u], x[u]));
+      x[t] = cscale(v, 1.0 / D[t][t].x);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NB; ++t)
+    if (t < kb) B[(k0 + t) + (int64_t)c * it.ldb] = x[t];
 }
+
+// B[k0+32:, cols] -= L[k0+32:, k0:k0+32] X_k, one 64x64 tile per workgroup.
+__global__ __launch_bounds__(NT) void k_trsm_update(const double2 *lbase, double2 *bbase,
+                                                    const TrsmItem *items, int k0, int tri,
+                                                    int tiles_c) {
+  __shared__ GemmSmem sm;
+  const TrsmItem it = items[blockIdx.y];
+  const int n = it.n;
+  const int m = n - k0 - NB;
+  if (m <= 0) return;
+  const int ncols = tri ? min(it.ncols, k0 + NB) : it.ncols;
+  const int ti = blockIdx.x / tiles_c, tj = blockIdx.x % tiles_c;
+  if (ti * TM >= m || tj * TN >= ncols) return;
+  const double2 *L = lbase + it.l;
+  double2 *B = bbase + it.b;
+  gemm_tile<OP_N, OP_N>(m, ncols, NB, 0, ti * TM, tj * TN, mk(-1.0, 0.0),
+                        L + (k0 + NB) + (int64_t)k0 * it.ldl, it.ldl, B + k0, it.ldb,
+                        mk(1.0, 0.0), B + k0 + NB, it.ldb, false, sm);
+}
+
+// ---- GEMM ----------------------------------------------------------------------------
 
 template <int OPA, int OPB>
 __global__ __launch_bounds__(NT) void k_gemm(double2 alpha, const double2 *abase,
                                              const double2 *bbase, double2 beta, double2 *cbase,
-                                             const GemmItem *items, int tiles_n) {
+                                             const GemmItem *items, int tiles_n, int mode) {
   __shared__ GemmSmem sm;
   const GemmItem it = items[blockIdx.y];
-  const int r0 = (blockIdx.x / tiles_n) * TM, c0 = (blockIdx.x % tiles_n) * TN;
+  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const int r0 = tm * TM, c0 = tn * TN;
   if (r0 >= it.m || c0 >= it.n) return;
-  gemm_tile<OPA, OPB>(it.m, it.n, it.k, r0, c0, alpha, abase + it.a, it.lda, bbase + it.b,
+  int kb = 0;
+  if (mode == GEMM_UPPER_LOWTRI) {
+    if (tm > tn) return;
+    kb = c0;   // X lower triangular: rows below max(r0, c0) = c0 only
+  }
+  gemm_tile<OPA, OPB>(it.m, it.n, it.k, kb, r0, c0, alpha, abase + it.a, it.lda, bbase + it.b,
                       it.ldb, beta, cbase + it.c, it.ldc, false, sm);
 }
 
 template <int OPA>
 void gemm_dispatch_b(int opb, dim3 g, hipStream_t s, double2 alpha, const double2 *a,
-                     const double2 *b, double2 beta, double2 *c, const GemmItem *it, int tn) {
-  if (opb == OP_N) hipLaunchKernelGGL((k_gemm<OPA, OP_N>), g, dim3(NT), 0, s, alpha, a, b, beta, c, it, tn);
-  else if (opb == OP_T) hipLaunchKernelGGL((k_gemm<OPA, OP_T>), g, dim3(NT), 0, s, alpha, a, b, beta, c, it, tn);
-  else hipLaunchKernelGGL((k_gemm<OPA, OP_C>), g, dim3(NT), 0, s, alpha, a, b, beta, c, it, tn);
+                     const double2 *b, double2 beta, double2 *c, const GemmItem *it, int tn,
+                     int mode) {
+  if (opb == OP_N) hipLaunchKernelGGL((k_gemm<OPA, OP_N>), g, dim3(NT), 0, s, alpha, a, b, beta, c, it, tn, mode);
+  else if (opb == OP_T) hipLaunchKernelGGL((k_gemm<OPA, OP_T>), g, dim3(NT), 0, s, alpha, a, b, beta, c, it, tn, mode);
+  else hipLaunchKernelGGL((k_gemm<OPA, OP_C>), g, dim3(NT), 0, s, alpha, a, b, beta, c, it, tn, mode);
 }
 
 }  // namespace
 
-void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *info_dev,
+void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *info_dev, int nmax,
                    hipStream_t s) {
-  if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_potrf, dim3(nitems), dim3(NT), 0, s, base, items_dev, info_dev);
+  if (nitems <= 0 || nmax <= 0) return;
+  HIP_OK(hipMemsetAsync(info_dev, 0, nitems * sizeof(int), s));
+  for (int k0 = 0; k0 < nmax; k0 += NB) {
+    hipLaunchKernelGGL(k_potrf_diag, dim3(nitems), dim3(NT), 0, s, base, items_dev, info_dev, k0);
+    const int rows = nmax - k0 - NB;
+    if (rows > 0) {
+      hipLaunchKernelGGL(k_potrf_panel, dim3(cdiv(rows, 64), nitems), dim3(64), 0, s, base,
+                         items_dev, info_dev, k0);
+      const int T = (int)cdiv(rows, TM);
+      hipLaunchKernelGGL(k_potrf_update, dim3(T * (T + 1) / 2, nitems), dim3(NT), 0, s, base,
+                         items_dev, info_dev, k0);
+    }
+  }
   LAUNCH_OK();
 }
 
 void trsm_batched(const double2 *lbase, double2 *bbase, const TrsmItem *items_dev, int nitems,
-                  int max_cols, hipStream_t s) {
-  if (nitems <= 0 || max_cols <= 0) return;
-  hipLaunchKernelGGL(k_trsm, dim3(cdiv(max_cols, TN), nitems), dim3(NT), 0, s, lbase, bbase,
-                     items_dev);
+                  int max_n, int max_cols, bool identity_rhs, hipStream_t s) {
+  if (nitems <= 0 || max_cols <= 0 || max_n <= 0) return;
+  const int tri = identity_rhs ? 1 : 0;
+  for (int k0 = 0; k0 < max_n; k0 += NB) {
+    const int cols = tri ? std::min(max_cols, k0 + NB) : max_cols;
+    hipLaunchKernelGGL(k_trsm_diag, dim3(cdiv(cols, 64), nitems), dim3(64), 0, s, lbase, bbase,
+                       items_dev, k0, tri);
+    const int rows = max_n - k0 - NB;
+    if (rows > 0) {
+      const int tc = (int)cdiv(cols, TN);
+      hipLaunchKernelGGL(k_trsm_update, dim3(cdiv(rows, TM) * tc, nitems), dim3(NT), 0, s, lbase,
+                         bbase, items_dev, k0, tri, tc);
+    }
+  }
   LAUNCH_OK();
 }
 
 void gemm_batched(int opa, int opb, double2 alpha, const double2 *abase, const double2 *bbase,
                   double2 beta, double2 *cbase, const GemmItem *items_dev, int nitems, int max_m,
-                  int max_n, hipStream_t s) {
+                  int max_n, hipStream_t s, int mode) {
   if (nitems <= 0 || max_m <= 0 || max_n <= 0) return;
   const int tm = (int)cdiv(max_m, TM), tn = (int)cdiv(max_n, TN);
   dim3 g(tm * tn, nitems);
-  if (opa == OP_N) gemm_dispatch_b<OP_N>(opb, g, s, alpha, abase, bbase, beta, cbase, items_dev, tn);
-  else if (opa == OP_T) gemm_dispatch_b<OP_T>(opb, g, s, alpha, abase, bbase, beta, cbase, items_dev, tn);
-  else gemm_dispatch_b<OP_C>(opb, g, s, alpha, abase, bbase, beta, cbase, items_dev, tn);
+  if (opa == OP_N) gemm_dispatch_b<OP_N>(opb, g, s, alpha, abase, bbase, beta, cbase, items_dev, tn, mode);
+  else if (opa == OP_T) gemm_dispatch_b<OP_T>(opb, g, s, alpha, abase, bbase, beta, cbase, items_dev, tn, mode);
+  else gemm_dispatch_b<OP_C>(opb, g, s, alpha, abase, bbase, beta, cbase, items_dev, tn, mode);
   LAUNCH_OK();
 }
 

@@ -3,6 +3,11 @@
 // normal / transposed / conjugate-transposed operands.  Every item of a batch
 // has its own sizes and leading dimensions; matrices are column-major and
 // addressed as base pointer + per-item element offset.
+//
+// The factorisations proceed by 32-wide panels, one launch per panel step:
+// a small kernel factors / solves the panel of every item, then the rank-32
+// update of the rest is spread over (64x64 tiles x items), so that large
+// blocks use the whole GPU instead of one compute unit each.
 #pragma once
 #include "common.hpp"
 
@@ -13,21 +18,25 @@ struct TrsmItem { int64_t l, b; int n, ncols, ldl, ldb; };
 struct GemmItem { int64_t a, b, c; int m, n, k, lda, ldb, ldc; };
 
 enum { OP_N = 0, OP_T = 1, OP_C = 2 };
+enum { GEMM_FULL = 0, GEMM_UPPER_LOWTRI = 1 };
 
 // In-place lower Cholesky A = L L^H of every item (upper triangle untouched).
-// info[item] = 0 on success, j+1 if pivot j was not positive.
-void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *info_dev,
+// info[item] = 0 on success, j+1 if pivot j was not positive.  nmax = largest n.
+void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *info_dev, int nmax,
                    hipStream_t s);
 
-// B <- L^-1 B for every item (L lower, from a Cholesky factor).  max_cols is
-// the largest ncols of the batch.
+// B <- L^-1 B for every item (L lower, from a Cholesky factor).  With
+// identity_rhs, B must hold the identity and only the lower-triangular part
+// of the result is formed (the rest stays zero).
 void trsm_batched(const double2 *lbase, double2 *bbase, const TrsmItem *items_dev, int nitems,
-                  int max_cols, hipStream_t s);
+                  int max_n, int max_cols, bool identity_rhs, hipStream_t s);
 
-// C <- alpha op(A) op(B) + beta C for every item.  max_m / max_n bound the
-// tile grid.
+// C <- alpha op(A) op(B) + beta C for every item.  mode GEMM_UPPER_LOWTRI
+// computes only the upper 64x64 tiles (tile row <= tile column) of a product
+// whose operands are lower triangular in the inner index (X^H X with X lower
+// triangular), starting the inner sum at the tile's diagonal.
 void gemm_batched(int opa, int opb, double2 alpha, const double2 *abase, const double2 *bbase,
                   double2 beta, double2 *cbase, const GemmItem *items_dev, int nitems, int max_m,
-                  int max_n, hipStream_t s);
+                  int max_n, hipStream_t s, int mode = GEMM_FULL);
 
 }  // namespace dpg

@@ -62,7 +62,8 @@ __global__ __launch_bounds__(256) void k_patch_gather(const double2 *__restrict_
   const int32_t *sl = pslot + p0 * 8;
   double2 *Sv = S + dst_off[blockIdx.x];
   const int64_t nb2 = (int64_t)nBf * nBf;
-  for (int64_t k = threadIdx.x; k < (int64_t)n * n; k += 256) {
+  const int64_t kend = min((int64_t)n * n, (int64_t)(blockIdx.y + 1) * 2048);
+  for (int64_t k = (int64_t)blockIdx.y * 2048 + threadIdx.x; k < kend; k += 256) {
     const int i = (int)(k % n), j = (int)(k / n);
     double2 acc = mk(0.0, 0.0);
     for (int c = 0; c < 8; ++c) {
@@ -382,11 +383,11 @@ void launch_copy_sub(const double2 *src, int64_t src_stride, int lds, int r0, in
 }
 
 void launch_patch_gather(const double2 *Mfull, int nBf, int Nc, const int64_t *patch_ptr,
-                         const int32_t *patch_slot, int v0, int count, const int64_t *dst_off,
-                         double2 *S, hipStream_t s) {
+                         const int32_t *patch_slot, int v0, int count, int nmax,
+                         const int64_t *dst_off, double2 *S, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_patch_gather, dim3(count), dim3(256), 0, s, Mfull, nBf, Nc, patch_ptr,
-                     patch_slot, v0, dst_off, S);
+  hipLaunchKernelGGL(k_patch_gather, dim3(count, cdiv((int64_t)nmax * nmax, 2048)), dim3(256), 0, s,
+                     Mfull, nBf, Nc, patch_ptr, patch_slot, v0, dst_off, S);
   LAUNCH_OK();
 }
 

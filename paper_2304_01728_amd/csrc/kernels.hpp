@@ -21,8 +21,8 @@ void launch_copy_sub(const double2 *src, int64_t src_stride, int lds, int r0, in
 // Patch block S_v (n_v x n_v) gathered from the macro blocks of the <= 8 coarse
 // cells around vertex v: S[i,j] = sum_c M_c[slot_c(i), slot_c(j)].
 void launch_patch_gather(const double2 *Mfull, int nBf, int Nc, const int64_t *patch_ptr,
-                         const int32_t *patch_slot, int v0, int count, const int64_t *dst_off,
-                         double2 *S, hipStream_t s);
+                         const int32_t *patch_slot, int v0, int count, int nmax,
+                         const int64_t *dst_off, double2 *S, hipStream_t s);
 
 // X[b] = identity of size n[b] (column-major, leading dimension n[b]).
 void launch_identity(const int64_t *off, const int32_t *n, int count, int nmax, double2 *X,
