@@ -21,69 +21,122 @@ template <typename C> __device__ inline C sel4(C v0, C v1, C v2, C v3, int i) {
   return r;
 }
 
-// One wave per (block, tile column J).
+template <typename C> __device__ __forceinline__ void load_tile(const C *__restrict__ tp, C t[16]) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) t[k] = tp[k * 64];
+}
+
+// The four entries of tile row I of a local vector that lane ra needs.
+template <typename C>
+__device__ __forceinline__ void load_x(const C *__restrict__ xl, int I, int ra, C xI[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) xI[i] = xl[32 * I + 4 * ra + i];
+}
+
+// Row sums of one tile into its partial slot; column sums accumulated.
+template <typename C>
+__device__ __forceinline__ void do_tile(const C t[16], const C xJ[4], const C xI[4], int I,
+                                        int J, int ra, int cb, C cacc[4], C *__restrict__ slot) {
+  C rs[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    C a;
+    a.x = 0;
+    a.y = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a = cfma(t[4 * i + j], xJ[j], a);
+    rs[i] = a;
+  }
+  if (I < J) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) cacc[j] = cfmaconj(t[4 * i + j], xI[i], cacc[j]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    rs[i] = cadd(rs[i], shfl_xor_c(rs[i], 1));
+    rs[i] = cadd(rs[i], shfl_xor_c(rs[i], 2));
+    rs[i] = cadd(rs[i], shfl_xor_c(rs[i], 4));
+  }
+  if (cb < 4) slot[4 * ra + cb] = sel4(rs[0], rs[1], rs[2], rs[3], cb);
+}
+
+// Tile columns are cut into segments of at most kSeg tiles, one wave each.
+constexpr int kSeg = 8;
+
+// Column-sum slots of a block: column J has ceil((J+1)/kSeg) segment slots;
+// colbase(J) = 32 sum_{j=1..J} ceil(j/kSeg).
+__host__ __device__ __forceinline__ int64_t colbase(int J) {
+  const int64_t q = J / kSeg, r = J % kSeg;
+  return 32 * (kSeg * q * (q + 1) / 2 + r * (q + 1));
+}
+
+// offset of the row-sum slot (I, J), I <= J, inside the row partials of a block
+__device__ __forceinline__ int64_t row_slot(int nt, int I, int J) {
+  return ((int64_t)I * nt - (int64_t)I * (I - 1) / 2 + (J - I)) * 32;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_x(int64_t nloc, const int32_t *__restrict__ gidx,
+                                                  const cplx_t<T> *__restrict__ x,
+                                                  cplx_t<T> *__restrict__ xl) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nloc) return;
+  const int32_t g = gidx[i];
+  cplx_t<T> v;
+  v.x = 0;
+  v.y = 0;
+  if (g >= 0) v = x[g];
+  xl[i] = v;
+}
+
+// One wave per (block, tile column J, segment of <= kSeg tile rows), two
+// tiles (and their x entries) in flight.
 template <typename T>
 __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ tiles,
-                                               const int2 *__restrict__ units, int64_t nunits,
+                                               const int4 *__restrict__ units, int64_t nunits,
                                                const int32_t *__restrict__ bn,
                                                const int64_t *__restrict__ tile_off,
-                                               const int64_t *__restrict__ part_off,
-                                               const int64_t *__restrict__ idx_off,
-                                               const int32_t *__restrict__ idx,
-                                               const cplx_t<T> *__restrict__ x,
+                                               const int64_t *__restrict__ cp_off,
+                                               const int64_t *__restrict__ rp_off,
+                                               const int64_t *__restrict__ loc_off,
+                                               const cplx_t<T> *__restrict__ xloc,
                                                cplx_t<T> *__restrict__ part) {
   using C = cplx_t<T>;
   const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wv >= nunits) return;
   const int lane = threadIdx.x & 63, ra = lane >> 3, cb = lane & 7;
-  const int2 u = units[wv];
-  const int b = u.x, J = u.y;
-  const int n = bn[b], nt = (n + 31) >> 5;
-  const int32_t *ix = idx + idx_off[b];
-  C zero;
-  zero.x = 0;
-  zero.y = 0;
+  const int4 u = units[wv];
+  const int b = u.x, J = u.y, I0 = u.z, seg = u.w;
+  const int I1 = min(I0 + kSeg, J + 1);
+  const int nt = (bn[b] + 31) >> 5;
+  const C *xl = xloc + loc_off[b];
   C xJ[4], cacc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int c = 32 * J + 4 * cb + j;
-    xJ[j] = c < n ? x[ix[c]] : zero;
-    cacc[j] = zero;
+    xJ[j] = xl[32 * J + 4 * cb + j];
+    cacc[j].x = 0;
+    cacc[j].y = 0;
   }
   const C *tp = tiles + (tile_off[b] + (int64_t)J * (J + 1) / 2) * 1024 + lane;
-  C *pb = part + part_off[b];
-  C *rp = pb + (int64_t)nt * 32 + (int64_t)J * (J + 1) / 2 * 32;
-  for (int I = 0; I <= J; ++I, tp += 1024) {
-    C t[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) t[k] = tp[k * 64];
-    C xI[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = 32 * I + 4 * ra + i;
-      xI[i] = r < n ? x[ix[r]] : zero;
+  C *rp = part + rp_off[b];
+  C t0[16], t1[16], x0[4], x1[4];
+  load_tile(tp + (int64_t)I0 * 1024, t0);
+  load_x(xl, I0, ra, x0);
+  for (int I = I0; I < I1; I += 2) {
+    if (I + 1 < I1) {
+      load_tile(tp + (int64_t)(I + 1) * 1024, t1);
+      load_x(xl, I + 1, ra, x1);
     }
-    C rs[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      C a = zero;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) a = cfma(t[4 * i + j], xJ[j], a);
-      rs[i] = a;
+    do_tile(t0, xJ, x0, I, J, ra, cb, cacc, rp + row_slot(nt, I, J));
+    if (I + 1 < I1) {
+      if (I + 2 < I1) {
+        load_tile(tp + (int64_t)(I + 2) * 1024, t0);
+        load_x(xl, I + 2, ra, x0);
+      }
+      do_tile(t1, xJ, x1, I + 1, J, ra, cb, cacc, rp + row_slot(nt, I + 1, J));
     }
-    if (I < J) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) cacc[j] = cfmaconj(t[4 * i + j], xI[i], cacc[j]);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      rs[i] = cadd(rs[i], shfl_xor_c(rs[i], 1));
-      rs[i] = cadd(rs[i], shfl_xor_c(rs[i], 2));
-      rs[i] = cadd(rs[i], shfl_xor_c(rs[i], 4));
-    }
-    if (cb < 4) rp[I * 32 + 4 * ra + cb] = sel4(rs[0], rs[1], rs[2], rs[3], cb);
   }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -91,31 +144,51 @@ __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ til
     cacc[j] = cadd(cacc[j], shfl_xor_c(cacc[j], 16));
     cacc[j] = cadd(cacc[j], shfl_xor_c(cacc[j], 32));
   }
-  if (ra < 4) pb[J * 32 + 4 * cb + ra] = sel4(cacc[0], cacc[1], cacc[2], cacc[3], ra);
+  if (ra < 4)
+    part[cp_off[b] + colbase(J) + seg * 32 + 4 * cb + ra] =
+        sel4(cacc[0], cacc[1], cacc[2], cacc[3], ra);
+}
+
+// Half a wave per (block, tile row I): y_loc rows of I = column sums of the
+// segments of tile column I + row sums of tiles (I, J >= I).
+template <typename T>
+__global__ __launch_bounds__(256) void k_rows(const int2 *__restrict__ rows, int64_t nrows,
+                                              const int32_t *__restrict__ bn,
+                                              const int64_t *__restrict__ cp_off,
+                                              const int64_t *__restrict__ rp_off,
+                                              const int64_t *__restrict__ loc_off,
+                                              const cplx_t<T> *__restrict__ part,
+                                              cplx_t<T> *__restrict__ yl) {
+  using C = cplx_t<T>;
+  const int64_t hw = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 5;
+  if (hw >= nrows) return;
+  const int r = threadIdx.x & 31;
+  const int2 bi = rows[hw];
+  const int nt = (bn[bi.x] + 31) >> 5, I = bi.y;
+  C acc;
+  acc.x = 0;
+  acc.y = 0;
+  const C *cp = part + cp_off[bi.x] + colbase(I) + r;
+  const int nseg = (I + kSeg) / kSeg;
+  for (int q = 0; q < nseg; ++q) acc = cadd(acc, cp[q * 32]);
+  const C *rp = part + rp_off[bi.x] + row_slot(nt, I, I) + r;
+  for (int q = 0; q < nt - I; ++q) acc = cadd(acc, rp[q * 32]);
+  yl[loc_off[bi.x] + 32 * I + r] = acc;
 }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_reduce(int64_t nvec, const int32_t *__restrict__ red_ptr,
-                                                const int2 *__restrict__ red_ent,
-                                                const int32_t *__restrict__ bn,
-                                                const int64_t *__restrict__ part_off,
-                                                const cplx_t<T> *__restrict__ part,
-                                                const cplx_t<T> *__restrict__ r,
-                                                cplx_t<T> *__restrict__ y, T theta) {
+__global__ __launch_bounds__(256) void k_scatter(int64_t nvec, const int32_t *__restrict__ red_ptr,
+                                                 const int32_t *__restrict__ red_ent,
+                                                 const cplx_t<T> *__restrict__ yl,
+                                                 const cplx_t<T> *__restrict__ r,
+                                                 cplx_t<T> *__restrict__ y, T theta) {
   using C = cplx_t<T>;
   const int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (d >= nvec) return;
   C acc;
   acc.x = 0;
   acc.y = 0;
-  for (int32_t k = red_ptr[d]; k < red_ptr[d + 1]; ++k) {
-    const int2 be = red_ent[k];
-    const int nt = (bn[be.x] + 31) >> 5, I = be.y >> 5, rr = be.y & 31;
-    const C *pb = part + part_off[be.x];
-    acc = cadd(acc, pb[I * 32 + rr]);
-    const C *rp = pb + (int64_t)nt * 32 + rr;
-    for (int J = I; J < nt; ++J) acc = cadd(acc, rp[((int64_t)J * (J + 1) / 2 + I) * 32]);
-  }
+  for (int32_t k = red_ptr[d]; k < red_ptr[d + 1]; ++k) acc = cadd(acc, yl[red_ent[k]]);
   if (MODE == RED_SET) y[d] = acc;
   else if (MODE == RED_RESID) y[d] = csub(r[d], acc);
   else if (MODE == RED_AXPY) y[d] = cadd(y[d], cscale(acc, theta));
@@ -150,67 +223,81 @@ __global__ __launch_bounds__(256) void k_pack(const int4 *__restrict__ tdesc, in
 
 }  // namespace
 
-int64_t HermSet::packed_entries() const {
-  int64_t s = 0;
-  for (int32_t n : n_h) s += (int64_t)n * (n + 1) / 2;
-  return s;
-}
-
 void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t> &idx_concat,
                     int64_t nvec_, bool fp64, bool fp32, Budget *bud, hipStream_t s) {
   nblk = (int)sizes.size();
   nvec = nvec_;
   n_h = sizes;
-  std::vector<int64_t> toff(nblk), poff(nblk), ioff(nblk);
-  int64_t t = 0, p = 0, ii = 0;
-  std::vector<int2> un;
+  std::vector<int64_t> toff(nblk), cpo(nblk), rpo(nblk), loff(nblk);
+  int64_t t = 0, p = 0, lo = 0, ii = 0;
+  packed = 0;
+  std::vector<int4> un;
+  std::vector<int2> rw;
   std::vector<int4> td;
+  std::vector<int32_t> gi;
   for (int b = 0; b < nblk; ++b) {
-    const int nt = (sizes[b] + 31) / 32;
+    const int n = sizes[b], nt = (n + 31) / 32;
     toff[b] = t;
-    poff[b] = p;
-    ioff[b] = ii;
+    cpo[b] = p;
+    p += colbase(nt);
+    rpo[b] = p;
+    p += (int64_t)nt * (nt + 1) / 2 * 32;
+    loff[b] = lo;
     t += (int64_t)nt * (nt + 1) / 2;
-    p += (int64_t)nt * 32 + (int64_t)nt * (nt + 1) / 2 * 32;
-    ii += sizes[b];
+    lo += (int64_t)nt * 32;
+    packed += (int64_t)n * (n + 1) / 2;
+    for (int i = 0; i < 32 * nt; ++i) gi.push_back(i < n ? idx_concat[ii + i] : -1);
+    ii += n;
     for (int J = 0; J < nt; ++J) {
-      un.push_back(make_int2(b, J));
+      for (int seg = 0; seg * kSeg <= J; ++seg) un.push_back(make_int4(b, J, seg * kSeg, seg));
+      rw.push_back(make_int2(b, J));
       for (int I = 0; I <= J; ++I) td.push_back(make_int4(b, I, J, 0));
     }
   }
   if (ii != (int64_t)idx_concat.size()) throw DpgError(-1, "HermSet: index list size mismatch");
-  std::stable_sort(un.begin(), un.end(), [](int2 a, int2 b) { return a.y > b.y; });
+  // longest segments first
+  std::stable_sort(un.begin(), un.end(), [](int4 a, int4 c) {
+    return std::min(kSeg, a.y + 1 - a.z) > std::min(kSeg, c.y + 1 - c.z);
+  });
   ntiles = t;
   npart = p;
+  nloc = lo;
   nunits = (int64_t)un.size();
+  nrows = (int64_t)rw.size();
   tile_off_h = toff;
-  // reduction lists: for every vector entry, the (block, row) pairs holding it
+  // reduction lists: for every vector entry, the local rows holding it
   std::vector<int32_t> cnt(nvec + 1, 0);
-  for (int32_t v : idx_concat) {
-    if (v < 0 || v >= nvec) throw DpgError(-1, "HermSet: index out of range");
-    cnt[v + 1]++;
+  for (int32_t v : gi) {
+    if (v >= nvec) throw DpgError(-1, "HermSet: index out of range");
+    if (v >= 0) cnt[v + 1]++;
   }
   for (int64_t d = 0; d < nvec; ++d) cnt[d + 1] += cnt[d];
-  std::vector<int2> ent(idx_concat.size());
+  std::vector<int32_t> ent(cnt[nvec]);
   std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
-  for (int b = 0; b < nblk; ++b)
-    for (int i = 0; i < sizes[b]; ++i) ent[fill[idx_concat[ioff[b] + i]]++] = make_int2(b, i);
+  for (int64_t k = 0; k < (int64_t)gi.size(); ++k)
+    if (gi[k] >= 0) ent[fill[gi[k]]++] = (int32_t)k;
   bn.upload(sizes, bud, s);
   tile_off.upload(toff, bud, s);
-  part_off.upload(poff, bud, s);
-  idx_off.upload(ioff, bud, s);
-  idx.upload(idx_concat, bud, s);
+  cp_off.upload(cpo, bud, s);
+  rp_off.upload(rpo, bud, s);
+  loc_off.upload(loff, bud, s);
+  gidx.upload(gi, bud, s);
   units.upload(un, bud, s);
+  rows.upload(rw, bud, s);
   tdesc.upload(td, bud, s);
   red_ptr.upload(cnt, bud, s);
   red_ent.upload(ent, bud, s);
   if (fp64) {
     t64.alloc(ntiles * 1024, bud);
     p64.alloc(npart, bud);
+    xl64.alloc(nloc, bud);
+    yl64.alloc(nloc, bud);
   }
   if (fp32) {
     t32.alloc(ntiles * 1024, bud);
     p32.alloc(npart, bud);
+    xl32.alloc(nloc, bud);
+    yl32.alloc(nloc, bud);
   }
   HIP_OK(hipStreamSynchronize(s));
 }
@@ -229,36 +316,50 @@ template <typename T>
 void herm_apply(HermSet &H, const cplx_t<T> *x, cplx_t<T> *y, const cplx_t<T> *r, int mode,
                 T theta, hipStream_t s) {
   const cplx_t<T> *tiles;
-  cplx_t<T> *part;
+  cplx_t<T> *part, *xl, *yl;
   if constexpr (sizeof(T) == 8) {
     tiles = H.t64.p;
     part = H.p64.p;
+    xl = H.xl64.p;
+    yl = H.yl64.p;
   } else {
     tiles = H.t32.p;
     part = H.p32.p;
+    xl = H.xl32.p;
+    yl = H.yl32.p;
   }
   if (!tiles || !part) throw DpgError(-6, "block set has no tiles of this precision");
+  {
+    ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
+    hipLaunchKernelGGL((k_gather_x<T>), dim3(cdiv(H.nloc, 256)), dim3(256), 0, s, H.nloc,
+                       H.gidx.p, x, xl);
+    LAUNCH_OK();
+  }
   {
     ProfScope ps(H.prof, sizeof(T) == 8 ? DPG_K_APPLY64 : DPG_K_APPLY32,
                  (double)H.packed_entries() * sizeof(cplx_t<T>), s);
     hipLaunchKernelGGL((k_units<T>), dim3(cdiv(H.nunits, 4)), dim3(256), 0, s, tiles, H.units.p,
-                       H.nunits, H.bn.p, H.tile_off.p, H.part_off.p, H.idx_off.p, H.idx.p, x, part);
+                       H.nunits, H.bn.p, H.tile_off.p, H.cp_off.p, H.rp_off.p, H.loc_off.p, xl,
+                       part);
     LAUNCH_OK();
   }
   ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
+  hipLaunchKernelGGL((k_rows<T>), dim3(cdiv(H.nrows, 8)), dim3(256), 0, s, H.rows.p, H.nrows,
+                     H.bn.p, H.cp_off.p, H.rp_off.p, H.loc_off.p, part, yl);
+  LAUNCH_OK();
   const dim3 g(cdiv(H.nvec, 256));
   switch (mode) {
     case RED_SET:
-      hipLaunchKernelGGL((k_reduce<T, RED_SET>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, H.bn.p, H.part_off.p, part, r, y, theta);
+      hipLaunchKernelGGL((k_scatter<T, RED_SET>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
       break;
     case RED_RESID:
-      hipLaunchKernelGGL((k_reduce<T, RED_RESID>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, H.bn.p, H.part_off.p, part, r, y, theta);
+      hipLaunchKernelGGL((k_scatter<T, RED_RESID>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
       break;
     case RED_AXPY:
-      hipLaunchKernelGGL((k_reduce<T, RED_AXPY>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, H.bn.p, H.part_off.p, part, r, y, theta);
+      hipLaunchKernelGGL((k_scatter<T, RED_AXPY>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
       break;
     default:
-      hipLaunchKernelGGL((k_reduce<T, RED_SET_SCALED>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, H.bn.p, H.part_off.p, part, r, y, theta);
+      hipLaunchKernelGGL((k_scatter<T, RED_SET_SCALED>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
   }
   LAUNCH_OK();
 }

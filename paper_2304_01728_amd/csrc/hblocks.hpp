@@ -9,11 +9,16 @@
 // lane = 8 (r/4) + c/4 and k = 4 (r%4) + c%4, so that one wave reads a tile
 // with 16 fully coalesced 64-lane loads and every lane holds a 4x4 sub-block.
 //
-// Apply (two kernels, deterministic): one wave per (block, tile column J)
-// streams the tiles of that column once, producing A_IJ x_J (row sums, per
-// tile) and sum_{I<J} A_IJ^H x_I (column sums, per column) into a partial
-// buffer; then one thread per vector entry adds the partials of every block
-// holding it, in a fixed order, and applies the epilogue.
+// Apply (four kernels, deterministic):
+//  1. gather:  x_loc[b] = R_b x, zero-padded to 32 nt_b entries;
+//  2. columns: one wave per (block, tile column J, segment of at most 8 tile
+//     rows) streams those tiles once (two tiles in flight), writing A_IJ x_J
+//     (row sums, one 32-vector per tile, laid out tile row by tile row) and
+//     sum_{I<J} A_IJ^H x_I over the segment (one 32-vector per segment);
+//  3. rows:    half a wave per (block, tile row I) adds the column partials
+//     of column I and the row partials of row I (contiguous) into y_loc[b];
+//  4. scatter: one thread per vector entry adds y_loc of every block holding
+//     it, in a fixed order, and applies the epilogue.
 #pragma once
 #include "common.hpp"
 
@@ -24,25 +29,26 @@ enum { RED_SET = 0, RED_RESID = 1, RED_AXPY = 2, RED_SET_SCALED = 3 };
 struct HermSet {
   int nblk = 0;
   int64_t nvec = 0;          // length of the target vector
-  int64_t ntiles = 0, npart = 0, nunits = 0;
+  int64_t ntiles = 0, npart = 0, nunits = 0, nrows = 0, nloc = 0, packed = 0;
   std::vector<int32_t> n_h;  // block sizes (host)
   std::vector<int64_t> tile_off_h;
   DevBuf<int32_t> bn;
-  DevBuf<int64_t> tile_off, part_off, idx_off;
-  DevBuf<int32_t> idx;       // concatenated vector indices of every block
-  DevBuf<int2> units;        // (block, J), largest columns first
+  DevBuf<int64_t> tile_off, cp_off, rp_off, loc_off;
+  DevBuf<int32_t> gidx;      // [nloc] vector index of each padded local row, -1 = padding
+  DevBuf<int4> units;        // (block, J, first tile row, segment), longest first
+  DevBuf<int2> rows;         // (block, I)
   DevBuf<int4> tdesc;        // (block, I, J, 0) per stored tile (packing)
   DevBuf<int32_t> red_ptr;   // CSR over vector entries
-  DevBuf<int2> red_ent;      // (block, local row)
+  DevBuf<int32_t> red_ent;   // offsets into the local vectors
   DevBuf<double2> t64;       // tiles, FP64
   DevBuf<float2> t32;        // tiles, FP32 (mixed precision)
-  DevBuf<double2> p64;       // partials
-  DevBuf<float2> p32;
+  DevBuf<double2> p64, xl64, yl64;   // partials and local vectors
+  DevBuf<float2> p32, xl32, yl32;
   Prof *prof = nullptr;      // kernel timing of the owning context
   int64_t bytes_fp64() const { return ntiles * 1024 * 16; }
   int64_t bytes_fp32() const { return ntiles * 1024 * 8; }
-  // algorithmic bytes: packed Hermitian n(n+1)/2 entries per block
-  int64_t packed_entries() const;
+  // algorithmic entries: packed Hermitian n(n+1)/2 per block
+  int64_t packed_entries() const { return packed; }
 
   // idx: per block the vector index of each local row (concatenated).
   void build(const std::vector<int32_t> &sizes, const std::vector<int32_t> &idx_concat,
