@@ -8,9 +8,12 @@
 // sixteen times inside the instruction, where vector FMAs would need one LDS
 // read per two complex multiply-adds.
 //
-// Factorisations run panel by panel (width 32), with one launch per step for
-// the panel itself (one workgroup per item, or per 64 rows) and one for the
-// trailing update (one workgroup per 64x64 tile per item).
+// Factorisations are blocked twice: 128-wide blocks, each processed in
+// 32-wide panel steps (one launch for the panel -- one workgroup per item or
+// per 64 rows -- and one for the rank-32 update, which stays inside the
+// 128-wide block), then one rank-128 update of the trailing matrix spread
+// over (64x64 tiles x items).  The trailing matrix is thus read and written
+// once per 128 columns.
 #include <cmath>
 
 #include "dense.hpp"
@@ -18,7 +21,7 @@
 namespace dpg {
 namespace {
 
-constexpr int TM = 64, TN = 64, TK = 16, NT = 256, NB = 32;
+constexpr int TM = 64, TN = 64, TK = 16, NT = 256, NB = 32, NBO = 128;
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 struct GemmSmem {
@@ -188,30 +191,22 @@ __global__ __launch_bounds__(64) void k_potrf_panel(double2 *base, const PotrfIt
   for (int t = 0; t < NB; ++t) A[r + (int64_t)(k0 + t) * lda] = x[t];
 }
 
-__device__ inline void tri_decode(int idx, int &ti, int &tj) {
-  // idx = ti (ti + 1) / 2 + tj, 0 <= tj <= ti
-  int t = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-  while ((t + 1) * (t + 2) / 2 <= idx) ++t;
-  while (t * (t + 1) / 2 > idx) --t;
-  ti = t;
-  tj = idx - t * (t + 1) / 2;
-}
-
-// Trailing update A22 -= X X^H (lower tiles) after panel k0.
+// Update C[r, c] -= sum_{k in [k_lo, k_hi)} A[r, k] conj(A[c, k]) for
+// c in [c_lo, c_hi), r >= c (lower triangle only).
 __global__ __launch_bounds__(NT) void k_potrf_update(double2 *base, const PotrfItem *items,
-                                                     const int *info, int k0) {
+                                                     const int *info, int k_lo, int k_hi,
+                                                     int c_lo, int c_hi, int tiles_c) {
   __shared__ GemmSmem sm;
   const PotrfItem it = items[blockIdx.y];
   const int n = it.n, lda = it.lda;
-  const int m = n - k0 - NB;
-  if (m <= 0 || info[blockIdx.y] != 0) return;
-  int ti, tj;
-  tri_decode(blockIdx.x, ti, tj);
-  if (ti * TM >= m) return;
+  const int m = n - c_lo, nc = min(c_hi, n) - c_lo, kw = min(k_hi, n) - k_lo;
+  if (m <= 0 || nc <= 0 || kw <= 0 || info[blockIdx.y] != 0) return;
+  const int ti = blockIdx.x / tiles_c, tj = blockIdx.x % tiles_c;
+  if (ti * TM >= m || tj * TN >= nc || ti < tj) return;
   double2 *A = base + it.a;
-  const double2 *P = A + (k0 + NB) + (int64_t)k0 * lda;
-  double2 *C = A + (k0 + NB) + (int64_t)(k0 + NB) * lda;
-  gemm_tile<OP_N, OP_C>(m, m, NB, 0, ti * TM, tj * TN, mk(-1.0, 0.0), P, lda, P, lda,
+  const double2 *P = A + c_lo + (int64_t)k_lo * lda;
+  double2 *C = A + c_lo + (int64_t)c_lo * lda;
+  gemm_tile<OP_N, OP_C>(m, nc, kw, 0, ti * TM, tj * TN, mk(-1.0, 0.0), P, lda, P, lda,
                         mk(1.0, 0.0), C, lda, ti == tj, sm);
 }
 
@@ -255,23 +250,24 @@ __global__ __launch_bounds__(64) void k_trsm_diag(const double2 *lbase, double2 
     if (t < kb) B[(k0 + t) + (int64_t)c * it.ldb] = x[t];
 }
 
-// B[k0+32:, cols] -= L[k0+32:, k0:k0+32] X_k, one 64x64 tile per workgroup.
+// B[r, c] -= sum_{k in [k_lo, k_hi)} L[r, k] X[k, c] for r in [r_lo, r_hi),
+// one 64x64 tile per workgroup.
 __global__ __launch_bounds__(NT) void k_trsm_update(const double2 *lbase, double2 *bbase,
-                                                    const TrsmItem *items, int k0, int tri,
-                                                    int tiles_c) {
+                                                    const TrsmItem *items, int k_lo, int k_hi,
+                                                    int r_lo, int r_hi, int tri, int tiles_c) {
   __shared__ GemmSmem sm;
   const TrsmItem it = items[blockIdx.y];
   const int n = it.n;
-  const int m = n - k0 - NB;
-  if (m <= 0) return;
-  const int ncols = tri ? min(it.ncols, k0 + NB) : it.ncols;
+  const int m = min(r_hi, n) - r_lo, kw = min(k_hi, n) - k_lo;
+  if (m <= 0 || kw <= 0) return;
+  const int ncols = tri ? min(it.ncols, k_hi) : it.ncols;
   const int ti = blockIdx.x / tiles_c, tj = blockIdx.x % tiles_c;
   if (ti * TM >= m || tj * TN >= ncols) return;
   const double2 *L = lbase + it.l;
   double2 *B = bbase + it.b;
-  gemm_tile<OP_N, OP_N>(m, ncols, NB, 0, ti * TM, tj * TN, mk(-1.0, 0.0),
-                        L + (k0 + NB) + (int64_t)k0 * it.ldl, it.ldl, B + k0, it.ldb,
-                        mk(1.0, 0.0), B + k0 + NB, it.ldb, false, sm);
+  gemm_tile<OP_N, OP_N>(m, ncols, kw, 0, ti * TM, tj * TN, mk(-1.0, 0.0),
+                        L + r_lo + (int64_t)k_lo * it.ldl, it.ldl, B + k_lo, it.ldb,
+                        mk(1.0, 0.0), B + r_lo, it.ldb, false, sm);
 }
 
 // ---- GEMM ----------------------------------------------------------------------------
@@ -309,15 +305,27 @@ void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *i
                    hipStream_t s) {
   if (nitems <= 0 || nmax <= 0) return;
   HIP_OK(hipMemsetAsync(info_dev, 0, nitems * sizeof(int), s));
-  for (int k0 = 0; k0 < nmax; k0 += NB) {
-    hipLaunchKernelGGL(k_potrf_diag, dim3(nitems), dim3(NT), 0, s, base, items_dev, info_dev, k0);
-    const int rows = nmax - k0 - NB;
-    if (rows > 0) {
+  for (int K0 = 0; K0 < nmax; K0 += NBO) {
+    const int K1 = std::min(K0 + NBO, nmax);
+    for (int k0 = K0; k0 < K1; k0 += NB) {
+      hipLaunchKernelGGL(k_potrf_diag, dim3(nitems), dim3(NT), 0, s, base, items_dev, info_dev, k0);
+      const int rows = nmax - k0 - NB;
+      if (rows <= 0) continue;
       hipLaunchKernelGGL(k_potrf_panel, dim3(cdiv(rows, 64), nitems), dim3(64), 0, s, base,
                          items_dev, info_dev, k0);
-      const int T = (int)cdiv(rows, TM);
-      hipLaunchKernelGGL(k_potrf_update, dim3(T * (T + 1) / 2, nitems), dim3(NT), 0, s, base,
-                         items_dev, info_dev, k0);
+      // rank-32 update of the rest of this block column only
+      const int c_lo = k0 + NB, c_hi = K1;
+      if (c_lo < c_hi) {
+        const int tr = (int)cdiv(nmax - c_lo, TM), tc = (int)cdiv(c_hi - c_lo, TN);
+        hipLaunchKernelGGL(k_potrf_update, dim3(tr * tc, nitems), dim3(NT), 0, s, base,
+                           items_dev, info_dev, k0, k0 + NB, c_lo, c_hi, tc);
+      }
+    }
+    // rank-128 update of the trailing matrix
+    if (K1 < nmax) {
+      const int t = (int)cdiv(nmax - K1, TM);
+      hipLaunchKernelGGL(k_potrf_update, dim3(t * t, nitems), dim3(NT), 0, s, base, items_dev,
+                         info_dev, K0, K1, K1, nmax, t);
     }
   }
   LAUNCH_OK();
@@ -327,15 +335,25 @@ void trsm_batched(const double2 *lbase, double2 *bbase, const TrsmItem *items_de
                   int max_n, int max_cols, bool identity_rhs, hipStream_t s) {
   if (nitems <= 0 || max_cols <= 0 || max_n <= 0) return;
   const int tri = identity_rhs ? 1 : 0;
-  for (int k0 = 0; k0 < max_n; k0 += NB) {
-    const int cols = tri ? std::min(max_cols, k0 + NB) : max_cols;
-    hipLaunchKernelGGL(k_trsm_diag, dim3(cdiv(cols, 64), nitems), dim3(64), 0, s, lbase, bbase,
-                       items_dev, k0, tri);
-    const int rows = max_n - k0 - NB;
-    if (rows > 0) {
+  for (int K0 = 0; K0 < max_n; K0 += NBO) {
+    const int K1 = std::min(K0 + NBO, max_n);
+    for (int k0 = K0; k0 < K1; k0 += NB) {
+      const int cols = tri ? std::min(max_cols, k0 + NB) : max_cols;
+      hipLaunchKernelGGL(k_trsm_diag, dim3(cdiv(cols, 64), nitems), dim3(64), 0, s, lbase, bbase,
+                         items_dev, k0, tri);
+      // rows of this block row below the solved 32
+      const int r_lo = k0 + NB, r_hi = K1;
+      if (r_lo < r_hi) {
+        const int tc = (int)cdiv(cols, TN);
+        hipLaunchKernelGGL(k_trsm_update, dim3(cdiv(r_hi - r_lo, TM) * tc, nitems), dim3(NT), 0,
+                           s, lbase, bbase, items_dev, k0, k0 + NB, r_lo, r_hi, tri, tc);
+      }
+    }
+    if (K1 < max_n) {
+      const int cols = tri ? std::min(max_cols, K1) : max_cols;
       const int tc = (int)cdiv(cols, TN);
-      hipLaunchKernelGGL(k_trsm_update, dim3(cdiv(rows, TM) * tc, nitems), dim3(NT), 0, s, lbase,
-                         bbase, items_dev, k0, tri, tc);
+      hipLaunchKernelGGL(k_trsm_update, dim3(cdiv(max_n - K1, TM) * tc, nitems), dim3(NT), 0, s,
+                         lbase, bbase, items_dev, K0, K1, K1, max_n, tri, tc);
     }
   }
   LAUNCH_OK();

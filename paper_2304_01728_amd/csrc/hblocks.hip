@@ -26,17 +26,10 @@ template <typename C> __device__ __forceinline__ void load_tile(const C *__restr
   for (int k = 0; k < 16; ++k) t[k] = tp[k * 64];
 }
 
-// The four entries of tile row I of a local vector that lane ra needs.
-template <typename C>
-__device__ __forceinline__ void load_x(const C *__restrict__ xl, int I, int ra, C xI[4]) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i) xI[i] = xl[32 * I + 4 * ra + i];
-}
-
 // Row sums of one tile into its partial slot; column sums accumulated.
 template <typename C>
-__device__ __forceinline__ void do_tile(const C t[16], const C xJ[4], const C xI[4], int I,
-                                        int J, int ra, int cb, C cacc[4], C *__restrict__ slot) {
+__device__ __forceinline__ void do_tile(const C t[16], const C xJ[4], const C *xr, int I, int J,
+                                        int ra, int cb, C cacc[4], C *__restrict__ slot) {
   C rs[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -47,7 +40,12 @@ __device__ __forceinline__ void do_tile(const C t[16], const C xJ[4], const C xI
     for (int j = 0; j < 4; ++j) a = cfma(t[4 * i + j], xJ[j], a);
     rs[i] = a;
   }
+  // column sums skip the diagonal tile (its lower half is the conjugate of
+  // the upper half, already counted by the row sums)
   if (I < J) {
+    C xI[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) xI[i] = xr[4 * ra + i];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -92,7 +90,9 @@ __global__ __launch_bounds__(256) void k_gather_x(int64_t nloc, const int32_t *_
 }
 
 // One wave per (block, tile column J, segment of <= kSeg tile rows), two
-// tiles (and their x entries) in flight.
+// tiles in flight.  The x entries of the segment's tile rows are staged in
+// LDS (wave-private), which keeps registers for the tiles and the vector
+// memory queue for tile data only.
 template <typename T>
 __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ tiles,
                                                const int4 *__restrict__ units, int64_t nunits,
@@ -104,7 +104,9 @@ __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ til
                                                const cplx_t<T> *__restrict__ xloc,
                                                cplx_t<T> *__restrict__ part) {
   using C = cplx_t<T>;
-  const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  __shared__ C xs[4][kSeg * 32];
+  const int wave = threadIdx.x >> 6;
+  const int64_t wv = (int64_t)blockIdx.x * 4 + wave;
   if (wv >= nunits) return;
   const int lane = threadIdx.x & 63, ra = lane >> 3, cb = lane & 7;
   const int4 u = units[wv];
@@ -112,32 +114,46 @@ __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ til
   const int I1 = min(I0 + kSeg, J + 1);
   const int nt = (bn[b] + 31) >> 5;
   const C *xl = xloc + loc_off[b];
-  C xJ[4], cacc[4];
+  const C *tp = tiles + (tile_off[b] + (int64_t)J * (J + 1) / 2) * 1024 + lane;
+  C *rp = part + rp_off[b];
+  C t0[16], t1[16], xJ[4], cacc[4];
+  load_tile(tp + (int64_t)I0 * 1024, t0);
+  // stage x of tile rows I0..I1-1 (4 entries per lane, rows past I1 unused)
+  C *xw = xs[wave];
+  {
+    const int nrow = 32 * (I1 - I0);
+    C v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = lane + 64 * q;
+      v[q].x = 0;
+      v[q].y = 0;
+      if (e < nrow) v[q] = xl[32 * I0 + e];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xw[lane + 64 * q] = v[q];
+  }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     xJ[j] = xl[32 * J + 4 * cb + j];
     cacc[j].x = 0;
     cacc[j].y = 0;
   }
-  const C *tp = tiles + (tile_off[b] + (int64_t)J * (J + 1) / 2) * 1024 + lane;
-  C *rp = part + rp_off[b];
-  C t0[16], t1[16], x0[4], x1[4];
-  load_tile(tp + (int64_t)I0 * 1024, t0);
-  load_x(xl, I0, ra, x0);
-  for (int I = I0; I < I1; I += 2) {
-    if (I + 1 < I1) {
-      load_tile(tp + (int64_t)(I + 1) * 1024, t1);
-      load_x(xl, I + 1, ra, x1);
-    }
-    do_tile(t0, xJ, x0, I, J, ra, cb, cacc, rp + row_slot(nt, I, J));
-    if (I + 1 < I1) {
-      if (I + 2 < I1) {
-        load_tile(tp + (int64_t)(I + 2) * 1024, t0);
-        load_x(xl, I + 2, ra, x0);
-      }
-      do_tile(t1, xJ, x1, I + 1, J, ra, cb, cacc, rp + row_slot(nt, I + 1, J));
-    }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // Every pass of the pair loop issues the same loads (the look-ahead address
+  // is clamped to the segment's last tile, a cache hit) so that the next tile
+  // stays in flight while one is being used.
+  int I = I0;
+  for (; I + 1 < I1; I += 2) {
+    load_tile(tp + (int64_t)(I + 1) * 1024, t1);
+    do_tile(t0, xJ, xw + 32 * (I - I0), I, J, ra, cb, cacc, rp + row_slot(nt, I, J));
+    load_tile(tp + (int64_t)min(I + 2, I1 - 1) * 1024, t0);
+    do_tile(t1, xJ, xw + 32 * (I + 1 - I0), I + 1, J, ra, cb, cacc,
+            rp + row_slot(nt, I + 1, J));
   }
+  if (I < I1) do_tile(t0, xJ, xw + 32 * (I - I0), I, J, ra, cb, cacc, rp + row_slot(nt, I, J));
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     cacc[j] = cadd(cacc[j], shfl_xor_c(cacc[j], 8));
