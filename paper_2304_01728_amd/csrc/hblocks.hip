@@ -21,6 +21,49 @@ template <typename C> __device__ inline C sel4(C v0, C v1, C v2, C v3, int i) {
   return r;
 }
 
+// Cross-lane moves inside rows of 16 lanes (DPP): quad_perm [1,0,3,2],
+// quad_perm [2,3,0,1] and the mirror inside each group of 8 lanes.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141;
+
+template <int CTRL> __device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp(double v) {
+  int2 i = __builtin_bit_cast(int2, v);
+  i.x = __builtin_amdgcn_update_dpp(0, i.x, CTRL, 0xF, 0xF, false);
+  i.y = __builtin_amdgcn_update_dpp(0, i.y, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, i);
+}
+template <int CTRL, typename C> __device__ __forceinline__ C dpp_c(C v) {
+  C r;
+  r.x = dpp<CTRL>(v.x);
+  r.y = dpp<CTRL>(v.y);
+  return r;
+}
+template <typename C> __device__ __forceinline__ C csel(bool c, C a, C b) {
+  C r;
+  r.x = c ? a.x : b.x;
+  r.y = c ? a.y : b.y;
+  return r;
+}
+
+// Reduce-scatter of four row values over the 8 lanes cb = 0..7 of a group:
+// lanes cb and cb^1 return the full sum of row cb/2.  Three exchange rounds
+// (partners 7-cb, cb^2, cb^1), each moving one value per lane after the
+// first, which moves two.
+template <typename C> __device__ __forceinline__ C rowsum_scatter(const C rs[4], int cb) {
+  const bool lo = cb < 4;
+  C k0 = csel(lo, rs[0], rs[2]), k1 = csel(lo, rs[1], rs[3]);
+  const C s0 = csel(lo, rs[2], rs[0]), s1 = csel(lo, rs[3], rs[1]);
+  k0 = cadd(k0, dpp_c<kDppHalfMirror>(s0));
+  k1 = cadd(k1, dpp_c<kDppHalfMirror>(s1));
+  const bool b1 = cb & 2;
+  C k = csel(b1, k1, k0);
+  k = cadd(k, dpp_c<kDppXor2>(csel(b1, k0, k1)));
+  return cadd(k, dpp_c<kDppXor1>(k));
+}
+
 template <typename C> __device__ __forceinline__ void load_tile(const C *__restrict__ tp, C t[16]) {
 #pragma unroll
   for (int k = 0; k < 16; ++k) t[k] = tp[k * 64];
@@ -51,17 +94,14 @@ __device__ __forceinline__ void do_tile(const C t[16], const C xJ[4], const C *x
 #pragma unroll
       for (int i = 0; i < 4; ++i) cacc[j] = cfmaconj(t[4 * i + j], xI[i], cacc[j]);
   }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    rs[i] = cadd(rs[i], shfl_xor_c(rs[i], 1));
-    rs[i] = cadd(rs[i], shfl_xor_c(rs[i], 2));
-    rs[i] = cadd(rs[i], shfl_xor_c(rs[i], 4));
-  }
-  if (cb < 4) slot[4 * ra + cb] = sel4(rs[0], rs[1], rs[2], rs[3], cb);
+  const C v = rowsum_scatter(rs, cb);
+  if (!(cb & 1)) slot[4 * ra + (cb >> 1)] = v;
 }
 
 // Tile columns are cut into segments of at most kSeg tiles, one wave each.
-constexpr int kSeg = 8;
+// Two tiles, both loaded before any arithmetic, stream fastest: longer
+// segments leave only one tile in flight while the other is being used.
+constexpr int kSeg = 2;
 
 // Column-sum slots of a block: column J has ceil((J+1)/kSeg) segment slots;
 // colbase(J) = 32 sum_{j=1..J} ceil(j/kSeg).
@@ -89,10 +129,9 @@ __global__ __launch_bounds__(256) void k_gather_x(int64_t nloc, const int32_t *_
   xl[i] = v;
 }
 
-// One wave per (block, tile column J, segment of <= kSeg tile rows), two
-// tiles in flight.  The x entries of the segment's tile rows are staged in
-// LDS (wave-private), which keeps registers for the tiles and the vector
-// memory queue for tile data only.
+// One wave per (block, tile column J, pair of tile rows I0, I0 + 1 <= J).  The
+// x entries of the two tile rows are staged in LDS (wave-private), which
+// keeps registers for the tiles and the vector memory queue for tile data.
 template <typename T>
 __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ tiles,
                                                const int4 *__restrict__ units, int64_t nunits,
@@ -103,6 +142,7 @@ __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ til
                                                const int64_t *__restrict__ loc_off,
                                                const cplx_t<T> *__restrict__ xloc,
                                                cplx_t<T> *__restrict__ part) {
+  static_assert(kSeg == 2, "k_units handles segments of two tile rows");
   using C = cplx_t<T>;
   __shared__ C xs[4][kSeg * 32];
   const int wave = threadIdx.x >> 6;
@@ -111,49 +151,33 @@ __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ til
   const int lane = threadIdx.x & 63, ra = lane >> 3, cb = lane & 7;
   const int4 u = units[wv];
   const int b = u.x, J = u.y, I0 = u.z, seg = u.w;
-  const int I1 = min(I0 + kSeg, J + 1);
+  const bool two = I0 + 1 <= J;
   const int nt = (bn[b] + 31) >> 5;
   const C *xl = xloc + loc_off[b];
-  const C *tp = tiles + (tile_off[b] + (int64_t)J * (J + 1) / 2) * 1024 + lane;
+  const C *tp = tiles + (tile_off[b] + (int64_t)J * (J + 1) / 2 + I0) * 1024 + lane;
   C *rp = part + rp_off[b];
   C t0[16], t1[16], xJ[4], cacc[4];
-  load_tile(tp + (int64_t)I0 * 1024, t0);
-  // stage x of tile rows I0..I1-1 (4 entries per lane, rows past I1 unused)
-  C *xw = xs[wave];
-  {
-    const int nrow = 32 * (I1 - I0);
-    C v[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = lane + 64 * q;
-      v[q].x = 0;
-      v[q].y = 0;
-      if (e < nrow) v[q] = xl[32 * I0 + e];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) xw[lane + 64 * q] = v[q];
-  }
+  // x first: loads complete in order, so the LDS staging below waits for x
+  // only, not for the tiles
+  C v;
+  v.x = 0;
+  v.y = 0;
+  if (lane < 32 * (1 + two)) v = xl[32 * I0 + lane];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     xJ[j] = xl[32 * J + 4 * cb + j];
     cacc[j].x = 0;
     cacc[j].y = 0;
   }
+  load_tile(tp, t0);
+  load_tile(tp + (two ? 1024 : 0), t1);  // a one-tile segment re-reads its tile (cache hit)
+  C *xw = xs[wave];
+  xw[lane] = v;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // Every pass of the pair loop issues the same loads (the look-ahead address
-  // is clamped to the segment's last tile, a cache hit) so that the next tile
-  // stays in flight while one is being used.
-  int I = I0;
-  for (; I + 1 < I1; I += 2) {
-    load_tile(tp + (int64_t)(I + 1) * 1024, t1);
-    do_tile(t0, xJ, xw + 32 * (I - I0), I, J, ra, cb, cacc, rp + row_slot(nt, I, J));
-    load_tile(tp + (int64_t)min(I + 2, I1 - 1) * 1024, t0);
-    do_tile(t1, xJ, xw + 32 * (I + 1 - I0), I + 1, J, ra, cb, cacc,
-            rp + row_slot(nt, I + 1, J));
-  }
-  if (I < I1) do_tile(t0, xJ, xw + 32 * (I - I0), I, J, ra, cb, cacc, rp + row_slot(nt, I, J));
+  do_tile(t0, xJ, xw, I0, J, ra, cb, cacc, rp + row_slot(nt, I0, J));
+  if (two) do_tile(t1, xJ, xw + 32, I0 + 1, J, ra, cb, cacc, rp + row_slot(nt, I0 + 1, J));
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     cacc[j] = cadd(cacc[j], shfl_xor_c(cacc[j], 8));

@@ -11,9 +11,9 @@
 //
 // Apply (four kernels, deterministic):
 //  1. gather:  x_loc[b] = R_b x, zero-padded to 32 nt_b entries;
-//  2. columns: one wave per (block, tile column J, segment of at most 8 tile
-//     rows) streams those tiles once (two tiles in flight), writing A_IJ x_J
-//     (row sums, one 32-vector per tile, laid out tile row by tile row) and
+//  2. columns: one wave per (block, tile column J, segment of two tile rows)
+//     loads both tiles before any arithmetic, writes A_IJ x_J (row sums, one
+//     32-vector per tile, laid out tile row by tile row) and
 //     sum_{I<J} A_IJ^H x_I over the segment (one 32-vector per segment);
 //  3. rows:    half a wave per (block, tile row I) adds the column partials
 //     of column I and the row partials of row I (contiguous) into y_loc[b];
