@@ -121,6 +121,8 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
   upload_items(dgS, gS, c);
   DevBuf<int> info;
   info.alloc(C, &c->bud);
+  DevBuf<double2> wk;   // diagonal-block inverses of the factorisations
+  wk.alloc(dense_work_size(C, nt), &c->bud);
   ElemGeom g{c->N, c->side / c->N, c->omega, 1.0, {c->org[0], c->org[1], c->org[2]}};
   const hipStream_t s = c->stream;
   for (int e0 = 0; e0 < nel; e0 += C) {
@@ -141,12 +143,12 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
     }
     {
       PROF(DPG_K_POTRF, cnt * f_potrf(nt));
-      potrf_batched(G.p, dpG.p, cnt, info.p, nt, s);
+      potrf_batched(G.p, dpG.p, cnt, info.p, nt, wk.p, s);
     }
     check_info(info, cnt, c, "element Gram matrix", e0);
     {
       PROF(DPG_K_TRSM, cnt * f_trsm(nt, mp));
-      trsm_batched(G.p, BL.p, dtG.p, cnt, nt, mp, false, s);
+      trsm_batched(G.p, BL.p, dtG.p, cnt, nt, mp, false, wk.p, true, s);
     }
     {
       PROF(DPG_K_GEMM, cnt * f_herk(mp, nt));
@@ -154,12 +156,12 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
     }
     {
       PROF(DPG_K_POTRF, cnt * f_potrf(nf));
-      potrf_batched(K.p, dpK.p, cnt, info.p, nf, s);
+      potrf_batched(K.p, dpK.p, cnt, info.p, nf, wk.p, s);
     }
     check_info(info, cnt, c, "element field block", e0);
     {
       PROF(DPG_K_TRSM, cnt * f_trsm(nf, mp - nf));
-      trsm_batched(K.p, K.p, dtK.p, cnt, nf, mp - nf, false, s);
+      trsm_batched(K.p, K.p, dtK.p, cnt, nf, mp - nf, false, wk.p, true, s);
     }
     {
       PROF(DPG_K_GEMM, cnt * f_herk(mp - nf, nf));
@@ -244,6 +246,8 @@ void build_macro_level(dpg_ctx *c, int l) {
   cmap.upload(f.mc.child_map, &c->bud, s);
   DevBuf<int> info;
   info.alloc(CB, &c->bud);
+  DevBuf<double2> wk;
+  wk.alloc(dense_work_size(CB, nI), &c->bud);
   for (int b0 = 0; b0 < nblk; b0 += CB) {
     const int cnt = std::min(CB, nblk - b0);
     {
@@ -252,12 +256,12 @@ void build_macro_level(dpg_ctx *c, int l) {
     }
     {
       PROF(DPG_K_POTRF, cnt * f_potrf(nI));
-      potrf_batched(T.p, dpII.p, cnt, info.p, nI, s);
+      potrf_batched(T.p, dpII.p, cnt, info.p, nI, wk.p, s);
     }
     check_info(info, cnt, c, "interior block of coarse element", b0);
     {
       PROF(DPG_K_TRSM, cnt * f_trsm(nI, nBf));
-      trsm_batched(T.p, T.p, dtIB.p, cnt, nI, nBf, false, s);
+      trsm_batched(T.p, T.p, dtIB.p, cnt, nI, nBf, false, wk.p, true, s);
     }
     {
       PROF(DPG_K_GEMM, cnt * f_herk(nBf, nI));
@@ -269,7 +273,7 @@ void build_macro_level(dpg_ctx *c, int l) {
     }
     {
       PROF(DPG_K_TRSM, cnt * f_trsm(nI, nI));
-      trsm_batched(T.p, Linv.p, dtLi.p, cnt, nI, nI, true, s);
+      trsm_batched(T.p, Linv.p, dtLi.p, cnt, nI, nI, true, wk.p, true, s);
     }
     {
       PROF(DPG_K_GEMM, cnt * f_herk(nI, nI));
@@ -332,6 +336,10 @@ void build_patches(dpg_ctx *c, int l) {
   X.alloc(ws, &c->bud);
   DevBuf<int> info;
   info.alloc(std::min(np, 65535), &c->bud);
+  int nv_max = 0;
+  for (int v = 0; v < np; ++v) nv_max = std::max(nv_max, (int)nv[v]);
+  DevBuf<double2> wk;
+  wk.alloc(dense_work_size(std::min(np, 65535), nv_max), &c->bud);
   std::vector<int64_t> soff_all(np, 0);
   DevBuf<int64_t> dsoff_all;
   DevBuf<int32_t> dld_all;
@@ -387,7 +395,7 @@ void build_patches(dpg_ctx *c, int l) {
     }
     {
       PROF(DPG_K_POTRF, fp);
-      potrf_batched(S.p, dpi.p, cnt, info.p, nmax, s);
+      potrf_batched(S.p, dpi.p, cnt, info.p, nmax, wk.p, s);
     }
     check_info(info, cnt, c, "vertex patch", v0);
     {
@@ -396,7 +404,7 @@ void build_patches(dpg_ctx *c, int l) {
     }
     {
       PROF(DPG_K_TRSM, ft);
-      trsm_batched(S.p, X.p, dti.p, cnt, nmax, nmax, true, s);
+      trsm_batched(S.p, X.p, dti.p, cnt, nmax, nmax, true, wk.p, true, s);
     }
     {
       PROF(DPG_K_GEMM, fg);
@@ -439,10 +447,12 @@ void build_coarsest(dpg_ctx *c) {
   dnn.upload(nn, &c->bud, s);
   DevBuf<int> info;
   info.alloc(1, &c->bud);
-  potrf_batched(F.p, dpi.p, 1, info.p, n0, s);
+  DevBuf<double2> wk;
+  wk.alloc(dense_work_size(1, n0), &c->bud);
+  potrf_batched(F.p, dpi.p, 1, info.p, n0, wk.p, s);
   check_info(info, 1, c, "coarsest operator", 0);
   launch_identity(doff.p, dnn.p, 1, n0, Li.p, s);
-  trsm_batched(F.p, Li.p, dti.p, 1, n0, n0, true, s);
+  trsm_batched(F.p, Li.p, dti.p, 1, n0, n0, true, wk.p, true, s);
   gemm_batched(OP_C, OP_N, mk(1, 0), Li.p, Li.p, mk(0, 0), Ti.p, dgi.p, 1, n0, n0, s,
                GEMM_UPPER_LOWTRI);
   std::vector<int32_t> ld{n0};

@@ -9,11 +9,12 @@
 // read per two complex multiply-adds.
 //
 // Factorisations are blocked twice: 128-wide blocks, each processed in
-// 32-wide panel steps (one launch for the panel -- one workgroup per item or
-// per 64 rows -- and one for the rank-32 update, which stays inside the
-// 128-wide block), then one rank-128 update of the trailing matrix spread
-// over (64x64 tiles x items).  The trailing matrix is thus read and written
-// once per 128 columns.
+// 64-wide panel steps, then one rank-128 update of the trailing matrix spread
+// over (64x64 tiles x items), so the trailing matrix is read and written once
+// per 128 columns.  A panel step factors (or, for the triangular solve, takes)
+// the 64x64 diagonal block and its inverse in LDS; the panel itself is then a
+// small product with that inverse on the matrix cores, and the update inside
+// the 128-wide block a rank-64 product.
 #include <cmath>
 
 #include "dense.hpp"
@@ -21,7 +22,7 @@
 namespace dpg {
 namespace {
 
-constexpr int TM = 64, TN = 64, TK = 16, NT = 256, NB = 32, NBO = 128;
+constexpr int TM = 64, TN = 64, TK = 16, NT = 256, NB = 64, NBO = 128;
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 struct GemmSmem {
@@ -37,19 +38,68 @@ template <int OP> __device__ inline double2 ld_op(const double2 *X, int ldx, int
   return v;
 }
 
+// One k-slice of op(A) (64 x 16) and op(B) (16 x 64), four entries of each per
+// thread, zero outside m x k and k x n.
+template <int OPA, int OPB>
+__device__ __forceinline__ void load_slice(int m, int n, int k, int k0, int r0, int c0,
+                                           const double2 *A, int lda, const double2 *B, int ldb,
+                                           double2 ra[4], double2 rb[4]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + NT * q;
+    int rr, kk;
+    if (OPA == OP_N) { rr = e % TM; kk = e / TM; } else { kk = e % TK; rr = e / TK; }
+    const int r = r0 + rr, kg = k0 + kk;
+    ra[q] = (r < m && kg < k) ? ld_op<OPA>(A, lda, r, kg) : mk(0.0, 0.0);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + NT * q;
+    int kk, cc;
+    if (OPB == OP_N) { kk = e % TK; cc = e / TK; } else { cc = e % TN; kk = e / TN; }
+    const int c = c0 + cc, kg = k0 + kk;
+    rb[q] = (c < n && kg < k) ? ld_op<OPB>(B, ldb, kg, c) : mk(0.0, 0.0);
+  }
+}
+
+template <int OPA, int OPB>
+__device__ __forceinline__ void store_slice(const double2 ra[4], const double2 rb[4],
+                                            GemmSmem &sm) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + NT * q;
+    int rr, kk;
+    if (OPA == OP_N) { rr = e % TM; kk = e / TM; } else { kk = e % TK; rr = e / TK; }
+    sm.As[rr][kk] = ra[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + NT * q;
+    int kk, cc;
+    if (OPB == OP_N) { kk = e % TK; cc = e / TK; } else { cc = e % TN; kk = e / TN; }
+    sm.Bs[kk][cc] = rb[q];
+  }
+}
+
 // C[r0:r0+64, c0:c0+64] (clipped to m x n) <- alpha op(A) op(B) + beta C with
 // inner indices k_begin..k-1.  lower_only leaves entries above the diagonal
-// alone.  Must be called by all 256 threads of the workgroup.
+// alone; columns c >= flip_col take -alpha.  Must be called by all 256
+// threads of the workgroup.  C may alias A or B when the tile's output covers
+// exactly the operand rows / columns it reads (all reads precede the writes).
 template <int OPA, int OPB>
 __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int r0, int c0, double2 alpha,
                           const double2 *A, int lda, const double2 *B, int ldb, double2 beta,
-                          double2 *C, int ldc, bool lower_only, GemmSmem &sm) {
+                          double2 *C, int ldc, bool lower_only, GemmSmem &sm,
+                          int flip_col = 0x7fffffff) {
   const int tid = threadIdx.x;
   // FP64 matrix cores: v_mfma_f64_16x16x4f64 computes D(16x16) += A(16x4) B(4x16)
   // with A[i][k] in lane i + 16k, B[k][j] in lane j + 16k and D[i][j] in
   // lane j + 16 (i % 4), element i / 4.  Wave w owns the 32x32 sub-tile at
   // (32 (w / 2), 32 (w % 2)) as 2x2 blocks; a complex product takes four real
-  // MFMAs (re*re - im*im, re*im + im*re).
+  // MFMAs (re*re - im*im, re*im + im*re), issued term by term so that two
+  // updates of one accumulator are never adjacent.
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = 32 * (wave >> 1), wc = 32 * (wave & 1);
   const int li = lane & 15, lk = lane >> 4;
@@ -61,21 +111,15 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int 
       acc_re[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
       acc_im[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
     }
+  // The next k-slice is fetched into registers while the current one is
+  // multiplied from LDS, so global latency hides behind the matrix cores.
+  double2 ra[4], rb[4];
+  if (k_begin < k) load_slice<OPA, OPB>(m, n, k, k_begin, r0, c0, A, lda, B, ldb, ra, rb);
 #pragma unroll 1
   for (int k0 = k_begin; k0 < k; k0 += TK) {
-    for (int e = tid; e < TM * TK; e += NT) {
-      int rr, kk;
-      if (OPA == OP_N) { rr = e % TM; kk = e / TM; } else { kk = e % TK; rr = e / TK; }
-      const int r = r0 + rr, kg = k0 + kk;
-      sm.As[rr][kk] = (r < m && kg < k) ? ld_op<OPA>(A, lda, r, kg) : mk(0.0, 0.0);
-    }
-    for (int e = tid; e < TK * TN; e += NT) {
-      int kk, cc;
-      if (OPB == OP_N) { kk = e % TK; cc = e / TK; } else { cc = e % TN; kk = e / TN; }
-      const int c = c0 + cc, kg = k0 + kk;
-      sm.Bs[kk][cc] = (c < n && kg < k) ? ld_op<OPB>(B, ldb, kg, c) : mk(0.0, 0.0);
-    }
+    store_slice<OPA, OPB>(ra, rb, sm);
     __syncthreads();
+    if (k0 + TK < k) load_slice<OPA, OPB>(m, n, k, k0 + TK, r0, c0, A, lda, B, ldb, ra, rb);
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 4) {
       double2 a[2], b[2];
@@ -86,12 +130,23 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int 
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < 2; ++j)
           acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc_re[i][j], 0, 0, 0);
-          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[i].y, b[j].y, acc_re[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
           acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].y, acc_im[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[i].y, b[j].y, acc_re[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
           acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].x, acc_im[i][j], 0, 0, 0);
-        }
     }
     __syncthreads();
   }
@@ -106,96 +161,169 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int 
         if (r < m && c < n && (!lower_only || c <= r)) {
           double2 *p = &C[r + (int64_t)c * ldc];
           double2 v = cmul(alpha, mk(acc_re[i][j][e], acc_im[i][j][e]));
+          if (c >= flip_col) v = mk(-v.x, -v.y);
           if (use_beta) v = cfma(beta, *p, v);
           *p = v;
         }
       }
 }
 
-// ---- Cholesky -------------------------------------------------------------------
+// ---- diagonal blocks -------------------------------------------------------------
 
-// Factor the diagonal block [k0, k0+32) of every item in LDS.
-__global__ __launch_bounds__(NT) void k_potrf_diag(double2 *base, const PotrfItem *items,
-                                                   int *info, int k0) {
-  __shared__ double2 D[NB][NB + 1];
+// Each thread owns up to kQ entries (i, c), c <= i, of a 64x64 lower triangle,
+// numbered row by row: entry e sits at i(i+1)/2 + c.
+constexpr int kQ = (NB * (NB + 1) / 2 + NT - 1) / NT;
+
+__device__ __forceinline__ void tri_index(int e, int &i, int &c) {
+  i = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
+  while ((i + 1) * (i + 2) / 2 <= e) ++i;
+  while (i * (i + 1) / 2 > e) --i;
+  c = e - i * (i + 1) / 2;
+}
+
+// Elimination of a kb x kb diagonal block held in registers (entries owned as
+// above), applied at the same time to an identity block so that it also
+// yields the inverse factor.  Step j broadcasts column j of the current
+// Schur complement and row j of the transformed identity through LDS (double
+// buffered, one barrier per step); the multiplier of row i is a_ij / a_jj.
+// FACTOR: a holds the block of A; it is eliminated (square-root free, the
+//   pivots d_j stay on the diagonal) and L = a_ic / sqrt(d_c), L^-1 = x / sqrt(d_i).
+// otherwise: a holds a lower triangular factor L (left unchanged) and the
+//   identity becomes L~^-1 with L~ = L diag(L)^-1, so L^-1 = x / l_ii.
+// scale[i] receives sqrt(d_i) or l_ii; the return value is 1 + the first
+// pivot that was not positive, or 0.
+template <bool FACTOR>
+__device__ int eliminate(double2 a[kQ], double2 x[kQ], const int ii[kQ], const int cc[kQ], int kb,
+                         double2 (*cb)[NB], double2 (*rb)[NB], double *scale) {
+  const int tid = threadIdx.x;
   __shared__ int fail;
-  const PotrfItem it = items[blockIdx.x];
-  const int n = it.n, lda = it.lda, tid = threadIdx.x;
-  if (k0 >= n || info[blockIdx.x] != 0) return;
-  double2 *A = base + it.a;
-  const int kb = min(NB, n - k0);
   if (tid == 0) fail = 0;
-  for (int e = tid; e < kb * kb; e += NT) {
-    const int i = e % kb, j = e / kb;
-    if (j <= i) D[i][j] = A[(k0 + i) + (int64_t)(k0 + j) * lda];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    if (ii[q] < 0) continue;
+    if (cc[q] == 0) cb[0][ii[q]] = a[q];
+    if (ii[q] == 0) rb[0][cc[q]] = x[q];
+    if (!FACTOR && ii[q] == cc[q]) scale[ii[q]] = a[q].x;
   }
   __syncthreads();
   for (int j = 0; j < kb; ++j) {
-    if (tid == 0) {
-      double d = D[j][j].x;
-      if (!(d > 0.0)) {
-        if (!fail) fail = k0 + j + 1;
-        d = 1.0;
+    const int u = j & 1;
+    const double d = cb[u][j].x;
+    const double inv = d > 0.0 ? 1.0 / d : 0.0;
+    if (FACTOR && tid == 0) {
+      scale[j] = d > 0.0 ? sqrt(d) : 1.0;
+      if (!(d > 0.0) && !fail) fail = j + 1;
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int i = ii[q], c = cc[q];
+      if (i <= j) continue;
+      const double2 mi = cscale(cb[u][i], inv);
+      if (FACTOR && c > j) a[q] = csub(a[q], cmul(mi, cconj(cb[u][c])));
+      else if (c <= j) x[q] = csub(x[q], cmul(mi, rb[u][c]));
+    }
+    if (j + 1 < kb) {
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        if (ii[q] < 0) continue;
+        if (cc[q] == j + 1) cb[u ^ 1][ii[q]] = a[q];
+        if (ii[q] == j + 1) rb[u ^ 1][cc[q]] = x[q];
       }
-      D[j][j] = mk(sqrt(d), 0.0);
-    }
-    __syncthreads();
-    const double inv = 1.0 / D[j][j].x;
-    for (int i = j + 1 + tid; i < kb; i += NT) D[i][j] = cscale(D[i][j], inv);
-    __syncthreads();
-    const int rem = kb - j - 1;
-    for (int e = tid; e < rem * rem; e += NT) {
-      const int i = j + 1 + e % rem, jj = j + 1 + e / rem;
-      if (jj <= i) D[i][jj] = csub(D[i][jj], cmul(D[i][j], cconj(D[jj][j])));
     }
     __syncthreads();
   }
-  if (fail) {
-    if (tid == 0) info[blockIdx.x] = fail;
-    return;
+  return fail;
+}
+
+// Write L^-1 (x / scale[i]) zero-padded to 64 x 64, column-major, to w.
+__device__ void store_inverse(const double2 x[kQ], const int ii[kQ], const int cc[kQ], int kb,
+                              const double *scale, double2 *w) {
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int i = ii[q], c = cc[q];
+    if (i < 0) continue;
+    w[i + c * NB] = cscale(x[q], 1.0 / scale[i]);
+    if (c < i) w[c + i * NB] = mk(0.0, 0.0);
   }
-  for (int e = tid; e < kb * kb; e += NT) {
-    const int i = e % kb, j = e / kb;
-    if (j <= i) A[(k0 + i) + (int64_t)(k0 + j) * lda] = D[i][j];
+  for (int e = threadIdx.x; e < NB * NB; e += NT) {
+    const int i = e % NB, c = e / NB;
+    if (i >= kb || c >= kb) w[e] = mk(0.0, 0.0);
   }
 }
 
-// Panel below the diagonal block: X = A_panel L_kk^-H, one row per thread.
-__global__ __launch_bounds__(64) void k_potrf_panel(double2 *base, const PotrfItem *items,
-                                                    const int *info, int k0) {
-  __shared__ double2 D[NB][NB + 1];
+// Owned entries of a kb x kb lower triangle (index -1: none).
+__device__ __forceinline__ void own_entries(int kb, int ii[kQ], int cc[kQ]) {
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int e = threadIdx.x + NT * q;
+    ii[q] = -1;
+    cc[q] = 0;
+    if (e < kb * (kb + 1) / 2) tri_index(e, ii[q], cc[q]);
+  }
+}
+
+// ---- Cholesky -------------------------------------------------------------------
+
+// Factor the diagonal block [k0, k0+kb) of every item, write L_kk back and
+// L_kk^-1 to the work area (slot k0 / 64 of the item).  A pivot that is not
+// positive marks the item as failed.
+__global__ __launch_bounds__(NT) void k_potrf_diag(double2 *base, const PotrfItem *items,
+                                                   int *info, int k0, int kend, double2 *work,
+                                                   int wslots) {
+  __shared__ double2 cb[2][NB], rb[2][NB];
+  __shared__ double scale[NB];
+  const PotrfItem it = items[blockIdx.x];
+  const int n = it.n, lda = it.lda;
+  const int kb = min(NB, min(kend, n) - k0);
+  if (kb <= 0 || info[blockIdx.x] != 0) return;
+  double2 *A = base + it.a + k0 + (int64_t)k0 * lda;
+  int ii[kQ], cc[kQ];
+  double2 a[kQ], x[kQ];
+  own_entries(kb, ii, cc);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    a[q] = ii[q] >= 0 ? A[ii[q] + (int64_t)cc[q] * lda] : mk(0.0, 0.0);
+    x[q] = mk(ii[q] >= 0 && ii[q] == cc[q] ? 1.0 : 0.0, 0.0);
+  }
+  const int f = eliminate<true>(a, x, ii, cc, kb, cb, rb, scale);
+  if (f) {
+    if (threadIdx.x == 0) info[blockIdx.x] = k0 + f;
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int i = ii[q], c = cc[q];
+    if (i < 0) continue;
+    A[i + (int64_t)c * lda] = i == c ? mk(scale[i], 0.0) : cscale(a[q], 1.0 / scale[c]);
+  }
+  store_inverse(x, ii, cc, kb, scale, work + ((int64_t)blockIdx.x * wslots + k0 / NB) * NB * NB);
+}
+
+// Panel below the diagonal block: X = A_panel L_kk^-H as a product with the
+// stored inverse, one 64-row tile per workgroup, in place.
+__global__ __launch_bounds__(NT) void k_potrf_panel(double2 *base, const PotrfItem *items,
+                                                    const int *info, int k0, int kend,
+                                                    const double2 *work, int wslots) {
+  __shared__ GemmSmem sm;
   const PotrfItem it = items[blockIdx.y];
-  const int n = it.n, lda = it.lda, tid = threadIdx.x;
-  if (k0 + NB >= n || info[blockIdx.y] != 0) return;
-  const int r0 = k0 + NB + blockIdx.x * 64;
-  if (r0 >= n) return;
-  double2 *A = base + it.a;
-  for (int e = tid; e < NB * NB; e += 64) {
-    const int i = e % NB, j = e / NB;
-    if (j <= i) D[i][j] = A[(k0 + i) + (int64_t)(k0 + j) * lda];
-  }
-  __syncthreads();
-  const int r = r0 + tid;
-  if (r >= n) return;
-  double2 x[NB];
-#pragma unroll
-  for (int t = 0; t < NB; ++t) x[t] = A[r + (int64_t)(k0 + t) * lda];
-#pragma unroll
-  for (int t = 0; t < NB; ++t) {
-    double2 v = x[t];
-#pragma unroll
-    for (int u = 0; u < t; ++u) v = csub(v, cmul(x[u], cconj(D[t][u])));
-    x[t] = cscale(v, 1.0 / D[t][t].x);
-  }
-#pragma unroll
-  for (int t = 0; t < NB; ++t) A[r + (int64_t)(k0 + t) * lda] = x[t];
+  const int n = it.n, lda = it.lda;
+  const int kb = min(NB, min(kend, n) - k0);
+  if (kb <= 0 || info[blockIdx.y] != 0) return;
+  const int m = n - (k0 + kb), r0 = blockIdx.x * TM;
+  if (r0 >= m) return;
+  double2 *P = base + it.a + (k0 + kb) + (int64_t)k0 * lda;
+  const double2 *W = work + ((int64_t)blockIdx.y * wslots + k0 / NB) * NB * NB;
+  gemm_tile<OP_N, OP_C>(m, kb, kb, 0, r0, 0, mk(1.0, 0.0), P, lda, W, NB, mk(0.0, 0.0), P, lda,
+                        false, sm);
 }
 
 // Update C[r, c] -= sum_{k in [k_lo, k_hi)} A[r, k] conj(A[c, k]) for
-// c in [c_lo, c_hi), r >= c (lower triangle only).
+// c in [c_lo, c_hi), r >= c (lower triangle only); columns c >= neg_from take
+// the opposite sign when k_hi <= neg_from.
 __global__ __launch_bounds__(NT) void k_potrf_update(double2 *base, const PotrfItem *items,
                                                      const int *info, int k_lo, int k_hi,
-                                                     int c_lo, int c_hi, int tiles_c) {
+                                                     int c_lo, int c_hi, int tiles_c,
+                                                     int neg_from) {
   __shared__ GemmSmem sm;
   const PotrfItem it = items[blockIdx.y];
   const int n = it.n, lda = it.lda;
@@ -206,48 +334,51 @@ __global__ __launch_bounds__(NT) void k_potrf_update(double2 *base, const PotrfI
   double2 *A = base + it.a;
   const double2 *P = A + c_lo + (int64_t)k_lo * lda;
   double2 *C = A + c_lo + (int64_t)c_lo * lda;
+  const int flip = k_hi <= neg_from ? max(neg_from - c_lo, 0) : 0x7fffffff;
   gemm_tile<OP_N, OP_C>(m, nc, kw, 0, ti * TM, tj * TN, mk(-1.0, 0.0), P, lda, P, lda,
-                        mk(1.0, 0.0), C, lda, ti == tj, sm);
+                        mk(1.0, 0.0), C, lda, ti == tj, sm, flip);
 }
 
 // ---- triangular solve -------------------------------------------------------------
 
-// Rows [k0, k0+32) of B: solve L_kk X = B_k, one column per thread.
-__global__ __launch_bounds__(64) void k_trsm_diag(const double2 *lbase, double2 *bbase,
-                                                  const TrsmItem *items, int k0, int tri) {
-  __shared__ double2 D[NB][NB + 1];
+// Inverse of every diagonal block of L (all blocks at once: L is final).
+__global__ __launch_bounds__(NT) void k_trsm_inv(const double2 *lbase, const TrsmItem *items,
+                                                 double2 *work, int wslots) {
+  __shared__ double2 cb[2][NB], rb[2][NB];
+  __shared__ double scale[NB];
   const TrsmItem it = items[blockIdx.y];
-  const int n = it.n, tid = threadIdx.x;
-  if (k0 >= n) return;
-  const int kb = min(NB, n - k0);
+  const int k0 = blockIdx.x * NB;
+  const int kb = min(NB, it.n - k0);
+  if (kb <= 0) return;
+  const double2 *L = lbase + it.l + k0 + (int64_t)k0 * it.ldl;
+  int ii[kQ], cc[kQ];
+  double2 a[kQ], x[kQ];
+  own_entries(kb, ii, cc);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    a[q] = ii[q] >= 0 ? L[ii[q] + (int64_t)cc[q] * it.ldl] : mk(0.0, 0.0);
+    x[q] = mk(ii[q] >= 0 && ii[q] == cc[q] ? 1.0 : 0.0, 0.0);
+  }
+  eliminate<false>(a, x, ii, cc, kb, cb, rb, scale);
+  store_inverse(x, ii, cc, kb, scale, work + ((int64_t)blockIdx.y * wslots + blockIdx.x) * NB * NB);
+}
+
+// Rows [k0, k0+kb) of B: X_k = L_kk^-1 B_k, one 64-column tile per workgroup,
+// in place.
+__global__ __launch_bounds__(NT) void k_trsm_solve(double2 *bbase, const TrsmItem *items, int k0,
+                                                   int kend, int tri, const double2 *work,
+                                                   int wslots) {
+  __shared__ GemmSmem sm;
+  const TrsmItem it = items[blockIdx.y];
+  const int kb = min(NB, min(kend, it.n) - k0);
+  if (kb <= 0) return;
   const int ncols = tri ? min(it.ncols, k0 + kb) : it.ncols;
-  const int c = blockIdx.x * 64 + tid;
-  if (blockIdx.x * 64 >= ncols) return;
-  const double2 *L = lbase + it.l;
-  double2 *B = bbase + it.b;
-  for (int e = tid; e < kb * kb; e += 64) {
-    const int i = e % kb, j = e / kb;
-    if (j <= i) D[i][j] = L[(k0 + i) + (int64_t)(k0 + j) * it.ldl];
-  }
-  __syncthreads();
-  if (c >= ncols) return;
-  double2 x[NB];
-#pragma unroll
-  for (int t = 0; t < NB; ++t)
-    if (t < kb) x[t] = B[(k0 + t) + (int64_t)c * it.ldb];
-#pragma unroll
-  for (int t = 0; t < NB; ++t) {
-    if (t < kb) {
-      double2 v = x[t];
-#pragma unroll
-      for (int u = 0; u < NB; ++u)
-        if (u < t) v = csub(v, cmul(D[t][u], x[u]));
-      x[t] = cscale(v, 1.0 / D[t][t].x);
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < NB; ++t)
-    if (t < kb) B[(k0 + t) + (int64_t)c * it.ldb] = x[t];
+  const int c0 = blockIdx.x * TN;
+  if (c0 >= ncols) return;
+  double2 *Bk = bbase + it.b + k0;
+  const double2 *W = work + ((int64_t)blockIdx.y * wslots + k0 / NB) * NB * NB;
+  gemm_tile<OP_N, OP_N>(kb, ncols, kb, 0, 0, c0, mk(1.0, 0.0), W, NB, Bk, it.ldb, mk(0.0, 0.0),
+                        Bk, it.ldb, false, sm);
 }
 
 // B[r, c] -= sum_{k in [k_lo, k_hi)} L[r, k] X[k, c] for r in [r_lo, r_hi),
@@ -301,52 +432,66 @@ void gemm_dispatch_b(int opb, dim3 g, hipStream_t s, double2 alpha, const double
 
 }  // namespace
 
+int64_t dense_work_size(int nitems, int nmax) {
+  return (int64_t)std::max(nitems, 0) * cdiv(std::max(nmax, 1), NB) * NB * NB;
+}
+
 void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *info_dev, int nmax,
-                   hipStream_t s) {
+                   double2 *work, hipStream_t s, int kstop, int neg_from) {
   if (nitems <= 0 || nmax <= 0) return;
+  const int kmax = std::min(kstop, nmax);
+  const int wslots = (int)cdiv(nmax, NB);
   HIP_OK(hipMemsetAsync(info_dev, 0, nitems * sizeof(int), s));
-  for (int K0 = 0; K0 < nmax; K0 += NBO) {
-    const int K1 = std::min(K0 + NBO, nmax);
+  for (int K0 = 0; K0 < kmax; K0 += NBO) {
+    const int K1 = std::min(K0 + NBO, kmax);
     for (int k0 = K0; k0 < K1; k0 += NB) {
-      hipLaunchKernelGGL(k_potrf_diag, dim3(nitems), dim3(NT), 0, s, base, items_dev, info_dev, k0);
-      const int rows = nmax - k0 - NB;
+      const int kb = std::min(NB, K1 - k0);
+      hipLaunchKernelGGL(k_potrf_diag, dim3(nitems), dim3(NT), 0, s, base, items_dev, info_dev, k0,
+                         K1, work, wslots);
+      const int rows = nmax - k0 - kb;
       if (rows <= 0) continue;
-      hipLaunchKernelGGL(k_potrf_panel, dim3(cdiv(rows, 64), nitems), dim3(64), 0, s, base,
-                         items_dev, info_dev, k0);
-      // rank-32 update of the rest of this block column only
-      const int c_lo = k0 + NB, c_hi = K1;
+      hipLaunchKernelGGL(k_potrf_panel, dim3(cdiv(rows, TM), nitems), dim3(NT), 0, s, base,
+                         items_dev, info_dev, k0, K1, (const double2 *)work, wslots);
+      // update of the rest of this block column only
+      const int c_lo = k0 + kb, c_hi = K1;
       if (c_lo < c_hi) {
         const int tr = (int)cdiv(nmax - c_lo, TM), tc = (int)cdiv(c_hi - c_lo, TN);
         hipLaunchKernelGGL(k_potrf_update, dim3(tr * tc, nitems), dim3(NT), 0, s, base,
-                           items_dev, info_dev, k0, k0 + NB, c_lo, c_hi, tc);
+                           items_dev, info_dev, k0, k0 + kb, c_lo, c_hi, tc, neg_from);
       }
     }
-    // rank-128 update of the trailing matrix
+    // block update of the trailing matrix
     if (K1 < nmax) {
       const int t = (int)cdiv(nmax - K1, TM);
       hipLaunchKernelGGL(k_potrf_update, dim3(t * t, nitems), dim3(NT), 0, s, base, items_dev,
-                         info_dev, K0, K1, K1, nmax, t);
+                         info_dev, K0, K1, K1, nmax, t, neg_from);
     }
   }
   LAUNCH_OK();
 }
 
 void trsm_batched(const double2 *lbase, double2 *bbase, const TrsmItem *items_dev, int nitems,
-                  int max_n, int max_cols, bool identity_rhs, hipStream_t s) {
+                  int max_n, int max_cols, bool identity_rhs, double2 *work, bool inverses_ready,
+                  hipStream_t s) {
   if (nitems <= 0 || max_cols <= 0 || max_n <= 0) return;
   const int tri = identity_rhs ? 1 : 0;
+  const int wslots = (int)cdiv(max_n, NB);
+  if (!inverses_ready)
+    hipLaunchKernelGGL(k_trsm_inv, dim3(wslots, nitems), dim3(NT), 0, s, lbase, items_dev, work,
+                       wslots);
   for (int K0 = 0; K0 < max_n; K0 += NBO) {
     const int K1 = std::min(K0 + NBO, max_n);
     for (int k0 = K0; k0 < K1; k0 += NB) {
-      const int cols = tri ? std::min(max_cols, k0 + NB) : max_cols;
-      hipLaunchKernelGGL(k_trsm_diag, dim3(cdiv(cols, 64), nitems), dim3(64), 0, s, lbase, bbase,
-                         items_dev, k0, tri);
-      // rows of this block row below the solved 32
-      const int r_lo = k0 + NB, r_hi = K1;
+      const int kb = std::min(NB, K1 - k0);
+      const int cols = tri ? std::min(max_cols, k0 + kb) : max_cols;
+      hipLaunchKernelGGL(k_trsm_solve, dim3(cdiv(cols, TN), nitems), dim3(NT), 0, s, bbase,
+                         items_dev, k0, K1, tri, (const double2 *)work, wslots);
+      // rows of this block row below the solved ones
+      const int r_lo = k0 + kb, r_hi = K1;
       if (r_lo < r_hi) {
         const int tc = (int)cdiv(cols, TN);
         hipLaunchKernelGGL(k_trsm_update, dim3(cdiv(r_hi - r_lo, TM) * tc, nitems), dim3(NT), 0,
-                           s, lbase, bbase, items_dev, k0, k0 + NB, r_lo, r_hi, tri, tc);
+                           s, lbase, bbase, items_dev, k0, k0 + kb, r_lo, r_hi, tri, tc);
       }
     }
     if (K1 < max_n) {

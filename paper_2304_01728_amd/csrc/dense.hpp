@@ -4,10 +4,13 @@
 // has its own sizes and leading dimensions; matrices are column-major and
 // addressed as base pointer + per-item element offset.
 //
-// The factorisations proceed by 32-wide panels, one launch per panel step:
-// a small kernel factors / solves the panel of every item, then the rank-32
-// update of the rest is spread over (64x64 tiles x items), so that large
-// blocks use the whole GPU instead of one compute unit each.
+// The factorisations proceed by 64-wide panels grouped in 128-wide blocks: a
+// small kernel factors the 64x64 diagonal block of every item and inverts it
+// in LDS, the panel is then a product with that inverse, and the updates are
+// spread over (64x64 tiles x items), so that large blocks use the whole GPU
+// instead of one compute unit each.  The diagonal-block inverses go to a
+// caller-provided work area (dense_work_size elements), where a following
+// triangular solve with the same factor can take them.
 #pragma once
 #include "common.hpp"
 
@@ -20,16 +23,29 @@ struct GemmItem { int64_t a, b, c; int m, n, k, lda, ldb, ldc; };
 enum { OP_N = 0, OP_T = 1, OP_C = 2 };
 enum { GEMM_FULL = 0, GEMM_UPPER_LOWTRI = 1 };
 
+// Work-area size (double2 elements) for nitems items of order <= nmax.
+int64_t dense_work_size(int nitems, int nmax);
+
 // In-place lower Cholesky A = L L^H of every item (upper triangle untouched).
 // info[item] = 0 on success, j+1 if pivot j was not positive.  nmax = largest n.
+// With kstop < n only the first kstop columns are factored and the trailing
+// block is left as the Schur complement.  Columns c >= neg_from receive the
+// updates from columns k < neg_from with the opposite sign (a factorisation
+// of diag(I, -I)-signed systems: trailing blocks that start at zero then hold
+// +B^H A^-1 B instead of its negative).  On return the work area holds the
+// inverse of every diagonal block that was factored.
 void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *info_dev, int nmax,
-                   hipStream_t s);
+                   double2 *work, hipStream_t s, int kstop = 0x7fffffff,
+                   int neg_from = 0x7fffffff);
 
 // B <- L^-1 B for every item (L lower, from a Cholesky factor).  With
 // identity_rhs, B must hold the identity and only the lower-triangular part
-// of the result is formed (the rest stays zero).
+// of the result is formed (the rest stays zero).  inverses_ready: the work
+// area already holds the diagonal-block inverses of L (left there by
+// potrf_batched with the same items and max_n).
 void trsm_batched(const double2 *lbase, double2 *bbase, const TrsmItem *items_dev, int nitems,
-                  int max_n, int max_cols, bool identity_rhs, hipStream_t s);
+                  int max_n, int max_cols, bool identity_rhs, double2 *work, bool inverses_ready,
+                  hipStream_t s);
 
 // C <- alpha op(A) op(B) + beta C for every item.  mode GEMM_UPPER_LOWTRI
 // computes only the upper 64x64 tiles (tile row <= tile column) of a product
