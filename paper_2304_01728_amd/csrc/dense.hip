@@ -38,6 +38,25 @@ template <int OP> __device__ inline double2 ld_op(const double2 *X, int ldx, int
   return v;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Tiled kernels (grid: tiles x items) remap the hardware id so that all
+// tiles of item 8 g + x run on XCD x, which keeps the operand panels an item's
+// tiles share in one L2 while items stay interleaved over the XCDs.  Items of
+// a last incomplete group of 8 keep the plain order.
+__device__ __forceinline__ void xcd_remap(int &bx, int &by) {
+  const int gx = gridDim.x;
+  const int64_t L = blockIdx.x + (int64_t)blockIdx.y * gx;
+  const int64_t grp = 8LL * gx, full = (int64_t)(gridDim.y / 8) * grp;
+  if (L < full) {
+    const int64_t g = L / grp, w = L % grp;
+    bx = (int)(w / 8);
+    by = (int)(8 * g + w % 8);
+  } else {
+    bx = (int)(L % gx);
+    by = (int)(L / gx);
+  }
+}
+
 // One k-slice of op(A) (64 x 16) and op(B) (16 x 64), four entries of each per
 // thread, zero outside m x k and k x n.
 template <int OPA, int OPB>
@@ -85,14 +104,12 @@ __device__ __forceinline__ void store_slice(const double2 ra[4], const double2 r
 
 // C[r0:r0+64, c0:c0+64] (clipped to m x n) <- alpha op(A) op(B) + beta C with
 // inner indices k_begin..k-1.  lower_only leaves entries above the diagonal
-// alone; columns c >= flip_col take -alpha.  Must be called by all 256
-// threads of the workgroup.  C may alias A or B when the tile's output covers
+// alone.  Must be called by all 256 threads of the workgroup.  C may alias A or B when the tile's output covers
 // exactly the operand rows / columns it reads (all reads precede the writes).
 template <int OPA, int OPB>
 __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int r0, int c0, double2 alpha,
                           const double2 *A, int lda, const double2 *B, int ldb, double2 beta,
-                          double2 *C, int ldc, bool lower_only, GemmSmem &sm,
-                          int flip_col = 0x7fffffff) {
+                          double2 *C, int ldc, bool lower_only, GemmSmem &sm) {
   const int tid = threadIdx.x;
   // FP64 matrix cores: v_mfma_f64_16x16x4f64 computes D(16x16) += A(16x4) B(4x16)
   // with A[i][k] in lane i + 16k, B[k][j] in lane j + 16k and D[i][j] in
@@ -161,7 +178,6 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int 
         if (r < m && c < n && (!lower_only || c <= r)) {
           double2 *p = &C[r + (int64_t)c * ldc];
           double2 v = cmul(alpha, mk(acc_re[i][j][e], acc_im[i][j][e]));
-          if (c >= flip_col) v = mk(-v.x, -v.y);
           if (use_beta) v = cfma(beta, *p, v);
           *p = v;
         }
@@ -305,38 +321,39 @@ __global__ __launch_bounds__(NT) void k_potrf_panel(double2 *base, const PotrfIt
                                                     const int *info, int k0, int kend,
                                                     const double2 *work, int wslots) {
   __shared__ GemmSmem sm;
-  const PotrfItem it = items[blockIdx.y];
+  int bx, by;
+  xcd_remap(bx, by);
+  const PotrfItem it = items[by];
   const int n = it.n, lda = it.lda;
   const int kb = min(NB, min(kend, n) - k0);
-  if (kb <= 0 || info[blockIdx.y] != 0) return;
-  const int m = n - (k0 + kb), r0 = blockIdx.x * TM;
+  if (kb <= 0 || info[by] != 0) return;
+  const int m = n - (k0 + kb), r0 = bx * TM;
   if (r0 >= m) return;
   double2 *P = base + it.a + (k0 + kb) + (int64_t)k0 * lda;
-  const double2 *W = work + ((int64_t)blockIdx.y * wslots + k0 / NB) * NB * NB;
+  const double2 *W = work + ((int64_t)by * wslots + k0 / NB) * NB * NB;
   gemm_tile<OP_N, OP_C>(m, kb, kb, 0, r0, 0, mk(1.0, 0.0), P, lda, W, NB, mk(0.0, 0.0), P, lda,
                         false, sm);
 }
 
 // Update C[r, c] -= sum_{k in [k_lo, k_hi)} A[r, k] conj(A[c, k]) for
-// c in [c_lo, c_hi), r >= c (lower triangle only); columns c >= neg_from take
-// the opposite sign when k_hi <= neg_from.
+// c in [c_lo, c_hi), r >= c (lower triangle only).
 __global__ __launch_bounds__(NT) void k_potrf_update(double2 *base, const PotrfItem *items,
                                                      const int *info, int k_lo, int k_hi,
-                                                     int c_lo, int c_hi, int tiles_c,
-                                                     int neg_from) {
+                                                     int c_lo, int c_hi, int tiles_c) {
   __shared__ GemmSmem sm;
-  const PotrfItem it = items[blockIdx.y];
+  int bx, by;
+  xcd_remap(bx, by);
+  const PotrfItem it = items[by];
   const int n = it.n, lda = it.lda;
   const int m = n - c_lo, nc = min(c_hi, n) - c_lo, kw = min(k_hi, n) - k_lo;
-  if (m <= 0 || nc <= 0 || kw <= 0 || info[blockIdx.y] != 0) return;
-  const int ti = blockIdx.x / tiles_c, tj = blockIdx.x % tiles_c;
+  if (m <= 0 || nc <= 0 || kw <= 0 || info[by] != 0) return;
+  const int ti = bx / tiles_c, tj = bx % tiles_c;
   if (ti * TM >= m || tj * TN >= nc || ti < tj) return;
   double2 *A = base + it.a;
   const double2 *P = A + c_lo + (int64_t)k_lo * lda;
   double2 *C = A + c_lo + (int64_t)c_lo * lda;
-  const int flip = k_hi <= neg_from ? max(neg_from - c_lo, 0) : 0x7fffffff;
   gemm_tile<OP_N, OP_C>(m, nc, kw, 0, ti * TM, tj * TN, mk(-1.0, 0.0), P, lda, P, lda,
-                        mk(1.0, 0.0), C, lda, ti == tj, sm, flip);
+                        mk(1.0, 0.0), C, lda, ti == tj, sm);
 }
 
 // ---- triangular solve -------------------------------------------------------------
@@ -369,14 +386,16 @@ __global__ __launch_bounds__(NT) void k_trsm_solve(double2 *bbase, const TrsmIte
                                                    int kend, int tri, const double2 *work,
                                                    int wslots) {
   __shared__ GemmSmem sm;
-  const TrsmItem it = items[blockIdx.y];
+  int bx, by;
+  xcd_remap(bx, by);
+  const TrsmItem it = items[by];
   const int kb = min(NB, min(kend, it.n) - k0);
   if (kb <= 0) return;
   const int ncols = tri ? min(it.ncols, k0 + kb) : it.ncols;
-  const int c0 = blockIdx.x * TN;
+  const int c0 = bx * TN;
   if (c0 >= ncols) return;
   double2 *Bk = bbase + it.b + k0;
-  const double2 *W = work + ((int64_t)blockIdx.y * wslots + k0 / NB) * NB * NB;
+  const double2 *W = work + ((int64_t)by * wslots + k0 / NB) * NB * NB;
   gemm_tile<OP_N, OP_N>(kb, ncols, kb, 0, 0, c0, mk(1.0, 0.0), W, NB, Bk, it.ldb, mk(0.0, 0.0),
                         Bk, it.ldb, false, sm);
 }
@@ -387,12 +406,14 @@ __global__ __launch_bounds__(NT) void k_trsm_update(const double2 *lbase, double
                                                     const TrsmItem *items, int k_lo, int k_hi,
                                                     int r_lo, int r_hi, int tri, int tiles_c) {
   __shared__ GemmSmem sm;
-  const TrsmItem it = items[blockIdx.y];
+  int bx, by;
+  xcd_remap(bx, by);
+  const TrsmItem it = items[by];
   const int n = it.n;
   const int m = min(r_hi, n) - r_lo, kw = min(k_hi, n) - k_lo;
   if (m <= 0 || kw <= 0) return;
   const int ncols = tri ? min(it.ncols, k_hi) : it.ncols;
-  const int ti = blockIdx.x / tiles_c, tj = blockIdx.x % tiles_c;
+  const int ti = bx / tiles_c, tj = bx % tiles_c;
   if (ti * TM >= m || tj * TN >= ncols) return;
   const double2 *L = lbase + it.l;
   double2 *B = bbase + it.b;
@@ -408,8 +429,10 @@ __global__ __launch_bounds__(NT) void k_gemm(double2 alpha, const double2 *abase
                                              const double2 *bbase, double2 beta, double2 *cbase,
                                              const GemmItem *items, int tiles_n, int mode) {
   __shared__ GemmSmem sm;
-  const GemmItem it = items[blockIdx.y];
-  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  int bx, by;
+  xcd_remap(bx, by);
+  const GemmItem it = items[by];
+  const int tm = bx / tiles_n, tn = bx % tiles_n;
   const int r0 = tm * TM, c0 = tn * TN;
   if (r0 >= it.m || c0 >= it.n) return;
   int kb = 0;
@@ -437,9 +460,9 @@ int64_t dense_work_size(int nitems, int nmax) {
 }
 
 void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *info_dev, int nmax,
-                   double2 *work, hipStream_t s, int kstop, int neg_from) {
+                   double2 *work, hipStream_t s) {
   if (nitems <= 0 || nmax <= 0) return;
-  const int kmax = std::min(kstop, nmax);
+  const int kmax = nmax;
   const int wslots = (int)cdiv(nmax, NB);
   HIP_OK(hipMemsetAsync(info_dev, 0, nitems * sizeof(int), s));
   for (int K0 = 0; K0 < kmax; K0 += NBO) {
@@ -457,14 +480,14 @@ void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *i
       if (c_lo < c_hi) {
         const int tr = (int)cdiv(nmax - c_lo, TM), tc = (int)cdiv(c_hi - c_lo, TN);
         hipLaunchKernelGGL(k_potrf_update, dim3(tr * tc, nitems), dim3(NT), 0, s, base,
-                           items_dev, info_dev, k0, k0 + kb, c_lo, c_hi, tc, neg_from);
+                           items_dev, info_dev, k0, k0 + kb, c_lo, c_hi, tc);
       }
     }
     // block update of the trailing matrix
     if (K1 < nmax) {
       const int t = (int)cdiv(nmax - K1, TM);
       hipLaunchKernelGGL(k_potrf_update, dim3(t * t, nitems), dim3(NT), 0, s, base, items_dev,
-                         info_dev, K0, K1, K1, nmax, t, neg_from);
+                         info_dev, K0, K1, K1, nmax, t);
     }
   }
   LAUNCH_OK();

@@ -28,15 +28,9 @@ int64_t dense_work_size(int nitems, int nmax);
 
 // In-place lower Cholesky A = L L^H of every item (upper triangle untouched).
 // info[item] = 0 on success, j+1 if pivot j was not positive.  nmax = largest n.
-// With kstop < n only the first kstop columns are factored and the trailing
-// block is left as the Schur complement.  Columns c >= neg_from receive the
-// updates from columns k < neg_from with the opposite sign (a factorisation
-// of diag(I, -I)-signed systems: trailing blocks that start at zero then hold
-// +B^H A^-1 B instead of its negative).  On return the work area holds the
-// inverse of every diagonal block that was factored.
+// On return the work area holds the inverse of every diagonal block.
 void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *info_dev, int nmax,
-                   double2 *work, hipStream_t s, int kstop = 0x7fffffff,
-                   int neg_from = 0x7fffffff);
+                   double2 *work, hipStream_t s);
 
 // B <- L^-1 B for every item (L lower, from a Cholesky factor).  With
 // identity_rhs, B must hold the identity and only the lower-triangular part
