@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
-FP64_PEAK_TFLOPS = 78.6      # 256 CU x 2.4 GHz x 128 FP64 flop/clk (vector = matrix peak)
+FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 matrix (= vector) peak
 FP32_PEAK_TFLOPS = 157.3
 
 
@@ -41,26 +41,75 @@ def loads_of(w):
     return [dict(dir=w.direction, amp=1.0)]
 
 
-def roofline_for(stats, precision):
-    """Roofline object for the kernel class with the largest total time."""
+# Classes timed around exactly one kernel symbol; the composite dense classes
+# (potrf, trsm, gemm) each cover several kernels and are reported separately.
+SINGLE_KERNEL = ("apply64", "apply32", "gram", "bmat", "load", "macro_asm", "patch_gather")
+DENSE = ("potrf", "trsm", "gemm")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def source_digest(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(symbol, workload):
+    """HBM bytes per launch of `symbol` from the recorded PMC runs, or None if
+    none were recorded for this workload or the kernel source changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(symbol)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("workload") != workload:
+        return None
+    if source_digest(os.path.join(ROOT, rec["source"])) != rec["source_sha256_16"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
+def roofline_for(stats, workload):
+    """Roofline object for the single kernel with the largest total time."""
     from paper_2304_01728_amd import dpgmg as D
-    cls, (n, ms, work) = max(stats.items(), key=lambda kv: kv[1][1])
+    single = {k: v for k, v in stats.items() if k in SINGLE_KERNEL}
+    cls, (n, ms, work) = max(single.items(), key=lambda kv: kv[1][1])
+    sym = D.KERNEL_SYMBOLS.get(cls, cls)
     avg_ms = ms / n
     if cls in ("apply64", "apply32"):
         achieved = work / n / (avg_ms * 1e-3) / 1e9
-        return {"kernel": D.KERNEL_SYMBOLS.get(cls, cls), "bound": "hbm", "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": None, "launches": n, "avg_ms": avg_ms,
+        return {"kernel": sym, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(sym, workload), "launches": n, "avg_ms": avg_ms,
                 "work_per_launch": work / n}
-    if work > 0:
-        achieved = work / n / (avg_ms * 1e-3) / 1e12
-        return {"kernel": D.KERNEL_SYMBOLS.get(cls, cls), "bound": "alu", "achieved": achieved,
-                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                "traffic": None, "launches": n, "avg_ms": avg_ms,
-                "work_per_launch": work / n}
-    return {"kernel": D.KERNEL_SYMBOLS.get(cls, cls), "bound": "hbm", "achieved": None,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None, "traffic": None,
-            "launches": n, "avg_ms": avg_ms}
+    return {"kernel": sym, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": None, "traffic": None, "launches": n, "avg_ms": avg_ms}
+
+
+def roofline_setup(stats):
+    """The dense setup routines (several kernels each) against the FP64 MFMA peak."""
+    out = {}
+    for cls in DENSE:
+        if cls in stats and stats[cls][2] > 0:
+            n, ms, work = stats[cls]
+            a = work / (ms * 1e-3) / 1e12
+            out[cls] = {"bound": "mfma", "achieved": a, "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": a / FP64_PEAK_TFLOPS, "ms": ms,
+                        "launches": n}
+    return out
+
+
+def calibrate_copy():
+    """A plain device copy of known size, for scaling HBM counters."""
+    import torch
+    nbytes = 1 << 30
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                      "launches": 3}), flush=True)
 
 
 def cpu_baseline(w, iters):
@@ -151,11 +200,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="plane_wave_16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(how it would shard is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     import torch
     from paper_2304_01728_amd import dpgmg as D
@@ -230,16 +284,10 @@ def main():
         "phases_ms": {k: 1e3 * v / args.steps for k, v in phase.items()},
         "setup_topology_ms": 1e3 * setup_s,
         "resident_GB": info.resident_bytes / 1e9,
-        "roofline": roofline_for(stats, w.precision),
+        "roofline": roofline_for(stats, w.name),
+        "roofline_setup": roofline_setup(stats),
         "kernels": {k: {"launches": n, "ms": ms, "work": wk} for k, (n, ms, wk) in stats.items()},
     }
-    if "apply64" in stats or "apply32" in stats:
-        k = "apply64" if "apply64" in stats else "apply32"
-        n, ms, wk = stats[k]
-        out["roofline_apply"] = {"kernel": D.KERNEL_SYMBOLS[k], "bound": "hbm",
-                                 "achieved": wk / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                                 "unit": "GB/s", "frac": wk / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                 "traffic": None}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, int(round(iters_per_step)))
     ctx.close()
