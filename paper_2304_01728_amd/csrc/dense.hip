@@ -186,40 +186,52 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int 
 
 // ---- diagonal blocks -------------------------------------------------------------
 
-// Each thread owns up to kQ entries (i, c), c <= i, of a 64x64 lower triangle,
-// numbered row by row: entry e sits at i(i+1)/2 + c.
-constexpr int kQ = (NB * (NB + 1) / 2 + NT - 1) / NT;
+// A 64x64 lower triangle in registers of 512 threads.  Rows i and 63 - i form
+// a pair with 65 entries, numbered (i, 0..i) then (63 - i, 0..63 - i); the 16
+// threads of pair p = t / 16 own entries t % 16 + 16 m, m < kQ.
+constexpr int NTD = 512, kQ = 5;
 
-__device__ __forceinline__ void tri_index(int e, int &i, int &c) {
-  i = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
-  while ((i + 1) * (i + 2) / 2 <= e) ++i;
-  while (i * (i + 1) / 2 > e) --i;
-  c = e - i * (i + 1) / 2;
+struct Slot { int i, c; bool on; };
+
+__device__ __forceinline__ Slot slot_of(int m, int kb) {
+  const int p = threadIdx.x >> 4, e = (threadIdx.x & 15) + 16 * m;
+  Slot s;
+  if (e <= p) { s.i = p; s.c = e; }
+  else { s.i = NB - 1 - p; s.c = e - p - 1; }
+  s.on = e <= NB && s.i < kb;   // e < 65 entries; c <= i < kb then holds
+  return s;
 }
 
-// Elimination of a kb x kb diagonal block held in registers (entries owned as
-// above), applied at the same time to an identity block so that it also
-// yields the inverse factor.  Step j broadcasts column j of the current
-// Schur complement and row j of the transformed identity through LDS (double
-// buffered, one barrier per step); the multiplier of row i is a_ij / a_jj.
+// Elimination of a kb x kb diagonal block held in registers, applied at the
+// same time to an identity block so that it also yields the inverse factor.
+// Step j broadcasts column j of the current Schur complement and row j of the
+// transformed identity through LDS (double buffered, one barrier per step);
+// the multiplier of row i is a_ij / a_jj.  The update reads every operand and
+// masks with zero multipliers instead of branching.
 // FACTOR: a holds the block of A; it is eliminated (square-root free, the
 //   pivots d_j stay on the diagonal) and L = a_ic / sqrt(d_c), L^-1 = x / sqrt(d_i).
 // otherwise: a holds a lower triangular factor L (left unchanged) and the
 //   identity becomes L~^-1 with L~ = L diag(L)^-1, so L^-1 = x / l_ii.
 // scale[i] receives sqrt(d_i) or l_ii; the return value is 1 + the first
-// pivot that was not positive, or 0.
+// pivot that was not positive, or 0.  All NTD threads must call it.
 template <bool FACTOR>
-__device__ int eliminate(double2 a[kQ], double2 x[kQ], const int ii[kQ], const int cc[kQ], int kb,
-                         double2 (*cb)[NB], double2 (*rb)[NB], double *scale) {
-  const int tid = threadIdx.x;
+__device__ int eliminate(double2 a[kQ], double2 x[kQ], int kb, double2 (*cb)[NB],
+                         double2 (*rb)[NB], double *scale) {
+  const int tid = threadIdx.x, p = tid >> 4;
   __shared__ int fail;
   if (tid == 0) fail = 0;
+  for (int e = tid; e < 2 * NB; e += NTD) {
+    cb[e / NB][e % NB] = mk(0.0, 0.0);
+    rb[e / NB][e % NB] = mk(0.0, 0.0);
+  }
+  __syncthreads();
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    if (ii[q] < 0) continue;
-    if (cc[q] == 0) cb[0][ii[q]] = a[q];
-    if (ii[q] == 0) rb[0][cc[q]] = x[q];
-    if (!FACTOR && ii[q] == cc[q]) scale[ii[q]] = a[q].x;
+  for (int m = 0; m < kQ; ++m) {
+    const Slot sl = slot_of(m, kb);
+    if (!sl.on) continue;
+    if (sl.c == 0) cb[0][sl.i] = a[m];
+    if (sl.i == 0) rb[0][0] = x[m];
+    if (!FACTOR && sl.i == sl.c) scale[sl.i] = a[m].x;
   }
   __syncthreads();
   for (int j = 0; j < kb; ++j) {
@@ -230,20 +242,31 @@ __device__ int eliminate(double2 a[kQ], double2 x[kQ], const int ii[kQ], const i
       scale[j] = d > 0.0 ? sqrt(d) : 1.0;
       if (!(d > 0.0) && !fail) fail = j + 1;
     }
+    const double2 m_lo = cscale(cb[u][p], inv), m_hi = cscale(cb[u][NB - 1 - p], inv);
+    double2 cv[kQ], rv[kQ];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      const int i = ii[q], c = cc[q];
-      if (i <= j) continue;
-      const double2 mi = cscale(cb[u][i], inv);
-      if (FACTOR && c > j) a[q] = csub(a[q], cmul(mi, cconj(cb[u][c])));
-      else if (c <= j) x[q] = csub(x[q], cmul(mi, rb[u][c]));
+    for (int m = 0; m < kQ; ++m) {
+      const Slot sl = slot_of(m, kb);
+      cv[m] = cb[u][sl.c & (NB - 1)];
+      rv[m] = rb[u][sl.c & (NB - 1)];
+    }
+#pragma unroll
+    for (int m = 0; m < kQ; ++m) {
+      const Slot sl = slot_of(m, kb);
+      const bool live = sl.on && sl.i > j;
+      const double2 mi = live ? (sl.i == p ? m_lo : m_hi) : mk(0.0, 0.0);
+      const double2 v = sl.c > j ? cconj(cv[m]) : rv[m];
+      const double2 pr = cmul(mi, v);
+      if (FACTOR) a[m] = csub(a[m], sl.c > j ? pr : mk(0.0, 0.0));
+      x[m] = csub(x[m], sl.c <= j ? pr : mk(0.0, 0.0));
     }
     if (j + 1 < kb) {
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) {
-        if (ii[q] < 0) continue;
-        if (cc[q] == j + 1) cb[u ^ 1][ii[q]] = a[q];
-        if (ii[q] == j + 1) rb[u ^ 1][cc[q]] = x[q];
+      for (int m = 0; m < kQ; ++m) {
+        const Slot sl = slot_of(m, kb);
+        if (!sl.on) continue;
+        if (sl.c == j + 1) cb[u ^ 1][sl.i] = a[m];
+        if (sl.i == j + 1) rb[u ^ 1][sl.c] = x[m];
       }
     }
     __syncthreads();
@@ -252,29 +275,29 @@ __device__ int eliminate(double2 a[kQ], double2 x[kQ], const int ii[kQ], const i
 }
 
 // Write L^-1 (x / scale[i]) zero-padded to 64 x 64, column-major, to w.
-__device__ void store_inverse(const double2 x[kQ], const int ii[kQ], const int cc[kQ], int kb,
-                              const double *scale, double2 *w) {
+__device__ void store_inverse(const double2 x[kQ], int kb, const double *scale, double2 *w) {
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const int i = ii[q], c = cc[q];
-    if (i < 0) continue;
-    w[i + c * NB] = cscale(x[q], 1.0 / scale[i]);
-    if (c < i) w[c + i * NB] = mk(0.0, 0.0);
+  for (int m = 0; m < kQ; ++m) {
+    const Slot sl = slot_of(m, kb);
+    if (!sl.on) continue;
+    w[sl.i + sl.c * NB] = cscale(x[m], 1.0 / scale[sl.i]);
+    if (sl.c < sl.i) w[sl.c + sl.i * NB] = mk(0.0, 0.0);
   }
-  for (int e = threadIdx.x; e < NB * NB; e += NT) {
+  for (int e = threadIdx.x; e < NB * NB; e += NTD) {
     const int i = e % NB, c = e / NB;
     if (i >= kb || c >= kb) w[e] = mk(0.0, 0.0);
   }
 }
 
-// Owned entries of a kb x kb lower triangle (index -1: none).
-__device__ __forceinline__ void own_entries(int kb, int ii[kQ], int cc[kQ]) {
+// Owned entries of a kb x kb lower triangle from column-major X (ld ldx);
+// x becomes the identity's share.
+__device__ __forceinline__ void load_block(const double2 *X, int ldx, int kb, double2 a[kQ],
+                                           double2 x[kQ]) {
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const int e = threadIdx.x + NT * q;
-    ii[q] = -1;
-    cc[q] = 0;
-    if (e < kb * (kb + 1) / 2) tri_index(e, ii[q], cc[q]);
+  for (int m = 0; m < kQ; ++m) {
+    const Slot sl = slot_of(m, kb);
+    a[m] = sl.on ? X[sl.i + (int64_t)sl.c * ldx] : mk(0.0, 0.0);
+    x[m] = mk(sl.on && sl.c == sl.i ? 1.0 : 0.0, 0.0);
   }
 }
 
@@ -283,9 +306,9 @@ __device__ __forceinline__ void own_entries(int kb, int ii[kQ], int cc[kQ]) {
 // Factor the diagonal block [k0, k0+kb) of every item, write L_kk back and
 // L_kk^-1 to the work area (slot k0 / 64 of the item).  A pivot that is not
 // positive marks the item as failed.
-__global__ __launch_bounds__(NT) void k_potrf_diag(double2 *base, const PotrfItem *items,
-                                                   int *info, int k0, int kend, double2 *work,
-                                                   int wslots) {
+__global__ __launch_bounds__(NTD) void k_potrf_diag(double2 *base, const PotrfItem *items,
+                                                    int *info, int k0, int kend, double2 *work,
+                                                    int wslots) {
   __shared__ double2 cb[2][NB], rb[2][NB];
   __shared__ double scale[NB];
   const PotrfItem it = items[blockIdx.x];
@@ -293,26 +316,21 @@ __global__ __launch_bounds__(NT) void k_potrf_diag(double2 *base, const PotrfIte
   const int kb = min(NB, min(kend, n) - k0);
   if (kb <= 0 || info[blockIdx.x] != 0) return;
   double2 *A = base + it.a + k0 + (int64_t)k0 * lda;
-  int ii[kQ], cc[kQ];
   double2 a[kQ], x[kQ];
-  own_entries(kb, ii, cc);
-#pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    a[q] = ii[q] >= 0 ? A[ii[q] + (int64_t)cc[q] * lda] : mk(0.0, 0.0);
-    x[q] = mk(ii[q] >= 0 && ii[q] == cc[q] ? 1.0 : 0.0, 0.0);
-  }
-  const int f = eliminate<true>(a, x, ii, cc, kb, cb, rb, scale);
+  load_block(A, lda, kb, a, x);
+  const int f = eliminate<true>(a, x, kb, cb, rb, scale);
   if (f) {
     if (threadIdx.x == 0) info[blockIdx.x] = k0 + f;
     return;
   }
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const int i = ii[q], c = cc[q];
-    if (i < 0) continue;
-    A[i + (int64_t)c * lda] = i == c ? mk(scale[i], 0.0) : cscale(a[q], 1.0 / scale[c]);
+  for (int m = 0; m < kQ; ++m) {
+    const Slot sl = slot_of(m, kb);
+    if (!sl.on) continue;
+    A[sl.i + (int64_t)sl.c * lda] =
+        sl.i == sl.c ? mk(scale[sl.i], 0.0) : cscale(a[m], 1.0 / scale[sl.c]);
   }
-  store_inverse(x, ii, cc, kb, scale, work + ((int64_t)blockIdx.x * wslots + k0 / NB) * NB * NB);
+  store_inverse(x, kb, scale, work + ((int64_t)blockIdx.x * wslots + k0 / NB) * NB * NB);
 }
 
 // Panel below the diagonal block: X = A_panel L_kk^-H as a product with the
@@ -359,7 +377,7 @@ __global__ __launch_bounds__(NT) void k_potrf_update(double2 *base, const PotrfI
 // ---- triangular solve -------------------------------------------------------------
 
 // Inverse of every diagonal block of L (all blocks at once: L is final).
-__global__ __launch_bounds__(NT) void k_trsm_inv(const double2 *lbase, const TrsmItem *items,
+__global__ __launch_bounds__(NTD) void k_trsm_inv(const double2 *lbase, const TrsmItem *items,
                                                  double2 *work, int wslots) {
   __shared__ double2 cb[2][NB], rb[2][NB];
   __shared__ double scale[NB];
@@ -367,17 +385,10 @@ __global__ __launch_bounds__(NT) void k_trsm_inv(const double2 *lbase, const Trs
   const int k0 = blockIdx.x * NB;
   const int kb = min(NB, it.n - k0);
   if (kb <= 0) return;
-  const double2 *L = lbase + it.l + k0 + (int64_t)k0 * it.ldl;
-  int ii[kQ], cc[kQ];
   double2 a[kQ], x[kQ];
-  own_entries(kb, ii, cc);
-#pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    a[q] = ii[q] >= 0 ? L[ii[q] + (int64_t)cc[q] * it.ldl] : mk(0.0, 0.0);
-    x[q] = mk(ii[q] >= 0 && ii[q] == cc[q] ? 1.0 : 0.0, 0.0);
-  }
-  eliminate<false>(a, x, ii, cc, kb, cb, rb, scale);
-  store_inverse(x, ii, cc, kb, scale, work + ((int64_t)blockIdx.y * wslots + blockIdx.x) * NB * NB);
+  load_block(lbase + it.l + k0 + (int64_t)k0 * it.ldl, it.ldl, kb, a, x);
+  eliminate<false>(a, x, kb, cb, rb, scale);
+  store_inverse(x, kb, scale, work + ((int64_t)blockIdx.y * wslots + blockIdx.x) * NB * NB);
 }
 
 // Rows [k0, k0+kb) of B: X_k = L_kk^-1 B_k, one 64-column tile per workgroup,
@@ -469,7 +480,7 @@ void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *i
     const int K1 = std::min(K0 + NBO, kmax);
     for (int k0 = K0; k0 < K1; k0 += NB) {
       const int kb = std::min(NB, K1 - k0);
-      hipLaunchKernelGGL(k_potrf_diag, dim3(nitems), dim3(NT), 0, s, base, items_dev, info_dev, k0,
+      hipLaunchKernelGGL(k_potrf_diag, dim3(nitems), dim3(NTD), 0, s, base, items_dev, info_dev, k0,
                          K1, work, wslots);
       const int rows = nmax - k0 - kb;
       if (rows <= 0) continue;
@@ -500,7 +511,7 @@ void trsm_batched(const double2 *lbase, double2 *bbase, const TrsmItem *items_de
   const int tri = identity_rhs ? 1 : 0;
   const int wslots = (int)cdiv(max_n, NB);
   if (!inverses_ready)
-    hipLaunchKernelGGL(k_trsm_inv, dim3(wslots, nitems), dim3(NT), 0, s, lbase, items_dev, work,
+    hipLaunchKernelGGL(k_trsm_inv, dim3(wslots, nitems), dim3(NTD), 0, s, lbase, items_dev, work,
                        wslots);
   for (int K0 = 0; K0 < max_n; K0 += NBO) {
     const int K1 = std::min(K0 + NBO, max_n);
