@@ -61,7 +61,8 @@ enum {
 };
 
 enum { DPG_FP64 = 0, DPG_MIXED = 1 };       /* dpg_options.precision          */
-enum { DPG_DEVICE_PTRS = 1 };               /* dpg_options.flags              */
+enum { DPG_DEVICE_PTRS = 1,                 /* dpg_options.flags              */
+       DPG_COLUMNWISE = 2 };                 /* solve nrhs > 1 column by column */
 
 /* Uniform mesh of the cube [origin, origin + side]^3 into n^3 equal boxes;
  * element e = i + n (j + n k). */
@@ -97,7 +98,7 @@ typedef struct {
   int32_t nu_post;
   int32_t nlevels;    /* 0: halve while n is even and n > 2 (n = 2: once)    */
   int32_t maxit;      /* outer CG iteration cap                              */
-  int32_t flags;      /* DPG_DEVICE_PTRS                                     */
+  int32_t flags;      /* DPG_DEVICE_PTRS | DPG_COLUMNWISE                    */
   double theta;       /* smoother damping; must be < 1/4                     */
   int64_t hbm_budget; /* bytes the context may allocate; 0 = no limit        */
   void *stream;       /* hipStream_t to launch on; NULL = default stream     */
@@ -142,7 +143,12 @@ int dpg_load_rhs(dpg_ctx *ctx, const dpg_load *loads, int nrhs, double *s_out);
  * condensed unknowns.  Outputs: x (n_trace x nrhs, canonical order),
  * iteration counts and final relative residuals (nrhs each; any may be
  * NULL).  Returns DPG_ENOCONV if some column hit maxit (its x is the last
- * iterate). */
+ * iterate).  With nrhs > 1 the columns are solved together, up to 32 at a
+ * time (multi-right-hand-side forms: every stored block streamed once per
+ * application for all columns, one V-cycle per iteration for all columns,
+ * per-column CG scalars; a converged column stops updating while the others
+ * continue); DPG_COLUMNWISE in the options' flags solves them one by one
+ * instead.  Both give each column the same iterates up to rounding. */
 int dpg_solve(dpg_ctx *ctx, const double *rhs, int nrhs, double tol, double *x_out,
               int32_t *iters_out, double *relres_out);
 

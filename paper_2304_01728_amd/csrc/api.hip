@@ -612,6 +612,218 @@ int solve_one(dpg_ctx *c, const double2 *sv, double tol, double2 *xout, int32_t 
   return status;
 }
 
+// ---- multi-right-hand-side solve -------------------------------------------------------------
+
+template <typename T> struct LBB;
+template <> struct LBB<double> {
+  static double2 *r(LevelData &f) { return f.br64.p; }
+  static double2 *x(LevelData &f) { return f.bx64.p; }
+  static double2 *res(LevelData &f) { return f.bres64.p; }
+  static double2 *rc(LevelData &f) { return f.brc64.p; }
+  static double2 *ec(LevelData &f) { return f.bec64.p; }
+  static double2 *cc(LevelData &f) { return f.bc64.p; }
+};
+template <> struct LBB<float> {
+  static float2 *r(LevelData &f) { return f.br32.p; }
+  static float2 *x(LevelData &f) { return f.bx32.p; }
+  static float2 *res(LevelData &f) { return f.bres32.p; }
+  static float2 *rc(LevelData &f) { return f.brc32.p; }
+  static float2 *ec(LevelData &f) { return f.bec32.p; }
+  static float2 *cc(LevelData &f) { return f.bc32.p; }
+};
+
+// Block work vectors for nr columns on every level (same shapes as the
+// single-column ones, times nr).
+void ensure_block(dpg_ctx *c, int nr) {
+  if (nr <= c->bcap) return;
+  const bool mixed = c->opt.precision == DPG_MIXED;
+  Budget *bd = &c->bud;
+  for (int l = 1; l <= c->L; ++l) {
+    LevelData &f = c->lv[l];
+    const int64_t nc = c->lv[l - 1].num.n, nM = f.nM, ncb = (int64_t)f.nblk * f.nBf;
+    if (mixed) {
+      f.br32.alloc(nM * nr, bd);
+      f.bx32.alloc(nM * nr, bd);
+      f.bres32.alloc(nM * nr, bd);
+      f.brc32.alloc(nc * nr, bd);
+      f.bec32.alloc(nc * nr, bd);
+      f.bc32.alloc(ncb * nr, bd);
+    } else {
+      f.br64.alloc(nM * nr, bd);
+      f.bx64.alloc(nM * nr, bd);
+      f.bres64.alloc(nM * nr, bd);
+      f.brc64.alloc(nc * nr, bd);
+      f.bec64.alloc(nc * nr, bd);
+    }
+    if (!mixed || l == c->L) f.bc64.alloc(ncb * nr, bd);
+    f.Mb.ensure(f.Mset, nr, f.Mset.t64.p != nullptr, f.Mset.t32.p != nullptr, bd);
+    f.Sb.ensure(f.Sset, nr, f.Sset.t64.p != nullptr, f.Sset.t32.p != nullptr, bd);
+    f.bcap = nr;
+  }
+  c->T0b.ensure(c->T0set, nr, c->T0set.t64.p != nullptr, c->T0set.t32.p != nullptr, bd);
+  LevelData &top = c->lv[c->L];
+  const int64_t nM = top.nM, nT = top.num.n;
+  for (auto *v : {&c->bb, &c->bx, &c->br, &c->bz, &c->bzo, &c->bp, &c->bq}) v->alloc(nM * nr, bd);
+  for (auto *v : {&c->bsv, &c->bxf, &c->bcols}) v->alloc(nT * nr, bd);
+  c->bpartial.alloc(2LL * kColDotBlocks * kMaxCols, bd);
+  c->bsc.alloc(8 * kMaxCols, bd);
+  c->bact.alloc(kMaxCols, bd);
+  if (!c->host_bsc) {
+    HIP_OK(hipHostMalloc((void **)&c->host_bsc, 8 * kMaxCols * sizeof(double), 0));
+    HIP_OK(hipHostMalloc((void **)&c->host_bact, kMaxCols * sizeof(int), 0));
+  }
+  c->bcap = nr;
+}
+
+template <typename T> void vcycle_blk(dpg_ctx *c, int l, int nr) {
+  using B = LB<T>;
+  using BB = LBB<T>;
+  LevelData &f = c->lv[l];
+  const hipStream_t s = c->stream;
+  const T th = (T)c->opt.theta;
+  auto r = BB::r(f), x = BB::x(f), res = BB::res(f), rc = BB::rc(f), ec = BB::ec(f);
+  if (c->opt.nu_pre == 0) HIP_OK(hipMemsetAsync(x, 0, f.nM * nr * sizeof(*x), s));
+  for (int k = 0; k < c->opt.nu_pre; ++k) {
+    if (k == 0) {
+      herm_apply_blk<T>(f.Sset, f.Sb, r, x, nullptr, RED_SET_SCALED, th, nr, s);
+    } else {
+      herm_apply_blk<T>(f.Mset, f.Mb, x, res, r, RED_RESID, (T)0, nr, s);
+      herm_apply_blk<T>(f.Sset, f.Sb, res, x, nullptr, RED_AXPY, th, nr, s);
+    }
+  }
+  herm_apply_blk<T>(f.Mset, f.Mb, x, res, r, RED_RESID, (T)0, nr, s);
+  LevelData &g = c->lv[l - 1];
+  {
+    PROF(DPG_K_TRANSFER, 0);
+    launch_csr_blk<T>(g.num.n, f.Ptptr.p, f.Ptcol.p, B::Ptv(f), res, rc, 0, nr, s);
+  }
+  if (l - 1 == 0) {
+    herm_apply_blk<T>(c->T0set, c->T0b, rc, ec, nullptr, RED_SET, (T)1, nr, s);
+  } else {
+    {
+      PROF(DPG_K_CONDENSE, 0);
+      launch_condense_blk<T>(B::WH(g), g.nI, g.nBf, g.blkI.p, g.nblk, g.nM, g.macroB.p,
+                             g.cred_ptr.p, g.cred_ent.p, rc, BB::cc(g), BB::r(g), nr, s);
+    }
+    vcycle_blk<T>(c, l - 1, nr);
+    PROF(DPG_K_EXPAND, 0);
+    launch_expand_blk<T>(B::WH(g), B::Ti(g), g.nI, g.nBf, g.blkI.p, g.blkBm.p, g.nblk, rc,
+                         BB::x(g), g.nM, g.macroB.p, ec, nr, s);
+  }
+  {
+    PROF(DPG_K_TRANSFER, 0);
+    launch_csr_blk<T>(f.nM, f.Pptr.p, f.Pcol.p, B::Pv(f), ec, x, 1, nr, s);
+  }
+  for (int k = 0; k < c->opt.nu_post; ++k) {
+    herm_apply_blk<T>(f.Mset, f.Mb, x, res, r, RED_RESID, (T)0, nr, s);
+    herm_apply_blk<T>(f.Sset, f.Sb, res, x, nullptr, RED_AXPY, th, nr, s);
+  }
+}
+
+void precondition_blk(dpg_ctx *c, const double2 *r, double2 *z, int nr) {
+  LevelData &top = c->lv[c->L];
+  const hipStream_t s = c->stream;
+  const int64_t n = top.nM * nr;
+  if (c->opt.precision == DPG_MIXED) {
+    launch_to32(n, r, top.br32.p, s);
+    vcycle_blk<float>(c, c->L, nr);
+    launch_to64(n, top.bx32.p, z, s);
+  } else {
+    HIP_OK(hipMemcpyAsync(top.br64.p, r, n * 16, hipMemcpyDeviceToDevice, s));
+    vcycle_blk<double>(c, c->L, nr);
+    HIP_OK(hipMemcpyAsync(z, top.bx64.p, n * 16, hipMemcpyDeviceToDevice, s));
+  }
+}
+
+// PCG for nr <= kMaxCols right-hand sides at once: sv_cols holds the trace
+// loads column by column ([nr][n_trace], device); the full trace solutions go
+// to xcols likewise.  Each column runs its own CG recurrence (its own alpha
+// and beta); the operator and the V-cycle are applied to all columns of the
+// block together, and a column that reached tol keeps its iterate.
+int solve_block(dpg_ctx *c, const double2 *sv_cols, int nr, double tol, double2 *xcols,
+                int32_t *iters, double *relres) {
+  ensure_block(c, nr);
+  LevelData &top = c->lv[c->L];
+  const hipStream_t s = c->stream;
+  const int64_t nM = top.nM, nT = top.num.n;
+  double *S = c->host_bsc;
+  int *act = c->host_bact;
+  launch_interleave(nT, nr, sv_cols, c->bsv.p, s);
+  launch_condense_blk<double>(top.WH.p, top.nI, top.nBf, top.blkI.p, top.nblk, nM, top.macroB.p,
+                              top.cred_ptr.p, top.cred_ent.p, c->bsv.p, top.bc64.p, c->bb.p, nr,
+                              s);
+  HIP_OK(hipMemsetAsync(c->bsc.p, 0, 8 * kMaxCols * sizeof(double), s));
+  cgb_dot(nM, nr, c->bb.p, c->bb.p, c->bpartial.p, c->bsc.p, 5, s);
+  HIP_OK(hipMemsetAsync(c->bx.p, 0, nM * nr * 16, s));
+  HIP_OK(hipMemcpyAsync(c->br.p, c->bb.p, nM * nr * 16, hipMemcpyDeviceToDevice, s));
+  auto read_bsc = [&]() {
+    HIP_OK(hipMemcpyAsync(S, c->bsc.p, 8 * kMaxCols * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+  };
+  read_bsc();
+  std::vector<double> bb(nr), rr(nr, 0.0);
+  int nact = 0;
+  for (int k = 0; k < nr; ++k) {
+    bb[k] = S[5 * kMaxCols + k];
+    if (!std::isfinite(bb[k])) throw DpgError(DPG_EINVAL, "right-hand side is not finite");
+    act[k] = bb[k] > 0.0;
+    nact += act[k];
+    iters[k] = 0;
+    rr[k] = act[k] ? 1.0 : 0.0;
+  }
+  for (int k = nr; k < kMaxCols; ++k) act[k] = 0;
+  auto push_act = [&]() {
+    HIP_OK(hipMemcpyAsync(c->bact.p, act, kMaxCols * sizeof(int), hipMemcpyHostToDevice, s));
+  };
+  push_act();
+  int it = 0, status = DPG_OK;
+  if (nact > 0) {
+    double2 *z = c->bz.p, *zo = c->bzo.p;
+    precondition_blk(c, c->br.p, z, nr);
+    cgb_dot(nM, nr, c->br.p, z, c->bpartial.p, c->bsc.p, 0, s);
+    HIP_OK(hipMemcpyAsync(c->bp.p, z, nM * nr * 16, hipMemcpyDeviceToDevice, s));
+    while (it < c->opt.maxit) {
+      herm_apply_blk<double>(top.Mset, top.Mb, c->bp.p, c->bq.p, nullptr, RED_SET, 1.0, nr, s);
+      {
+        PROF(DPG_K_CG, 0);
+        cgb_alpha(nM, nr, c->bp.p, c->bq.p, c->bpartial.p, c->bsc.p, c->bact.p, s);
+        cgb_update_xr(nM, nr, c->bx.p, c->br.p, c->bp.p, c->bq.p, c->bpartial.p, c->bsc.p, s);
+      }
+      ++it;
+      read_bsc();
+      bool changed = false;
+      for (int k = 0; k < nr; ++k) {
+        if (!act[k]) continue;
+        if (S[6 * kMaxCols + k] != 0.0)
+          throw DpgError(DPG_EBREAKDOWN, "CG breakdown in column " + std::to_string(k) +
+                                             " at iteration " + std::to_string(it));
+        rr[k] = std::sqrt(S[4 * kMaxCols + k] / bb[k]);
+        if (!std::isfinite(rr[k])) throw DpgError(DPG_EBREAKDOWN, "residual is not finite");
+        iters[k] = it;
+        if (rr[k] <= tol) {
+          act[k] = 0;
+          --nact;
+          changed = true;
+        }
+      }
+      if (nact == 0) break;
+      if (changed) push_act();
+      std::swap(z, zo);
+      precondition_blk(c, c->br.p, z, nr);
+      PROF(DPG_K_CG, 0);
+      cgb_beta(nM, nr, c->br.p, z, zo, c->bpartial.p, c->bsc.p, c->bact.p, s);
+      cgb_update_p(nM, nr, c->bp.p, z, c->bsc.p, s);
+    }
+    if (nact > 0) status = DPG_ENOCONV;
+  }
+  launch_expand_blk<double>(top.WH.p, top.Tinv.p, top.nI, top.nBf, top.blkI.p, top.blkBm.p,
+                            top.nblk, c->bsv.p, c->bx.p, nM, top.macroB.p, c->bxf.p, nr, s);
+  launch_deinterleave(nT, nr, c->bxf.p, xcols, s);
+  HIP_OK(hipStreamSynchronize(s));
+  for (int k = 0; k < nr; ++k) relres[k] = rr[k];
+  return status;
+}
+
 template <typename V> int64_t put(const std::vector<V> &v, void *out, int64_t cap) {
   if (out && cap > 0) std::memcpy(out, v.data(), sizeof(V) * std::min<int64_t>(cap, (int64_t)v.size()));
   return (int64_t)v.size();
@@ -900,25 +1112,53 @@ int dpg_solve(dpg_ctx *c, const double *rhs, int nrhs, double tol, double *x_out
     const int64_t nT = top.num.n;
     const bool dev = c->opt.flags & DPG_DEVICE_PTRS;
     int status = DPG_OK;
-    for (int k = 0; k < nrhs; ++k) {
-      const double2 *sv;
-      if (rhs) {
-        HIP_OK(hipMemcpyAsync(c->sB.p, rhs + 2 * nT * k, nT * 16,
-                              dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
-        sv = c->sB.p;
-      } else {
-        sv = c->s_asm.p + nT * k;
+    if (nrhs > 1 && !(c->opt.flags & DPG_COLUMNWISE)) {
+      for (int k0 = 0; k0 < nrhs; k0 += kMaxCols) {
+        const int nr = std::min(kMaxCols, nrhs - k0);
+        ensure_block(c, nr);
+        const double2 *sv;
+        if (rhs) {
+          HIP_OK(hipMemcpyAsync(c->bcols.p, rhs + 2 * nT * k0, nT * nr * 16,
+                                dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+          sv = c->bcols.p;
+        } else {
+          sv = c->s_asm.p + nT * k0;
+        }
+        std::vector<int32_t> it(nr);
+        std::vector<double> rr(nr);
+        const int st = solve_block(c, sv, nr, tol, c->bcols.p, it.data(), rr.data());
+        if (st != DPG_OK) status = st;
+        for (int k = 0; k < nr; ++k) {
+          if (iters_out) iters_out[k0 + k] = it[k];
+          if (relres_out) relres_out[k0 + k] = rr[k];
+        }
+        if (x_out) {
+          HIP_OK(hipMemcpyAsync(x_out + 2 * nT * k0, c->bcols.p, nT * nr * 16,
+                                dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+          HIP_OK(hipStreamSynchronize(c->stream));
+        }
       }
-      int32_t it = 0;
-      double rr = 0;
-      const int st = solve_one(c, sv, tol, c->xfull.p, &it, &rr);
-      if (st != DPG_OK) status = st;
-      if (iters_out) iters_out[k] = it;
-      if (relres_out) relres_out[k] = rr;
-      if (x_out) {
-        HIP_OK(hipMemcpyAsync(x_out + 2 * nT * k, c->xfull.p, nT * 16,
-                              dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
-        HIP_OK(hipStreamSynchronize(c->stream));
+    } else {
+      for (int k = 0; k < nrhs; ++k) {
+        const double2 *sv;
+        if (rhs) {
+          HIP_OK(hipMemcpyAsync(c->sB.p, rhs + 2 * nT * k, nT * 16,
+                                dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+          sv = c->sB.p;
+        } else {
+          sv = c->s_asm.p + nT * k;
+        }
+        int32_t it = 0;
+        double rr = 0;
+        const int st = solve_one(c, sv, tol, c->xfull.p, &it, &rr);
+        if (st != DPG_OK) status = st;
+        if (iters_out) iters_out[k] = it;
+        if (relres_out) relres_out[k] = rr;
+        if (x_out) {
+          HIP_OK(hipMemcpyAsync(x_out + 2 * nT * k, c->xfull.p, nT * 16,
+                                dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+          HIP_OK(hipStreamSynchronize(c->stream));
+        }
       }
     }
     c->prof.flush();
@@ -1123,6 +1363,8 @@ int64_t dpg_export(const dpg_ctx *cc, int what, int level, void *out, int64_t ca
 void dpg_destroy(dpg_ctx *c) {
   if (!c) return;
   if (c->host_sc) (void)hipHostFree(c->host_sc);
+  if (c->host_bsc) (void)hipHostFree(c->host_bsc);
+  if (c->host_bact) (void)hipHostFree(c->host_bact);
   delete c;
 }
 

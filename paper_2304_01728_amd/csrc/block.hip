@@ -1,0 +1,546 @@
+// Multi-right-hand-side kernels (see block.hpp).
+#include <algorithm>
+
+#include "block.hpp"
+
+namespace dpg {
+namespace {
+
+constexpr int kBMaxI = 1024;   // interior unknowns per macro block (as the single path)
+constexpr int KC = 4;          // columns per workgroup in the condensation kernels
+
+template <typename C> __device__ inline C czero() {
+  C r;
+  r.x = 0;
+  r.y = 0;
+  return r;
+}
+
+// ---- Hermitian block sets ------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_blk(int64_t nloc, int nr,
+                                                    const int32_t *__restrict__ gidx,
+                                                    const cplx_t<T> *__restrict__ x,
+                                                    cplx_t<T> *__restrict__ xl) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nloc * nr) return;
+  const int64_t i = e / nr;
+  const int k = (int)(e % nr);
+  const int32_t g = gidx[i];
+  xl[e] = g >= 0 ? x[(int64_t)g * nr + k] : czero<cplx_t<T>>();
+}
+
+// One wave per (block b, tile row I): Y_I (32 x nr) = sum_J A_IJ X_J over the
+// stored upper tiles of row I (J >= I) and the conjugate transposes of the
+// stored tiles of column I (J < I), so no partial sums leave the wave.  Each
+// tile is staged in LDS in the orientation needed; lane (a, q) accumulates the
+// 4 x 4 panel rows 4a.., columns 4q.. in registers.
+template <typename T>
+__global__ __launch_bounds__(64) void k_rows_blk(const cplx_t<T> *__restrict__ tiles,
+                                                 const int2 *__restrict__ rows, int64_t nrows,
+                                                 const int32_t *__restrict__ bn,
+                                                 const int64_t *__restrict__ tile_off,
+                                                 const int64_t *__restrict__ loc_off,
+                                                 const cplx_t<T> *__restrict__ xl,
+                                                 cplx_t<T> *__restrict__ yl, int nr) {
+  using C = cplx_t<T>;
+  __shared__ C Ts[32][33];
+  __shared__ C Xs[32][kMaxCols + 1];
+  const int64_t w = blockIdx.x;
+  if (w >= nrows) return;
+  const int lane = threadIdx.x, a = lane >> 3, q = lane & 7;
+  const int2 bi = rows[w];
+  const int b = bi.x, I = bi.y;
+  const int nt = (bn[b] + 31) >> 5;
+  const C *xb = xl + loc_off[b] * nr;
+  C acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = czero<C>();
+  for (int J = 0; J < nt; ++J) {
+    const bool up = J >= I;
+    const int64_t tix = tile_off[b] + (up ? (int64_t)J * (J + 1) / 2 + I : (int64_t)I * (I + 1) / 2 + J);
+    const C *tp = tiles + tix * 1024 + lane;
+    C t[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t[k] = tp[k * 64];
+    for (int e = lane; e < 32 * nr; e += 64) Xs[e / nr][e % nr] = xb[(int64_t)32 * J * nr + e];
+    // the lane holds stored entries (4a + i, 4q + j) at k = 4i + j
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (up) Ts[4 * a + i][4 * q + j] = t[4 * i + j];
+        else Ts[4 * q + j][4 * a + i] = cconj(t[4 * i + j]);
+      }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int c = 0; c < 32; ++c) {
+      C ta[4], xv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ta[i] = Ts[4 * a + i][c];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xv[j] = Xs[c][4 * q + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = cfma(ta[i], xv[j], acc[i][j]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  C *yb = yl + (loc_off[b] + 32 * I) * nr;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (4 * q + j < nr) yb[(int64_t)(4 * a + i) * nr + 4 * q + j] = acc[i][j];
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_scatter_blk(int64_t nvec, int nr,
+                                                     const int32_t *__restrict__ red_ptr,
+                                                     const int32_t *__restrict__ red_ent,
+                                                     const cplx_t<T> *__restrict__ yl,
+                                                     const cplx_t<T> *__restrict__ r,
+                                                     cplx_t<T> *__restrict__ y, T theta) {
+  using C = cplx_t<T>;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nvec * nr) return;
+  const int64_t d = e / nr;
+  const int k = (int)(e % nr);
+  C acc = czero<C>();
+  for (int32_t j = red_ptr[d]; j < red_ptr[d + 1]; ++j)
+    acc = cadd(acc, yl[(int64_t)red_ent[j] * nr + k]);
+  if (MODE == RED_SET) y[e] = acc;
+  else if (MODE == RED_RESID) y[e] = csub(r[e], acc);
+  else if (MODE == RED_AXPY) y[e] = cadd(y[e], cscale(acc, theta));
+  else y[e] = cscale(acc, theta);
+}
+
+// ---- transfers and condensation ----------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_csr_blk(int64_t nrows, int nr,
+                                                 const int64_t *__restrict__ ptr,
+                                                 const int32_t *__restrict__ col,
+                                                 const T *__restrict__ val,
+                                                 const cplx_t<T> *__restrict__ x,
+                                                 cplx_t<T> *__restrict__ y, int add) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nrows * nr) return;
+  const int64_t i = e / nr;
+  const int k = (int)(e % nr);
+  cplx_t<T> acc = czero<cplx_t<T>>();
+  for (int64_t j = ptr[i]; j < ptr[i + 1]; ++j)
+    acc = cadd(acc, cscale(x[(int64_t)col[j] * nr + k], val[j]));
+  y[e] = add ? cadd(y[e], acc) : acc;
+}
+
+// c_b[sl, k] = sum_i WH_b[sl, i] rc[I_b(i), k] for the KC columns of blockIdx.y.
+template <typename T>
+__global__ __launch_bounds__(256) void k_condense_local_blk(const cplx_t<T> *__restrict__ WH,
+                                                            int nI, int nBf,
+                                                            const int32_t *__restrict__ blkI,
+                                                            const cplx_t<T> *__restrict__ rc,
+                                                            cplx_t<T> *__restrict__ c, int nr) {
+  using C = cplx_t<T>;
+  __shared__ C rI[kBMaxI][KC];
+  const int b = blockIdx.x, k0 = blockIdx.y * KC, kc = min(KC, nr - k0);
+  for (int e = threadIdx.x; e < nI * KC; e += 256) {
+    const int i = e / KC, k = e % KC;
+    rI[i][k] = k < kc ? rc[(int64_t)blkI[(int64_t)b * nI + i] * nr + k0 + k] : czero<C>();
+  }
+  __syncthreads();
+  const C *W = WH + (int64_t)b * nBf * nI;
+  for (int sl = threadIdx.x; sl < nBf; sl += 256) {
+    C acc[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) acc[k] = czero<C>();
+    for (int i = 0; i < nI; ++i) {
+      const C wv = W[sl + (int64_t)i * nBf];
+#pragma unroll
+      for (int k = 0; k < KC; ++k) acc[k] = cfma(wv, rI[i][k], acc[k]);
+    }
+    for (int k = 0; k < kc; ++k) c[((int64_t)b * nBf + sl) * nr + k0 + k] = acc[k];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_condense_reduce_blk(int64_t nM, int nr,
+                                                             const int64_t *__restrict__ macro_B,
+                                                             const int32_t *__restrict__ red_ptr,
+                                                             const int32_t *__restrict__ red_ent,
+                                                             const cplx_t<T> *__restrict__ rc,
+                                                             const cplx_t<T> *__restrict__ c,
+                                                             cplx_t<T> *__restrict__ rB) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nM * nr) return;
+  const int64_t m = e / nr;
+  const int k = (int)(e % nr);
+  cplx_t<T> acc = rc[macro_B[m] * nr + k];
+  for (int32_t j = red_ptr[m]; j < red_ptr[m + 1]; ++j)
+    acc = csub(acc, c[(int64_t)red_ent[j] * nr + k]);
+  rB[e] = acc;
+}
+
+template <typename C> __device__ inline C wave_sum_c(C v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o, 64);
+    v.y += __shfl_xor(v.y, o, 64);
+  }
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter_macro_blk(int64_t nM, int nr,
+                                                           const int64_t *__restrict__ macro_B,
+                                                           const cplx_t<T> *__restrict__ eB,
+                                                           cplx_t<T> *__restrict__ ec) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < nM * nr) ec[macro_B[e / nr] * nr + e % nr] = eB[e];
+}
+
+// ec[I_b(i), k] = sum_j conj(Tinv[j, i]) rc[I_b(j), k] - sum_sl conj(WH[sl, i]) eB_b[sl, k],
+// one wave per interior unknown i, KC columns per workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void k_expand_blk(const cplx_t<T> *__restrict__ WH,
+                                                    const cplx_t<T> *__restrict__ Tinv, int nI,
+                                                    int nBf, const int32_t *__restrict__ blkI,
+                                                    const int32_t *__restrict__ blkBm,
+                                                    const cplx_t<T> *__restrict__ rc,
+                                                    const cplx_t<T> *__restrict__ eB,
+                                                    cplx_t<T> *__restrict__ ec, int nr) {
+  using C = cplx_t<T>;
+  extern __shared__ __align__(16) char smem[];
+  C(*eBs)[KC] = reinterpret_cast<C(*)[KC]>(smem);
+  C(*rIs)[KC] = reinterpret_cast<C(*)[KC]>(smem + sizeof(C) * KC * nBf);
+  const int b = blockIdx.x, k0 = blockIdx.y * KC, kc = min(KC, nr - k0);
+  for (int e = threadIdx.x; e < nBf * KC; e += 256) {
+    const int sl = e / KC, k = e % KC;
+    const int m = blkBm[(int64_t)b * nBf + sl];
+    eBs[sl][k] = (m >= 0 && k < kc) ? eB[(int64_t)m * nr + k0 + k] : czero<C>();
+  }
+  for (int e = threadIdx.x; e < nI * KC; e += 256) {
+    const int i = e / KC, k = e % KC;
+    rIs[i][k] = k < kc ? rc[(int64_t)blkI[(int64_t)b * nI + i] * nr + k0 + k] : czero<C>();
+  }
+  __syncthreads();
+  const C *W = WH + (int64_t)b * nBf * nI;
+  const C *Ti = Tinv + (int64_t)b * nI * nI;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < nI; i += 4) {
+    C acc[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) acc[k] = czero<C>();
+    for (int j = lane; j < nI; j += 64) {
+      const C tv = cconj(Ti[j + (int64_t)i * nI]);
+#pragma unroll
+      for (int k = 0; k < KC; ++k) acc[k] = cfma(tv, rIs[j][k], acc[k]);
+    }
+    for (int sl = lane; sl < nBf; sl += 64) {
+      const C wv = cconj(W[sl + (int64_t)i * nBf]);
+#pragma unroll
+      for (int k = 0; k < KC; ++k) acc[k] = csub(acc[k], cmul(wv, eBs[sl][k]));
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) acc[k] = wave_sum_c(acc[k]);
+    if (lane < kc) {
+      C v = acc[0];
+#pragma unroll
+      for (int k = 1; k < KC; ++k)
+        if (lane == k) v = acc[k];
+      ec[(int64_t)blkI[(int64_t)b * nI + i] * nr + k0 + lane] = v;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_interleave(int64_t n, int nr, const double2 *__restrict__ cols,
+                                                    double2 *__restrict__ blk, int dir) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * nr) return;
+  const int64_t d = e / nr;
+  const int k = (int)(e % nr);
+  if (dir == 0) blk[e] = cols[(int64_t)k * n + d];
+  else blk[(int64_t)k * n + d] = cols[e];
+}
+
+// ---- per-column CG --------------------------------------------------------------------
+
+// Per workgroup and column: sums of Re(a^H b) (and Re(a^H c) when c).
+__global__ __launch_bounds__(256) void k_coldot(int64_t n, int nr, const double2 *__restrict__ a,
+                                                const double2 *__restrict__ bv,
+                                                const double2 *__restrict__ cv,
+                                                double *__restrict__ partial) {
+  __shared__ double sh[2][256];
+  const int t = threadIdx.x, rpb = 256 / nr, k = t % nr;
+  const bool on = t < rpb * nr;
+  double s = 0.0, u = 0.0;
+  if (on)
+    for (int64_t i = (int64_t)blockIdx.x * rpb + t / nr; i < n; i += (int64_t)gridDim.x * rpb) {
+      const double2 x = a[i * nr + k], y = bv[i * nr + k];
+      s += x.x * y.x + x.y * y.y;
+      if (cv) {
+        const double2 z = cv[i * nr + k];
+        u += x.x * z.x + x.y * z.y;
+      }
+    }
+  sh[0][t] = s;
+  sh[1][t] = u;
+  __syncthreads();
+  if (t < nr) {
+    double ss = 0.0, uu = 0.0;
+    for (int j = 0; j < rpb; ++j) {
+      ss += sh[0][t + j * nr];
+      uu += sh[1][t + j * nr];
+    }
+    partial[(int64_t)blockIdx.x * kMaxCols + t] = ss;
+    partial[(int64_t)(kColDotBlocks + blockIdx.x) * kMaxCols + t] = uu;
+  }
+}
+
+// Column reductions and the scalar updates of the CG step (mode: 0 store the
+// dot in slot q, 1 alpha, 2 ||r||^2, 3 flexible beta).
+__global__ __launch_bounds__(64) void k_colfinal(const double *__restrict__ partial, int nr,
+                                                 double *__restrict__ sc,
+                                                 const int *__restrict__ act, int mode, int q) {
+  const int k = threadIdx.x;
+  if (k >= nr) return;
+  double s = 0.0, u = 0.0;
+  for (int j = 0; j < kColDotBlocks; ++j) {
+    s += partial[(int64_t)j * kMaxCols + k];
+    u += partial[(int64_t)(kColDotBlocks + j) * kMaxCols + k];
+  }
+  double *S = sc;
+  const bool on = act ? act[k] != 0 : true;
+  if (mode == 0) {
+    S[q * kMaxCols + k] = s;
+  } else if (mode == 1) {
+    S[1 * kMaxCols + k] = s;
+    if (on && (!(s > 0.0) || !isfinite(s))) S[6 * kMaxCols + k] = 1.0;
+    S[2 * kMaxCols + k] = on ? S[0 * kMaxCols + k] / s : 0.0;
+  } else if (mode == 2) {
+    S[4 * kMaxCols + k] = s;
+  } else {
+    // flexible (Polak-Ribiere) beta = Re(r^H (z - z_old)) / Re(r_old^H z_old)
+    const double beta = on ? (s - u) / S[0 * kMaxCols + k] : 0.0;
+    S[3 * kMaxCols + k] = beta;
+    S[7 * kMaxCols + k] = u;
+    S[0 * kMaxCols + k] = s;
+    if (on && !isfinite(beta)) S[6 * kMaxCols + k] = 1.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_update_xr_blk(int64_t n, int nr, double2 *__restrict__ x,
+                                                       double2 *__restrict__ r,
+                                                       const double2 *__restrict__ p,
+                                                       const double2 *__restrict__ qv,
+                                                       double *__restrict__ partial,
+                                                       const double *__restrict__ sc) {
+  __shared__ double sh[256];
+  const int t = threadIdx.x, rpb = 256 / nr, k = t % nr;
+  const bool on = t < rpb * nr;
+  const double al = on ? sc[2 * kMaxCols + k] : 0.0;
+  double s = 0.0;
+  if (on)
+    for (int64_t i = (int64_t)blockIdx.x * rpb + t / nr; i < n; i += (int64_t)gridDim.x * rpb) {
+      const int64_t e = i * nr + k;
+      x[e] = mk(x[e].x + al * p[e].x, x[e].y + al * p[e].y);
+      const double2 ri = mk(r[e].x - al * qv[e].x, r[e].y - al * qv[e].y);
+      r[e] = ri;
+      s += ri.x * ri.x + ri.y * ri.y;
+    }
+  sh[t] = s;
+  __syncthreads();
+  if (t < nr) {
+    double ss = 0.0;
+    for (int j = 0; j < rpb; ++j) ss += sh[t + j * nr];
+    partial[(int64_t)blockIdx.x * kMaxCols + t] = ss;
+    partial[(int64_t)(kColDotBlocks + blockIdx.x) * kMaxCols + t] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_update_p_blk(int64_t n, int nr, double2 *__restrict__ p,
+                                                      const double2 *__restrict__ z,
+                                                      const double *__restrict__ sc) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * nr) return;
+  const double be = sc[3 * kMaxCols + (int)(e % nr)];
+  p[e] = mk(z[e].x + be * p[e].x, z[e].y + be * p[e].y);
+}
+
+}  // namespace
+
+void HermBlockBufs::ensure(const HermSet &H, int nr, bool fp64, bool fp32, Budget *bud) {
+  if (nr <= cap) return;
+  if (fp64) {
+    xl64.alloc(H.nloc * nr, bud);
+    yl64.alloc(H.nloc * nr, bud);
+  }
+  if (fp32) {
+    xl32.alloc(H.nloc * nr, bud);
+    yl32.alloc(H.nloc * nr, bud);
+  }
+  cap = nr;
+}
+
+template <typename T>
+void herm_apply_blk(HermSet &H, HermBlockBufs &W, const cplx_t<T> *X, cplx_t<T> *Y,
+                    const cplx_t<T> *R, int mode, T theta, int nr, hipStream_t s) {
+  if (nr < 1 || nr > kMaxCols || nr > W.cap) throw DpgError(-1, "block apply: bad column count");
+  const cplx_t<T> *tiles;
+  cplx_t<T> *xl, *yl;
+  if constexpr (sizeof(T) == 8) {
+    tiles = H.t64.p;
+    xl = W.xl64.p;
+    yl = W.yl64.p;
+  } else {
+    tiles = H.t32.p;
+    xl = W.xl32.p;
+    yl = W.yl32.p;
+  }
+  if (!tiles || !xl) throw DpgError(-6, "block set has no tiles of this precision");
+  {
+    ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
+    hipLaunchKernelGGL((k_gather_blk<T>), dim3(cdiv(H.nloc * nr, 256)), dim3(256), 0, s, H.nloc,
+                       nr, H.gidx.p, X, xl);
+    LAUNCH_OK();
+  }
+  {
+    ProfScope ps(H.prof, sizeof(T) == 8 ? DPG_K_APPLY64 : DPG_K_APPLY32,
+                 (double)H.packed_entries() * sizeof(cplx_t<T>), s);
+    hipLaunchKernelGGL((k_rows_blk<T>), dim3((unsigned)H.nrows), dim3(64), 0, s, tiles, H.rows.p,
+                       H.nrows, H.bn.p, H.tile_off.p, H.loc_off.p, xl, yl, nr);
+    LAUNCH_OK();
+  }
+  ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
+  const dim3 g(cdiv(H.nvec * nr, 256));
+  switch (mode) {
+    case RED_SET:
+      hipLaunchKernelGGL((k_scatter_blk<T, RED_SET>), g, dim3(256), 0, s, H.nvec, nr, H.red_ptr.p, H.red_ent.p, yl, R, Y, theta);
+      break;
+    case RED_RESID:
+      hipLaunchKernelGGL((k_scatter_blk<T, RED_RESID>), g, dim3(256), 0, s, H.nvec, nr, H.red_ptr.p, H.red_ent.p, yl, R, Y, theta);
+      break;
+    case RED_AXPY:
+      hipLaunchKernelGGL((k_scatter_blk<T, RED_AXPY>), g, dim3(256), 0, s, H.nvec, nr, H.red_ptr.p, H.red_ent.p, yl, R, Y, theta);
+      break;
+    default:
+      hipLaunchKernelGGL((k_scatter_blk<T, RED_SET_SCALED>), g, dim3(256), 0, s, H.nvec, nr, H.red_ptr.p, H.red_ent.p, yl, R, Y, theta);
+  }
+  LAUNCH_OK();
+}
+
+template <typename T>
+void launch_csr_blk(int64_t nrows, const int64_t *ptr, const int32_t *col, const T *val,
+                    const cplx_t<T> *x, cplx_t<T> *y, int add, int nr, hipStream_t s) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL((k_csr_blk<T>), dim3(cdiv(nrows * nr, 256)), dim3(256), 0, s, nrows, nr, ptr,
+                     col, val, x, y, add);
+  LAUNCH_OK();
+}
+
+template <typename T>
+void launch_condense_blk(const cplx_t<T> *WH, int nI, int nBf, const int32_t *blkI, int nblk,
+                         int64_t nM, const int64_t *macro_B, const int32_t *red_ptr,
+                         const int32_t *red_ent, const cplx_t<T> *rc, cplx_t<T> *c,
+                         cplx_t<T> *rB, int nr, hipStream_t s) {
+  if (nI > kBMaxI) throw DpgError(-1, "macro block too large");
+  hipLaunchKernelGGL((k_condense_local_blk<T>), dim3(nblk, cdiv(nr, KC)), dim3(256), 0, s, WH, nI,
+                     nBf, blkI, rc, c, nr);
+  LAUNCH_OK();
+  hipLaunchKernelGGL((k_condense_reduce_blk<T>), dim3(cdiv(nM * nr, 256)), dim3(256), 0, s, nM, nr,
+                     macro_B, red_ptr, red_ent, rc, c, rB);
+  LAUNCH_OK();
+}
+
+template <typename T>
+void launch_expand_blk(const cplx_t<T> *WH, const cplx_t<T> *Tinv, int nI, int nBf,
+                       const int32_t *blkI, const int32_t *blkBm, int nblk, const cplx_t<T> *rc,
+                       const cplx_t<T> *eB, int64_t nM, const int64_t *macro_B, cplx_t<T> *ec,
+                       int nr, hipStream_t s) {
+  const size_t lds = sizeof(cplx_t<T>) * KC * ((size_t)nBf + nI);
+  if (lds > 64 * 1024) throw DpgError(-1, "macro block too large for the block expansion");
+  hipLaunchKernelGGL((k_scatter_macro_blk<T>), dim3(cdiv(nM * nr, 256)), dim3(256), 0, s, nM, nr,
+                     macro_B, eB, ec);
+  LAUNCH_OK();
+  hipLaunchKernelGGL((k_expand_blk<T>), dim3(nblk, cdiv(nr, KC)), dim3(256), lds, s, WH, Tinv, nI,
+                     nBf, blkI, blkBm, rc, eB, ec, nr);
+  LAUNCH_OK();
+}
+
+void launch_interleave(int64_t n, int nr, const double2 *cols, double2 *blk, hipStream_t s) {
+  hipLaunchKernelGGL(k_interleave, dim3(cdiv(n * nr, 256)), dim3(256), 0, s, n, nr, cols, blk, 0);
+  LAUNCH_OK();
+}
+void launch_deinterleave(int64_t n, int nr, const double2 *blk, double2 *cols, hipStream_t s) {
+  hipLaunchKernelGGL(k_interleave, dim3(cdiv(n * nr, 256)), dim3(256), 0, s, n, nr, blk, cols, 1);
+  LAUNCH_OK();
+}
+
+void cgb_dot(int64_t n, int nr, const double2 *a, const double2 *b, double *partial, double *sc,
+             int q, hipStream_t s) {
+  hipLaunchKernelGGL(k_coldot, dim3(kColDotBlocks), dim3(256), 0, s, n, nr, a, b,
+                     (const double2 *)nullptr, partial);
+  hipLaunchKernelGGL(k_colfinal, dim3(1), dim3(64), 0, s, partial, nr, sc, (const int *)nullptr, 0,
+                     q);
+  LAUNCH_OK();
+}
+
+void cgb_alpha(int64_t n, int nr, const double2 *p, const double2 *qv, double *partial,
+               double *sc, const int *act, hipStream_t s) {
+  hipLaunchKernelGGL(k_coldot, dim3(kColDotBlocks), dim3(256), 0, s, n, nr, p, qv,
+                     (const double2 *)nullptr, partial);
+  hipLaunchKernelGGL(k_colfinal, dim3(1), dim3(64), 0, s, partial, nr, sc, act, 1, 0);
+  LAUNCH_OK();
+}
+
+void cgb_update_xr(int64_t n, int nr, double2 *x, double2 *r, const double2 *p, const double2 *qv,
+                   double *partial, double *sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_xr_blk, dim3(kColDotBlocks), dim3(256), 0, s, n, nr, x, r, p, qv,
+                     partial, sc);
+  hipLaunchKernelGGL(k_colfinal, dim3(1), dim3(64), 0, s, partial, nr, sc, (const int *)nullptr, 2,
+                     0);
+  LAUNCH_OK();
+}
+
+void cgb_beta(int64_t n, int nr, const double2 *r, const double2 *z, const double2 *zold,
+              double *partial, double *sc, const int *act, hipStream_t s) {
+  hipLaunchKernelGGL(k_coldot, dim3(kColDotBlocks), dim3(256), 0, s, n, nr, r, z, zold, partial);
+  hipLaunchKernelGGL(k_colfinal, dim3(1), dim3(64), 0, s, partial, nr, sc, act, 3, 0);
+  LAUNCH_OK();
+}
+
+void cgb_update_p(int64_t n, int nr, double2 *p, const double2 *z, const double *sc,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_update_p_blk, dim3(cdiv(n * nr, 256)), dim3(256), 0, s, n, nr, p, z, sc);
+  LAUNCH_OK();
+}
+
+template void herm_apply_blk<double>(HermSet &, HermBlockBufs &, const double2 *, double2 *,
+                                     const double2 *, int, double, int, hipStream_t);
+template void herm_apply_blk<float>(HermSet &, HermBlockBufs &, const float2 *, float2 *,
+                                    const float2 *, int, float, int, hipStream_t);
+template void launch_csr_blk<double>(int64_t, const int64_t *, const int32_t *, const double *,
+                                     const double2 *, double2 *, int, int, hipStream_t);
+template void launch_csr_blk<float>(int64_t, const int64_t *, const int32_t *, const float *,
+                                    const float2 *, float2 *, int, int, hipStream_t);
+template void launch_condense_blk<double>(const double2 *, int, int, const int32_t *, int, int64_t,
+                                          const int64_t *, const int32_t *, const int32_t *,
+                                          const double2 *, double2 *, double2 *, int, hipStream_t);
+template void launch_condense_blk<float>(const float2 *, int, int, const int32_t *, int, int64_t,
+                                         const int64_t *, const int32_t *, const int32_t *,
+                                         const float2 *, float2 *, float2 *, int, hipStream_t);
+template void launch_expand_blk<double>(const double2 *, const double2 *, int, int,
+                                        const int32_t *, const int32_t *, int, const double2 *,
+                                        const double2 *, int64_t, const int64_t *, double2 *, int,
+                                        hipStream_t);
+template void launch_expand_blk<float>(const float2 *, const float2 *, int, int, const int32_t *,
+                                       const int32_t *, int, const float2 *, const float2 *,
+                                       int64_t, const int64_t *, float2 *, int, hipStream_t);
+
+}  // namespace dpg

@@ -1,0 +1,70 @@
+// Multi-right-hand-side forms of the solve phase (nr columns at once).
+//
+// Block vectors hold nr columns interleaved: entry (d, k) of an n x nr block
+// sits at d * nr + k, so the gathers and scatters of the single-column path
+// move nr contiguous values per index.  The operators are the same objects as
+// in the single-column path (Hermitian block sets, transfer CSR matrices,
+// condensation blocks); each stored block is streamed once per application
+// for all nr columns, which turns the matrix-vector products into products
+// with 32 x nr panels.
+#pragma once
+#include "common.hpp"
+#include "hblocks.hpp"
+
+namespace dpg {
+
+constexpr int kMaxCols = 32;   // columns per block solve
+
+// Work vectors of one Hermitian block set for nr columns.
+struct HermBlockBufs {
+  int cap = 0;
+  DevBuf<double2> xl64, yl64;
+  DevBuf<float2> xl32, yl32;
+  void ensure(const HermSet &H, int nr, bool fp64, bool fp32, Budget *bud);
+};
+
+// Y <- epilogue(sum_b R_b^T A_b R_b X) for nr columns (modes as herm_apply).
+template <typename T>
+void herm_apply_blk(HermSet &H, HermBlockBufs &W, const cplx_t<T> *X, cplx_t<T> *Y,
+                    const cplx_t<T> *R, int mode, T theta, int nr, hipStream_t s);
+
+// y[i, k] (+)= sum_j val[j] x[col[j], k] over CSR rows.
+template <typename T>
+void launch_csr_blk(int64_t nrows, const int64_t *ptr, const int32_t *col, const T *val,
+                    const cplx_t<T> *x, cplx_t<T> *y, int add, int nr, hipStream_t s);
+
+// Macro condensation and expansion of nr columns (see launch_condense_local,
+// launch_condense_reduce, launch_expand).
+template <typename T>
+void launch_condense_blk(const cplx_t<T> *WH, int nI, int nBf, const int32_t *blkI, int nblk,
+                         int64_t nM, const int64_t *macro_B, const int32_t *red_ptr,
+                         const int32_t *red_ent, const cplx_t<T> *rc, cplx_t<T> *c,
+                         cplx_t<T> *rB, int nr, hipStream_t s);
+template <typename T>
+void launch_expand_blk(const cplx_t<T> *WH, const cplx_t<T> *Tinv, int nI, int nBf,
+                       const int32_t *blkI, const int32_t *blkBm, int nblk, const cplx_t<T> *rc,
+                       const cplx_t<T> *eB, int64_t nM, const int64_t *macro_B, cplx_t<T> *ec,
+                       int nr, hipStream_t s);
+
+// Column-major [nr][n] <-> interleaved [n][nr] (FP64).
+void launch_interleave(int64_t n, int nr, const double2 *cols, double2 *blk, hipStream_t s);
+void launch_deinterleave(int64_t n, int nr, const double2 *blk, double2 *cols, hipStream_t s);
+
+// ---- per-column CG on interleaved FP64 blocks ----------------------------------------
+// Device scalars sc[q * kMaxCols + k] for column k: q = 0 rz, 1 pq, 2 alpha,
+// 3 beta, 4 ||r||^2, 5 ||b||^2, 6 breakdown flag, 7 r^H z_old.  act[k] != 0
+// marks a column that still iterates; a frozen column takes alpha = beta = 0,
+// so its x, r and p stay as they are.
+constexpr int kColDotBlocks = 256;
+void cgb_dot(int64_t n, int nr, const double2 *a, const double2 *b, double *partial, double *sc,
+             int q, hipStream_t s);                                  // sc[q] = Re(a^H b)
+void cgb_alpha(int64_t n, int nr, const double2 *p, const double2 *qv, double *partial,
+               double *sc, const int *act, hipStream_t s);
+void cgb_update_xr(int64_t n, int nr, double2 *x, double2 *r, const double2 *p, const double2 *qv,
+                   double *partial, double *sc, hipStream_t s);
+void cgb_beta(int64_t n, int nr, const double2 *r, const double2 *z, const double2 *zold,
+              double *partial, double *sc, const int *act, hipStream_t s);
+void cgb_update_p(int64_t n, int nr, double2 *p, const double2 *z, const double *sc,
+                  hipStream_t s);
+
+}  // namespace dpg

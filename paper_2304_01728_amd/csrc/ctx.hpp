@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "../../include/dpgmg.h"
+#include "block.hpp"
 #include "common.hpp"
 #include "dense.hpp"
 #include "element.hpp"
@@ -44,6 +45,11 @@ struct LevelData {
   // mesh's traces; c = per-block condensation contributions of this level.
   DevBuf<double2> r64, x64, res64, rc64, ec64, c64;
   DevBuf<float2> r32, x32, res32, rc32, ec32, c32;
+  // the same for block (multi-right-hand-side) solves, bcap columns
+  int bcap = 0;
+  DevBuf<double2> br64, bx64, bres64, brc64, bec64, bc64;
+  DevBuf<float2> br32, bx32, bres32, brc32, bec32, bc32;
+  HermBlockBufs Mb, Sb;
 };
 
 }  // namespace dpg
@@ -81,6 +87,14 @@ struct dpg_ctx {
   dpg::DevBuf<double2> b, x, r, z, zo, pv, q, xfull, sB;
   dpg::DevBuf<double> partial, sc;
   double *host_sc = nullptr;         // pinned
+  // block PCG (interleaved [n][nr] vectors), allocated at the first block solve
+  int bcap = 0;
+  dpg::HermBlockBufs T0b;
+  dpg::DevBuf<double2> bb, bx, br, bz, bzo, bp, bq, bsv, bxf, bcols;
+  dpg::DevBuf<double> bpartial, bsc;
+  dpg::DevBuf<int> bact;
+  double *host_bsc = nullptr;        // pinned, 8 x kMaxCols
+  int *host_bact = nullptr;          // pinned, kMaxCols
   double ms[4] = {0, 0, 0, 0};
   dpg::Prof prof;
 };

@@ -16,6 +16,7 @@ DPG_OK, DPG_EINVAL, DPG_ENOMEM, DPG_ENOTPD, DPG_ENOCONV, DPG_EBREAKDOWN, DPG_EST
     0, -1, -2, -3, -4, -5, -6, -7
 DPG_FP64, DPG_MIXED = 0, 1
 DPG_DEVICE_PTRS = 1
+DPG_COLUMNWISE = 2
 (X_ELEM_DOFS, X_MACRO_B, X_BLOCK_B, X_BLOCK_I, X_PATCHES, X_PROLONG, X_ELEM_S, X_ELEM_RHS,
  X_MACRO_M, X_COARSE_E, X_PATCH_INV, X_COARSEST, X_PROLONG_VAL, X_ASM_RHS) = range(1, 15)
 

@@ -1,0 +1,117 @@
+"""Multi-right-hand-side solves: the block path (every stored block streamed
+once per application for all columns, per-column CG scalars, converged
+columns frozen) against the column-by-column path and against the oracle.
+
+Tolerances: the two GPU paths run the same recurrences per column with the
+products summed in a different order, so their iterates differ by rounding
+only: iteration counts +-1, solutions within 1e-10 (FP64, tol 1e-12) or 1e-8
+(mixed, tol 1e-10) of each other, and each within the same bounds of the
+FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import dpg, multigrid
+from paper_2304_01728_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _D():
+    from paper_2304_01728_amd import dpgmg as D
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return D
+
+
+def _ctx(D, N, p, omega, loads, precision="fp64", flags=0, nu=(1, 1)):
+    opt = D.dpg_default_options(nu_pre=nu[0], nu_post=nu[1], flags=flags,
+                                precision=D.DPG_MIXED if precision == "mixed" else D.DPG_FP64)
+    print(f"[multirhs] N={N} p={p} nrhs={len(loads)} {precision} flags={flags}", flush=True)
+    ctx = D.dpg_setup(N, p, omega, loads, options=opt)
+    D.dpg_assemble(ctx)
+    D.dpg_build_hierarchy(ctx)
+    return ctx
+
+
+def _sources(seed, count, sigma=0.08):
+    cen = workloads.source_centres(seed, count)
+    amps = [complex(1.0 + 0.1 * k, 0.5 - 0.05 * k) for k in range(count)]
+    loads = [dict(dir=(0, 0, 1), amp=0.0, sources=[[*c0, sigma, a.real, a.imag]])
+             for c0, a in zip(cen, amps)]
+    fs = [dict(f=dpg.gaussian_sources([c0], sigma, [a])) for c0, a in zip(cen, amps)]
+    return loads, fs
+
+
+def _oracle(N, p, omega, fs, nu=(1, 1)):
+    pr = dpg.Problem(N, p, omega, fs)
+    S, s, _ = pr.condensed()
+    rhs = dpg.assemble_vector(pr.edofs, s, pr.num.n)
+    H = multigrid.Hierarchy(N, p, S, nu_pre=nu[0], nu_post=nu[1])
+    return H, rhs
+
+
+def _relerr(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("N,p,omega,nu", [(4, 2, 3 * np.pi, (1, 1)), (8, 2, 4 * np.pi, (2, 2))])
+def test_block_fp64_matches_columnwise_and_oracle(N, p, omega, nu):
+    D = _D()
+    loads, fs = _sources(3, 5)
+    blk = _ctx(D, N, p, omega, loads, nu=nu)
+    col = _ctx(D, N, p, omega, loads, flags=D.DPG_COLUMNWISE, nu=nu)
+    xb, itb, rrb, cb = D.dpg_solve(blk, nrhs=5, tol=1e-12)
+    xc, itc, rrc, cc = D.dpg_solve(col, nrhs=5, tol=1e-12)
+    assert cb == D.DPG_OK and cc == D.DPG_OK
+    assert np.all(rrb <= 1e-12)
+    H, rhs = _oracle(N, p, omega, fs, nu)
+    for k in range(5):
+        assert abs(int(itb[k]) - int(itc[k])) <= 1
+        assert _relerr(xb[k], xc[k]) <= 1e-10
+        xo, ito, _ = H.solve(rhs[:, k], 1e-12)
+        assert abs(int(itb[k]) - ito) <= 1
+        assert _relerr(xb[k], xo) <= 1e-10
+
+
+def test_block_mixed_matches_columnwise_and_fp64_oracle():
+    D = _D()
+    N, p, omega = 4, 2, 3 * np.pi
+    loads, fs = _sources(5, 4)
+    blk = _ctx(D, N, p, omega, loads, precision="mixed")
+    col = _ctx(D, N, p, omega, loads, precision="mixed", flags=D.DPG_COLUMNWISE)
+    xb, itb, _, cb = D.dpg_solve(blk, nrhs=4, tol=1e-10)
+    xc, itc, _, cc = D.dpg_solve(col, nrhs=4, tol=1e-10)
+    assert cb == D.DPG_OK and cc == D.DPG_OK
+    H, rhs = _oracle(N, p, omega, fs)
+    for k in range(4):
+        assert abs(int(itb[k]) - int(itc[k])) <= 1
+        assert _relerr(xb[k], xc[k]) <= 1e-8
+        xo, _, _ = H.solve(rhs[:, k], 1e-12)
+        assert _relerr(xb[k], xo) <= 1e-8
+
+
+def test_block_more_than_32_columns_and_a_zero_column():
+    """35 columns: a block of 32 and one of 3; explicit right-hand sides with
+    one zero column (0 iterations, x = 0) and one column repeated in both
+    blocks (the per-column dot products sum in an order that depends on the
+    block width, so the two agree to rounding)."""
+    D = _D()
+    N, p, omega = 4, 1, 2.5
+    loads, fs = _sources(7, 2)
+    ctx = _ctx(D, N, p, omega, loads)
+    H, rhs = _oracle(N, p, omega, fs)
+    rng = np.random.default_rng(11)
+    n = rhs.shape[0]
+    B = (rng.standard_normal((35, n)) + 1j * rng.standard_normal((35, n)))
+    B[3] = 0.0
+    B[20] = rhs[:, 0]
+    B[34] = rhs[:, 0]
+    x, it, rr, code = D.dpg_solve(ctx, rhs=B, nrhs=35, tol=1e-12)
+    assert code == D.DPG_OK
+    assert it[3] == 0 and np.all(x[3] == 0)
+    assert abs(int(it[20]) - int(it[34])) <= 1 and _relerr(x[34], x[20]) <= 1e-10
+    for k in (0, 17, 20, 31, 32, 34):
+        xo, ito, _ = H.solve(B[k], 1e-12)
+        assert abs(int(it[k]) - ito) <= 1
+        assert _relerr(x[k], xo) <= 1e-10

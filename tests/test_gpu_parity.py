@@ -250,8 +250,8 @@ def test_mixed_precision_error_vs_fp64_oracle(two_level):
 
 
 def test_multiple_rhs_point_sources():
-    """Several Gaussian point sources, homogeneous impedance data: every
-    column matches the oracle, and matches its own single-column solve."""
+    """Several Gaussian point sources, homogeneous impedance data, solved as a
+    block: every column matches the oracle, and its own single-column solve."""
     D = _D()
     N, p, omega = 4, 2, 3 * np.pi
     cen = workloads.source_centres(3, 3)
@@ -269,8 +269,9 @@ def test_multiple_rhs_point_sources():
         xo, ito, _ = H.solve(rhs[:, k], 1e-12)
         assert np.linalg.norm(x[k] - xo) <= 1e-10 * np.linalg.norm(xo)
         assert abs(int(it[k]) - ito) <= 1
+        # the single-column path sums the products in another order
         xs, _, _, _ = D.dpg_solve(ctx, rhs=rhs[:, k][None, :], tol=1e-12)
-        assert rel(xs[0], x[k]) <= 1e-12
+        assert rel(xs[0], x[k]) <= 1e-10
     f = D.dpg_get_fields(ctx, x)
     fo = dpg.recover_fields(rec, pr.edofs, x.T)
     assert rel(f, fo.transpose(2, 0, 1)) <= 1e-10
