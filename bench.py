@@ -26,11 +26,11 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 matrix (= vector) peak
 FP32_PEAK_TFLOPS = 157.3
 
 
-def make_options(D, w, torch_stream=None, device_ptrs=True):
+def make_options(D, w, torch_stream=None, device_ptrs=True, columnwise=False):
     return D.dpg_default_options(
         nu_pre=w.nu_pre, nu_post=w.nu_post, theta=w.theta,
         precision=D.DPG_MIXED if w.precision == "mixed" else D.DPG_FP64,
-        flags=D.DPG_DEVICE_PTRS if device_ptrs else 0,
+        flags=(D.DPG_DEVICE_PTRS if device_ptrs else 0) | (D.DPG_COLUMNWISE if columnwise else 0),
         stream=torch_stream)
 
 
@@ -97,6 +97,47 @@ def roofline_setup(stats):
                         "unit": "TFLOP/s", "frac": a / FP64_PEAK_TFLOPS, "ms": ms,
                         "launches": n}
     return out
+
+
+def compare_precision(workload):
+    """Time to tolerance of the FP64 and the mixed-precision path on the same
+    workload (setup excluded), and the mixed solution's relative error against
+    the FP64 GPU solution (the FP64 path is the one proven against the oracle
+    at sizes the oracle can run)."""
+    import dataclasses
+    import torch
+    from paper_2304_01728_amd import dpgmg as D
+    from paper_2304_01728_amd import workloads as W
+    base = W.ALL[workload]()
+    out = {"workload": base.name, "tol": base.tol}
+    xs = {}
+    for prec in ("fp64", "mixed"):
+        w = dataclasses.replace(base, precision=prec)
+        torch.cuda.set_device(0)
+        stream = torch.cuda.current_stream()
+        ctx = D.dpg_setup(w.N, w.p, w.omega, loads_of(w), dp=w.dp,
+                          options=make_options(D, w, torch_stream=stream.cuda_stream))
+        nT = D.dpg_info(ctx).n_trace
+        x = torch.zeros((w.nrhs, nT), dtype=torch.complex128, device="cuda:0")
+        D.dpg_assemble(ctx)
+        D.dpg_build_hierarchy(ctx)
+        D.dpg_solve(ctx, nrhs=w.nrhs, tol=w.tol, x_out=x, device=True)   # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, it, rr, code = D.dpg_solve(ctx, nrhs=w.nrhs, tol=w.tol, x_out=x, device=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[prec] = {"time_to_tol_ms": 1e3 * t, "iterations": [int(v) for v in it],
+                     "relres": float(np.max(rr)), "status": int(code),
+                     "resident_GB": D.dpg_info(ctx).resident_bytes / 1e9}
+        xs[prec] = x.cpu().numpy()
+        ctx.close()
+        del x
+        torch.cuda.empty_cache()
+    d = xs["mixed"] - xs["fp64"]
+    out["mixed_rel_error_vs_fp64"] = float(np.linalg.norm(d) / np.linalg.norm(xs["fp64"]))
+    out["speedup_mixed"] = out["fp64"]["time_to_tol_ms"] / out["mixed"]["time_to_tol_ms"]
+    print(json.dumps(out), flush=True)
 
 
 def calibrate_copy():
@@ -200,6 +241,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="plane_wave_16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--columnwise", action="store_true",
+                    help="solve several right-hand sides one by one instead of as a block")
+    ap.add_argument("--compare-precision", action="store_true",
+                    help="solve the workload in FP64 and in mixed precision; report times "
+                         "to tolerance and the mixed solution's error against the FP64 one")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -210,6 +256,9 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
+    if args.compare_precision:
+        compare_precision(args.workload)
+        return
 
     import torch
     from paper_2304_01728_amd import dpgmg as D
@@ -219,7 +268,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    opt = make_options(D, w, torch_stream=stream.cuda_stream)
+    opt = make_options(D, w, torch_stream=stream.cuda_stream, columnwise=args.columnwise)
     t0 = time.perf_counter()
     ctx = D.dpg_setup(w.N, w.p, w.omega, loads_of(w), dp=w.dp, options=opt)
     setup_s = time.perf_counter() - t0
@@ -252,6 +301,7 @@ def main():
         phase["hierarchy"] += tc - tb
         phase["solve"] += td - tc
         iters_total += int(np.sum(it))
+        iters_cols = [int(v) for v in it]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     stats = D.dpg_kernel_stats(ctx)
@@ -277,10 +327,13 @@ def main():
                    "precision": w.precision, "nrhs": w.nrhs, "n_trace": nT,
                    "n_macro": info.n_macro, "levels": list(info.level_n)[:info.nlevels]},
         "iterations": iters_per_step,
+        "iterations_per_column": iters_cols if w.nrhs > 1 else None,
         "relres": float(np.max(rr)),
         "time_to_tol_ms": 1e3 * solve_s,
         "solve_only": {"value": nT * iters_per_step / solve_s, "unit": "trace-DOF*PCG-iters/s",
-                       "ms_per_iteration": 1e3 * solve_s / max(iters_per_step, 1)},
+                       "ms_per_iteration": 1e3 * solve_s / max(iters_per_step, 1),
+                       "solves_per_s": w.nrhs / solve_s,
+                       "rhs_mode": "columnwise" if args.columnwise or w.nrhs == 1 else "block"},
         "phases_ms": {k: 1e3 * v / args.steps for k, v in phase.items()},
         "setup_topology_ms": 1e3 * setup_s,
         "resident_GB": info.resident_bytes / 1e9,

@@ -58,6 +58,14 @@ def plane_wave_32_mixed():
                     direction=plane_wave_direction(2))
 
 
+def plane_wave_32():
+    """The 32^3, p = 4 plane wave solved in FP64 throughout, for the
+    time-to-tolerance comparison with the mixed-precision path."""
+    return Workload("plane-wave N=32 p=4 omega=16pi V(2,2) fp64", N=32, p=4,
+                    omega=16 * np.pi, nu_pre=2, nu_post=2, tol=1e-8,
+                    direction=plane_wave_direction(2))
+
+
 def point_sources_24():
     return Workload("point-sources N=24 p=3 omega=12pi 32 rhs mixed", N=24, p=3,
                     omega=12 * np.pi, nu_pre=2, nu_post=2, tol=1e-8, precision="mixed",
@@ -65,4 +73,5 @@ def point_sources_24():
 
 
 ALL = {"plane_wave_4": plane_wave_4, "plane_wave_16": plane_wave_16,
-       "plane_wave_32_mixed": plane_wave_32_mixed, "point_sources_24": point_sources_24}
+       "plane_wave_32_mixed": plane_wave_32_mixed, "plane_wave_32": plane_wave_32,
+       "point_sources_24": point_sources_24}
