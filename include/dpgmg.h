@@ -101,7 +101,8 @@ typedef struct {
   int32_t flags;      /* DPG_DEVICE_PTRS | DPG_COLUMNWISE                    */
   double theta;       /* smoother damping; must be < 1/4                     */
   int64_t hbm_budget; /* bytes the context may allocate; 0 = no limit        */
-  void *stream;       /* hipStream_t to launch on; NULL = default stream     */
+  void *stream;       /* hipStream_t to launch on; NULL: a stream the context
+                         creates (blocking, i.e. ordered with the null stream) */
 } dpg_options;
 
 typedef struct dpg_ctx dpg_ctx;

@@ -496,7 +496,7 @@ template <typename T> void vcycle(dpg_ctx *c, int l) {
   const hipStream_t s = c->stream;
   const T th = (T)c->opt.theta;
   auto r = B::r(f), x = B::x(f), res = B::res(f), rc = B::rc(f), ec = B::ec(f);
-  if (c->opt.nu_pre == 0) HIP_OK(hipMemsetAsync(x, 0, f.nM * sizeof(*x), s));
+  if (c->opt.nu_pre == 0) launch_zero(f.nM, x, s);
   for (int k = 0; k < c->opt.nu_pre; ++k) {
     if (k == 0) {
       herm_apply<T>(f.Sset, r, x, nullptr, RED_SET_SCALED, th, s);
@@ -555,6 +555,34 @@ void read_sc(dpg_ctx *c) {
   HIP_OK(hipStreamSynchronize(c->stream));
 }
 
+// Instantiated HIP graphs of one solve, destroyed with the object.
+struct GraphSet {
+  hipGraphExec_t a = nullptr, b[2] = {nullptr, nullptr};
+  ~GraphSet() {
+    for (hipGraphExec_t g : {a, b[0], b[1]})
+      if (g) (void)hipGraphExecDestroy(g);
+  }
+};
+
+// Capture the launches of f on stream s into an executable graph.  A capture
+// that fails is ended and discarded, so the stream is never left capturing.
+template <class F> hipGraphExec_t capture(hipStream_t s, F &&f) {
+  HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipGraph_t g = nullptr;
+  try {
+    f();
+  } catch (...) {
+    if (hipStreamEndCapture(s, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HIP_OK(hipStreamEndCapture(s, &g));
+  hipGraphExec_t e = nullptr;
+  const hipError_t st = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIP_OK(st);
+  return e;
+}
+
 // PCG on the finest macro grid for one trace right-hand side s (device);
 // full trace solution into xout (device).  Returns DPG_OK / ENOCONV.
 int solve_one(dpg_ctx *c, const double2 *sv, double tol, double2 *xout, int32_t *iters,
@@ -581,13 +609,33 @@ int solve_one(dpg_ctx *c, const double2 *sv, double tol, double2 *xout, int32_t 
     dot_re(nM, c->r.p, z, c->partial.p, c->sc.p + 0, s);
     HIP_OK(hipMemcpyAsync(c->pv.p, z, nM * 16, hipMemcpyDeviceToDevice, s));
     rr = 1.0;
-    while (it < c->opt.maxit) {
+    // One iteration is two fixed launch sequences around the host's
+    // convergence check: (A) matvec, alpha, x and r; (B) V-cycle, beta, p.
+    // Without per-kernel profiling they are captured once per solve as HIP
+    // graphs and replayed (B in two versions: z and z_old swap every
+    // iteration), which removes the launch gaps between the ~130 kernels.
+    auto part_a = [&]() {
       herm_apply<double>(top.Mset, c->pv.p, c->q.p, nullptr, RED_SET, 1.0, s);
-      {
-        PROF(DPG_K_CG, 0);
-        cg_alpha(nM, c->pv.p, c->q.p, c->partial.p, c->sc.p, s);
-        cg_update_xr(nM, c->x.p, c->r.p, c->pv.p, c->q.p, c->partial.p, c->sc.p, s);
-      }
+      PROF(DPG_K_CG, 0);
+      cg_alpha(nM, c->pv.p, c->q.p, c->partial.p, c->sc.p, s);
+      cg_update_xr(nM, c->x.p, c->r.p, c->pv.p, c->q.p, c->partial.p, c->sc.p, s);
+    };
+    auto part_b = [&](double2 *zn, double2 *zp) {
+      precondition(c, c->r.p, zn);
+      PROF(DPG_K_CG, 0);
+      cg_beta(nM, c->r.p, zn, zp, c->partial.p, c->sc.p, s);
+      cg_update_p(nM, c->pv.p, zn, c->sc.p, s);
+    };
+    GraphSet gs;
+    const bool graphs = !c->prof.on;
+    if (graphs) {
+      gs.a = capture(s, part_a);
+      gs.b[0] = capture(s, [&]() { part_b(c->zo.p, c->z.p); });   // odd iterations
+      gs.b[1] = capture(s, [&]() { part_b(c->z.p, c->zo.p); });   // even iterations
+    }
+    while (it < c->opt.maxit) {
+      if (graphs) HIP_OK(hipGraphLaunch(gs.a, s));
+      else part_a();
       ++it;
       read_sc(c);
       if (c->host_sc[6] != 0.0)
@@ -597,10 +645,8 @@ int solve_one(dpg_ctx *c, const double2 *sv, double tol, double2 *xout, int32_t 
       if (!std::isfinite(rr)) throw DpgError(DPG_EBREAKDOWN, "residual is not finite");
       if (rr <= tol) break;
       std::swap(z, zo);
-      precondition(c, c->r.p, z);
-      PROF(DPG_K_CG, 0);
-      cg_beta(nM, c->r.p, z, zo, c->partial.p, c->sc.p, s);
-      cg_update_p(nM, c->pv.p, z, c->sc.p, s);
+      if (graphs) HIP_OK(hipGraphLaunch(gs.b[it & 1 ? 0 : 1], s));
+      else part_b(z, zo);
     }
     if (rr > tol) status = DPG_ENOCONV;
   }
@@ -682,7 +728,7 @@ template <typename T> void vcycle_blk(dpg_ctx *c, int l, int nr) {
   const hipStream_t s = c->stream;
   const T th = (T)c->opt.theta;
   auto r = BB::r(f), x = BB::x(f), res = BB::res(f), rc = BB::rc(f), ec = BB::ec(f);
-  if (c->opt.nu_pre == 0) HIP_OK(hipMemsetAsync(x, 0, f.nM * nr * sizeof(*x), s));
+  if (c->opt.nu_pre == 0) launch_zero(f.nM * nr, x, s);
   for (int k = 0; k < c->opt.nu_pre; ++k) {
     if (k == 0) {
       herm_apply_blk<T>(f.Sset, f.Sb, r, x, nullptr, RED_SET_SCALED, th, nr, s);
@@ -870,6 +916,13 @@ int dpg_setup(const dpg_mesh *mesh, int p, int dp, double omega, const dpg_mater
     if (c->opt.precision != DPG_FP64 && c->opt.precision != DPG_MIXED)
       throw DpgError(DPG_EINVAL, "unknown precision mode");
     c->stream = (hipStream_t)c->opt.stream;
+    if (!c->stream) {
+      // an own stream (blocking, so ordered with the caller's null-stream
+      // work): the solve captures launch sequences as graphs, which the
+      // null stream does not allow
+      HIP_OK(hipStreamCreate(&c->own_stream));
+      c->stream = c->own_stream;
+    }
     c->bud.limit = c->opt.hbm_budget;
     c->N = mesh->n;
     c->p = p;
@@ -1363,6 +1416,11 @@ int64_t dpg_export(const dpg_ctx *cc, int what, int level, void *out, int64_t ca
 void dpg_destroy(dpg_ctx *c) {
   if (!c) return;
   if (c->host_sc) (void)hipHostFree(c->host_sc);
+  if (c->own_stream) {
+    (void)hipStreamSynchronize(c->own_stream);
+    (void)hipStreamDestroy(c->own_stream);
+    c->own_stream = nullptr;
+  }
   if (c->host_bsc) (void)hipHostFree(c->host_bsc);
   if (c->host_bact) (void)hipHostFree(c->host_bact);
   delete c;

@@ -61,6 +61,7 @@ struct dpg_ctx {
   double omega = 0, side = 1, org[3] = {0, 0, 0};
   dpg_options opt{};
   hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;  // created when the options give no stream
   dpg::Budget bud;
   dpg::ElementLayout el;
   int n_test = 0, n_field = 0, n_tr = 0, m = 0;

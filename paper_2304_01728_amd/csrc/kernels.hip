@@ -65,6 +65,7 @@ __global__ __launch_bounds__(256) void k_patch_gather(const double2 *__restrict_
   const int64_t kend = min((int64_t)n * n, (int64_t)(blockIdx.y + 1) * 2048);
   for (int64_t k = (int64_t)blockIdx.y * 2048 + threadIdx.x; k < kend; k += 256) {
     const int i = (int)(k % n), j = (int)(k / n);
+    if (j > i) continue;   // the Cholesky that follows reads the lower triangle only
     double2 acc = mk(0.0, 0.0);
     for (int c = 0; c < 8; ++c) {
       if (blk[c] < 0) continue;
@@ -164,6 +165,11 @@ template <typename C> __device__ inline C wave_sum(C v) {
   return v;
 }
 
+// One workgroup per (block, group of kExpRows interior unknowns), one wave
+// per unknown at a time: many short workgroups instead of one long one per
+// block keep the GPU busy when a level has few blocks.
+constexpr int kExpRows = 16;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_expand(const cplx_t<T> *__restrict__ WH,
                                                 const cplx_t<T> *__restrict__ Tinv, int nI,
@@ -175,7 +181,7 @@ __global__ __launch_bounds__(256) void k_expand(const cplx_t<T> *__restrict__ WH
   using C = cplx_t<T>;
   __shared__ C eBs[kMaxB];
   __shared__ C rI[kMaxI];
-  const int b = blockIdx.x;
+  const int b = blockIdx.x, i0 = blockIdx.y * kExpRows, i1 = min(nI, i0 + kExpRows);
   for (int sl = threadIdx.x; sl < nBf; sl += 256) {
     const int m = blkBm[(int64_t)b * nBf + sl];
     C v;
@@ -189,7 +195,7 @@ __global__ __launch_bounds__(256) void k_expand(const cplx_t<T> *__restrict__ WH
   const C *W = WH + (int64_t)b * nBf * nI;
   const C *Ti = Tinv + (int64_t)b * nI * nI;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = wave; i < nI; i += 4) {
+  for (int i = i0 + wave; i < i1; i += 4) {
     C u, v;
     u.x = u.y = 0;
     v.x = v.y = 0;
@@ -254,6 +260,14 @@ __global__ __launch_bounds__(256) void k_fields(const double2 *__restrict__ recL
     __syncthreads();
   }
   for (int i = threadIdx.x; i < nf; i += 256) out[(int64_t)e * nf + i] = v[i];
+}
+
+template <typename C> __global__ void k_zero(int64_t n, C *a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    a[i].x = 0;
+    a[i].y = 0;
+  }
 }
 
 __global__ void k_to32(int64_t n, const double2 *a, float2 *b) {
@@ -440,8 +454,8 @@ void launch_expand(const cplx_t<T> *WH, const cplx_t<T> *Tinv, int nI, int nBf,
   hipLaunchKernelGGL((k_scatter_macro<T>), dim3(cdiv(nM, 256)), dim3(256), 0, s, nM, macro_B, eB,
                      ec);
   LAUNCH_OK();
-  hipLaunchKernelGGL((k_expand<T>), dim3(nblk), dim3(256), 0, s, WH, Tinv, nI, nBf, blkI, blkBm,
-                     rc, eB, ec);
+  hipLaunchKernelGGL((k_expand<T>), dim3(nblk, cdiv(nI, kExpRows)), dim3(256), 0, s, WH, Tinv, nI,
+                     nBf, blkI, blkBm, rc, eB, ec);
   LAUNCH_OK();
 }
 
@@ -459,6 +473,14 @@ void launch_fields(const double2 *recL, const double2 *recY, int nf, int ntr, in
                      x, out);
   LAUNCH_OK();
 }
+
+template <typename C> void launch_zero(int64_t n, C *a, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_zero<C>), dim3(cdiv(n, 256)), dim3(256), 0, s, n, a);
+  LAUNCH_OK();
+}
+template void launch_zero<double2>(int64_t, double2 *, hipStream_t);
+template void launch_zero<float2>(int64_t, float2 *, hipStream_t);
 
 void launch_to32(int64_t n, const double2 *a, float2 *b, hipStream_t s) {
   hipLaunchKernelGGL(k_to32, dim3(cdiv(n, 256)), dim3(256), 0, s, n, a, b);

@@ -18,8 +18,9 @@ void launch_copy_sub(const double2 *src, int64_t src_stride, int lds, int r0, in
                      int cols, double2 *dst, int64_t dst_stride, int ldd, int count,
                      hipStream_t s);
 
-// Patch block S_v (n_v x n_v) gathered from the macro blocks of the <= 8 coarse
-// cells around vertex v: S[i,j] = sum_c M_c[slot_c(i), slot_c(j)].
+// Lower triangle of the patch block S_v (n_v x n_v) gathered from the macro
+// blocks of the <= 8 coarse cells around vertex v: S[i,j] = sum_c M_c[slot_c(i),
+// slot_c(j)], j <= i.
 void launch_patch_gather(const double2 *Mfull, int nBf, int Nc, const int64_t *patch_ptr,
                          const int32_t *patch_slot, int v0, int count, int nmax,
                          const int64_t *dst_off, double2 *S, hipStream_t s);
@@ -67,6 +68,9 @@ void launch_assemble_vec(int64_t n, const int32_t *ptr, const int32_t *ent, cons
 // Y = L^-1 [K_ft | b_f] kept from the element stage.  out[e][nf].
 void launch_fields(const double2 *recL, const double2 *recY, int nf, int ntr, int nrhs, int col,
                    const int32_t *edofs, int nel, const double2 *x, double2 *out, hipStream_t s);
+
+// a[0..n) = 0 (a kernel, not a memset: safe inside captured graphs).
+template <typename C> void launch_zero(int64_t n, C *a, hipStream_t s);
 
 // Conversions between the FP64 and FP32 copies of a vector.
 void launch_to32(int64_t n, const double2 *a, float2 *b, hipStream_t s);
