@@ -69,34 +69,43 @@ void set_loads(dpg_ctx *c, const dpg_load *loads, int nrhs) {
   HIP_OK(hipStreamSynchronize(c->stream));
 }
 
-template <class Item> void upload_items(DevBuf<Item> &d, const std::vector<Item> &h, dpg_ctx *c) {
-  d.upload(h, &c->bud, c->stream);
-}
-
-void check_info(DevBuf<int> &info, int count, dpg_ctx *c, const char *what, int base) {
+// Throws DPG_ENOTPD for the first item whose Cholesky met a non-positive
+// pivot (info[i] = j + 1 for pivot j of item i).
+void check_infos(const int *info, int64_t count, hipStream_t s, const char *what) {
+  if (count <= 0) return;
   std::vector<int> h(count);
-  HIP_OK(hipMemcpyAsync(h.data(), info.p, count * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIP_OK(hipStreamSynchronize(c->stream));
-  for (int i = 0; i < count; ++i)
+  HIP_OK(hipMemcpyAsync(h.data(), info, count * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  for (int64_t i = 0; i < count; ++i)
     if (h[i] != 0)
-      throw DpgError(DPG_ENOTPD, std::string(what) + " " + std::to_string(base + i) +
+      throw DpgError(DPG_ENOTPD, std::string(what) + " " + std::to_string(i) +
                                      ": Cholesky pivot " + std::to_string(h[i] - 1) +
                                      " is not positive");
 }
 
+// Make stream b wait for everything queued on stream a so far.
+void stream_wait(hipStream_t a, hipStream_t b, hipEvent_t ev) {
+  HIP_OK(hipEventRecord(ev, a));
+  HIP_OK(hipStreamWaitEvent(b, ev, 0));
+}
+
 // ---- element stage -----------------------------------------------------------------
 
-void element_stage(dpg_ctx *c, bool write_matrices) {
-  LevelData &f = c->lv[c->L];
-  const int nt = c->n_test, nf = c->n_field, ntr = c->n_tr, m = c->m, nr = c->nrhs;
-  const int mp = m + nr;
-  const int nel = f.nel;
+void plan_elements(dpg_ctx *c) {
+  ElemPlan &P = c->ep;
+  const int nt = c->n_test, nf = c->n_field, mp = c->m + c->nrhs;
+  if (P.mp == mp) return;
+  const int nel = c->lv[c->L].nel;
   const int64_t per = 16LL * ((int64_t)nt * nt + (int64_t)nt * mp + (int64_t)mp * mp);
-  int C = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nel, 2500000000LL / per, 65535}));
-  DevBuf<double2> G, BL, K;
-  G.alloc((int64_t)C * nt * nt, &c->bud);
-  BL.alloc((int64_t)C * nt * mp, &c->bud);
-  K.alloc((int64_t)C * mp * mp, &c->bud);
+  const int C = (int)std::max<int64_t>(
+      1, std::min<int64_t>({(int64_t)(nel + 1) / 2, 2500000000LL / per, 65535}));
+  Budget *bd = &c->bud;
+  for (int k = 0; k < 2; ++k) {
+    P.G[k].ensure((int64_t)C * nt * nt, bd);
+    P.BL[k].ensure((int64_t)C * nt * mp, bd);
+    P.K[k].ensure((int64_t)C * mp * mp, bd);
+    P.wk[k].ensure(dense_work_size(C, nt), bd);
+  }
   std::vector<PotrfItem> pG(C), pK(C);
   std::vector<TrsmItem> tG(C), tK(C);
   std::vector<GemmItem> gK(C), gS(C);
@@ -110,105 +119,114 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
     gS[i] = {oK + (int64_t)nf * mp, oK + (int64_t)nf * mp, oK + nf + (int64_t)nf * mp,
              mp - nf, mp - nf, nf, mp, mp, mp};
   }
-  DevBuf<PotrfItem> dpG, dpK;
-  DevBuf<TrsmItem> dtG, dtK;
-  DevBuf<GemmItem> dgK, dgS;
-  upload_items(dpG, pG, c);
-  upload_items(dpK, pK, c);
-  upload_items(dtG, tG, c);
-  upload_items(dtK, tK, c);
-  upload_items(dgK, gK, c);
-  upload_items(dgS, gS, c);
-  DevBuf<int> info;
-  info.alloc(C, &c->bud);
-  DevBuf<double2> wk;   // diagonal-block inverses of the factorisations
-  wk.alloc(dense_work_size(C, nt), &c->bud);
+  P.pG.upload(pG, bd, c->stream);
+  P.pK.upload(pK, bd, c->stream);
+  P.tG.upload(tG, bd, c->stream);
+  P.tK.upload(tK, bd, c->stream);
+  P.gK.upload(gK, bd, c->stream);
+  P.gS.upload(gS, bd, c->stream);
+  P.info.ensure(2LL * nel, bd);
+  HIP_OK(hipStreamSynchronize(c->stream));
+  P.C = C;
+  P.mp = mp;
+}
+
+// Per element (Sec. 1.2): Gram matrix G and [B | l]; G = L L^H;
+// W = L^-1 [B | l]; K = W^H W; static condensation of the field block of K.
+// Chunks of elements alternate between the context's two streams.
+void element_stage(dpg_ctx *c, bool write_matrices) {
+  plan_elements(c);
+  ElemPlan &P = c->ep;
+  LevelData &f = c->lv[c->L];
+  const int nt = c->n_test, nf = c->n_field, ntr = c->n_tr, m = c->m, nr = c->nrhs;
+  const int mp = m + nr, C = P.C, nel = f.nel;
   ElemGeom g{c->N, c->side / c->N, c->omega, 1.0, {c->org[0], c->org[1], c->org[2]}};
-  const hipStream_t s = c->stream;
-  for (int e0 = 0; e0 < nel; e0 += C) {
-    const int cnt = std::min(C, nel - e0);
+  stream_wait(c->stream, c->aux, c->ev_fork);
+  for (int e0 = 0, k = 0; e0 < nel; e0 += C, ++k) {
+    const int cnt = std::min(C, nel - e0), u = k & 1;
+    const hipStream_t s = u ? c->aux : c->stream;
+    double2 *G = P.G[u].p, *BL = P.BL[u].p, *K = P.K[u].p, *wk = P.wk[u].p;
     {
-      PROF(DPG_K_GRAM, 0);
-      launch_gram(c->tables.p, c->testd.p, nt, g, c->kappa.p, e0, cnt, G.p, s);
+      ProfScope ps(&c->prof, DPG_K_GRAM, 0, s);
+      launch_gram(c->tables.p, c->testd.p, nt, g, c->kappa.p, e0, cnt, G, s);
     }
     {
-      PROF(DPG_K_BMAT, 0);
+      ProfScope ps(&c->prof, DPG_K_BMAT, 0, s);
       launch_bmat(c->tables.p, c->testd.p, c->triald.p, nt, m, g, c->kappa.p, c->Zel.p, e0, cnt,
-                  BL.p, (int64_t)nt * mp, s);
+                  BL, (int64_t)nt * mp, s);
     }
     {
-      PROF(DPG_K_LOAD, 0);
-      launch_load(c->tables.p, nt, m, g, c->Zel.p, c->ld.p, c->src.p, nr, e0, cnt, BL.p,
+      ProfScope ps(&c->prof, DPG_K_LOAD, 0, s);
+      launch_load(c->tables.p, nt, m, g, c->Zel.p, c->ld.p, c->src.p, nr, e0, cnt, BL,
                   (int64_t)nt * mp, s);
     }
     {
-      PROF(DPG_K_POTRF, cnt * f_potrf(nt));
-      potrf_batched(G.p, dpG.p, cnt, info.p, nt, wk.p, s);
-    }
-    check_info(info, cnt, c, "element Gram matrix", e0);
-    {
-      PROF(DPG_K_TRSM, cnt * f_trsm(nt, mp));
-      trsm_batched(G.p, BL.p, dtG.p, cnt, nt, mp, false, wk.p, true, s);
+      ProfScope ps(&c->prof, DPG_K_POTRF, cnt * f_potrf(nt), s);
+      potrf_batched(G, P.pG.p, cnt, P.info.p + e0, nt, wk, s);
     }
     {
-      PROF(DPG_K_GEMM, cnt * f_herk(mp, nt));
-      gemm_batched(OP_C, OP_N, mk(1, 0), BL.p, BL.p, mk(0, 0), K.p, dgK.p, cnt, mp, mp, s);
+      ProfScope ps(&c->prof, DPG_K_TRSM, cnt * f_trsm(nt, mp), s);
+      trsm_batched(G, BL, P.tG.p, cnt, nt, mp, false, wk, true, s);
     }
     {
-      PROF(DPG_K_POTRF, cnt * f_potrf(nf));
-      potrf_batched(K.p, dpK.p, cnt, info.p, nf, wk.p, s);
-    }
-    check_info(info, cnt, c, "element field block", e0);
-    {
-      PROF(DPG_K_TRSM, cnt * f_trsm(nf, mp - nf));
-      trsm_batched(K.p, K.p, dtK.p, cnt, nf, mp - nf, false, wk.p, true, s);
+      ProfScope ps(&c->prof, DPG_K_GEMM, cnt * f_herk(mp, nt), s);
+      gemm_batched(OP_C, OP_N, mk(1, 0), BL, BL, mk(0, 0), K, P.gK.p, cnt, mp, mp, s);
     }
     {
-      PROF(DPG_K_GEMM, cnt * f_herk(mp - nf, nf));
-      gemm_batched(OP_C, OP_N, mk(-1, 0), K.p, K.p, mk(1, 0), K.p, dgS.p, cnt, mp - nf, mp - nf, s);
+      ProfScope ps(&c->prof, DPG_K_POTRF, cnt * f_potrf(nf), s);
+      potrf_batched(K, P.pK.p, cnt, P.info.p + nel + e0, nf, wk, s);
+    }
+    {
+      ProfScope ps(&c->prof, DPG_K_TRSM, cnt * f_trsm(nf, mp - nf), s);
+      trsm_batched(K, K, P.tK.p, cnt, nf, mp - nf, false, wk, true, s);
+    }
+    {
+      ProfScope ps(&c->prof, DPG_K_GEMM, cnt * f_herk(mp - nf, nf), s);
+      gemm_batched(OP_C, OP_N, mk(-1, 0), K, K, mk(1, 0), K, P.gS.p, cnt, mp - nf, mp - nf, s);
     }
     if (write_matrices)
-      launch_copy_sub(K.p, (int64_t)mp * mp, mp, nf, nf, ntr, ntr, f.E.p + (int64_t)e0 * ntr * ntr,
+      launch_copy_sub(K, (int64_t)mp * mp, mp, nf, nf, ntr, ntr, f.E.p + (int64_t)e0 * ntr * ntr,
                       (int64_t)ntr * ntr, ntr, cnt, s);
     for (int r = 0; r < nr; ++r)
-      launch_copy_sub(K.p, (int64_t)mp * mp, mp, nf, m + r, ntr, 1,
+      launch_copy_sub(K, (int64_t)mp * mp, mp, nf, m + r, ntr, 1,
                       c->s_elem.p + ((int64_t)r * nel + e0) * ntr, ntr, ntr, cnt, s);
     if (c->keep_recovery) {
-      launch_copy_sub(K.p, (int64_t)mp * mp, mp, 0, 0, nf, nf, c->rec_L.p + (int64_t)e0 * nf * nf,
+      launch_copy_sub(K, (int64_t)mp * mp, mp, 0, 0, nf, nf, c->rec_L.p + (int64_t)e0 * nf * nf,
                       (int64_t)nf * nf, nf, cnt, s);
-      launch_copy_sub(K.p, (int64_t)mp * mp, mp, 0, nf, nf, mp - nf,
+      launch_copy_sub(K, (int64_t)mp * mp, mp, 0, nf, nf, mp - nf,
                       c->rec_Y.p + (int64_t)e0 * nf * (mp - nf), (int64_t)nf * (mp - nf), nf, cnt,
                       s);
     }
   }
+  stream_wait(c->aux, c->stream, c->ev_join);
   // assembled loads
   for (int r = 0; r < nr; ++r)
     launch_assemble_vec(f.num.n, c->asm_ptr.p, c->asm_ent.p, c->s_elem.p + (int64_t)r * nel * ntr,
-                        0, c->s_asm.p + (int64_t)r * f.num.n, s);
-  HIP_OK(hipStreamSynchronize(s));
+                        0, c->s_asm.p + (int64_t)r * f.num.n, c->stream);
+  check_infos(P.info.p, nel, c->stream, "element Gram matrix");
+  check_infos(P.info.p + nel, nel, c->stream, "element field block");
 }
 
 // ---- hierarchy -------------------------------------------------------------------------
 
-void build_macro_level(dpg_ctx *c, int l) {
+// Chunk size of the macro blocks of a level and the shared workspace sizes.
+int macro_chunk(dpg_ctx *c, const LevelData &f) {
+  const int ntr = c->n_tr, nBf = f.nBf, nI = f.nI, nT = nBf + nI;
+  const int64_t per = 16LL * ((int64_t)nT * nT + (int64_t)nI * nI + (int64_t)nBf * ntr);
+  return (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)f.nblk, 2500000000LL / per, 65535}));
+}
+
+void plan_macro(dpg_ctx *c, int l) {
   LevelData &f = c->lv[l];
-  LevelData &cl = c->lv[l - 1];
+  MacroPlan &P = f.mp;
+  if (P.ready) return;
   const hipStream_t s = c->stream;
+  Budget *bd = &c->bud;
   const int ntr = c->n_tr, nBf = f.nBf, nI = f.nI, nT = nBf + nI, nblk = f.nblk;
-  cl.E.alloc((int64_t)nblk * ntr * ntr, &c->bud);
-  f.Mfull.alloc((int64_t)nblk * nBf * nBf, &c->bud);
-  f.Tinv.alloc((int64_t)nblk * nI * nI, &c->bud);
-  f.WH.alloc((int64_t)nblk * nBf * nI, &c->bud);
+  const int CB = macro_chunk(c, f);
   std::vector<double2> ploc_h(f.P.local.size());
   for (size_t i = 0; i < ploc_h.size(); ++i) ploc_h[i] = mk(f.P.local[i], 0.0);
-  DevBuf<double2> Ploc;
-  Ploc.upload(ploc_h, &c->bud, s);
-  const int64_t per = 16LL * ((int64_t)nT * nT + (int64_t)nI * nI + (int64_t)nBf * ntr);
-  const int CB = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nblk, 2500000000LL / per, 65535}));
-  DevBuf<double2> T, Linv, X;
-  T.alloc((int64_t)CB * nT * nT, &c->bud);
-  Linv.alloc((int64_t)CB * nI * nI, &c->bud);
-  X.alloc((int64_t)CB * nBf * ntr, &c->bud);
+  P.Ploc.upload(ploc_h, bd, s);
   std::vector<PotrfItem> pII(CB);
   std::vector<TrsmItem> tIB(CB), tLi(CB);
   std::vector<GemmItem> gS(CB), gTi(CB), gWH(CB), gX(CB), gA(CB);
@@ -227,125 +245,130 @@ void build_macro_level(dpg_ctx *c, int l) {
     gA[i] = {0, (int64_t)i * nBf * ntr, (int64_t)i * ntr * ntr, ntr, ntr, nBf, nBf, nBf, ntr};
     idoff[i] = oL;
   }
-  DevBuf<PotrfItem> dpII;
-  DevBuf<TrsmItem> dtIB, dtLi;
-  DevBuf<GemmItem> dgS, dgTi, dgWH, dgX, dgA;
-  DevBuf<int64_t> didoff;
-  DevBuf<int32_t> didn;
-  upload_items(dpII, pII, c);
-  upload_items(dtIB, tIB, c);
-  upload_items(dtLi, tLi, c);
-  upload_items(dgS, gS, c);
-  upload_items(dgTi, gTi, c);
-  upload_items(dgWH, gWH, c);
-  upload_items(dgX, gX, c);
-  upload_items(dgA, gA, c);
-  didoff.upload(idoff, &c->bud, s);
-  didn.upload(idn, &c->bud, s);
-  DevBuf<int32_t> cmap;
-  cmap.upload(f.mc.child_map, &c->bud, s);
-  DevBuf<int> info;
-  info.alloc(CB, &c->bud);
-  DevBuf<double2> wk;
-  wk.alloc(dense_work_size(CB, nI), &c->bud);
-  for (int b0 = 0; b0 < nblk; b0 += CB) {
-    const int cnt = std::min(CB, nblk - b0);
-    {
-      PROF(DPG_K_MACRO_ASM, 0);
-      launch_macro_assemble(f.E.p, ntr, cmap.p, f.N, b0, cnt, nT, T.p, s);
-    }
-    {
-      PROF(DPG_K_POTRF, cnt * f_potrf(nI));
-      potrf_batched(T.p, dpII.p, cnt, info.p, nI, wk.p, s);
-    }
-    check_info(info, cnt, c, "interior block of coarse element", b0);
-    {
-      PROF(DPG_K_TRSM, cnt * f_trsm(nI, nBf));
-      trsm_batched(T.p, T.p, dtIB.p, cnt, nI, nBf, false, wk.p, true, s);
-    }
-    {
-      PROF(DPG_K_GEMM, cnt * f_herk(nBf, nI));
-      gemm_batched(OP_C, OP_N, mk(-1, 0), T.p, T.p, mk(1, 0), T.p, dgS.p, cnt, nBf, nBf, s);
-    }
-    {
-      PROF(DPG_K_OTHER, 0);
-      launch_identity(didoff.p, didn.p, cnt, nI, Linv.p, s);
-    }
-    {
-      PROF(DPG_K_TRSM, cnt * f_trsm(nI, nI));
-      trsm_batched(T.p, Linv.p, dtLi.p, cnt, nI, nI, true, wk.p, true, s);
-    }
-    {
-      PROF(DPG_K_GEMM, cnt * f_herk(nI, nI));
-      gemm_batched(OP_C, OP_N, mk(1, 0), Linv.p, Linv.p, mk(0, 0), f.Tinv.p + (int64_t)b0 * nI * nI,
-                   dgTi.p, cnt, nI, nI, s);
-    }
-    {
-      PROF(DPG_K_GEMM, cnt * f_gemm(nBf, nI, nI));
-      gemm_batched(OP_C, OP_N, mk(1, 0), T.p, Linv.p, mk(0, 0), f.WH.p + (int64_t)b0 * nBf * nI,
-                   dgWH.p, cnt, nBf, nI, s);
-    }
-    {
-      PROF(DPG_K_OTHER, 0);
-      launch_copy_sub(T.p, (int64_t)nT * nT, nT, 0, 0, nBf, nBf, f.Mfull.p + (int64_t)b0 * nBf * nBf,
-                      (int64_t)nBf * nBf, nBf, cnt, s);
-    }
-    {
-      PROF(DPG_K_GEMM, cnt * (f_gemm(nBf, ntr, nBf) + f_gemm(ntr, ntr, nBf)));
-      gemm_batched(OP_N, OP_N, mk(1, 0), T.p, Ploc.p, mk(0, 0), X.p, dgX.p, cnt, nBf, ntr, s);
-      gemm_batched(OP_T, OP_N, mk(1, 0), Ploc.p, X.p, mk(0, 0), cl.E.p + (int64_t)b0 * ntr * ntr,
-                   dgA.p, cnt, ntr, ntr, s);
-    }
-  }
-  HIP_OK(hipStreamSynchronize(s));
-  if (c->opt.precision == DPG_MIXED && l < c->L) {
-    f.Tinv32.alloc(f.Tinv.n, &c->bud);
-    f.WH32.alloc(f.WH.n, &c->bud);
-    launch_to32(f.Tinv.n, f.Tinv.p, f.Tinv32.p, s);
-    launch_to32(f.WH.n, f.WH.p, f.WH32.p, s);
-  }
-  // macro blocks -> packed tiles (present slots only)
+  P.pII.upload(pII, bd, s);
+  P.tIB.upload(tIB, bd, s);
+  P.tLi.upload(tLi, bd, s);
+  P.gS.upload(gS, bd, s);
+  P.gTi.upload(gTi, bd, s);
+  P.gWH.upload(gWH, bd, s);
+  P.gX.upload(gX, bd, s);
+  P.gA.upload(gA, bd, s);
+  P.idoff.upload(idoff, bd, s);
+  P.idn.upload(idn, bd, s);
+  P.cmap.upload(f.mc.child_map, bd, s);
   std::vector<int64_t> soff(nblk), moff(nblk);
   std::vector<int32_t> sld(nblk, nBf);
   for (int b = 0; b < nblk; ++b) {
     soff[b] = (int64_t)b * nBf * nBf;
     moff[b] = f.mc.blkB_ptr[b];
   }
-  DevBuf<int64_t> dsoff, dmoff;
-  DevBuf<int32_t> dsld, dmap;
-  dsoff.upload(soff, &c->bud, s);
-  dmoff.upload(moff, &c->bud, s);
-  dsld.upload(sld, &c->bud, s);
-  dmap.upload(f.mc.blkB_present, &c->bud, s);
-  f.Mset.pack(f.Mfull.p, dsoff.p, dsld.p, dmoff.p, dmap.p, s);
+  P.soff.upload(soff, bd, s);
+  P.moff.upload(moff, bd, s);
+  P.sld.upload(sld, bd, s);
+  P.map.upload(f.mc.blkB_present, bd, s);
+  P.info.ensure(nblk, bd);
+  // level outputs and the shared workspaces (the finest level has the most blocks)
+  LevelData &cl = c->lv[l - 1];
+  cl.E.ensure((int64_t)nblk * ntr * ntr, bd);
+  f.Mfull.ensure((int64_t)nblk * nBf * nBf, bd);
+  f.Tinv.ensure((int64_t)nblk * nI * nI, bd);
+  f.WH.ensure((int64_t)nblk * nBf * nI, bd);
+  if (c->opt.precision == DPG_MIXED && l < c->L) {
+    f.Tinv32.ensure(f.Tinv.n, bd);
+    f.WH32.ensure(f.WH.n, bd);
+  }
+  if (c->mT.n < (int64_t)CB * nT * nT) c->mT.alloc((int64_t)CB * nT * nT, bd);
+  if (c->mLinv.n < (int64_t)CB * nI * nI) c->mLinv.alloc((int64_t)CB * nI * nI, bd);
+  if (c->mX.n < (int64_t)CB * nBf * ntr) c->mX.alloc((int64_t)CB * nBf * ntr, bd);
+  if (c->mwk.n < dense_work_size(CB, nI)) c->mwk.alloc(dense_work_size(CB, nI), bd);
   HIP_OK(hipStreamSynchronize(s));
+  P.CB = CB;
+  P.ready = true;
 }
 
-void build_patches(dpg_ctx *c, int l) {
+// Macro condensation of level l (Sec. 3) and the Galerkin element matrices of
+// level l - 1, on the main stream.
+void build_macro_level(dpg_ctx *c, int l) {
   LevelData &f = c->lv[l];
+  LevelData &cl = c->lv[l - 1];
+  MacroPlan &P = f.mp;
   const hipStream_t s = c->stream;
+  const int ntr = c->n_tr, nBf = f.nBf, nI = f.nI, nT = nBf + nI, nblk = f.nblk, CB = P.CB;
+  double2 *T = c->mT.p, *Linv = c->mLinv.p, *X = c->mX.p, *wk = c->mwk.p;
+  for (int b0 = 0; b0 < nblk; b0 += CB) {
+    const int cnt = std::min(CB, nblk - b0);
+    {
+      PROF(DPG_K_MACRO_ASM, 0);
+      launch_macro_assemble(f.E.p, ntr, P.cmap.p, f.N, b0, cnt, nT, T, s);
+    }
+    {
+      PROF(DPG_K_POTRF, cnt * f_potrf(nI));
+      potrf_batched(T, P.pII.p, cnt, P.info.p + b0, nI, wk, s);
+    }
+    {
+      PROF(DPG_K_TRSM, cnt * f_trsm(nI, nBf));
+      trsm_batched(T, T, P.tIB.p, cnt, nI, nBf, false, wk, true, s);
+    }
+    {
+      PROF(DPG_K_GEMM, cnt * f_herk(nBf, nI));
+      gemm_batched(OP_C, OP_N, mk(-1, 0), T, T, mk(1, 0), T, P.gS.p, cnt, nBf, nBf, s);
+    }
+    {
+      PROF(DPG_K_OTHER, 0);
+      launch_identity(P.idoff.p, P.idn.p, cnt, nI, Linv, s);
+    }
+    {
+      PROF(DPG_K_TRSM, cnt * f_trsm(nI, nI));
+      trsm_batched(T, Linv, P.tLi.p, cnt, nI, nI, true, wk, true, s);
+    }
+    {
+      PROF(DPG_K_GEMM, cnt * f_herk(nI, nI));
+      gemm_batched(OP_C, OP_N, mk(1, 0), Linv, Linv, mk(0, 0), f.Tinv.p + (int64_t)b0 * nI * nI,
+                   P.gTi.p, cnt, nI, nI, s);
+    }
+    {
+      PROF(DPG_K_GEMM, cnt * f_gemm(nBf, nI, nI));
+      gemm_batched(OP_C, OP_N, mk(1, 0), T, Linv, mk(0, 0), f.WH.p + (int64_t)b0 * nBf * nI,
+                   P.gWH.p, cnt, nBf, nI, s);
+    }
+    {
+      PROF(DPG_K_OTHER, 0);
+      launch_copy_sub(T, (int64_t)nT * nT, nT, 0, 0, nBf, nBf, f.Mfull.p + (int64_t)b0 * nBf * nBf,
+                      (int64_t)nBf * nBf, nBf, cnt, s);
+    }
+    {
+      PROF(DPG_K_GEMM, cnt * (f_gemm(nBf, ntr, nBf) + f_gemm(ntr, ntr, nBf)));
+      gemm_batched(OP_N, OP_N, mk(1, 0), T, P.Ploc.p, mk(0, 0), X, P.gX.p, cnt, nBf, ntr, s);
+      gemm_batched(OP_T, OP_N, mk(1, 0), P.Ploc.p, X, mk(0, 0), cl.E.p + (int64_t)b0 * ntr * ntr,
+                   P.gA.p, cnt, ntr, ntr, s);
+    }
+  }
+  if (c->opt.precision == DPG_MIXED && l < c->L) {
+    launch_to32(f.Tinv.n, f.Tinv.p, f.Tinv32.p, s);
+    launch_to32(f.WH.n, f.WH.p, f.WH32.p, s);
+  }
+  // macro blocks -> packed tiles (present slots only)
+  f.Mset.pack(f.Mfull.p, P.soff.p, P.sld.p, P.moff.p, P.map.p, s);
+}
+
+void plan_patches(dpg_ctx *c, int l) {
+  LevelData &f = c->lv[l];
+  PatchPlan &P = f.pp;
+  if (P.ready) return;
+  const hipStream_t s = c->stream;
+  Budget *bd = &c->bud;
   const int np = (int)f.mc.patch_ptr.size() - 1;
   std::vector<int32_t> nv(np);
-  for (int v = 0; v < np; ++v) nv[v] = (int32_t)(f.mc.patch_ptr[v + 1] - f.mc.patch_ptr[v]);
-  const int64_t cap = 6000000000LL / 16;   // entries per workspace (S and X): 6 GB each
-  int64_t maxent = 0;
-  for (int v = 0; v < np; ++v) maxent = std::max<int64_t>(maxent, (int64_t)nv[v] * nv[v]);
-  const int64_t ws = std::max(cap, maxent);
-  DevBuf<double2> S, X;
-  S.alloc(ws, &c->bud);
-  X.alloc(ws, &c->bud);
-  DevBuf<int> info;
-  info.alloc(std::min(np, 65535), &c->bud);
   int nv_max = 0;
-  for (int v = 0; v < np; ++v) nv_max = std::max(nv_max, (int)nv[v]);
-  DevBuf<double2> wk;
-  wk.alloc(dense_work_size(std::min(np, 65535), nv_max), &c->bud);
+  int64_t maxent = 0;
+  for (int v = 0; v < np; ++v) {
+    nv[v] = (int32_t)(f.mc.patch_ptr[v + 1] - f.mc.patch_ptr[v]);
+    nv_max = std::max(nv_max, (int)nv[v]);
+    maxent = std::max<int64_t>(maxent, (int64_t)nv[v] * nv[v]);
+  }
+  const int64_t ws = std::max<int64_t>(6000000000LL / 16, maxent);   // entries of S and X: 6 GB each
   std::vector<int64_t> soff_all(np, 0);
-  DevBuf<int64_t> dsoff_all;
-  DevBuf<int32_t> dld_all;
-  dsoff_all.alloc(np, &c->bud);
-  dld_all.upload(nv, &c->bud, s);
-  int v0 = 0;
+  int v0 = 0, maxcnt = 0;
   while (v0 < np) {
     int cnt = 0;
     int64_t used = 0;
@@ -353,113 +376,149 @@ void build_patches(dpg_ctx *c, int l) {
       used += (int64_t)nv[v0 + cnt] * nv[v0 + cnt];
       ++cnt;
     }
+    PatchBatch B;
+    B.v0 = v0;
+    B.cnt = cnt;
     std::vector<int64_t> off(cnt);
     std::vector<int32_t> nn(cnt);
     std::vector<PotrfItem> pi(cnt);
     std::vector<TrsmItem> ti(cnt);
     std::vector<GemmItem> gi(cnt);
     int64_t o = 0;
-    int nmax = 0;
     for (int i = 0; i < cnt; ++i) {
       const int n = nv[v0 + i];
       off[i] = o;
       nn[i] = n;
-      nmax = std::max(nmax, n);
+      B.nmax = std::max(B.nmax, n);
       pi[i] = {o, n, n};
       ti[i] = {o, o, n, n, n, n};
       gi[i] = {o, o, o, n, n, n, n, n, n};
       soff_all[v0 + i] = o;
       o += (int64_t)n * n;
+      B.fp += f_potrf(n);
+      B.ft += f_trsm(n, n) / 3.0;   // identity right-hand side: L^-1 only
+      B.fg += f_herk(n, n) / 3.0;   // X^H X with X triangular
     }
-    DevBuf<int64_t> doff;
-    DevBuf<int32_t> dnn;
-    DevBuf<PotrfItem> dpi;
-    DevBuf<TrsmItem> dti;
-    DevBuf<GemmItem> dgi;
-    doff.upload(off, &c->bud, s);
-    dnn.upload(nn, &c->bud, s);
-    upload_items(dpi, pi, c);
-    upload_items(dti, ti, c);
-    upload_items(dgi, gi, c);
-    HIP_OK(hipMemcpyAsync(dsoff_all.p, soff_all.data(), np * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    double fp = 0, ft = 0, fg = 0;
-    for (int i = 0; i < cnt; ++i) {
-      fp += f_potrf(nn[i]);
-      ft += f_trsm(nn[i], nn[i]) / 3.0;   // identity right-hand side: L^-1 only
-      fg += f_herk(nn[i], nn[i]) / 3.0;   // X^H X with X triangular
+    B.off.upload(off, bd, s);
+    B.nn.upload(nn, bd, s);
+    B.pi.upload(pi, bd, s);
+    B.ti.upload(ti, bd, s);
+    B.gi.upload(gi, bd, s);
+    B.t0 = f.Sset.tile_off_h[v0];
+    B.t1 = (v0 + cnt < np) ? f.Sset.tile_off_h[v0 + cnt] : f.Sset.ntiles;
+    maxcnt = std::max(maxcnt, cnt);
+    P.batches.push_back(std::move(B));
+    v0 += cnt;
+  }
+  P.soff_all.upload(soff_all, bd, s);
+  P.ld_all.upload(nv, bd, s);
+  P.info.ensure(np, bd);
+  if (c->pS.n < ws) c->pS.alloc(ws, bd);
+  if (c->pX.n < ws) c->pX.alloc(ws, bd);
+  if (c->pwk.n < dense_work_size(maxcnt, nv_max)) c->pwk.alloc(dense_work_size(maxcnt, nv_max), bd);
+  HIP_OK(hipStreamSynchronize(s));
+  P.ready = true;
+}
+
+// Patch blocks of level l (Sec. 3 smoother): gather, Cholesky, explicit
+// inverse, packed tiles; on stream s.
+void build_patches(dpg_ctx *c, int l, hipStream_t s) {
+  LevelData &f = c->lv[l];
+  PatchPlan &P = f.pp;
+  double2 *S = c->pS.p, *X = c->pX.p, *wk = c->pwk.p;
+  for (PatchBatch &B : P.batches) {
+    {
+      ProfScope ps(&c->prof, DPG_K_PATCH_GATHER, 0, s);
+      launch_patch_gather(f.Mfull.p, f.nBf, f.mc.Nc, f.patch_ptr.p, f.patch_slot.p, B.v0, B.cnt,
+                          B.nmax, B.off.p, S, s);
     }
     {
-      PROF(DPG_K_PATCH_GATHER, 0);
-      launch_patch_gather(f.Mfull.p, f.nBf, f.mc.Nc, f.patch_ptr.p, f.patch_slot.p, v0, cnt, nmax,
-                          doff.p, S.p, s);
+      ProfScope ps(&c->prof, DPG_K_POTRF, B.fp, s);
+      potrf_batched(S, B.pi.p, B.cnt, P.info.p + B.v0, B.nmax, wk, s);
     }
     {
-      PROF(DPG_K_POTRF, fp);
-      potrf_batched(S.p, dpi.p, cnt, info.p, nmax, wk.p, s);
-    }
-    check_info(info, cnt, c, "vertex patch", v0);
-    {
-      PROF(DPG_K_OTHER, 0);
-      launch_identity(doff.p, dnn.p, cnt, nmax, X.p, s);
+      ProfScope ps(&c->prof, DPG_K_OTHER, 0, s);
+      launch_identity(B.off.p, B.nn.p, B.cnt, B.nmax, X, s);
     }
     {
-      PROF(DPG_K_TRSM, ft);
-      trsm_batched(S.p, X.p, dti.p, cnt, nmax, nmax, true, wk.p, true, s);
+      ProfScope ps(&c->prof, DPG_K_TRSM, B.ft, s);
+      trsm_batched(S, X, B.ti.p, B.cnt, B.nmax, B.nmax, true, wk, true, s);
     }
     {
-      PROF(DPG_K_GEMM, fg);
-      gemm_batched(OP_C, OP_N, mk(1, 0), X.p, X.p, mk(0, 0), S.p, dgi.p, cnt, nmax, nmax, s,
+      ProfScope ps(&c->prof, DPG_K_GEMM, B.fg, s);
+      gemm_batched(OP_C, OP_N, mk(1, 0), X, X, mk(0, 0), S, B.gi.p, B.cnt, B.nmax, B.nmax, s,
                    GEMM_UPPER_LOWTRI);
     }
-    const int64_t t0 = f.Sset.tile_off_h[v0];
-    const int64_t t1 = (v0 + cnt < np) ? f.Sset.tile_off_h[v0 + cnt] : f.Sset.ntiles;
-    f.Sset.pack(S.p, dsoff_all.p, dld_all.p, nullptr, nullptr, s, t0, t1 - t0);
-    HIP_OK(hipStreamSynchronize(s));
-    v0 += cnt;
+    f.Sset.pack(S, P.soff_all.p, P.ld_all.p, nullptr, nullptr, s, B.t0, B.t1 - B.t0);
   }
 }
 
+void plan_coarsest(dpg_ctx *c) {
+  if (c->zpi.p) return;
+  LevelData &z = c->lv[0];
+  const hipStream_t s = c->stream;
+  Budget *bd = &c->bud;
+  const int n0 = (int)z.num.n;
+  c->T0.ensure((int64_t)n0 * n0, bd);
+  c->zF.ensure((int64_t)n0 * n0, bd);
+  c->zLi.ensure((int64_t)n0 * n0, bd);
+  c->zTi.ensure((int64_t)n0 * n0, bd);
+  c->zwk.ensure(dense_work_size(1, n0), bd);
+  c->zpi.upload(std::vector<PotrfItem>{{0, n0, n0}}, bd, s);
+  c->zti.upload(std::vector<TrsmItem>{{0, 0, n0, n0, n0, n0}}, bd, s);
+  c->zgi.upload(std::vector<GemmItem>{{0, 0, 0, n0, n0, n0, n0, n0, n0}}, bd, s);
+  c->zoff.upload(std::vector<int64_t>{0}, bd, s);
+  c->znn.upload(std::vector<int32_t>{n0}, bd, s);
+  c->zld.upload(std::vector<int32_t>{n0}, bd, s);
+  c->zinfo.ensure(1, bd);
+  HIP_OK(hipStreamSynchronize(s));
+}
+
+// Coarsest operator T_0: assembled, Cholesky, explicit inverse, packed tiles.
 void build_coarsest(dpg_ctx *c) {
   LevelData &z = c->lv[0];
   const hipStream_t s = c->stream;
   const int n0 = (int)z.num.n;
-  c->T0.alloc((int64_t)n0 * n0, &c->bud);
   launch_assemble_dense(z.E.p, c->n_tr, z.edofs.p, z.nel, n0, c->T0.p, s);
-  DevBuf<double2> F, Li, Ti;
-  F.alloc((int64_t)n0 * n0, &c->bud);
-  Li.alloc((int64_t)n0 * n0, &c->bud);
-  Ti.alloc((int64_t)n0 * n0, &c->bud);
-  HIP_OK(hipMemcpyAsync(F.p, c->T0.p, (size_t)n0 * n0 * 16, hipMemcpyDeviceToDevice, s));
-  std::vector<PotrfItem> pi{{0, n0, n0}};
-  std::vector<TrsmItem> ti{{0, 0, n0, n0, n0, n0}};
-  std::vector<GemmItem> gi{{0, 0, 0, n0, n0, n0, n0, n0, n0}};
-  std::vector<int64_t> off{0};
-  std::vector<int32_t> nn{n0};
-  DevBuf<PotrfItem> dpi;
-  DevBuf<TrsmItem> dti;
-  DevBuf<GemmItem> dgi;
-  DevBuf<int64_t> doff;
-  DevBuf<int32_t> dnn;
-  upload_items(dpi, pi, c);
-  upload_items(dti, ti, c);
-  upload_items(dgi, gi, c);
-  doff.upload(off, &c->bud, s);
-  dnn.upload(nn, &c->bud, s);
-  DevBuf<int> info;
-  info.alloc(1, &c->bud);
-  DevBuf<double2> wk;
-  wk.alloc(dense_work_size(1, n0), &c->bud);
-  potrf_batched(F.p, dpi.p, 1, info.p, n0, wk.p, s);
-  check_info(info, 1, c, "coarsest operator", 0);
-  launch_identity(doff.p, dnn.p, 1, n0, Li.p, s);
-  trsm_batched(F.p, Li.p, dti.p, 1, n0, n0, true, wk.p, true, s);
-  gemm_batched(OP_C, OP_N, mk(1, 0), Li.p, Li.p, mk(0, 0), Ti.p, dgi.p, 1, n0, n0, s,
-               GEMM_UPPER_LOWTRI);
-  std::vector<int32_t> ld{n0};
-  DevBuf<int32_t> dld;
-  dld.upload(ld, &c->bud, s);
-  c->T0set.pack(Ti.p, doff.p, dld.p, nullptr, nullptr, s);
-  HIP_OK(hipStreamSynchronize(s));
+  HIP_OK(hipMemcpyAsync(c->zF.p, c->T0.p, (size_t)n0 * n0 * 16, hipMemcpyDeviceToDevice, s));
+  potrf_batched(c->zF.p, c->zpi.p, 1, c->zinfo.p, n0, c->zwk.p, s);
+  launch_identity(c->zoff.p, c->znn.p, 1, n0, c->zLi.p, s);
+  trsm_batched(c->zF.p, c->zLi.p, c->zti.p, 1, n0, n0, true, c->zwk.p, true, s);
+  gemm_batched(OP_C, OP_N, mk(1, 0), c->zLi.p, c->zLi.p, mk(0, 0), c->zTi.p, c->zgi.p, 1, n0, n0,
+               s, GEMM_UPPER_LOWTRI);
+  c->T0set.pack(c->zTi.p, c->zoff.p, c->zld.p, nullptr, nullptr, s);
+}
+
+// The whole hierarchy: macro levels one after the other on the main stream;
+// the patches of level l, which need only that level's macro blocks, on the
+// second stream, overlapping the coarser levels.
+void build_hierarchy(dpg_ctx *c) {
+  for (int l = c->L; l >= 1; --l) {
+    plan_macro(c, l);
+    plan_patches(c, l);
+  }
+  plan_coarsest(c);
+  if ((int)c->ev_level.size() < c->L + 1) {
+    for (int l = (int)c->ev_level.size(); l <= c->L; ++l) {
+      hipEvent_t e;
+      HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      c->ev_level.push_back(e);
+    }
+  }
+  stream_wait(c->stream, c->aux, c->ev_fork);
+  for (int l = c->L; l >= 1; --l) {
+    build_macro_level(c, l);
+    stream_wait(c->stream, c->aux, c->ev_level[l]);
+    build_patches(c, l, c->aux);
+  }
+  build_coarsest(c);
+  stream_wait(c->aux, c->stream, c->ev_join);
+  for (int l = c->L; l >= 1; --l) {
+    check_infos(c->lv[l].mp.info.p, c->lv[l].nblk, c->stream, "interior block of coarse element");
+    check_infos(c->lv[l].pp.info.p, (int64_t)c->lv[l].mc.patch_ptr.size() - 1, c->stream,
+                "vertex patch");
+  }
+  check_infos(c->zinfo.p, 1, c->stream, "coarsest operator");
 }
 
 // ---- V-cycle -----------------------------------------------------------------------------
@@ -923,6 +982,9 @@ int dpg_setup(const dpg_mesh *mesh, int p, int dp, double omega, const dpg_mater
       HIP_OK(hipStreamCreate(&c->own_stream));
       c->stream = c->own_stream;
     }
+    HIP_OK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     c->bud.limit = c->opt.hbm_budget;
     c->N = mesh->n;
     c->p = p;
@@ -1096,12 +1158,12 @@ int dpg_assemble(dpg_ctx *c) {
     if (c->stage < 1) throw DpgError(DPG_ESTATE, "dpg_setup first");
     auto t0 = clk::now();
     LevelData &top = c->lv[c->L];
-    top.E.alloc((int64_t)top.nel * c->n_tr * c->n_tr, &c->bud);
-    c->s_elem.alloc(std::max<int64_t>(1, (int64_t)c->nrhs * top.nel * c->n_tr), &c->bud);
-    c->s_asm.alloc(std::max<int64_t>(1, (int64_t)c->nrhs * top.num.n), &c->bud);
+    top.E.ensure((int64_t)top.nel * c->n_tr * c->n_tr, &c->bud);
+    c->s_elem.ensure(std::max<int64_t>(1, (int64_t)c->nrhs * top.nel * c->n_tr), &c->bud);
+    c->s_asm.ensure(std::max<int64_t>(1, (int64_t)c->nrhs * top.num.n), &c->bud);
     if (c->keep_recovery) {
-      c->rec_L.alloc((int64_t)top.nel * c->n_field * c->n_field, &c->bud);
-      c->rec_Y.alloc((int64_t)top.nel * c->n_field * (c->n_tr + c->nrhs), &c->bud);
+      c->rec_L.ensure((int64_t)top.nel * c->n_field * c->n_field, &c->bud);
+      c->rec_Y.ensure((int64_t)top.nel * c->n_field * (c->n_tr + c->nrhs), &c->bud);
     }
     element_stage(c, true);
     c->prof.flush();
@@ -1116,11 +1178,7 @@ int dpg_build_hierarchy(dpg_ctx *c) {
   return guarded(c, [&]() {
     if (c->stage < 2) throw DpgError(DPG_ESTATE, "dpg_assemble first");
     auto t0 = clk::now();
-    for (int l = c->L; l >= 1; --l) {
-      build_macro_level(c, l);
-      build_patches(c, l);
-    }
-    build_coarsest(c);
+    build_hierarchy(c);
     c->prof.flush();
     c->ms[2] = ms_since(t0);
     c->stage = 3;
@@ -1135,11 +1193,11 @@ int dpg_load_rhs(dpg_ctx *c, const dpg_load *loads, int nrhs, double *s_out) {
     if (nrhs < 1 || !loads) throw DpgError(DPG_EINVAL, "need at least one load");
     LevelData &top = c->lv[c->L];
     set_loads(c, loads, nrhs);
-    c->s_elem.alloc((int64_t)nrhs * top.nel * c->n_tr, &c->bud);
-    c->s_asm.alloc((int64_t)nrhs * top.num.n, &c->bud);
+    c->s_elem.ensure((int64_t)nrhs * top.nel * c->n_tr, &c->bud);
+    c->s_asm.ensure((int64_t)nrhs * top.num.n, &c->bud);
     if (c->keep_recovery) {
-      c->rec_L.alloc((int64_t)top.nel * c->n_field * c->n_field, &c->bud);
-      c->rec_Y.alloc((int64_t)top.nel * c->n_field * (c->n_tr + c->nrhs), &c->bud);
+      c->rec_L.ensure((int64_t)top.nel * c->n_field * c->n_field, &c->bud);
+      c->rec_Y.ensure((int64_t)top.nel * c->n_field * (c->n_tr + c->nrhs), &c->bud);
     }
     element_stage(c, false);
     c->prof.flush();
@@ -1416,6 +1474,13 @@ int64_t dpg_export(const dpg_ctx *cc, int what, int level, void *out, int64_t ca
 void dpg_destroy(dpg_ctx *c) {
   if (!c) return;
   if (c->host_sc) (void)hipHostFree(c->host_sc);
+  if (c->aux) {
+    (void)hipStreamSynchronize(c->aux);
+    (void)hipStreamDestroy(c->aux);
+  }
+  for (hipEvent_t e : {c->ev_fork, c->ev_join})
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->ev_level) (void)hipEventDestroy(e);
   if (c->own_stream) {
     (void)hipStreamSynchronize(c->own_stream);
     (void)hipStreamDestroy(c->own_stream);

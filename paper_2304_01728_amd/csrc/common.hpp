@@ -100,6 +100,10 @@ template <typename T> struct DevBuf {
     n = count;
     if (b) b->used += bytes;
   }
+  // alloc unless the buffer already has exactly count elements (contents kept)
+  void ensure(int64_t count, Budget *b) {
+    if (!(p && n == count)) alloc(count, b);
+  }
   void upload(const std::vector<T> &h, Budget *b, hipStream_t s) {
     alloc((int64_t)h.size(), b);
     if (n) HIP_OK(hipMemcpyAsync(p, h.data(), n * sizeof(T), hipMemcpyHostToDevice, s));

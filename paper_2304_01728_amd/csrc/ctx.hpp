@@ -15,6 +15,54 @@
 
 namespace dpg {
 
+// Prepared once per mesh (and per number of loads): item tables on the device
+// and fixed workspaces, so that the setup phases only queue kernels.
+
+// Element stage: chunks of C elements alternate between two streams, each
+// with its own G, [B l], K and diagonal-block-inverse buffers.
+struct ElemPlan {
+  int C = 0, mp = -1;
+  DevBuf<double2> G[2], BL[2], K[2], wk[2];
+  DevBuf<PotrfItem> pG, pK;
+  DevBuf<TrsmItem> tG, tK;
+  DevBuf<GemmItem> gK, gS;
+  DevBuf<int> info;    // [2 nel]: Gram factor, then field block, per element
+};
+
+// Macro condensation and Galerkin step of one level (workspaces shared by
+// all levels: the levels run one after the other on one stream).
+struct MacroPlan {
+  bool ready = false;
+  int CB = 0;
+  DevBuf<double2> Ploc;
+  DevBuf<PotrfItem> pII;
+  DevBuf<TrsmItem> tIB, tLi;
+  DevBuf<GemmItem> gS, gTi, gWH, gX, gA;
+  DevBuf<int64_t> idoff, soff, moff;
+  DevBuf<int32_t> idn, cmap, sld, map;
+  DevBuf<int> info;    // [nblk]
+};
+
+// Patch factors and inverses of one level, in batches that fit the patch
+// workspaces.
+struct PatchBatch {
+  int v0 = 0, cnt = 0, nmax = 0;
+  int64_t t0 = 0, t1 = 0;
+  double fp = 0, ft = 0, fg = 0;
+  DevBuf<int64_t> off;
+  DevBuf<int32_t> nn;
+  DevBuf<PotrfItem> pi;
+  DevBuf<TrsmItem> ti;
+  DevBuf<GemmItem> gi;
+};
+struct PatchPlan {
+  bool ready = false;
+  std::vector<PatchBatch> batches;
+  DevBuf<int64_t> soff_all;
+  DevBuf<int32_t> ld_all;
+  DevBuf<int> info;    // [npatch]
+};
+
 // One mesh of the hierarchy.  Level 0 is the coarsest mesh, level L the finest.
 struct LevelData {
   int N = 0, nel = 0;
@@ -50,6 +98,8 @@ struct LevelData {
   DevBuf<double2> br64, bx64, bres64, brc64, bec64, bc64;
   DevBuf<float2> br32, bx32, bres32, brc32, bec32, bc32;
   HermBlockBufs Mb, Sb;
+  MacroPlan mp;
+  PatchPlan pp;
 };
 
 }  // namespace dpg
@@ -62,6 +112,9 @@ struct dpg_ctx {
   dpg_options opt{};
   hipStream_t stream = nullptr;
   hipStream_t own_stream = nullptr;  // created when the options give no stream
+  hipStream_t aux = nullptr;         // second stream of the setup phases
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  std::vector<hipEvent_t> ev_level;  // per level: macro blocks ready for the patches
   dpg::Budget bud;
   dpg::ElementLayout el;
   int n_test = 0, n_field = 0, n_tr = 0, m = 0;
@@ -84,6 +137,17 @@ struct dpg_ctx {
   // coarsest mesh
   dpg::DevBuf<double2> T0;
   dpg::HermSet T0set;
+  // setup-phase plans and workspaces
+  dpg::ElemPlan ep;
+  dpg::DevBuf<double2> mT, mLinv, mX, mwk;         // macro levels
+  dpg::DevBuf<double2> pS, pX, pwk;                // patches
+  dpg::DevBuf<double2> zF, zLi, zTi, zwk;          // coarsest
+  dpg::DevBuf<dpg::PotrfItem> zpi;
+  dpg::DevBuf<dpg::TrsmItem> zti;
+  dpg::DevBuf<dpg::GemmItem> zgi;
+  dpg::DevBuf<int64_t> zoff;
+  dpg::DevBuf<int32_t> znn, zld;
+  dpg::DevBuf<int> zinfo;
   // outer CG (FP64, finest macro grid)
   dpg::DevBuf<double2> b, x, r, z, zo, pv, q, xfull, sB;
   dpg::DevBuf<double> partial, sc;
