@@ -366,67 +366,85 @@ void plan_patches(dpg_ctx *c, int l) {
     nv_max = std::max(nv_max, (int)nv[v]);
     maxent = std::max<int64_t>(maxent, (int64_t)nv[v] * nv[v]);
   }
-  const int64_t ws = std::max<int64_t>(6000000000LL / 16, maxent);   // entries of S and X: 6 GB each
+  // two halves of about equal factorisation work (sum n^3), one per stream,
+  // each cut into batches that fit its workspaces (S and X: 3 GB each)
+  const int64_t ws = std::max<int64_t>(3000000000LL / 16, maxent);
+  double tot = 0.0;
+  for (int v = 0; v < np; ++v) tot += (double)nv[v] * nv[v] * nv[v];
+  int vsplit = 0;
+  for (double acc = 0.0; vsplit < np && acc < 0.5 * tot; ++vsplit)
+    acc += (double)nv[vsplit] * nv[vsplit] * nv[vsplit];
   std::vector<int64_t> soff_all(np, 0);
-  int v0 = 0, maxcnt = 0;
-  while (v0 < np) {
-    int cnt = 0;
-    int64_t used = 0;
-    while (v0 + cnt < np && cnt < 65535 && (cnt == 0 || used + (int64_t)nv[v0 + cnt] * nv[v0 + cnt] <= ws)) {
-      used += (int64_t)nv[v0 + cnt] * nv[v0 + cnt];
-      ++cnt;
+  int maxcnt[2] = {0, 0};
+  for (int half = 0; half < 2; ++half) {
+    int v0 = half ? vsplit : 0;
+    const int vend = half ? np : vsplit;
+    while (v0 < vend) {
+      int cnt = 0;
+      int64_t used = 0;
+      while (v0 + cnt < vend && cnt < 65535 &&
+             (cnt == 0 || used + (int64_t)nv[v0 + cnt] * nv[v0 + cnt] <= ws)) {
+        used += (int64_t)nv[v0 + cnt] * nv[v0 + cnt];
+        ++cnt;
+      }
+      PatchBatch B;
+      B.half = half;
+      B.v0 = v0;
+      B.cnt = cnt;
+      std::vector<int64_t> off(cnt);
+      std::vector<int32_t> nn(cnt);
+      std::vector<PotrfItem> pi(cnt);
+      std::vector<TrsmItem> ti(cnt);
+      std::vector<GemmItem> gi(cnt);
+      int64_t o = 0;
+      for (int i = 0; i < cnt; ++i) {
+        const int n = nv[v0 + i];
+        off[i] = o;
+        nn[i] = n;
+        B.nmax = std::max(B.nmax, n);
+        pi[i] = {o, n, n};
+        ti[i] = {o, o, n, n, n, n};
+        gi[i] = {o, o, o, n, n, n, n, n, n};
+        soff_all[v0 + i] = o;
+        o += (int64_t)n * n;
+        B.fp += f_potrf(n);
+        B.ft += f_trsm(n, n) / 3.0;   // identity right-hand side: L^-1 only
+        B.fg += f_herk(n, n) / 3.0;   // X^H X with X triangular
+      }
+      B.off.upload(off, bd, s);
+      B.nn.upload(nn, bd, s);
+      B.pi.upload(pi, bd, s);
+      B.ti.upload(ti, bd, s);
+      B.gi.upload(gi, bd, s);
+      B.t0 = f.Sset.tile_off_h[v0];
+      B.t1 = (v0 + cnt < np) ? f.Sset.tile_off_h[v0 + cnt] : f.Sset.ntiles;
+      maxcnt[half] = std::max(maxcnt[half], cnt);
+      P.batches.push_back(std::move(B));
+      v0 += cnt;
     }
-    PatchBatch B;
-    B.v0 = v0;
-    B.cnt = cnt;
-    std::vector<int64_t> off(cnt);
-    std::vector<int32_t> nn(cnt);
-    std::vector<PotrfItem> pi(cnt);
-    std::vector<TrsmItem> ti(cnt);
-    std::vector<GemmItem> gi(cnt);
-    int64_t o = 0;
-    for (int i = 0; i < cnt; ++i) {
-      const int n = nv[v0 + i];
-      off[i] = o;
-      nn[i] = n;
-      B.nmax = std::max(B.nmax, n);
-      pi[i] = {o, n, n};
-      ti[i] = {o, o, n, n, n, n};
-      gi[i] = {o, o, o, n, n, n, n, n, n};
-      soff_all[v0 + i] = o;
-      o += (int64_t)n * n;
-      B.fp += f_potrf(n);
-      B.ft += f_trsm(n, n) / 3.0;   // identity right-hand side: L^-1 only
-      B.fg += f_herk(n, n) / 3.0;   // X^H X with X triangular
-    }
-    B.off.upload(off, bd, s);
-    B.nn.upload(nn, bd, s);
-    B.pi.upload(pi, bd, s);
-    B.ti.upload(ti, bd, s);
-    B.gi.upload(gi, bd, s);
-    B.t0 = f.Sset.tile_off_h[v0];
-    B.t1 = (v0 + cnt < np) ? f.Sset.tile_off_h[v0 + cnt] : f.Sset.ntiles;
-    maxcnt = std::max(maxcnt, cnt);
-    P.batches.push_back(std::move(B));
-    v0 += cnt;
   }
   P.soff_all.upload(soff_all, bd, s);
   P.ld_all.upload(nv, bd, s);
   P.info.ensure(np, bd);
-  if (c->pS.n < ws) c->pS.alloc(ws, bd);
-  if (c->pX.n < ws) c->pX.alloc(ws, bd);
-  if (c->pwk.n < dense_work_size(maxcnt, nv_max)) c->pwk.alloc(dense_work_size(maxcnt, nv_max), bd);
+  for (int h = 0; h < 2; ++h) {
+    if (!maxcnt[h]) continue;
+    if (c->pS[h].n < ws) c->pS[h].alloc(ws, bd);
+    if (c->pX[h].n < ws) c->pX[h].alloc(ws, bd);
+    if (c->pwk[h].n < dense_work_size(maxcnt[h], nv_max))
+      c->pwk[h].alloc(dense_work_size(maxcnt[h], nv_max), bd);
+  }
   HIP_OK(hipStreamSynchronize(s));
   P.ready = true;
 }
 
 // Patch blocks of level l (Sec. 3 smoother): gather, Cholesky, explicit
-// inverse, packed tiles; on stream s.
-void build_patches(dpg_ctx *c, int l, hipStream_t s) {
+// inverse, packed tiles; the batches of one half, on stream s.
+void build_patches(dpg_ctx *c, int l, int half, hipStream_t s) {
   LevelData &f = c->lv[l];
   PatchPlan &P = f.pp;
-  double2 *S = c->pS.p, *X = c->pX.p, *wk = c->pwk.p;
+  double2 *S = c->pS[half].p, *X = c->pX[half].p, *wk = c->pwk[half].p;
   for (PatchBatch &B : P.batches) {
+    if (B.half != half) continue;
     {
       ProfScope ps(&c->prof, DPG_K_PATCH_GATHER, 0, s);
       launch_patch_gather(f.Mfull.p, f.nBf, f.mc.Nc, f.patch_ptr.p, f.patch_slot.p, B.v0, B.cnt,
@@ -490,8 +508,11 @@ void build_coarsest(dpg_ctx *c) {
 }
 
 // The whole hierarchy: macro levels one after the other on the main stream;
-// the patches of level l, which need only that level's macro blocks, on the
-// second stream, overlapping the coarser levels.
+// the patches of level l need only that level's macro blocks.  Half of them
+// (by work) run on the second stream as soon as the level's blocks exist,
+// overlapping the coarser levels; the other half on the main stream after the
+// coarsest level, so that the latency-bound steps of one half overlap the
+// matrix-core updates of the other.
 void build_hierarchy(dpg_ctx *c) {
   for (int l = c->L; l >= 1; --l) {
     plan_macro(c, l);
@@ -509,9 +530,10 @@ void build_hierarchy(dpg_ctx *c) {
   for (int l = c->L; l >= 1; --l) {
     build_macro_level(c, l);
     stream_wait(c->stream, c->aux, c->ev_level[l]);
-    build_patches(c, l, c->aux);
+    build_patches(c, l, 0, c->aux);
   }
   build_coarsest(c);
+  for (int l = c->L; l >= 1; --l) build_patches(c, l, 1, c->stream);
   stream_wait(c->aux, c->stream, c->ev_join);
   for (int l = c->L; l >= 1; --l) {
     check_infos(c->lv[l].mp.info.p, c->lv[l].nblk, c->stream, "interior block of coarse element");

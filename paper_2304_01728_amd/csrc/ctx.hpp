@@ -46,6 +46,7 @@ struct MacroPlan {
 // Patch factors and inverses of one level, in batches that fit the patch
 // workspaces.
 struct PatchBatch {
+  int half = 0;                      // 0: second stream, 1: main stream (own workspaces)
   int v0 = 0, cnt = 0, nmax = 0;
   int64_t t0 = 0, t1 = 0;
   double fp = 0, ft = 0, fg = 0;
@@ -140,7 +141,7 @@ struct dpg_ctx {
   // setup-phase plans and workspaces
   dpg::ElemPlan ep;
   dpg::DevBuf<double2> mT, mLinv, mX, mwk;         // macro levels
-  dpg::DevBuf<double2> pS, pX, pwk;                // patches
+  dpg::DevBuf<double2> pS[2], pX[2], pwk[2];       // patches, one set per half
   dpg::DevBuf<double2> zF, zLi, zTi, zwk;          // coarsest
   dpg::DevBuf<dpg::PotrfItem> zpi;
   dpg::DevBuf<dpg::TrsmItem> zti;
