@@ -71,7 +71,7 @@ template <typename C> __device__ __forceinline__ void load_tile(const C *__restr
 
 // Row sums of one tile into its partial slot; column sums accumulated.
 template <typename C>
-__device__ __forceinline__ void do_tile(const C t[16], const C xJ[4], const C *xr, int I, int J,
+__device__ __forceinline__ void do_tile(const C t[16], const C xJ[4], const C *xr, bool off,
                                         int ra, int cb, C cacc[4], C *__restrict__ slot) {
   C rs[4];
 #pragma unroll
@@ -85,7 +85,7 @@ __device__ __forceinline__ void do_tile(const C t[16], const C xJ[4], const C *x
   }
   // column sums skip the diagonal tile (its lower half is the conjugate of
   // the upper half, already counted by the row sums)
-  if (I < J) {
+  if (off) {
     C xI[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) xI[i] = xr[4 * ra + i];
@@ -111,7 +111,7 @@ __host__ __device__ __forceinline__ int64_t colbase(int J) {
 }
 
 // offset of the row-sum slot (I, J), I <= J, inside the row partials of a block
-__device__ __forceinline__ int64_t row_slot(int nt, int I, int J) {
+__host__ __device__ __forceinline__ int64_t row_slot(int nt, int I, int J) {
   return ((int64_t)I * nt - (int64_t)I * (I - 1) / 2 + (J - I)) * 32;
 }
 
@@ -130,16 +130,13 @@ __global__ __launch_bounds__(256) void k_gather_x(int64_t nloc, const int32_t *_
 }
 
 // One wave per (block, tile column J, pair of tile rows I0, I0 + 1 <= J).  The
-// x entries of the two tile rows are staged in LDS (wave-private), which
-// keeps registers for the tiles and the vector memory queue for tile data.
+// unit's descriptor (two int4, see HermSet::build) holds every address the
+// wave needs, so the tile loads follow a single descriptor load.  The x
+// entries of the two tile rows are staged in LDS (wave-private), which keeps
+// registers for the tiles and the vector memory queue for tile data.
 template <typename T>
 __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ tiles,
                                                const int4 *__restrict__ units, int64_t nunits,
-                                               const int32_t *__restrict__ bn,
-                                               const int64_t *__restrict__ tile_off,
-                                               const int64_t *__restrict__ cp_off,
-                                               const int64_t *__restrict__ rp_off,
-                                               const int64_t *__restrict__ loc_off,
                                                const cplx_t<T> *__restrict__ xloc,
                                                cplx_t<T> *__restrict__ part) {
   static_assert(kSeg == 2, "k_units handles segments of two tile rows");
@@ -149,23 +146,20 @@ __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ til
   const int64_t wv = (int64_t)blockIdx.x * 4 + wave;
   if (wv >= nunits) return;
   const int lane = threadIdx.x & 63, ra = lane >> 3, cb = lane & 7;
-  const int4 u = units[wv];
-  const int b = u.x, J = u.y, I0 = u.z, seg = u.w;
-  const bool two = I0 + 1 <= J;
-  const int nt = (bn[b] + 31) >> 5;
-  const C *xl = xloc + loc_off[b];
-  const C *tp = tiles + (tile_off[b] + (int64_t)J * (J + 1) / 2 + I0) * 1024 + lane;
-  C *rp = part + rp_off[b];
+  const int4 d0 = units[2 * wv], d1 = units[2 * wv + 1];
+  const int64_t tile = (int64_t)(uint32_t)d0.x | ((int64_t)d0.y << 32);
+  const bool two = d1.w & 1, off0 = d1.w & 2, off1 = d1.w & 4;
+  const C *tp = tiles + tile * 1024 + lane;
   C t0[16], t1[16], xJ[4], cacc[4];
   // x first: loads complete in order, so the LDS staging below waits for x
   // only, not for the tiles
   C v;
   v.x = 0;
   v.y = 0;
-  if (lane < 32 * (1 + two)) v = xl[32 * I0 + lane];
+  if (lane < 32 * (1 + two)) v = xloc[d0.z + lane];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    xJ[j] = xl[32 * J + 4 * cb + j];
+    xJ[j] = xloc[d0.w + 4 * cb + j];
     cacc[j].x = 0;
     cacc[j].y = 0;
   }
@@ -176,17 +170,15 @@ __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ til
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  do_tile(t0, xJ, xw, I0, J, ra, cb, cacc, rp + row_slot(nt, I0, J));
-  if (two) do_tile(t1, xJ, xw + 32, I0 + 1, J, ra, cb, cacc, rp + row_slot(nt, I0 + 1, J));
+  do_tile(t0, xJ, xw, off0, ra, cb, cacc, part + d1.x);
+  if (two) do_tile(t1, xJ, xw + 32, off1, ra, cb, cacc, part + d1.x + d1.y);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     cacc[j] = cadd(cacc[j], shfl_xor_c(cacc[j], 8));
     cacc[j] = cadd(cacc[j], shfl_xor_c(cacc[j], 16));
     cacc[j] = cadd(cacc[j], shfl_xor_c(cacc[j], 32));
   }
-  if (ra < 4)
-    part[cp_off[b] + colbase(J) + seg * 32 + 4 * cb + ra] =
-        sel4(cacc[0], cacc[1], cacc[2], cacc[3], ra);
+  if (ra < 4) part[d1.z + 4 * cb + ra] = sel4(cacc[0], cacc[1], cacc[2], cacc[3], ra);
 }
 
 // Half a wave per (block, tile row I): y_loc rows of I = column sums of the
@@ -303,6 +295,25 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
   npart = p;
   nloc = lo;
   nunits = (int64_t)un.size();
+  if (npart >= (1LL << 31) || nloc >= (1LL << 31))
+    throw DpgError(-1, "HermSet: partial or local vectors beyond 32-bit offsets");
+  // unit descriptors: {tile index lo, hi, x offset of tile row I0, of tile
+  // column J}, {row-partial slot of (I0, J), step to the slot of (I0 + 1, J),
+  // column-partial slot, flags: 1 two tiles, 2 first tile off-diagonal, 4
+  // second tile off-diagonal}
+  std::vector<int4> ud(2 * un.size());
+  for (size_t k = 0; k < un.size(); ++k) {
+    const int b = un[k].x, J = un[k].y, I0 = un[k].z, seg = un[k].w;
+    const int nt = (sizes[b] + 31) / 32;
+    const int64_t tile = toff[b] + (int64_t)J * (J + 1) / 2 + I0;
+    const int64_t r0 = rpo[b] + row_slot(nt, I0, J);
+    const int64_t rd = I0 + 1 <= J ? row_slot(nt, I0 + 1, J) - row_slot(nt, I0, J) : 0;
+    const int64_t cs = cpo[b] + colbase(J) + seg * 32;
+    const int flags = (I0 + 1 <= J ? 1 : 0) | (I0 < J ? 2 : 0) | (I0 + 1 < J ? 4 : 0);
+    ud[2 * k] = make_int4((int)(uint32_t)(tile & 0xffffffff), (int)(tile >> 32),
+                          (int)(loff[b] + 32 * I0), (int)(loff[b] + 32 * J));
+    ud[2 * k + 1] = make_int4((int)r0, (int)rd, (int)cs, flags);
+  }
   nrows = (int64_t)rw.size();
   tile_off_h = toff;
   // reduction lists: for every vector entry, the local rows holding it
@@ -322,7 +333,7 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
   rp_off.upload(rpo, bud, s);
   loc_off.upload(loff, bud, s);
   gidx.upload(gi, bud, s);
-  units.upload(un, bud, s);
+  units.upload(ud, bud, s);
   rows.upload(rw, bud, s);
   tdesc.upload(td, bud, s);
   red_ptr.upload(cnt, bud, s);
@@ -379,8 +390,7 @@ void herm_apply(HermSet &H, const cplx_t<T> *x, cplx_t<T> *y, const cplx_t<T> *r
     ProfScope ps(H.prof, sizeof(T) == 8 ? DPG_K_APPLY64 : DPG_K_APPLY32,
                  (double)H.packed_entries() * sizeof(cplx_t<T>), s);
     hipLaunchKernelGGL((k_units<T>), dim3(cdiv(H.nunits, 4)), dim3(256), 0, s, tiles, H.units.p,
-                       H.nunits, H.bn.p, H.tile_off.p, H.cp_off.p, H.rp_off.p, H.loc_off.p, xl,
-                       part);
+                       H.nunits, xl, part);
     LAUNCH_OK();
   }
   ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);

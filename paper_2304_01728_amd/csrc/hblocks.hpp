@@ -35,7 +35,7 @@ struct HermSet {
   DevBuf<int32_t> bn;
   DevBuf<int64_t> tile_off, cp_off, rp_off, loc_off;
   DevBuf<int32_t> gidx;      // [nloc] vector index of each padded local row, -1 = padding
-  DevBuf<int4> units;        // (block, J, first tile row, segment), longest first
+  DevBuf<int4> units;        // two int4 descriptors per (block, J, tile-row pair), longest first
   DevBuf<int2> rows;         // (block, I)
   DevBuf<int4> tdesc;        // (block, I, J, 0) per stored tile (packing)
   DevBuf<int32_t> red_ptr;   // CSR over vector entries
