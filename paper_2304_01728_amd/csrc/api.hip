@@ -97,8 +97,10 @@ void plan_elements(dpg_ctx *c) {
   if (P.mp == mp) return;
   const int nel = c->lv[c->L].nel;
   const int64_t per = 16LL * ((int64_t)nt * nt + (int64_t)nt * mp + (int64_t)mp * mp);
-  const int C = (int)std::max<int64_t>(
-      1, std::min<int64_t>({(int64_t)(nel + 1) / 2, 2500000000LL / per, 65535}));
+  // an even number of about equal chunks, so that both streams get the same work
+  const int64_t cmax = std::max<int64_t>(1, std::min<int64_t>(2500000000LL / per, 65535));
+  const int64_t pairs = (nel + 2 * cmax - 1) / (2 * cmax);
+  const int C = (int)std::max<int64_t>(1, (nel + 2 * pairs - 1) / (2 * pairs));
   Budget *bd = &c->bud;
   for (int k = 0; k < 2; ++k) {
     P.G[k].ensure((int64_t)C * nt * nt, bd);
@@ -213,7 +215,10 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
 int macro_chunk(dpg_ctx *c, const LevelData &f) {
   const int ntr = c->n_tr, nBf = f.nBf, nI = f.nI, nT = nBf + nI;
   const int64_t per = 16LL * ((int64_t)nT * nT + (int64_t)nI * nI + (int64_t)nBf * ntr);
-  return (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)f.nblk, 2500000000LL / per, 65535}));
+  const int64_t cmax = std::max<int64_t>(1, std::min<int64_t>(2500000000LL / per, 65535));
+  if (f.nblk <= cmax) return f.nblk;
+  const int64_t pairs = (f.nblk + 2 * cmax - 1) / (2 * cmax);   // an even number of chunks
+  return (int)((f.nblk + 2 * pairs - 1) / (2 * pairs));
 }
 
 void plan_macro(dpg_ctx *c, int l) {
@@ -277,72 +282,79 @@ void plan_macro(dpg_ctx *c, int l) {
     f.Tinv32.ensure(f.Tinv.n, bd);
     f.WH32.ensure(f.WH.n, bd);
   }
-  if (c->mT.n < (int64_t)CB * nT * nT) c->mT.alloc((int64_t)CB * nT * nT, bd);
-  if (c->mLinv.n < (int64_t)CB * nI * nI) c->mLinv.alloc((int64_t)CB * nI * nI, bd);
-  if (c->mX.n < (int64_t)CB * nBf * ntr) c->mX.alloc((int64_t)CB * nBf * ntr, bd);
-  if (c->mwk.n < dense_work_size(CB, nI)) c->mwk.alloc(dense_work_size(CB, nI), bd);
+  for (int h = 0; h < (nblk > CB ? 2 : 1); ++h) {
+    if (c->mT[h].n < (int64_t)CB * nT * nT) c->mT[h].alloc((int64_t)CB * nT * nT, bd);
+    if (c->mLinv[h].n < (int64_t)CB * nI * nI) c->mLinv[h].alloc((int64_t)CB * nI * nI, bd);
+    if (c->mX[h].n < (int64_t)CB * nBf * ntr) c->mX[h].alloc((int64_t)CB * nBf * ntr, bd);
+    if (c->mwk[h].n < dense_work_size(CB, nI)) c->mwk[h].alloc(dense_work_size(CB, nI), bd);
+  }
   HIP_OK(hipStreamSynchronize(s));
   P.CB = CB;
   P.ready = true;
 }
 
 // Macro condensation of level l (Sec. 3) and the Galerkin element matrices of
-// level l - 1, on the main stream.
+// level l - 1.  Chunks of coarse elements alternate between the two streams
+// (each with its own workspaces); on return the main stream has everything.
 void build_macro_level(dpg_ctx *c, int l) {
   LevelData &f = c->lv[l];
   LevelData &cl = c->lv[l - 1];
   MacroPlan &P = f.mp;
-  const hipStream_t s = c->stream;
   const int ntr = c->n_tr, nBf = f.nBf, nI = f.nI, nT = nBf + nI, nblk = f.nblk, CB = P.CB;
-  double2 *T = c->mT.p, *Linv = c->mLinv.p, *X = c->mX.p, *wk = c->mwk.p;
-  for (int b0 = 0; b0 < nblk; b0 += CB) {
-    const int cnt = std::min(CB, nblk - b0);
+  const bool two = nblk > CB;
+  if (two) stream_wait(c->stream, c->aux, c->ev_fork);
+  for (int b0 = 0, k = 0; b0 < nblk; b0 += CB, ++k) {
+    const int cnt = std::min(CB, nblk - b0), u = two ? (k & 1) : 0;
+    const hipStream_t s = u ? c->aux : c->stream;
+    double2 *T = c->mT[u].p, *Linv = c->mLinv[u].p, *X = c->mX[u].p, *wk = c->mwk[u].p;
     {
-      PROF(DPG_K_MACRO_ASM, 0);
+      ProfScope ps(&c->prof, DPG_K_MACRO_ASM, 0, s);
       launch_macro_assemble(f.E.p, ntr, P.cmap.p, f.N, b0, cnt, nT, T, s);
     }
     {
-      PROF(DPG_K_POTRF, cnt * f_potrf(nI));
+      ProfScope ps(&c->prof, DPG_K_POTRF, cnt * f_potrf(nI), s);
       potrf_batched(T, P.pII.p, cnt, P.info.p + b0, nI, wk, s);
     }
     {
-      PROF(DPG_K_TRSM, cnt * f_trsm(nI, nBf));
+      ProfScope ps(&c->prof, DPG_K_TRSM, cnt * f_trsm(nI, nBf), s);
       trsm_batched(T, T, P.tIB.p, cnt, nI, nBf, false, wk, true, s);
     }
     {
-      PROF(DPG_K_GEMM, cnt * f_herk(nBf, nI));
+      ProfScope ps(&c->prof, DPG_K_GEMM, cnt * f_herk(nBf, nI), s);
       gemm_batched(OP_C, OP_N, mk(-1, 0), T, T, mk(1, 0), T, P.gS.p, cnt, nBf, nBf, s);
     }
     {
-      PROF(DPG_K_OTHER, 0);
+      ProfScope ps(&c->prof, DPG_K_OTHER, 0, s);
       launch_identity(P.idoff.p, P.idn.p, cnt, nI, Linv, s);
     }
     {
-      PROF(DPG_K_TRSM, cnt * f_trsm(nI, nI));
+      ProfScope ps(&c->prof, DPG_K_TRSM, cnt * f_trsm(nI, nI), s);
       trsm_batched(T, Linv, P.tLi.p, cnt, nI, nI, true, wk, true, s);
     }
     {
-      PROF(DPG_K_GEMM, cnt * f_herk(nI, nI));
+      ProfScope ps(&c->prof, DPG_K_GEMM, cnt * f_herk(nI, nI), s);
       gemm_batched(OP_C, OP_N, mk(1, 0), Linv, Linv, mk(0, 0), f.Tinv.p + (int64_t)b0 * nI * nI,
                    P.gTi.p, cnt, nI, nI, s);
     }
     {
-      PROF(DPG_K_GEMM, cnt * f_gemm(nBf, nI, nI));
+      ProfScope ps(&c->prof, DPG_K_GEMM, cnt * f_gemm(nBf, nI, nI), s);
       gemm_batched(OP_C, OP_N, mk(1, 0), T, Linv, mk(0, 0), f.WH.p + (int64_t)b0 * nBf * nI,
                    P.gWH.p, cnt, nBf, nI, s);
     }
     {
-      PROF(DPG_K_OTHER, 0);
+      ProfScope ps(&c->prof, DPG_K_OTHER, 0, s);
       launch_copy_sub(T, (int64_t)nT * nT, nT, 0, 0, nBf, nBf, f.Mfull.p + (int64_t)b0 * nBf * nBf,
                       (int64_t)nBf * nBf, nBf, cnt, s);
     }
     {
-      PROF(DPG_K_GEMM, cnt * (f_gemm(nBf, ntr, nBf) + f_gemm(ntr, ntr, nBf)));
+      ProfScope ps(&c->prof, DPG_K_GEMM, cnt * (f_gemm(nBf, ntr, nBf) + f_gemm(ntr, ntr, nBf)), s);
       gemm_batched(OP_N, OP_N, mk(1, 0), T, P.Ploc.p, mk(0, 0), X, P.gX.p, cnt, nBf, ntr, s);
       gemm_batched(OP_T, OP_N, mk(1, 0), P.Ploc.p, X, mk(0, 0), cl.E.p + (int64_t)b0 * ntr * ntr,
                    P.gA.p, cnt, ntr, ntr, s);
     }
   }
+  if (two) stream_wait(c->aux, c->stream, c->ev_join);
+  const hipStream_t s = c->stream;
   if (c->opt.precision == DPG_MIXED && l < c->L) {
     launch_to32(f.Tinv.n, f.Tinv.p, f.Tinv32.p, s);
     launch_to32(f.WH.n, f.WH.p, f.WH32.p, s);

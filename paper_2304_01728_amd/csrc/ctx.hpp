@@ -140,7 +140,7 @@ struct dpg_ctx {
   dpg::HermSet T0set;
   // setup-phase plans and workspaces
   dpg::ElemPlan ep;
-  dpg::DevBuf<double2> mT, mLinv, mX, mwk;         // macro levels
+  dpg::DevBuf<double2> mT[2], mLinv[2], mX[2], mwk[2];   // macro levels, one set per stream
   dpg::DevBuf<double2> pS[2], pX[2], pwk[2];       // patches, one set per half
   dpg::DevBuf<double2> zF, zLi, zTi, zwk;          // coarsest
   dpg::DevBuf<dpg::PotrfItem> zpi;
