@@ -43,7 +43,8 @@ def loads_of(w):
 
 # Classes timed around exactly one kernel symbol; the composite dense classes
 # (potrf, trsm, gemm) each cover several kernels and are reported separately.
-SINGLE_KERNEL = ("apply64", "apply32", "gram", "bmat", "load", "macro_asm", "patch_gather")
+SINGLE_KERNEL = ("apply64", "apply32", "applyb64", "applyb32", "gram", "bmat", "load",
+                 "macro_asm", "patch_gather")
 DENSE = ("potrf", "trsm", "gemm")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -82,6 +83,16 @@ def roofline_for(stats, workload):
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic(sym, workload), "launches": n, "avg_ms": avg_ms,
                 "work_per_launch": work / n}
+    if cls == "applyb32":   # FP32 matrix cores; work = algorithmic flops
+        achieved = work / n / (avg_ms * 1e-3) / 1e12
+        return {"kernel": sym, "bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                "launches": n, "avg_ms": avg_ms, "work_per_launch": work / n}
+    if cls == "applyb64":   # FP64 vector FMA
+        achieved = work / n / (avg_ms * 1e-3) / 1e12
+        return {"kernel": sym, "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                "launches": n, "avg_ms": avg_ms, "work_per_launch": work / n}
     return {"kernel": sym, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": None, "traffic": None, "launches": n, "avg_ms": avg_ms}
 

@@ -172,7 +172,7 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
     }
     {
       ProfScope ps(&c->prof, DPG_K_GEMM, cnt * f_herk(mp, nt), s);
-      gemm_batched(OP_C, OP_N, mk(1, 0), BL, BL, mk(0, 0), K, P.gK.p, cnt, mp, mp, s);
+      gemm_batched(OP_C, OP_N, mk(1, 0), BL, BL, mk(0, 0), K, P.gK.p, cnt, mp, mp, s, GEMM_HERM);
     }
     {
       ProfScope ps(&c->prof, DPG_K_POTRF, cnt * f_potrf(nf), s);
@@ -184,7 +184,8 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
     }
     {
       ProfScope ps(&c->prof, DPG_K_GEMM, cnt * f_herk(mp - nf, nf), s);
-      gemm_batched(OP_C, OP_N, mk(-1, 0), K, K, mk(1, 0), K, P.gS.p, cnt, mp - nf, mp - nf, s);
+      gemm_batched(OP_C, OP_N, mk(-1, 0), K, K, mk(1, 0), K, P.gS.p, cnt, mp - nf, mp - nf, s,
+                   GEMM_HERM);
     }
     if (write_matrices)
       launch_copy_sub(K, (int64_t)mp * mp, mp, nf, nf, ntr, ntr, f.E.p + (int64_t)e0 * ntr * ntr,
@@ -321,7 +322,7 @@ void build_macro_level(dpg_ctx *c, int l) {
     }
     {
       ProfScope ps(&c->prof, DPG_K_GEMM, cnt * f_herk(nBf, nI), s);
-      gemm_batched(OP_C, OP_N, mk(-1, 0), T, T, mk(1, 0), T, P.gS.p, cnt, nBf, nBf, s);
+      gemm_batched(OP_C, OP_N, mk(-1, 0), T, T, mk(1, 0), T, P.gS.p, cnt, nBf, nBf, s, GEMM_HERM);
     }
     {
       ProfScope ps(&c->prof, DPG_K_OTHER, 0, s);
@@ -334,7 +335,7 @@ void build_macro_level(dpg_ctx *c, int l) {
     {
       ProfScope ps(&c->prof, DPG_K_GEMM, cnt * f_herk(nI, nI), s);
       gemm_batched(OP_C, OP_N, mk(1, 0), Linv, Linv, mk(0, 0), f.Tinv.p + (int64_t)b0 * nI * nI,
-                   P.gTi.p, cnt, nI, nI, s);
+                   P.gTi.p, cnt, nI, nI, s, GEMM_HERM_LOWTRI);
     }
     {
       ProfScope ps(&c->prof, DPG_K_GEMM, cnt * f_gemm(nBf, nI, nI), s);

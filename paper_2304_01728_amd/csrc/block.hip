@@ -101,6 +101,104 @@ __global__ __launch_bounds__(64) void k_rows_blk(const cplx_t<T> *__restrict__ t
       if (4 * q + j < nr) yb[(int64_t)(4 * a + i) * nr + 4 * q + j] = acc[i][j];
 }
 
+// FP32 form of k_rows_blk on the matrix cores.  Y_I (32 x 32, columns past
+// nr are padding) accumulates four real 32x32x32 products per tile,
+//   Re Y += Re A Re X - Im A Im X,   Im Y += Re A Im X + Im A Re X,
+// with v_mfma_f32_32x32x2f32: lane l supplies A[l%32][k] and B[k][l%32] for
+// k = l/32 of each two-column slice, and receives result row
+// 8(v/4) + 4(l/32) + v%4, column l%32 in register v.  The tile A_IJ is
+// staged in LDS column by column (double-buffered, rows XOR-swizzled per
+// group of four columns); X_J goes straight from global memory into the
+// B operands, which for nr = 32 are contiguous 512-byte rows.  The next
+// tile and X_J are loaded while the current ones are multiplied.
+// Workgroup g runs on XCD g % 8, so each XCD is given a contiguous range of
+// tile rows: the rows of one block then share its tiles and X in one L2.
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(64) void k_rows_mfma(const float2 *__restrict__ tiles,
+                                                  const int2 *__restrict__ rows, int64_t nrows,
+                                                  const int32_t *__restrict__ bn,
+                                                  const int64_t *__restrict__ tile_off,
+                                                  const int64_t *__restrict__ loc_off,
+                                                  const float2 *__restrict__ xl,
+                                                  float2 *__restrict__ yl, int nr) {
+  __shared__ float2 As[2][32 * 32];
+  const int64_t per = (nrows + 7) / 8;
+  const int64_t w = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (w >= nrows) return;
+  const int lane = threadIdx.x, a = lane >> 3, q = lane & 7;
+  const int kk = lane >> 5, n = lane & 31;
+  // columns past nr read column nr - 1: B column n only feeds result column
+  // n, and those results are not stored
+  const int ncl = n < nr ? n : nr - 1;
+  const int2 bi = rows[w];
+  const int b = bi.x, I = bi.y;
+  const int nt = (bn[b] + 31) >> 5;
+  const int64_t t0 = tile_off[b];
+  const float2 *xb = xl + loc_off[b] * nr + ncl;
+  auto load = [&](int J, float2 *tt, float2 *xx) {
+    const int64_t tix = t0 + (J >= I ? (int64_t)J * (J + 1) / 2 + I : (int64_t)I * (I + 1) / 2 + J);
+    const float2 *tp = tiles + tix * 1024 + lane;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) tt[k] = tp[k * 64];
+    const float2 *xp = xb + (int64_t)(32 * J + kk) * nr;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) xx[s] = xp[(int64_t)2 * s * nr];
+  };
+  v16f accr, acci;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    accr[v] = 0.f;
+    acci[v] = 0.f;
+  }
+  // one tile: start loading tile Jn into tn/xn, stage t as A_IJ in LDS,
+  // multiply; the scheduling barriers keep the loads ahead of the products
+  auto step = [&](int J, int Jn, const float2 *t, const float2 *x, float2 *tn, float2 *xn) {
+    load(Jn, tn, xn);
+    __builtin_amdgcn_sched_barrier(0);
+    const bool up = J >= I;
+    float2 *buf = As[J & 1];
+    // the lane holds stored entries (4a + i, 4q + j) at 4i + j; A_IJ is the
+    // stored tile (J >= I) or the conjugate transpose of tile (J, I)
+    const float sg = up ? 1.f : -1.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = up ? 4 * q + j : 4 * a + i;
+        const int m = up ? 4 * a + i : 4 * q + j;
+        const float2 v = t[4 * i + j];
+        buf[c * 32 + (m ^ (2 * ((c >> 2) & 7)))] = make_float2(v.x, sg * v.y);
+      }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const float2 av = buf[(2 * s + kk) * 32 + (n ^ (2 * (s >> 1)))];
+      accr = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, x[s].x, accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, x[s].y, acci, 0, 0, 0);
+      accr = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, -x[s].y, accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, x[s].x, acci, 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  // two register sets in turn; the load after the last tile repeats it
+  float2 tA[16], xA[16], tB[16], xB[16];
+  load(0, tA, xA);
+  int J = 0;
+  for (; J + 1 < nt; J += 2) {
+    step(J, J + 1, tA, xA, tB, xB);
+    step(J + 1, J + 2 < nt ? J + 2 : J + 1, tB, xB, tA, xA);
+  }
+  if (J < nt) step(J, J, tA, xA, tB, xB);
+  if (n >= nr) return;
+  float2 *yb = yl + (loc_off[b] + 32 * I) * nr + n;
+#pragma unroll
+  for (int v = 0; v < 16; ++v)
+    yb[(int64_t)(8 * (v >> 2) + 4 * kk + (v & 3)) * nr] = make_float2(accr[v], acci[v]);
+}
+
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_scatter_blk(int64_t nvec, int nr,
                                                      const int32_t *__restrict__ red_ptr,
@@ -411,10 +509,17 @@ void herm_apply_blk(HermSet &H, HermBlockBufs &W, const cplx_t<T> *X, cplx_t<T> 
     LAUNCH_OK();
   }
   {
-    ProfScope ps(H.prof, sizeof(T) == 8 ? DPG_K_APPLY64 : DPG_K_APPLY32,
-                 (double)H.packed_entries() * sizeof(cplx_t<T>), s);
-    hipLaunchKernelGGL((k_rows_blk<T>), dim3((unsigned)H.nrows), dim3(64), 0, s, tiles, H.rows.p,
-                       H.nrows, H.bn.p, H.tile_off.p, H.loc_off.p, xl, yl, nr);
+    ProfScope ps(H.prof, sizeof(T) == 8 ? DPG_K_APPLYB64 : DPG_K_APPLYB32,
+                 8.0 * (double)H.full * nr, s);
+    if constexpr (sizeof(T) == 4) {
+      const int64_t per = (H.nrows + 7) / 8;
+      if (8 * per > INT32_MAX) throw DpgError(-1, "block apply: too many tile rows");
+      hipLaunchKernelGGL(k_rows_mfma, dim3((unsigned)(8 * per)), dim3(64), 0, s, tiles, H.rows.p,
+                         H.nrows, H.bn.p, H.tile_off.p, H.loc_off.p, xl, yl, nr);
+    } else {
+      hipLaunchKernelGGL((k_rows_blk<T>), dim3((unsigned)H.nrows), dim3(64), 0, s, tiles,
+                         H.rows.p, H.nrows, H.bn.p, H.tile_off.p, H.loc_off.p, xl, yl, nr);
+    }
     LAUNCH_OK();
   }
   ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);

@@ -38,6 +38,18 @@ template <int OP> __device__ inline double2 ld_op(const double2 *X, int ldx, int
   return v;
 }
 
+// Position (lo, hi), lo <= hi, of index t in the column-major enumeration of
+// a triangle: (0,0) (0,1) (1,1) (0,2) (1,2) (2,2) ...  Triangular tile sets
+// are launched as exactly these tiles: workgroups that exit at once still
+// cost dispatch time.
+__device__ __forceinline__ void tri_index(int t, int &lo, int &hi) {
+  int h = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((h + 1) * (h + 2) / 2 <= t) ++h;
+  while (h * (h + 1) / 2 > t) --h;
+  hi = h;
+  lo = t - h * (h + 1) / 2;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  Tiled kernels (grid: tiles x items) remap the hardware id so that all
 // tiles of item 8 g + x run on XCD x, which keeps the operand panels an item's
@@ -104,12 +116,14 @@ __device__ __forceinline__ void store_slice(const double2 ra[4], const double2 r
 
 // C[r0:r0+64, c0:c0+64] (clipped to m x n) <- alpha op(A) op(B) + beta C with
 // inner indices k_begin..k-1.  lower_only leaves entries above the diagonal
-// alone.  Must be called by all 256 threads of the workgroup.  C may alias A or B when the tile's output covers
+// alone; mirror also stores the conjugate of each result at the transposed
+// position.  Must be called by all 256 threads of the workgroup.  C may alias A or B when the tile's output covers
 // exactly the operand rows / columns it reads (all reads precede the writes).
 template <int OPA, int OPB>
 __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int r0, int c0, double2 alpha,
                           const double2 *A, int lda, const double2 *B, int ldb, double2 beta,
-                          double2 *C, int ldc, bool lower_only, GemmSmem &sm) {
+                          double2 *C, int ldc, bool lower_only, GemmSmem &sm,
+                          bool mirror = false) {
   const int tid = threadIdx.x;
   // FP64 matrix cores: v_mfma_f64_16x16x4f64 computes D(16x16) += A(16x4) B(4x16)
   // with A[i][k] in lane i + 16k, B[k][j] in lane j + 16k and D[i][j] in
@@ -180,6 +194,7 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int 
           double2 v = cmul(alpha, mk(acc_re[i][j][e], acc_im[i][j][e]));
           if (use_beta) v = cfma(beta, *p, v);
           *p = v;
+          if (mirror) C[c + (int64_t)r * ldc] = cconj(v);
         }
       }
 }
@@ -358,6 +373,8 @@ __global__ __launch_bounds__(NT) void k_potrf_panel(double2 *base, const PotrfIt
 __global__ __launch_bounds__(NT) void k_potrf_update(double2 *base, const PotrfItem *items,
                                                      const int *info, int k_lo, int k_hi,
                                                      int c_lo, int c_hi, int tiles_c) {
+  // tiles_c > 0: grid of tiles_c tile columns; tiles_c = 0: the lower
+  // triangle of tiles (ti >= tj) enumerated by tri_index
   __shared__ GemmSmem sm;
   int bx, by;
   xcd_remap(bx, by);
@@ -365,7 +382,13 @@ __global__ __launch_bounds__(NT) void k_potrf_update(double2 *base, const PotrfI
   const int n = it.n, lda = it.lda;
   const int m = n - c_lo, nc = min(c_hi, n) - c_lo, kw = min(k_hi, n) - k_lo;
   if (m <= 0 || nc <= 0 || kw <= 0 || info[by] != 0) return;
-  const int ti = bx / tiles_c, tj = bx % tiles_c;
+  int ti, tj;
+  if (tiles_c > 0) {
+    ti = bx / tiles_c;
+    tj = bx % tiles_c;
+  } else {
+    tri_index(bx, tj, ti);
+  }
   if (ti * TM >= m || tj * TN >= nc || ti < tj) return;
   double2 *A = base + it.a;
   const double2 *P = A + c_lo + (int64_t)k_lo * lda;
@@ -443,16 +466,22 @@ __global__ __launch_bounds__(NT) void k_gemm(double2 alpha, const double2 *abase
   int bx, by;
   xcd_remap(bx, by);
   const GemmItem it = items[by];
-  const int tm = bx / tiles_n, tn = bx % tiles_n;
+  // GEMM_FULL: tiles_n tile columns; otherwise the upper tiles by tri_index
+  int tm, tn;
+  if (mode == GEMM_FULL) {
+    tm = bx / tiles_n;
+    tn = bx % tiles_n;
+  } else {
+    tri_index(bx, tm, tn);
+  }
   const int r0 = tm * TM, c0 = tn * TN;
   if (r0 >= it.m || c0 >= it.n) return;
   int kb = 0;
-  if (mode == GEMM_UPPER_LOWTRI) {
-    if (tm > tn) return;
+  if (mode == GEMM_UPPER_LOWTRI || mode == GEMM_HERM_LOWTRI)
     kb = c0;   // X lower triangular: rows below max(r0, c0) = c0 only
-  }
+  const bool mirror = (mode == GEMM_HERM || mode == GEMM_HERM_LOWTRI) && tm < tn;
   gemm_tile<OPA, OPB>(it.m, it.n, it.k, kb, r0, c0, alpha, abase + it.a, it.lda, bbase + it.b,
-                      it.ldb, beta, cbase + it.c, it.ldc, false, sm);
+                      it.ldb, beta, cbase + it.c, it.ldc, false, sm, mirror);
 }
 
 template <int OPA>
@@ -497,8 +526,8 @@ void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *i
     // block update of the trailing matrix
     if (K1 < nmax) {
       const int t = (int)cdiv(nmax - K1, TM);
-      hipLaunchKernelGGL(k_potrf_update, dim3(t * t, nitems), dim3(NT), 0, s, base, items_dev,
-                         info_dev, K0, K1, K1, nmax, t);
+      hipLaunchKernelGGL(k_potrf_update, dim3(t * (t + 1) / 2, nitems), dim3(NT), 0, s, base,
+                         items_dev, info_dev, K0, K1, K1, nmax, 0);
     }
   }
   LAUNCH_OK();
@@ -542,8 +571,8 @@ void gemm_batched(int opa, int opb, double2 alpha, const double2 *abase, const d
                   double2 beta, double2 *cbase, const GemmItem *items_dev, int nitems, int max_m,
                   int max_n, hipStream_t s, int mode) {
   if (nitems <= 0 || max_m <= 0 || max_n <= 0) return;
-  const int tm = (int)cdiv(max_m, TM), tn = (int)cdiv(max_n, TN);
-  dim3 g(tm * tn, nitems);
+  const int tm = (int)cdiv(max_m, TM), tn = (int)cdiv(max_n, TN), t = std::max(tm, tn);
+  dim3 g(mode == GEMM_FULL ? tm * tn : t * (t + 1) / 2, nitems);
   if (opa == OP_N) gemm_dispatch_b<OP_N>(opb, g, s, alpha, abase, bbase, beta, cbase, items_dev, tn, mode);
   else if (opa == OP_T) gemm_dispatch_b<OP_T>(opb, g, s, alpha, abase, bbase, beta, cbase, items_dev, tn, mode);
   else gemm_dispatch_b<OP_C>(opb, g, s, alpha, abase, bbase, beta, cbase, items_dev, tn, mode);

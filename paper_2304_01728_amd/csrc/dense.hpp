@@ -21,7 +21,7 @@ struct TrsmItem { int64_t l, b; int n, ncols, ldl, ldb; };
 struct GemmItem { int64_t a, b, c; int m, n, k, lda, ldb, ldc; };
 
 enum { OP_N = 0, OP_T = 1, OP_C = 2 };
-enum { GEMM_FULL = 0, GEMM_UPPER_LOWTRI = 1 };
+enum { GEMM_FULL = 0, GEMM_UPPER_LOWTRI = 1, GEMM_HERM = 2, GEMM_HERM_LOWTRI = 3 };
 
 // Work-area size (double2 elements) for nitems items of order <= nmax.
 int64_t dense_work_size(int nitems, int nmax);
@@ -44,7 +44,11 @@ void trsm_batched(const double2 *lbase, double2 *bbase, const TrsmItem *items_de
 // C <- alpha op(A) op(B) + beta C for every item.  mode GEMM_UPPER_LOWTRI
 // computes only the upper 64x64 tiles (tile row <= tile column) of a product
 // whose operands are lower triangular in the inner index (X^H X with X lower
-// triangular), starting the inner sum at the tile's diagonal.
+// triangular), starting the inner sum at the tile's diagonal.  GEMM_HERM and
+// GEMM_HERM_LOWTRI are for Hermitian results (m = n, and C Hermitian on entry
+// when beta != 0): they compute the upper tiles, as GEMM_FULL and
+// GEMM_UPPER_LOWTRI do, and also store the conjugate transpose of each
+// off-diagonal tile in the lower triangle.
 void gemm_batched(int opa, int opb, double2 alpha, const double2 *abase, const double2 *bbase,
                   double2 beta, double2 *cbase, const GemmItem *items_dev, int nitems, int max_m,
                   int max_n, hipStream_t s, int mode = GEMM_FULL);

@@ -263,6 +263,7 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
   std::vector<int64_t> toff(nblk), cpo(nblk), rpo(nblk), loff(nblk);
   int64_t t = 0, p = 0, lo = 0, ii = 0;
   packed = 0;
+  full = 0;
   std::vector<int4> un;
   std::vector<int2> rw;
   std::vector<int4> td;
@@ -278,6 +279,7 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
     t += (int64_t)nt * (nt + 1) / 2;
     lo += (int64_t)nt * 32;
     packed += (int64_t)n * (n + 1) / 2;
+    full += (int64_t)n * n;
     for (int i = 0; i < 32 * nt; ++i) gi.push_back(i < n ? idx_concat[ii + i] : -1);
     ii += n;
     for (int J = 0; J < nt; ++J) {

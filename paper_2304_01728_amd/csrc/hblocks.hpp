@@ -30,6 +30,7 @@ struct HermSet {
   int nblk = 0;
   int64_t nvec = 0;          // length of the target vector
   int64_t ntiles = 0, npart = 0, nunits = 0, nrows = 0, nloc = 0, packed = 0;
+  int64_t full = 0;          // sum of n_b^2 (entries of the full blocks)
   std::vector<int32_t> n_h;  // block sizes (host)
   std::vector<int64_t> tile_off_h;
   DevBuf<int32_t> bn;

@@ -60,12 +60,14 @@ class dpg_kstat(C.Structure):
 
 
 KERNEL_CLASSES = ["gram", "bmat", "load", "potrf", "trsm", "gemm", "macro_asm", "patch_gather",
-                  "apply64", "apply32", "reduce", "condense", "expand", "transfer", "cg", "other"]
+                  "apply64", "apply32", "reduce", "condense", "expand", "transfer", "cg", "other",
+                  "applyb64", "applyb32"]
 # kernel symbols behind each class (for matching a rocprofv3 trace)
 KERNEL_SYMBOLS = {"gram": "k_gram", "bmat": "k_bmat", "load": "k_load", "potrf": "k_potrf",
                   "trsm": "k_trsm", "gemm": "k_gemm", "macro_asm": "k_macro_assemble",
                   "patch_gather": "k_patch_gather", "apply64": "k_units<double>",
-                  "apply32": "k_units<float>", "reduce": "k_reduce"}
+                  "apply32": "k_units<float>", "reduce": "k_reduce",
+                  "applyb64": "k_rows_blk<double>", "applyb32": "k_rows_mfma"}
 
 
 class DPGError(RuntimeError):
