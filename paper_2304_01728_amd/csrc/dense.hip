@@ -318,34 +318,251 @@ __device__ __forceinline__ void load_block(const double2 *X, int ldx, int kb, do
 
 // ---- Cholesky -------------------------------------------------------------------
 
+// Diagonal blocks in 16 x 16 sub-blocks.  The 64 x 64 block (padded beyond
+// kb with the identity) and its inverse live in LDS as packed lower
+// triangles (67 KB, two workgroups per compute unit).  For each sub-block
+// column: one wave factors the diagonal sub-block by elimination, applying
+// the same row operations to an identity, which also yields the sub-block's
+// inverse; the sub-blocks below become products with that inverse and the
+// trailing lower triangle is updated, both by the whole workgroup.  The
+// off-diagonal sub-blocks of L^-1 then follow by distance from the diagonal,
+// X_rs = -X_rr sum_{t=s}^{r-1} L_rt X_ts.
+constexpr int DB = 16, NTB = 256, NPK = NB * (NB + 1) / 2;
+
+// packed column-major lower triangle: entry (i, j), i >= j
+__device__ __forceinline__ int pk(int i, int j) { return j * NB - (j * (j - 1)) / 2 + (i - j); }
+
+struct DiagSmem {
+  double2 L[NPK];
+  double2 X[NPK];   // L^-1
+  double2 row_a[DB], row_x[DB];
+  int fail;         // 1 + first pivot (in the block) that was not positive
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 1 / d for d > 0: hardware reciprocal estimate and two Newton steps
+// r <- r (2 - d r), each of which squares the relative error.
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
+// Wave 0: sub-block (o, o) -> L_oo in place, L_oo^-1 into X.  Lane (i, g)
+// holds row i, columns 4g..4g+3 of the full Hermitian sub-block and of the
+// identity.  Step k eliminates column k below the pivot with multipliers
+// m_i = a_ik / a_kk (a_ik = conj(a_ki)); columns j > k of a and j <= k of the
+// identity take the update, so that a keeps a_ij at step j and the identity
+// becomes the inverse of the unit factor.  The only exchange per step is the
+// pivot row, through LDS; each lane keeps the pivots it needs.
+__device__ void factor_sub(DiagSmem &sm, int o) {
+  const int lane = threadIdx.x, i = lane & 15, g = lane >> 4;
+  double2 a[4], x[4];
+  double di = 1.0, dj[4] = {1.0, 1.0, 1.0, 1.0};
+  int fail = 0;
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) {
+    const int j = 4 * g + jj;
+    a[jj] = i >= j ? sm.L[pk(o + i, o + j)] : cconj(sm.L[pk(o + j, o + i)]);
+    x[jj] = mk(i == j ? 1.0 : 0.0, 0.0);
+  }
+#pragma unroll 1
+  for (int k = 0; k < DB; ++k) {
+    if (i == k) {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        sm.row_a[4 * g + jj] = a[jj];
+        sm.row_x[4 * g + jj] = x[jj];
+      }
+    }
+    wave_sync();
+    const double d = sm.row_a[k].x;
+    const double2 ri = sm.row_a[i];
+    double2 ra[4], rx[4];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      ra[jj] = sm.row_a[4 * g + jj];
+      rx[jj] = sm.row_x[4 * g + jj];
+    }
+    const bool ok = d > 0.0;
+    if (!ok && fail == 0) fail = k + 1;
+    const double inv = ok ? recip(d) : 0.0;
+    if (i == k) di = d;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+      if (4 * g + jj == k) dj[jj] = d;
+    const double2 m = cscale(cconj(ri), i > k ? inv : 0.0);
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int j = 4 * g + jj;
+      const double2 ma = j > k ? m : mk(0.0, 0.0), mx = j > k ? mk(0.0, 0.0) : m;
+      a[jj] = csub(a[jj], cmul(ma, ra[jj]));
+      x[jj] = csub(x[jj], cmul(mx, rx[jj]));
+    }
+    wave_sync();
+  }
+  if (fail) {
+    if (lane == 0 && sm.fail == 0) sm.fail = o + fail;
+    return;
+  }
+  // L_ij = a_ij / sqrt(d_j) below the diagonal, L_ii = sqrt(d_i);
+  // (L^-1)_ij = x_ij / sqrt(d_i)
+  const double si = sqrt(di), rsi = 1.0 / si;
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) {
+    const int j = 4 * g + jj;
+    if (i > j) sm.L[pk(o + i, o + j)] = cscale(a[jj], 1.0 / sqrt(dj[jj]));
+    else if (i == j) sm.L[pk(o + i, o + i)] = mk(si, 0.0);
+    if (i >= j) sm.X[pk(o + i, o + j)] = cscale(x[jj], rsi);
+  }
+}
+
 // Factor the diagonal block [k0, k0+kb) of every item, write L_kk back and
-// L_kk^-1 to the work area (slot k0 / 64 of the item).  A pivot that is not
-// positive marks the item as failed.
-__global__ __launch_bounds__(NTD) void k_potrf_diag(double2 *base, const PotrfItem *items,
+// L_kk^-1 (zero-padded to 64 x 64) to the work area (slot k0 / 64 of the
+// item).  A pivot that is not positive marks the item as failed.
+__global__ __launch_bounds__(NTB, 2) void k_potrf_diag(double2 *base, const PotrfItem *items,
                                                     int *info, int k0, int kend, double2 *work,
                                                     int wslots) {
-  __shared__ double2 cb[2][NB], rb[2][NB];
-  __shared__ double scale[NB];
+  __shared__ DiagSmem sm;
   const PotrfItem it = items[blockIdx.x];
   const int n = it.n, lda = it.lda;
   const int kb = min(NB, min(kend, n) - k0);
   if (kb <= 0 || info[blockIdx.x] != 0) return;
   double2 *A = base + it.a + k0 + (int64_t)k0 * lda;
-  double2 a[kQ], x[kQ];
-  load_block(A, lda, kb, a, x);
-  const int f = eliminate<true>(a, x, kb, cb, rb, scale);
-  if (f) {
-    if (threadIdx.x == 0) info[blockIdx.x] = k0 + f;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NB * NB; e += NTB) {
+    const int i = e % NB, j = e / NB;
+    if (i < j) continue;
+    double2 v = mk(i == j ? 1.0 : 0.0, 0.0);
+    if (i < kb && j < kb) v = A[i + (int64_t)j * lda];
+    sm.L[pk(i, j)] = v;
+    sm.X[pk(i, j)] = mk(0.0, 0.0);
+  }
+  if (tid == 0) sm.fail = 0;
+  __syncthreads();
+  for (int s = 0; s < NB / DB; ++s) {
+    const int o = s * DB, r0 = o + DB, prow = NB - r0;
+    if (tid < 64) factor_sub(sm, o);
+    __syncthreads();
+    if (sm.fail || prow == 0) break;
+    // sub-blocks below: L_rs = A_rs L_ss^-H (X_ss lower: terms t <= j); a
+    // thread forms one row and four columns
+    double2 pv[4];
+    const bool pon = tid < prow * 4;
+    const int pi = r0 + tid % max(prow, 1), pj = 4 * (tid / max(prow, 1));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) pv[c] = mk(0.0, 0.0);
+    if (pon) {
+#pragma unroll 4
+      for (int t = 0; t < DB; ++t) {
+        const double2 av = sm.L[pk(pi, o + t)];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int j = pj + c;
+          const double2 xv = sm.X[pk(o + j, o + min(t, j))];
+          pv[c] = cfmaconj(t <= j ? xv : mk(0.0, 0.0), av, pv[c]);
+        }
+      }
+    }
+    __syncthreads();
+    if (pon) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sm.L[pk(pi, o + pj + c)] = pv[c];
+    }
+    __syncthreads();
+    // trailing lower triangle: A_ij -= sum_t L_it conj(L_jt), 2 x 2 entries per thread
+    const int m2 = prow / 2;
+    for (int b = tid; b < m2 * m2; b += NTB) {
+      const int hi = b % m2, lo = b / m2;
+      if (hi < lo) continue;
+      const int i0 = r0 + 2 * hi, j0 = r0 + 2 * lo;
+      double2 c00 = mk(0.0, 0.0), c01 = c00, c10 = c00, c11 = c00;
+#pragma unroll 4
+      for (int t = 0; t < DB; ++t) {
+        const int c = o + t;
+        const double2 li0 = sm.L[pk(i0, c)], li1 = sm.L[pk(i0 + 1, c)];
+        const double2 lj0 = sm.L[pk(j0, c)], lj1 = sm.L[pk(j0 + 1, c)];
+        c00 = cfmaconj(lj0, li0, c00);
+        c01 = cfmaconj(lj1, li0, c01);
+        c10 = cfmaconj(lj0, li1, c10);
+        c11 = cfmaconj(lj1, li1, c11);
+      }
+      sm.L[pk(i0, j0)] = csub(sm.L[pk(i0, j0)], c00);
+      sm.L[pk(i0 + 1, j0)] = csub(sm.L[pk(i0 + 1, j0)], c10);
+      sm.L[pk(i0 + 1, j0 + 1)] = csub(sm.L[pk(i0 + 1, j0 + 1)], c11);
+      if (hi != lo) sm.L[pk(i0, j0 + 1)] = csub(sm.L[pk(i0, j0 + 1)], c01);
+    }
+    __syncthreads();
+  }
+  if (sm.fail) {
+    if (tid == 0) info[blockIdx.x] = k0 + sm.fail;
     return;
   }
+  // off-diagonal sub-blocks of L^-1 by distance dd = r - s
+  for (int dd = 1; dd < NB / DB; ++dd) {
+    const int np = NB / DB - dd;
+    // T_rs = sum_{t=s}^{r-1} L_rt X_ts into the (r, s) slot of X (no slot of
+    // distance dd is read here; X_ss is lower, so terms u < j vanish); a
+    // thread forms one row and four columns of one pair
+    const bool von = tid < np * DB * 4;
+    const int sb = tid / (DB * 4), vi = tid % DB, vj = 4 * ((tid / DB) % 4);
+    const int rr = DB * (sb + dd), cc = DB * sb;
+    double2 tv[4];
 #pragma unroll
-  for (int m = 0; m < kQ; ++m) {
-    const Slot sl = slot_of(m, kb);
-    if (!sl.on) continue;
-    A[sl.i + (int64_t)sl.c * lda] =
-        sl.i == sl.c ? mk(scale[sl.i], 0.0) : cscale(a[m], 1.0 / scale[sl.c]);
+    for (int c = 0; c < 4; ++c) tv[c] = mk(0.0, 0.0);
+    if (von) {
+#pragma unroll 4
+      for (int u = 0; u < DB; ++u) {
+        const double2 lv = sm.L[pk(rr + vi, cc + u)];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int j = vj + c;
+          const double2 xv = sm.X[pk(cc + max(u, j), cc + j)];
+          tv[c] = cfma(lv, u >= j ? xv : mk(0.0, 0.0), tv[c]);
+        }
+      }
+      for (int u = cc + DB; u < rr; ++u) {
+        const double2 lv = sm.L[pk(rr + vi, u)];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) tv[c] = cfma(lv, sm.X[pk(u, cc + vj + c)], tv[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sm.X[pk(rr + vi, cc + vj + c)] = tv[c];
+    }
+    __syncthreads();
+    // X_rs = -X_rr T_rs (X_rr lower: terms u <= i)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) tv[c] = mk(0.0, 0.0);
+    if (von) {
+#pragma unroll 4
+      for (int u = 0; u < DB; ++u) {
+        const double2 xr = sm.X[pk(rr + vi, rr + min(u, vi))];
+        const double2 xm = u <= vi ? xr : mk(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) tv[c] = csub(tv[c], cmul(xm, sm.X[pk(rr + u, cc + vj + c)]));
+      }
+    }
+    __syncthreads();
+    if (von) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sm.X[pk(rr + vi, cc + vj + c)] = tv[c];
+    }
+    __syncthreads();
   }
-  store_inverse(x, kb, scale, work + ((int64_t)blockIdx.x * wslots + k0 / NB) * NB * NB);
+  for (int e = tid; e < kb * kb; e += NTB) {
+    const int i = e % kb, j = e / kb;
+    if (i >= j) A[i + (int64_t)j * lda] = sm.L[pk(i, j)];
+  }
+  double2 *w = work + ((int64_t)blockIdx.x * wslots + k0 / NB) * NB * NB;
+  for (int e = tid; e < NB * NB; e += NTB) {
+    const int i = e % NB, j = e / NB;
+    w[e] = (i >= j && i < kb && j < kb) ? sm.X[pk(i, j)] : mk(0.0, 0.0);
+  }
 }
 
 // Panel below the diagonal block: X = A_panel L_kk^-H as a product with the
@@ -509,7 +726,7 @@ void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *i
     const int K1 = std::min(K0 + NBO, kmax);
     for (int k0 = K0; k0 < K1; k0 += NB) {
       const int kb = std::min(NB, K1 - k0);
-      hipLaunchKernelGGL(k_potrf_diag, dim3(nitems), dim3(NTD), 0, s, base, items_dev, info_dev, k0,
+      hipLaunchKernelGGL(k_potrf_diag, dim3(nitems), dim3(NTB), 0, s, base, items_dev, info_dev, k0,
                          K1, work, wslots);
       const int rows = nmax - k0 - kb;
       if (rows <= 0) continue;
