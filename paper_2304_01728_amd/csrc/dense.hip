@@ -567,7 +567,7 @@ __global__ __launch_bounds__(NTB, 2) void k_potrf_diag(double2 *base, const Potr
 
 // Panel below the diagonal block: X = A_panel L_kk^-H as a product with the
 // stored inverse, one 64-row tile per workgroup, in place.
-__global__ __launch_bounds__(NT) void k_potrf_panel(double2 *base, const PotrfItem *items,
+__global__ __launch_bounds__(NT, 3) void k_potrf_panel(double2 *base, const PotrfItem *items,
                                                     const int *info, int k0, int kend,
                                                     const double2 *work, int wslots) {
   __shared__ GemmSmem sm;
@@ -587,7 +587,7 @@ __global__ __launch_bounds__(NT) void k_potrf_panel(double2 *base, const PotrfIt
 
 // Update C[r, c] -= sum_{k in [k_lo, k_hi)} A[r, k] conj(A[c, k]) for
 // c in [c_lo, c_hi), r >= c (lower triangle only).
-__global__ __launch_bounds__(NT) void k_potrf_update(double2 *base, const PotrfItem *items,
+__global__ __launch_bounds__(NT, 3) void k_potrf_update(double2 *base, const PotrfItem *items,
                                                      const int *info, int k_lo, int k_hi,
                                                      int c_lo, int c_hi, int tiles_c) {
   // tiles_c > 0: grid of tiles_c tile columns; tiles_c = 0: the lower
@@ -633,7 +633,7 @@ __global__ __launch_bounds__(NTD) void k_trsm_inv(const double2 *lbase, const Tr
 
 // Rows [k0, k0+kb) of B: X_k = L_kk^-1 B_k, one 64-column tile per workgroup,
 // in place.
-__global__ __launch_bounds__(NT) void k_trsm_solve(double2 *bbase, const TrsmItem *items, int k0,
+__global__ __launch_bounds__(NT, 3) void k_trsm_solve(double2 *bbase, const TrsmItem *items, int k0,
                                                    int kend, int tri, const double2 *work,
                                                    int wslots) {
   __shared__ GemmSmem sm;
@@ -653,7 +653,7 @@ __global__ __launch_bounds__(NT) void k_trsm_solve(double2 *bbase, const TrsmIte
 
 // B[r, c] -= sum_{k in [k_lo, k_hi)} L[r, k] X[k, c] for r in [r_lo, r_hi),
 // one 64x64 tile per workgroup.
-__global__ __launch_bounds__(NT) void k_trsm_update(const double2 *lbase, double2 *bbase,
+__global__ __launch_bounds__(NT, 3) void k_trsm_update(const double2 *lbase, double2 *bbase,
                                                     const TrsmItem *items, int k_lo, int k_hi,
                                                     int r_lo, int r_hi, int tri, int tiles_c) {
   __shared__ GemmSmem sm;
@@ -676,7 +676,7 @@ __global__ __launch_bounds__(NT) void k_trsm_update(const double2 *lbase, double
 // ---- GEMM ----------------------------------------------------------------------------
 
 template <int OPA, int OPB>
-__global__ __launch_bounds__(NT) void k_gemm(double2 alpha, const double2 *abase,
+__global__ __launch_bounds__(NT, 3) void k_gemm(double2 alpha, const double2 *abase,
                                              const double2 *bbase, double2 beta, double2 *cbase,
                                              const GemmItem *items, int tiles_n, int mode) {
   __shared__ GemmSmem sm;
