@@ -1,0 +1,123 @@
+"""Layered media and the serving loop on the GPU.
+
+* A medium in four z-layers (wave speed c per element, impedance Z = c on
+  the boundary) against the oracle with kappa = c^-2 and Z = c: solution
+  within 1e-10 (both sides at tol 1e-12), iteration counts +-1 at 1e-8.
+* Requests served together (concurrent operators, batched right-hand sides,
+  eviction under a small memory budget) against the same requests solved one
+  at a time on their own: each column of a block solve runs the recurrences
+  of a single solve with products summed in another order, so solutions
+  agree within 1e-10 at tol 1e-12 (FP64) and within 1e-8 at tol 1e-10
+  (mixed precision).
+"""
+import numpy as np
+import pytest
+
+from oracle import dpg, multigrid
+
+pytestmark = pytest.mark.gpu
+
+
+def _D():
+    from paper_2304_01728_amd import dpgmg as D
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return D
+
+
+def _relerr(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+INTERFACES = (0.25, 0.5, 0.75)
+SPEEDS = (1.0, 2.5, 1.7, 3.6)
+
+
+def test_layered_medium_matches_oracle():
+    D = _D()
+    from paper_2304_01728_amd import serving
+    N, p = 4, 2
+    c = serving.layered_speed(N, INTERFACES, SPEEDS)
+    omega = 2 * np.pi * min(SPEEDS) / (5.0 / N)
+    centre, sigma, amp = (0.45, 0.55, 0.4), 0.08, complex(1.0, 0.3)
+    print(f"[serving] layered N={N} p={p} omega={omega:.3f}", flush=True)
+    opt = D.dpg_default_options(nu_pre=1, nu_post=1)
+    ctx = D.dpg_setup(N, p, omega, [dict(dir=(0, 0, 1), amp=0.0,
+                                         sources=[[*centre, sigma, amp.real, amp.imag]])],
+                      c=c, options=opt)
+    D.dpg_assemble(ctx)
+    D.dpg_build_hierarchy(ctx)
+    x, it, rr, code = D.dpg_solve(ctx, tol=1e-12)
+    _, it8, _, _ = D.dpg_solve(ctx, tol=1e-8)
+    ctx.close()
+    pr = dpg.Problem(N, p, omega, [dict(f=dpg.gaussian_sources([centre], sigma, [amp]))],
+                     kappa=c ** -2, Zel=c)
+    S, s, _ = pr.condensed()
+    rhs = dpg.assemble_vector(pr.edofs, s, pr.num.n)[:, 0]
+    H = multigrid.Hierarchy(N, p, S, nu_pre=1, nu_post=1)
+    xo, _, _ = H.solve(rhs, 1e-12)
+    _, ito8, _ = H.solve(rhs, 1e-8)
+    err = _relerr(x[0], xo)
+    print(f"[serving] layered: rel err {err:.2e}, iterations {int(it8[0])} vs {ito8}", flush=True)
+    assert code == D.DPG_OK and err <= 1e-10
+    assert abs(int(it8[0]) - ito8) <= 1
+
+
+def _pool(precision, tol):
+    from paper_2304_01728_amd import serving
+    ops = []
+    for key, (N, p) in enumerate([(4, 2), (4, 3), (6, 2)]):
+        c = serving.layered_speed(N, INTERFACES, SPEEDS[key:] + SPEEDS[:key])
+        omega = 2 * np.pi * min(SPEEDS) / (5.0 / N)
+        ops.append(serving.Operator(key, N, p, omega, c, precision=precision, tol=tol))
+    return ops
+
+
+def _requests(ops, n, seed):
+    from paper_2304_01728_amd import serving
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        ns = int(rng.integers(1, 4))
+        cen = rng.uniform(0.2, 0.8, size=(ns, 3))
+        amp = rng.uniform(0.5, 1.5, size=ns)
+        src = np.column_stack([cen, np.full(ns, 0.08), amp, 0.3 * amp])
+        reqs.append(serving.Request(i, int(rng.integers(len(ops))), src, 0.002 * i))
+    return reqs
+
+
+@pytest.mark.parametrize("precision,tol,bound", [("fp64", 1e-12, 1e-10), ("mixed", 1e-10, 1e-8)])
+def test_served_results_equal_solves_alone(precision, tol, bound):
+    D = _D()
+    from paper_2304_01728_amd import serving
+    ops = _pool(precision, tol)
+    # alone: one context per operator, one request at a time
+    alone = {}
+    for op in ops:
+        print(f"[serving] alone op {op.key} N={op.N} p={op.p} {precision}", flush=True)
+        ctx = op.build()
+        for r in _requests(ops, 12, 7):
+            if r.op_key != op.key:
+                continue
+            D.dpg_load_rhs(ctx, [r.load()], want=False)
+            x, it, rr, code = D.dpg_solve(ctx, nrhs=1, tol=tol)
+            assert code == D.DPG_OK
+            alone[r.rid] = x[0].copy()
+        ctx.close()
+    # in the mix: all operators resident, then a budget that holds one of them
+    for budget in (1 << 40, 1):
+        print(f"[serving] mix {precision} budget={budget}", flush=True)
+        srv = serving.Server(ops, budget_bytes=budget, max_active=3)
+        reqs = _requests(ops, 12, 7)
+        try:
+            wall, lat = serving.run_stream(srv, reqs)
+        finally:
+            srv.close()
+        assert len(lat) == len(reqs) and np.all(lat > 0)
+        worst = max(_relerr(r.x, alone[r.rid]) for r in reqs)
+        print(f"[serving] budget={budget}: {len(reqs)} requests in {wall:.2f} s, batches "
+              f"{sorted(r.batch for r in reqs)}, builds {srv.builds}, evictions "
+              f"{srv.evictions}, worst difference {worst:.2e}", flush=True)
+        assert worst <= bound
+        if budget == 1:
+            assert srv.evictions >= 1
