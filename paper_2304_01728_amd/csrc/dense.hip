@@ -321,12 +321,12 @@ __device__ __forceinline__ void load_block(const double2 *X, int ldx, int kb, do
 // Diagonal blocks in 16 x 16 sub-blocks.  The 64 x 64 block (padded beyond
 // kb with the identity) and its inverse live in LDS as packed lower
 // triangles (67 KB, two workgroups per compute unit).  For each sub-block
-// column: one wave factors the diagonal sub-block by elimination, applying
+// column s: one wave factors the diagonal sub-block by elimination, applying
 // the same row operations to an identity, which also yields the sub-block's
-// inverse; the sub-blocks below become products with that inverse and the
-// trailing lower triangle is updated, both by the whole workgroup.  The
-// off-diagonal sub-blocks of L^-1 then follow by distance from the diagonal,
-// X_rs = -X_rr sum_{t=s}^{r-1} L_rt X_ts.
+// inverse X_ss; the sub-blocks below become products with X_ss and the
+// trailing lower triangle is updated, both by the whole workgroup, in the
+// same two phases as the block forward elimination of the identity that
+// gives the rest of L^-1 (X_st = X_ss Y_st, then Y_rt -= L_rs X_st).
 constexpr int DB = 16, NTB = 256, NPK = NB * (NB + 1) / 2;
 
 // packed column-major lower triangle: entry (i, j), i >= j
@@ -445,18 +445,25 @@ __global__ __launch_bounds__(NTB, 2) void k_potrf_diag(double2 *base, const Potr
   }
   if (tid == 0) sm.fail = 0;
   __syncthreads();
+  // Block forward elimination of the identity runs along (X = L^-1): the
+  // (r, t) slots of X (r > t) accumulate Y_rt = -sum_u L_ru X_ut over the
+  // steps u < r, and step r turns them into X_rt = X_rr Y_rt.
   for (int s = 0; s < NB / DB; ++s) {
     const int o = s * DB, r0 = o + DB, prow = NB - r0;
     if (tid < 64) factor_sub(sm, o);
     __syncthreads();
-    if (sm.fail || prow == 0) break;
-    // sub-blocks below: L_rs = A_rs L_ss^-H (X_ss lower: terms t <= j); a
-    // thread forms one row and four columns
+    if (sm.fail) break;
+    // (a) sub-blocks below: L_rs = A_rs L_ss^-H (X_ss lower: terms t <= j),
+    //     threads [0, 4 prow): one row and four columns each;
+    // (b) X_st = X_ss Y_st for t < s (X_ss lower: terms k <= i), threads
+    //     [4 prow, 192): one row and four columns of one block each
     double2 pv[4];
-    const bool pon = tid < prow * 4;
-    const int pi = r0 + tid % max(prow, 1), pj = 4 * (tid / max(prow, 1));
 #pragma unroll
     for (int c = 0; c < 4; ++c) pv[c] = mk(0.0, 0.0);
+    const int npan = prow * 4;
+    const bool pon = tid < npan, xon = tid >= npan && tid < npan + 64 * s;
+    const int pi = r0 + tid % max(prow, 1), pj = 4 * (tid / max(prow, 1));
+    const int xu = tid - npan, xt = DB * (xu / 64), xi = xu % DB, xj = 4 * ((xu / DB) % 4);
     if (pon) {
 #pragma unroll 4
       for (int t = 0; t < DB; ++t) {
@@ -468,91 +475,79 @@ __global__ __launch_bounds__(NTB, 2) void k_potrf_diag(double2 *base, const Potr
           pv[c] = cfmaconj(t <= j ? xv : mk(0.0, 0.0), av, pv[c]);
         }
       }
+    } else if (xon) {
+#pragma unroll 4
+      for (int k = 0; k < DB; ++k) {
+        const double2 xr = sm.X[pk(o + xi, o + min(k, xi))];
+        const double2 xm = k <= xi ? xr : mk(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pv[c] = cfma(xm, sm.X[pk(o + k, xt + xj + c)], pv[c]);
+      }
     }
     __syncthreads();
     if (pon) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) sm.L[pk(pi, o + pj + c)] = pv[c];
+    } else if (xon) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sm.X[pk(o + xi, xt + xj + c)] = pv[c];
     }
     __syncthreads();
-    // trailing lower triangle: A_ij -= sum_t L_it conj(L_jt), 2 x 2 entries per thread
-    const int m2 = prow / 2;
-    for (int b = tid; b < m2 * m2; b += NTB) {
-      const int hi = b % m2, lo = b / m2;
-      if (hi < lo) continue;
-      const int i0 = r0 + 2 * hi, j0 = r0 + 2 * lo;
-      double2 c00 = mk(0.0, 0.0), c01 = c00, c10 = c00, c11 = c00;
+    if (prow == 0) break;
+    // (c) trailing lower triangle: A_ij -= sum_t L_it conj(L_jt), 2 x 2 entries
+    //     per item; (d) Y_rt -= L_rs X_st for r > s, t <= s, one row and four
+    //     columns per item (X_ss lower: terms k >= j).  Neither reads what the
+    //     other writes.
+    const int m2 = prow / 2, ntr = m2 * m2, nt1 = s + 1;
+    for (int b = tid; b < ntr + 64 * nt1 * (3 - s); b += NTB) {
+      if (b < ntr) {
+        const int hi = b % m2, lo = b / m2;
+        if (hi < lo) continue;
+        const int i0 = r0 + 2 * hi, j0 = r0 + 2 * lo;
+        double2 c00 = mk(0.0, 0.0), c01 = c00, c10 = c00, c11 = c00;
 #pragma unroll 4
-      for (int t = 0; t < DB; ++t) {
-        const int c = o + t;
-        const double2 li0 = sm.L[pk(i0, c)], li1 = sm.L[pk(i0 + 1, c)];
-        const double2 lj0 = sm.L[pk(j0, c)], lj1 = sm.L[pk(j0 + 1, c)];
-        c00 = cfmaconj(lj0, li0, c00);
-        c01 = cfmaconj(lj1, li0, c01);
-        c10 = cfmaconj(lj0, li1, c10);
-        c11 = cfmaconj(lj1, li1, c11);
+        for (int t = 0; t < DB; ++t) {
+          const int c = o + t;
+          const double2 li0 = sm.L[pk(i0, c)], li1 = sm.L[pk(i0 + 1, c)];
+          const double2 lj0 = sm.L[pk(j0, c)], lj1 = sm.L[pk(j0 + 1, c)];
+          c00 = cfmaconj(lj0, li0, c00);
+          c01 = cfmaconj(lj1, li0, c01);
+          c10 = cfmaconj(lj0, li1, c10);
+          c11 = cfmaconj(lj1, li1, c11);
+        }
+        sm.L[pk(i0, j0)] = csub(sm.L[pk(i0, j0)], c00);
+        sm.L[pk(i0 + 1, j0)] = csub(sm.L[pk(i0 + 1, j0)], c10);
+        sm.L[pk(i0 + 1, j0 + 1)] = csub(sm.L[pk(i0 + 1, j0 + 1)], c11);
+        if (hi != lo) sm.L[pk(i0, j0 + 1)] = csub(sm.L[pk(i0, j0 + 1)], c01);
+      } else {
+        const int u = b - ntr, blk = u / 64;
+        const int rr = DB * (s + 1 + blk / nt1), tt = DB * (blk % nt1);
+        const int i = u % DB, j0 = 4 * ((u / DB) % 4);
+        double2 acc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = mk(0.0, 0.0);
+#pragma unroll 4
+        for (int k = 0; k < DB; ++k) {
+          const double2 lv = sm.L[pk(rr + i, o + k)];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int j = tt + j0 + c;
+            const double2 xv = sm.X[pk(max(o + k, j), j)];
+            acc[c] = cfma(lv, o + k >= j ? xv : mk(0.0, 0.0), acc[c]);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int q = pk(rr + i, tt + j0 + c);
+          sm.X[q] = csub(sm.X[q], acc[c]);
+        }
       }
-      sm.L[pk(i0, j0)] = csub(sm.L[pk(i0, j0)], c00);
-      sm.L[pk(i0 + 1, j0)] = csub(sm.L[pk(i0 + 1, j0)], c10);
-      sm.L[pk(i0 + 1, j0 + 1)] = csub(sm.L[pk(i0 + 1, j0 + 1)], c11);
-      if (hi != lo) sm.L[pk(i0, j0 + 1)] = csub(sm.L[pk(i0, j0 + 1)], c01);
     }
     __syncthreads();
   }
   if (sm.fail) {
     if (tid == 0) info[blockIdx.x] = k0 + sm.fail;
     return;
-  }
-  // off-diagonal sub-blocks of L^-1 by distance dd = r - s
-  for (int dd = 1; dd < NB / DB; ++dd) {
-    const int np = NB / DB - dd;
-    // T_rs = sum_{t=s}^{r-1} L_rt X_ts into the (r, s) slot of X (no slot of
-    // distance dd is read here; X_ss is lower, so terms u < j vanish); a
-    // thread forms one row and four columns of one pair
-    const bool von = tid < np * DB * 4;
-    const int sb = tid / (DB * 4), vi = tid % DB, vj = 4 * ((tid / DB) % 4);
-    const int rr = DB * (sb + dd), cc = DB * sb;
-    double2 tv[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) tv[c] = mk(0.0, 0.0);
-    if (von) {
-#pragma unroll 4
-      for (int u = 0; u < DB; ++u) {
-        const double2 lv = sm.L[pk(rr + vi, cc + u)];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int j = vj + c;
-          const double2 xv = sm.X[pk(cc + max(u, j), cc + j)];
-          tv[c] = cfma(lv, u >= j ? xv : mk(0.0, 0.0), tv[c]);
-        }
-      }
-      for (int u = cc + DB; u < rr; ++u) {
-        const double2 lv = sm.L[pk(rr + vi, u)];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) tv[c] = cfma(lv, sm.X[pk(u, cc + vj + c)], tv[c]);
-      }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) sm.X[pk(rr + vi, cc + vj + c)] = tv[c];
-    }
-    __syncthreads();
-    // X_rs = -X_rr T_rs (X_rr lower: terms u <= i)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) tv[c] = mk(0.0, 0.0);
-    if (von) {
-#pragma unroll 4
-      for (int u = 0; u < DB; ++u) {
-        const double2 xr = sm.X[pk(rr + vi, rr + min(u, vi))];
-        const double2 xm = u <= vi ? xr : mk(0.0, 0.0);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) tv[c] = csub(tv[c], cmul(xm, sm.X[pk(rr + u, cc + vj + c)]));
-      }
-    }
-    __syncthreads();
-    if (von) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) sm.X[pk(rr + vi, cc + vj + c)] = tv[c];
-    }
-    __syncthreads();
   }
   for (int e = tid; e < kb * kb; e += NTB) {
     const int i = e % kb, j = e / kb;
