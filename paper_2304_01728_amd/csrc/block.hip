@@ -568,8 +568,14 @@ void launch_expand_blk(const cplx_t<T> *WH, const cplx_t<T> *Tinv, int nI, int n
                        const int32_t *blkI, const int32_t *blkBm, int nblk, const cplx_t<T> *rc,
                        const cplx_t<T> *eB, int64_t nM, const int64_t *macro_B, cplx_t<T> *ec,
                        int nr, hipStream_t s) {
+  // the boundary and interior values of KC columns of one macro block stay in
+  // LDS; beyond 64 KB (order 4 in FP64) the kernel asks for more, up to the
+  // 160 KB a gfx950 workgroup can hold
   const size_t lds = sizeof(cplx_t<T>) * KC * ((size_t)nBf + nI);
-  if (lds > 64 * 1024) throw DpgError(-1, "macro block too large for the block expansion");
+  if (lds > 160 * 1024) throw DpgError(-1, "macro block too large for the block expansion");
+  if (lds > 64 * 1024)
+    HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_expand_blk<T>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL((k_scatter_macro_blk<T>), dim3(cdiv(nM * nr, 256)), dim3(256), 0, s, nM, nr,
                      macro_B, eB, ec);
   LAUNCH_OK();

@@ -55,7 +55,8 @@ def _relerr(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("N,p,omega,nu", [(4, 2, 3 * np.pi, (1, 1)), (8, 2, 4 * np.pi, (2, 2))])
+@pytest.mark.parametrize("N,p,omega,nu", [(4, 2, 3 * np.pi, (1, 1)), (8, 2, 4 * np.pi, (2, 2)),
+                                         (4, 4, 3 * np.pi, (1, 1))])
 def test_block_fp64_matches_columnwise_and_oracle(N, p, omega, nu):
     D = _D()
     loads, fs = _sources(3, 5)
