@@ -150,6 +150,15 @@ int dpg_load_rhs(dpg_ctx *ctx, const dpg_load *loads, int nrhs, double *s_out);
  * per-column CG scalars; a converged column stops updating while the others
  * continue); DPG_COLUMNWISE in the options' flags solves them one by one
  * instead.  Both give each column the same iterates up to rounding. */
+/* Frees what only dpg_assemble and dpg_build_hierarchy use: the element and
+ * coarse element matrices, the full condensed macro blocks, the dense
+ * coarsest operator and the setup work areas.  Solves, dpg_load_rhs and
+ * dpg_get_fields keep working; dpg_assemble, dpg_build_hierarchy and the
+ * exports of the freed matrices return DPG_ESTATE afterwards.  For callers
+ * that keep many hierarchies resident (a solve server).  Requires a built
+ * hierarchy (DPG_ESTATE otherwise). */
+int dpg_release_setup(dpg_ctx *ctx);
+
 int dpg_solve(dpg_ctx *ctx, const double *rhs, int nrhs, double tol, double *x_out,
               int32_t *iters_out, double *relres_out);
 

@@ -1191,6 +1191,7 @@ int dpg_assemble(dpg_ctx *c) {
   if (!c) return DPG_EINVAL;
   return guarded(c, [&]() {
     if (c->stage < 1) throw DpgError(DPG_ESTATE, "dpg_setup first");
+    if (c->released) throw DpgError(DPG_ESTATE, "setup data released");
     auto t0 = clk::now();
     LevelData &top = c->lv[c->L];
     top.E.ensure((int64_t)top.nel * c->n_tr * c->n_tr, &c->bud);
@@ -1212,11 +1213,41 @@ int dpg_build_hierarchy(dpg_ctx *c) {
   if (!c) return DPG_EINVAL;
   return guarded(c, [&]() {
     if (c->stage < 2) throw DpgError(DPG_ESTATE, "dpg_assemble first");
+    if (c->released) throw DpgError(DPG_ESTATE, "setup data released");
     auto t0 = clk::now();
     build_hierarchy(c);
     c->prof.flush();
     c->ms[2] = ms_since(t0);
     c->stage = 3;
+    return DPG_OK;
+  });
+}
+
+int dpg_release_setup(dpg_ctx *c) {
+  if (!c) return DPG_EINVAL;
+  return guarded(c, [&]() {
+    if (c->stage < 3) throw DpgError(DPG_ESTATE, "dpg_build_hierarchy first");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    HIP_OK(hipStreamSynchronize(c->aux));
+    for (LevelData &f : c->lv) {
+      f.E.release();
+      f.Mfull.release();
+    }
+    for (int k = 0; k < 2; ++k) {
+      c->mT[k].release();
+      c->mLinv[k].release();
+      c->mX[k].release();
+      c->mwk[k].release();
+      c->pS[k].release();
+      c->pX[k].release();
+      c->pwk[k].release();
+    }
+    c->zF.release();
+    c->zLi.release();
+    c->zTi.release();
+    c->zwk.release();
+    c->T0.release();
+    c->released = true;
     return DPG_OK;
   });
 }
@@ -1434,6 +1465,7 @@ int64_t dpg_export(const dpg_ctx *cc, int what, int level, void *out, int64_t ca
       case DPG_X_PROLONG_VAL: need_macro(); rc = put(f.P.val, out, cap); break;
       case DPG_X_ELEM_S:
       case DPG_X_COARSE_E: {
+        if (c->released) throw DpgError(DPG_ESTATE, "setup data released");
         if (!f.E.p) throw DpgError(DPG_ESTATE, "element matrices not computed yet");
         rc = put(f.E.download(s), out, cap);
         break;
@@ -1450,6 +1482,7 @@ int64_t dpg_export(const dpg_ctx *cc, int what, int level, void *out, int64_t ca
       }
       case DPG_X_MACRO_M: {
         need_macro();
+        if (c->released) throw DpgError(DPG_ESTATE, "setup data released");
         if (!f.Mfull.p) throw DpgError(DPG_ESTATE, "dpg_build_hierarchy first");
         std::vector<double2> full = f.Mfull.download(s), v;
         for (int b = 0; b < f.nblk; ++b) {
@@ -1496,6 +1529,7 @@ int64_t dpg_export(const dpg_ctx *cc, int what, int level, void *out, int64_t ca
       }
       case DPG_X_COARSEST: {
         if (c->stage < 3) throw DpgError(DPG_ESTATE, "dpg_build_hierarchy first");
+        if (c->released) throw DpgError(DPG_ESTATE, "setup data released");
         rc = put(c->T0.download(s), out, cap);
         break;
       }

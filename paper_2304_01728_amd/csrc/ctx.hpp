@@ -108,6 +108,7 @@ struct LevelData {
 struct dpg_ctx {
   std::string err;
   int stage = 0;                     // 1 set up, 2 assembled, 3 hierarchy built
+  bool released = false;             // setup-only data freed (dpg_release_setup)
   int N = 0, p = 0, dp = 1, nrhs = 0;
   double omega = 0, side = 1, org[3] = {0, 0, 0};
   dpg_options opt{};

@@ -25,7 +25,8 @@ _DOUBLE_EXPORTS = {X_PROLONG_VAL}
 
 SYMBOLS = ["dpg_default_options", "dpg_setup", "dpg_assemble", "dpg_build_hierarchy",
            "dpg_load_rhs", "dpg_solve", "dpg_get_fields", "dpg_info", "dpg_export",
-           "dpg_profile", "dpg_kernel_stats", "dpg_last_error", "dpg_destroy"]
+           "dpg_profile", "dpg_kernel_stats", "dpg_last_error", "dpg_destroy",
+           "dpg_release_setup"]
 
 
 class dpg_mesh(C.Structure):
@@ -93,7 +94,7 @@ def lib():
                                 C.POINTER(dpg_material), C.POINTER(dpg_load), C.c_int,
                                 C.POINTER(dpg_options), C.POINTER(vp)]
         L.dpg_setup.restype = C.c_int
-        for name in ("dpg_assemble", "dpg_build_hierarchy"):
+        for name in ("dpg_assemble", "dpg_build_hierarchy", "dpg_release_setup"):
             getattr(L, name).argtypes = [vp]
             getattr(L, name).restype = C.c_int
         L.dpg_load_rhs.argtypes = [vp, C.POINTER(dpg_load), C.c_int, vp]
@@ -192,6 +193,10 @@ def dpg_assemble(ctx):
 
 def dpg_build_hierarchy(ctx):
     _check(ctx.h, lib().dpg_build_hierarchy(ctx.h))
+
+
+def dpg_release_setup(ctx):
+    _check(ctx.h, lib().dpg_release_setup(ctx.h))
 
 
 def dpg_info(ctx):

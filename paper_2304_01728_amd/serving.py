@@ -46,6 +46,7 @@ class Operator:
                           dp=self.dp, c=self.c, options=opt)
         D.dpg_assemble(ctx)
         D.dpg_build_hierarchy(ctx)
+        D.dpg_release_setup(ctx)   # keep only what solves and new loads need
         return ctx
 
 

@@ -121,3 +121,37 @@ def test_served_results_equal_solves_alone(precision, tol, bound):
         assert worst <= bound
         if budget == 1:
             assert srv.evictions >= 1
+
+
+def test_release_setup_keeps_solves_and_new_loads():
+    D = _D()
+    N, p, omega = 4, 2, 3 * np.pi
+    load_a = [dict(dir=(0, 0, 1), amp=0.0, sources=[[0.4, 0.5, 0.6, 0.08, 1.0, 0.2]])]
+    load_b = [dict(dir=(0, 0, 1), amp=0.0, sources=[[0.6, 0.3, 0.5, 0.08, 0.7, -0.4]]),
+              dict(dir=(0.6, 0.0, 0.8), amp=1.0)]
+    print("[serving] release_setup", flush=True)
+    ctx = D.dpg_setup(N, p, omega, load_a)
+    D.dpg_assemble(ctx)
+    D.dpg_build_hierarchy(ctx)
+    before = D.dpg_info(ctx).resident_bytes
+    xa, _, _, _ = D.dpg_solve(ctx, tol=1e-12)
+    D.dpg_release_setup(ctx)
+    after = D.dpg_info(ctx).resident_bytes
+    xa2, _, _, code = D.dpg_solve(ctx, tol=1e-12)
+    assert code == D.DPG_OK and after < before
+    assert _relerr(xa2[0], xa[0]) == 0.0
+    D.dpg_load_rhs(ctx, load_b, want=False)
+    xb, _, _, code = D.dpg_solve(ctx, nrhs=2, tol=1e-12)
+    assert code == D.DPG_OK
+    ref = D.dpg_setup(N, p, omega, load_b)
+    D.dpg_assemble(ref)
+    D.dpg_build_hierarchy(ref)
+    xr, _, _, _ = D.dpg_solve(ref, nrhs=2, tol=1e-12)
+    for k in range(2):
+        assert _relerr(xb[k], xr[k]) <= 1e-12
+    for call in (lambda: D.dpg_assemble(ctx), lambda: D.dpg_build_hierarchy(ctx),
+                 lambda: D.dpg_export(ctx, D.X_ELEM_S)):
+        with pytest.raises(D.DPGError):
+            call()
+    ctx.close()
+    ref.close()

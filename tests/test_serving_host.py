@@ -52,6 +52,9 @@ class FakeLib:
     def dpg_build_hierarchy(self, ctx):
         pass
 
+    def dpg_release_setup(self, ctx):
+        pass
+
     def dpg_info(self, ctx):
         return types.SimpleNamespace(resident_bytes=self.per * ctx.N ** 3)
 
