@@ -261,7 +261,15 @@ void plan_macro(dpg_ctx *c, int l) {
   P.gA.upload(gA, bd, s);
   P.idoff.upload(idoff, bd, s);
   P.idn.upload(idn, bd, s);
-  P.cmap.upload(f.mc.child_map, bd, s);
+  std::vector<int32_t> cinv((size_t)8 * nT, -1);
+  for (int ch = 0; ch < 8; ++ch)
+    for (int k = 0; k < ntr; ++k) {
+      const int32_t slot = f.mc.child_map[(size_t)ch * ntr + k];
+      if (slot < 0 || slot >= nT || cinv[(size_t)ch * nT + slot] >= 0)
+        throw DpgError(-1, "child map is not one-to-one");
+      cinv[(size_t)ch * nT + slot] = k;
+    }
+  P.cmap.upload(cinv, bd, s);
   std::vector<int64_t> soff(nblk), moff(nblk);
   std::vector<int32_t> sld(nblk, nBf);
   for (int b = 0; b < nblk; ++b) {
@@ -364,6 +372,12 @@ void build_macro_level(dpg_ctx *c, int l) {
   f.Mset.pack(f.Mfull.p, P.soff.p, P.sld.p, P.moff.p, P.map.p, s);
 }
 
+// Share of each level's patch work on the second stream.  Equal halves
+// measured best (0.4: +1.2 ms, 0.6: +3.8 ms, 0.7: +5.4 ms of hierarchy time
+// at 16^3 / p = 3): the second stream's large patch kernels slow down the
+// small kernels of the coarse-level chain on the main stream.
+constexpr double kAuxPatchShare = 0.5;
+
 void plan_patches(dpg_ctx *c, int l) {
   LevelData &f = c->lv[l];
   PatchPlan &P = f.pp;
@@ -379,13 +393,13 @@ void plan_patches(dpg_ctx *c, int l) {
     nv_max = std::max(nv_max, (int)nv[v]);
     maxent = std::max<int64_t>(maxent, (int64_t)nv[v] * nv[v]);
   }
-  // two halves of about equal factorisation work (sum n^3), one per stream,
-  // each cut into batches that fit its workspaces (S and X: 3 GB each)
+  // two parts by factorisation work (sum n^3), one per stream, each cut into
+  // batches that fit its workspaces (S and X: 3 GB each)
   const int64_t ws = std::max<int64_t>(3000000000LL / 16, maxent);
   double tot = 0.0;
   for (int v = 0; v < np; ++v) tot += (double)nv[v] * nv[v] * nv[v];
   int vsplit = 0;
-  for (double acc = 0.0; vsplit < np && acc < 0.5 * tot; ++vsplit)
+  for (double acc = 0.0; vsplit < np && acc < kAuxPatchShare * tot; ++vsplit)
     acc += (double)nv[vsplit] * nv[vsplit] * nv[vsplit];
   std::vector<int64_t> soff_all(np, 0);
   int maxcnt[2] = {0, 0};

@@ -8,27 +8,29 @@ constexpr int kMaxB = 2048, kMaxI = 1024;
 
 // ---- setup -----------------------------------------------------------------------
 
+// Gather form: a thread forms one entry (r, c) of T[b] as the sum, in child
+// order, of the entries of the children that hold both r and c; a workgroup
+// covers 256 rows of one column, so the column's child indices are uniform.
+// Every entry is written once and the grid spreads over (rows, columns,
+// blocks), so a level with few blocks still fills the GPU.
 __global__ __launch_bounds__(256) void k_macro_assemble(const double2 *__restrict__ E, int n_tr,
-                                                        const int32_t *__restrict__ child_map,
+                                                        const int32_t *__restrict__ child_inv,
                                                         int N, int b0, int nT,
                                                         double2 *__restrict__ T) {
-  const int Nc = N / 2, b = b0 + blockIdx.x;
+  const int r = blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+  if (r >= nT) return;
+  const int Nc = N / 2, b = b0 + blockIdx.z;
   const int ci = b % Nc, cj = (b / Nc) % Nc, ck = b / (Nc * Nc);
-  double2 *Tb = T + (int64_t)blockIdx.x * nT * nT;
-  for (int64_t k = threadIdx.x; k < (int64_t)nT * nT; k += 256) Tb[k] = mk(0.0, 0.0);
-  __syncthreads();
-  const int n2 = n_tr * n_tr;
-  for (int c = 0; c < 8; ++c) {
-    const int e = (2 * ci + (c & 1)) + N * ((2 * cj + ((c >> 1) & 1)) + N * (2 * ck + (c >> 2)));
-    const double2 *Ee = E + (int64_t)e * n2;
-    const int32_t *mp = child_map + c * n_tr;
-    for (int k = threadIdx.x; k < n2; k += 256) {
-      const int i = k % n_tr, j = k / n_tr;
-      double2 *dst = &Tb[mp[i] + (int64_t)mp[j] * nT];
-      *dst = cadd(*dst, Ee[k]);
+  double2 acc = mk(0.0, 0.0);
+#pragma unroll
+  for (int ch = 0; ch < 8; ++ch) {
+    const int lr = child_inv[ch * nT + r], lc = child_inv[ch * nT + c];
+    if (lr >= 0 && lc >= 0) {
+      const int e = (2 * ci + (ch & 1)) + N * ((2 * cj + ((ch >> 1) & 1)) + N * (2 * ck + (ch >> 2)));
+      acc = cadd(acc, E[(int64_t)e * n_tr * n_tr + lr + (int64_t)lc * n_tr]);
     }
-    __syncthreads();
   }
+  T[(int64_t)blockIdx.z * nT * nT + r + (int64_t)c * nT] = acc;
 }
 
 __global__ __launch_bounds__(256) void k_copy_sub(const double2 *__restrict__ src,
@@ -379,11 +381,12 @@ __global__ __launch_bounds__(256) void k_update_p(int64_t n, double2 *__restrict
 
 // ---- launchers --------------------------------------------------------------------------
 
-void launch_macro_assemble(const double2 *E, int n_tr, const int32_t *child_map, int N, int b0,
+void launch_macro_assemble(const double2 *E, int n_tr, const int32_t *child_inv, int N, int b0,
                            int count, int nT, double2 *T, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_macro_assemble, dim3(count), dim3(256), 0, s, E, n_tr, child_map, N, b0,
-                     nT, T);
+  if (count > 65535 || nT > 65535) throw DpgError(-1, "macro assembly grid too large");
+  hipLaunchKernelGGL(k_macro_assemble, dim3(cdiv(nT, 256), nT, count), dim3(256), 0, s, E, n_tr,
+                     child_inv, N, b0, nT, T);
   LAUNCH_OK();
 }
 

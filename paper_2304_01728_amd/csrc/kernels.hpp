@@ -8,9 +8,9 @@ namespace dpg {
 // ---- hierarchy setup (FP64) ----------------------------------------------------
 
 // T[b] (nT x nT, nT = nBf + nI) = sum over the 8 children of coarse element
-// b0 + b of their element matrices E (n_tr x n_tr), scattered through
-// child_map [8][n_tr] (positions in [B slots | I]).
-void launch_macro_assemble(const double2 *E, int n_tr, const int32_t *child_map, int N, int b0,
+// b0 + b of their element matrices E (n_tr x n_tr).  child_inv [8][nT] gives
+// each position of [B slots | I] its local index in each child, or -1.
+void launch_macro_assemble(const double2 *E, int n_tr, const int32_t *child_inv, int N, int b0,
                            int count, int nT, double2 *T, hipStream_t s);
 
 // dst[b][i + j ldd] = src[b][r0 + i + (c0 + j) lds] for i < rows, j < cols.
