@@ -102,8 +102,11 @@ __global__ __launch_bounds__(64) void k_rows_blk(const cplx_t<T> *__restrict__ t
 }
 
 // FP32 form of k_rows_blk on the matrix cores.  Y_I (32 x 32, columns past
-// nr are padding) accumulates four real 32x32x32 products per tile,
-//   Re Y += Re A Re X - Im A Im X,   Im Y += Re A Im X + Im A Re X,
+// nr are padding) accumulates three real 32x32x32 products per tile (the
+// three-multiplication complex product: a quarter fewer matrix-core
+// operations, and an imaginary part formed as p3 - p1 - p2, which in FP32
+// can lose digits when it is small against |A||X|; this path is the
+// mixed-precision preconditioner, corrected by the FP64 outer iteration),
 // with v_mfma_f32_32x32x2f32: lane l supplies A[l%32][k] and B[k][l%32] for
 // k = l/32 of each two-column slice, and receives result row
 // 8(v/4) + 4(l/32) + v%4, column l%32 in register v.  The tile A_IJ is
@@ -145,11 +148,14 @@ __global__ __launch_bounds__(64) void k_rows_mfma(const float2 *__restrict__ til
 #pragma unroll
     for (int s = 0; s < 16; ++s) xx[s] = xp[(int64_t)2 * s * nr];
   };
-  v16f accr, acci;
+  // three real products (Gauss): p1 = Re A Re X, p2 = Im A Im X,
+  // p3 = (Re A + Im A)(Re X + Im X); Re Y = p1 - p2, Im Y = p3 - p1 - p2
+  v16f p1, p2, p3;
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
-    accr[v] = 0.f;
-    acci[v] = 0.f;
+    p1[v] = 0.f;
+    p2[v] = 0.f;
+    p3[v] = 0.f;
   }
   // one tile: start loading tile Jn into tn/xn, stage t as A_IJ in LDS,
   // multiply; the scheduling barriers keep the loads ahead of the products
@@ -176,10 +182,9 @@ __global__ __launch_bounds__(64) void k_rows_mfma(const float2 *__restrict__ til
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const float2 av = buf[(2 * s + kk) * 32 + (n ^ (2 * (s >> 1)))];
-      accr = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, x[s].x, accr, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, x[s].y, acci, 0, 0, 0);
-      accr = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, -x[s].y, accr, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, x[s].x, acci, 0, 0, 0);
+      p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, x[s].x, p1, 0, 0, 0);
+      p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, x[s].y, p2, 0, 0, 0);
+      p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x + av.y, x[s].x + x[s].y, p3, 0, 0, 0);
     }
     __builtin_amdgcn_sched_barrier(0);
   };
@@ -196,7 +201,8 @@ __global__ __launch_bounds__(64) void k_rows_mfma(const float2 *__restrict__ til
   float2 *yb = yl + (loc_off[b] + 32 * I) * nr + n;
 #pragma unroll
   for (int v = 0; v < 16; ++v)
-    yb[(int64_t)(8 * (v >> 2) + 4 * kk + (v & 3)) * nr] = make_float2(accr[v], acci[v]);
+    yb[(int64_t)(8 * (v >> 2) + 4 * kk + (v & 3)) * nr] =
+        make_float2(p1[v] - p2[v], p3[v] - p1[v] - p2[v]);
 }
 
 template <typename T, int MODE>
