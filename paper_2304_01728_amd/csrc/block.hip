@@ -33,75 +33,9 @@ __global__ __launch_bounds__(256) void k_gather_blk(int64_t nloc, int nr,
 
 // One wave per (block b, tile row I): Y_I (32 x nr) = sum_J A_IJ X_J over the
 // stored upper tiles of row I (J >= I) and the conjugate transposes of the
-// stored tiles of column I (J < I), so no partial sums leave the wave.  Each
-// tile is staged in LDS in the orientation needed; lane (a, q) accumulates the
-// 4 x 4 panel rows 4a.., columns 4q.. in registers.
-template <typename T>
-__global__ __launch_bounds__(64) void k_rows_blk(const cplx_t<T> *__restrict__ tiles,
-                                                 const int2 *__restrict__ rows, int64_t nrows,
-                                                 const int32_t *__restrict__ bn,
-                                                 const int64_t *__restrict__ tile_off,
-                                                 const int64_t *__restrict__ loc_off,
-                                                 const cplx_t<T> *__restrict__ xl,
-                                                 cplx_t<T> *__restrict__ yl, int nr) {
-  using C = cplx_t<T>;
-  __shared__ C Ts[32][33];
-  __shared__ C Xs[32][kMaxCols + 1];
-  const int64_t w = blockIdx.x;
-  if (w >= nrows) return;
-  const int lane = threadIdx.x, a = lane >> 3, q = lane & 7;
-  const int2 bi = rows[w];
-  const int b = bi.x, I = bi.y;
-  const int nt = (bn[b] + 31) >> 5;
-  const C *xb = xl + loc_off[b] * nr;
-  C acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = czero<C>();
-  for (int J = 0; J < nt; ++J) {
-    const bool up = J >= I;
-    const int64_t tix = tile_off[b] + (up ? (int64_t)J * (J + 1) / 2 + I : (int64_t)I * (I + 1) / 2 + J);
-    const C *tp = tiles + tix * 1024 + lane;
-    C t[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) t[k] = tp[k * 64];
-    for (int e = lane; e < 32 * nr; e += 64) Xs[e / nr][e % nr] = xb[(int64_t)32 * J * nr + e];
-    // the lane holds stored entries (4a + i, 4q + j) at k = 4i + j
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (up) Ts[4 * a + i][4 * q + j] = t[4 * i + j];
-        else Ts[4 * q + j][4 * a + i] = cconj(t[4 * i + j]);
-      }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int c = 0; c < 32; ++c) {
-      C ta[4], xv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) ta[i] = Ts[4 * a + i][c];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) xv[j] = Xs[c][4 * q + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = cfma(ta[i], xv[j], acc[i][j]);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-  C *yb = yl + (loc_off[b] + 32 * I) * nr;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (4 * q + j < nr) yb[(int64_t)(4 * a + i) * nr + 4 * q + j] = acc[i][j];
-}
-
-// FP32 form of k_rows_blk on the matrix cores.  Y_I (32 x 32, columns past
+// stored tiles of column I (J < I), so no partial sums leave the wave.
+//
+// FP32, on the matrix cores.  Y_I (32 x 32, columns past
 // nr are padding) accumulates three real 32x32x32 products per tile (the
 // three-multiplication complex product: a quarter fewer matrix-core
 // operations, and an imaginary part formed as p3 - p1 - p2, which in FP32
@@ -117,6 +51,7 @@ __global__ __launch_bounds__(64) void k_rows_blk(const cplx_t<T> *__restrict__ t
 // Workgroup g runs on XCD g % 8, so each XCD is given a contiguous range of
 // tile rows: the rows of one block then share its tiles and X in one L2.
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(64) void k_rows_mfma(const float2 *__restrict__ tiles,
                                                   const int2 *__restrict__ rows, int64_t nrows,
@@ -203,6 +138,124 @@ __global__ __launch_bounds__(64) void k_rows_mfma(const float2 *__restrict__ til
   for (int v = 0; v < 16; ++v)
     yb[(int64_t)(8 * (v >> 2) + 4 * kk + (v & 3)) * nr] =
         make_float2(p1[v] - p2[v], p3[v] - p1[v] - p2[v]);
+}
+
+// FP64 form on the matrix cores (v_mfma_f64_16x16x4f64: lane l supplies
+// A[l%16][k] and B[k][l%16] for k = l/16 of each four-column step, and
+// receives result row 4v + l/16, column l%16 in element v).  A wave forms
+// Y_I as 2 x 2 blocks of 16 x 16, each complex product as four real ones
+// (the outer-iteration operator keeps full FP64 accuracy).  The tile A_IJ is
+// staged in LDS column by column (stride 33, double-buffered); X_J goes from
+// global memory straight into the B operands; the next tile and X_J are
+// loaded into a second register set while the current ones are multiplied
+// (one wave per SIMD, eight independent accumulators).
+__global__ __launch_bounds__(64) void k_rows_mfma64(const double2 *__restrict__ tiles,
+                                                    const int2 *__restrict__ rows, int64_t nrows,
+                                                    const int32_t *__restrict__ bn,
+                                                    const int64_t *__restrict__ tile_off,
+                                                    const int64_t *__restrict__ loc_off,
+                                                    const double2 *__restrict__ xl,
+                                                    double2 *__restrict__ yl, int nr) {
+  __shared__ double2 As[2][32 * 33];
+  const int64_t per = (nrows + 7) / 8;
+  const int64_t w = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (w >= nrows) return;
+  const int lane = threadIdx.x, a = lane >> 3, q = lane & 7;
+  const int li = lane & 15, lk = lane >> 4;
+  // columns past nr read column nr - 1; their results are not stored
+  const int c0 = li < nr ? li : nr - 1, c1 = 16 + li < nr ? 16 + li : nr - 1;
+  const int2 bi = rows[w];
+  const int b = bi.x, I = bi.y;
+  const int nt = (bn[b] + 31) >> 5;
+  const int64_t t0 = tile_off[b];
+  const double2 *xb = xl + loc_off[b] * nr;
+  auto load = [&](int J, double2 *tt, double2 *xx) {
+    const int64_t tix = t0 + (J >= I ? (int64_t)J * (J + 1) / 2 + I : (int64_t)I * (I + 1) / 2 + J);
+    const double2 *tp = tiles + tix * 1024 + lane;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) tt[k] = tp[k * 64];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const double2 *xr = xb + (int64_t)(32 * J + 4 * ks + lk) * nr;
+      xx[2 * ks] = xr[c0];
+      xx[2 * ks + 1] = xr[c1];
+    }
+  };
+  v4d are[2][2], aim[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      are[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      aim[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+  auto step = [&](int J, int Jn, const double2 *t, const double2 *x, double2 *tn, double2 *xn) {
+    load(Jn, tn, xn);
+    __builtin_amdgcn_sched_barrier(0);
+    const bool up = J >= I;
+    double2 *buf = As[J & 1];
+    // the lane holds stored entries (4a + i, 4q + j) at 4i + j; A_IJ is the
+    // stored tile (J >= I) or the conjugate transpose of tile (J, I)
+    const double sg = up ? 1.0 : -1.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = up ? 4 * q + j : 4 * a + i;
+        const int m = up ? 4 * a + i : 4 * q + j;
+        const double2 v = t[4 * i + j];
+        buf[c * 33 + m] = make_double2(v.x, sg * v.y);
+      }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int c = 4 * ks + lk;
+      const double2 ar[2] = {buf[c * 33 + li], buf[c * 33 + 16 + li]};
+      const double2 xv[2] = {x[2 * ks], x[2 * ks + 1]};
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          are[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i].x, xv[j].x, are[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          aim[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i].x, xv[j].y, aim[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          are[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar[i].y, xv[j].y, are[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          aim[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i].y, xv[j].x, aim[i][j], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  double2 tA[16], xA[16], tB[16], xB[16];
+  load(0, tA, xA);
+  int J = 0;
+  for (; J + 1 < nt; J += 2) {
+    step(J, J + 1, tA, xA, tB, xB);
+    step(J + 1, J + 2 < nt ? J + 2 : J + 1, tB, xB, tA, xA);
+  }
+  if (J < nt) step(J, J, tA, xA, tB, xB);
+  double2 *yb = yl + (loc_off[b] + 32 * I) * nr;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = 16 * j + li;
+      if (col >= nr) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        yb[(int64_t)(16 * i + 4 * v + lk) * nr + col] = make_double2(are[i][j][v], aim[i][j][v]);
+    }
 }
 
 template <typename T, int MODE>
@@ -523,7 +576,9 @@ void herm_apply_blk(HermSet &H, HermBlockBufs &W, const cplx_t<T> *X, cplx_t<T> 
       hipLaunchKernelGGL(k_rows_mfma, dim3((unsigned)(8 * per)), dim3(64), 0, s, tiles, H.rows.p,
                          H.nrows, H.bn.p, H.tile_off.p, H.loc_off.p, xl, yl, nr);
     } else {
-      hipLaunchKernelGGL((k_rows_blk<T>), dim3((unsigned)H.nrows), dim3(64), 0, s, tiles,
+      const int64_t per = (H.nrows + 7) / 8;
+      if (8 * per > INT32_MAX) throw DpgError(-1, "block apply: too many tile rows");
+      hipLaunchKernelGGL(k_rows_mfma64, dim3((unsigned)(8 * per)), dim3(64), 0, s, tiles,
                          H.rows.p, H.nrows, H.bn.p, H.tile_off.p, H.loc_off.p, xl, yl, nr);
     }
     LAUNCH_OK();

@@ -68,7 +68,7 @@ KERNEL_SYMBOLS = {"gram": "k_gram", "bmat": "k_bmat", "load": "k_load", "potrf":
                   "trsm": "k_trsm", "gemm": "k_gemm", "macro_asm": "k_macro_assemble",
                   "patch_gather": "k_patch_gather", "apply64": "k_units<double>",
                   "apply32": "k_units<float>", "reduce": "k_reduce",
-                  "applyb64": "k_rows_blk<double>", "applyb32": "k_rows_mfma"}
+                  "applyb64": "k_rows_mfma64", "applyb32": "k_rows_mfma"}
 
 
 class DPGError(RuntimeError):
