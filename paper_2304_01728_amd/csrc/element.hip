@@ -107,6 +107,7 @@ __global__ __launch_bounds__(256) void k_gram(const ElemTables *__restrict__ tb,
   if (idx >= (int64_t)nt * nt) return;
   const int e = e0 + blockIdx.y;
   const int i = (int)(idx % nt), j = (int)(idx / nt);
+  if (i < j) return;   // Hermitian: the Cholesky that follows reads the lower triangle only
   const int4 ti = test[i], tj = test[j];
   const double hh = 0.5 * g.h, w = g.omega, kap = kappa ? kappa[e] : 1.0;
   const int a[3] = {ti.y, ti.z, ti.w}, b[3] = {tj.y, tj.z, tj.w};

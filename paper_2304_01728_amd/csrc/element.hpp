@@ -48,7 +48,8 @@ void build_elem_tables(int p, int dp, ElemTables &t);
 // point; 5..10 = flux on face 0..5 with in-plane degrees (m, n, 0)).
 void build_descriptors(int p, int dp, std::vector<int4> &test, std::vector<int4> &trial);
 
-// G[e][nt x nt] for elements e0 .. e0+count-1 (column-major per element).
+// G[e][nt x nt] for elements e0 .. e0+count-1 (column-major per element);
+// only the lower triangle (diagonal included) is written.
 void launch_gram(const ElemTables *tb, const int4 *test, int nt, ElemGeom g, const double *kappa,
                  int e0, int count, double2 *G, hipStream_t s);
 // B part of [B | l]: nt x m columns of BL[e] (leading dimension nt).
