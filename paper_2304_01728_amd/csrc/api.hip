@@ -1526,13 +1526,15 @@ int64_t dpg_export(const dpg_ctx *cc, int what, int level, void *out, int64_t ca
           std::vector<double2> A((size_t)n * n);
           for (int J = 0; J < nt; ++J)
             for (int I = 0; I <= J; ++I) {
-              const double2 *tp = t.data() + (H.tile_off_h[b] + (int64_t)J * (J + 1) / 2 + I) * 1024;
-              for (int e = 0; e < 1024; ++e) {
-                const int k = e >> 6, lane = e & 63;
-                const int row = 32 * I + 4 * (lane >> 3) + (k >> 2), col = 32 * J + 4 * (lane & 7) + (k & 3);
+              const double2 *tp = t.data() + H.ent_off_h[b] + tile_entry(I, J);
+              for (int e = 0; e < kTileFull; ++e) {
+                const int k = e >> 6, lane = e & 63, ra = lane >> 3, cb = lane & 7;
+                if (I == J && ra > cb) continue;   // not stored: mirrored from (cb, ra)
+                const double2 v = tp[I == J ? k * kDiagSlots + diag_slot(ra, cb) : e];
+                const int row = 32 * I + 4 * ra + (k >> 2), col = 32 * J + 4 * cb + (k & 3);
                 if (row < n && col < n) {
-                  A[row + (size_t)col * n] = tp[e];
-                  if (I < J) A[col + (size_t)row * n] = mk(tp[e].x, -tp[e].y);
+                  A[row + (size_t)col * n] = v;
+                  if (I < J || ra < cb) A[col + (size_t)row * n] = mk(v.x, -v.y);
                 }
               }
             }

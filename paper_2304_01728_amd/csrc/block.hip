@@ -53,10 +53,10 @@ __global__ __launch_bounds__(256) void k_gather_blk(int64_t nloc, int nr,
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(64) void k_rows_mfma(const float2 *__restrict__ tiles,
+__global__ __launch_bounds__(64, 2) void k_rows_mfma(const float2 *__restrict__ tiles,
                                                   const int2 *__restrict__ rows, int64_t nrows,
                                                   const int32_t *__restrict__ bn,
-                                                  const int64_t *__restrict__ tile_off,
+                                                  const int64_t *__restrict__ ent_off,
                                                   const int64_t *__restrict__ loc_off,
                                                   const float2 *__restrict__ xl,
                                                   float2 *__restrict__ yl, int nr) {
@@ -72,13 +72,24 @@ __global__ __launch_bounds__(64) void k_rows_mfma(const float2 *__restrict__ til
   const int2 bi = rows[w];
   const int b = bi.x, I = bi.y;
   const int nt = (bn[b] + 31) >> 5;
-  const int64_t t0 = tile_off[b];
+  const int64_t e0 = ent_off[b];
+  // a diagonal tile stores the sub-blocks a <= q only (slot diag_slot(a, q))
+  const bool dup = a <= q;
+  const int dsl = dup ? diag_slot(a, q) : 0;
   const float2 *xb = xl + loc_off[b] * nr + ncl;
   auto load = [&](int J, float2 *tt, float2 *xx) {
-    const int64_t tix = t0 + (J >= I ? (int64_t)J * (J + 1) / 2 + I : (int64_t)I * (I + 1) / 2 + J);
-    const float2 *tp = tiles + tix * 1024 + lane;
+    // (wave-uniform branch, constant strides: immediate load offsets); lanes
+    // below the diagonal of a diagonal tile read slot 0 (in range), their
+    // values are not staged
+    if (J != I) {
+      const float2 *tp = tiles + e0 + (J > I ? tile_entry(I, J) : tile_entry(J, I)) + lane;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) tt[k] = tp[k * 64];
+      for (int k = 0; k < 16; ++k) tt[k] = tp[k * 64];
+    } else {
+      const float2 *tp = tiles + e0 + tile_entry(I, I) + dsl;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) tt[k] = tp[k * kDiagSlots];
+    }
     const float2 *xp = xb + (int64_t)(32 * J + kk) * nr;
 #pragma unroll
     for (int s = 0; s < 16; ++s) xx[s] = xp[(int64_t)2 * s * nr];
@@ -101,16 +112,30 @@ __global__ __launch_bounds__(64) void k_rows_mfma(const float2 *__restrict__ til
     float2 *buf = As[J & 1];
     // the lane holds stored entries (4a + i, 4q + j) at 4i + j; A_IJ is the
     // stored tile (J >= I) or the conjugate transpose of tile (J, I)
-    const float sg = up ? 1.f : -1.f;
+    if (J != I) {
+      const float sg = up ? 1.f : -1.f;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int c = up ? 4 * q + j : 4 * a + i;
-        const int m = up ? 4 * a + i : 4 * q + j;
-        const float2 v = t[4 * i + j];
-        buf[c * 32 + (m ^ (2 * ((c >> 2) & 7)))] = make_float2(v.x, sg * v.y);
-      }
+        for (int j = 0; j < 4; ++j) {
+          const int c = up ? 4 * q + j : 4 * a + i;
+          const int m = up ? 4 * a + i : 4 * q + j;
+          const float2 v = t[4 * i + j];
+          buf[c * 32 + (m ^ (2 * ((c >> 2) & 7)))] = make_float2(v.x, sg * v.y);
+        }
+    } else {
+      // diagonal tile: lanes a <= q write their sub-block, lanes a < q also
+      // its conjugate transpose below the diagonal
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = 4 * q + j, m = 4 * a + i;
+          const float2 v = t[4 * i + j];
+          if (dup) buf[c * 32 + (m ^ (2 * ((c >> 2) & 7)))] = v;
+          if (a < q) buf[m * 32 + (c ^ (2 * ((m >> 2) & 7)))] = make_float2(v.x, -v.y);
+        }
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -152,7 +177,7 @@ __global__ __launch_bounds__(64) void k_rows_mfma(const float2 *__restrict__ til
 __global__ __launch_bounds__(64) void k_rows_mfma64(const double2 *__restrict__ tiles,
                                                     const int2 *__restrict__ rows, int64_t nrows,
                                                     const int32_t *__restrict__ bn,
-                                                    const int64_t *__restrict__ tile_off,
+                                                    const int64_t *__restrict__ ent_off,
                                                     const int64_t *__restrict__ loc_off,
                                                     const double2 *__restrict__ xl,
                                                     double2 *__restrict__ yl, int nr) {
@@ -167,13 +192,24 @@ __global__ __launch_bounds__(64) void k_rows_mfma64(const double2 *__restrict__ 
   const int2 bi = rows[w];
   const int b = bi.x, I = bi.y;
   const int nt = (bn[b] + 31) >> 5;
-  const int64_t t0 = tile_off[b];
+  const int64_t e0 = ent_off[b];
+  // a diagonal tile stores the sub-blocks a <= q only (slot diag_slot(a, q))
+  const bool dup = a <= q;
+  const int dsl = dup ? diag_slot(a, q) : 0;
   const double2 *xb = xl + loc_off[b] * nr;
   auto load = [&](int J, double2 *tt, double2 *xx) {
-    const int64_t tix = t0 + (J >= I ? (int64_t)J * (J + 1) / 2 + I : (int64_t)I * (I + 1) / 2 + J);
-    const double2 *tp = tiles + tix * 1024 + lane;
+    // (wave-uniform branch, constant strides: immediate load offsets); lanes
+    // below the diagonal of a diagonal tile read slot 0 (in range), their
+    // values are not staged
+    if (J != I) {
+      const double2 *tp = tiles + e0 + (J > I ? tile_entry(I, J) : tile_entry(J, I)) + lane;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) tt[k] = tp[k * 64];
+      for (int k = 0; k < 16; ++k) tt[k] = tp[k * 64];
+    } else {
+      const double2 *tp = tiles + e0 + tile_entry(I, I) + dsl;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) tt[k] = tp[k * kDiagSlots];
+    }
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
       const double2 *xr = xb + (int64_t)(32 * J + 4 * ks + lk) * nr;
@@ -196,16 +232,30 @@ __global__ __launch_bounds__(64) void k_rows_mfma64(const double2 *__restrict__ 
     double2 *buf = As[J & 1];
     // the lane holds stored entries (4a + i, 4q + j) at 4i + j; A_IJ is the
     // stored tile (J >= I) or the conjugate transpose of tile (J, I)
-    const double sg = up ? 1.0 : -1.0;
+    if (J != I) {
+      const double sg = up ? 1.0 : -1.0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int c = up ? 4 * q + j : 4 * a + i;
-        const int m = up ? 4 * a + i : 4 * q + j;
-        const double2 v = t[4 * i + j];
-        buf[c * 33 + m] = make_double2(v.x, sg * v.y);
-      }
+        for (int j = 0; j < 4; ++j) {
+          const int c = up ? 4 * q + j : 4 * a + i;
+          const int m = up ? 4 * a + i : 4 * q + j;
+          const double2 v = t[4 * i + j];
+          buf[c * 33 + m] = make_double2(v.x, sg * v.y);
+        }
+    } else {
+      // diagonal tile: lanes a <= q write their sub-block, lanes a < q also
+      // its conjugate transpose below the diagonal
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = 4 * q + j, m = 4 * a + i;
+          const double2 v = t[4 * i + j];
+          if (dup) buf[c * 33 + m] = v;
+          if (a < q) buf[m * 33 + c] = make_double2(v.x, -v.y);
+        }
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -574,12 +624,12 @@ void herm_apply_blk(HermSet &H, HermBlockBufs &W, const cplx_t<T> *X, cplx_t<T> 
       const int64_t per = (H.nrows + 7) / 8;
       if (8 * per > INT32_MAX) throw DpgError(-1, "block apply: too many tile rows");
       hipLaunchKernelGGL(k_rows_mfma, dim3((unsigned)(8 * per)), dim3(64), 0, s, tiles, H.rows.p,
-                         H.nrows, H.bn.p, H.tile_off.p, H.loc_off.p, xl, yl, nr);
+                         H.nrows, H.bn.p, H.ent_off.p, H.loc_off.p, xl, yl, nr);
     } else {
       const int64_t per = (H.nrows + 7) / 8;
       if (8 * per > INT32_MAX) throw DpgError(-1, "block apply: too many tile rows");
       hipLaunchKernelGGL(k_rows_mfma64, dim3((unsigned)(8 * per)), dim3(64), 0, s, tiles,
-                         H.rows.p, H.nrows, H.bn.p, H.tile_off.p, H.loc_off.p, xl, yl, nr);
+                         H.rows.p, H.nrows, H.bn.p, H.ent_off.p, H.loc_off.p, xl, yl, nr);
     }
     LAUNCH_OK();
   }

@@ -69,7 +69,22 @@ template <typename C> __device__ __forceinline__ void load_tile(const C *__restr
   for (int k = 0; k < 16; ++k) t[k] = tp[k * 64];
 }
 
-// Row sums of one tile into its partial slot; column sums accumulated.
+// Diagonal tile: lanes of stored sub-blocks (on) read their slot, the others
+// (below the diagonal) hold zeros.
+template <typename C>
+__device__ __forceinline__ void load_diag(const C *__restrict__ tp, bool on, C t[16]) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    t[k].x = 0;
+    t[k].y = 0;
+    if (on) t[k] = tp[k * kDiagSlots];
+  }
+}
+
+// Row sums of one tile into its partial slot; column sums accumulated where
+// off holds: every sub-block of an off-diagonal tile, the sub-blocks strictly
+// above the diagonal of a diagonal tile (their conjugate transposes are the
+// sub-blocks below it, which are not stored).
 template <typename C>
 __device__ __forceinline__ void do_tile(const C t[16], const C xJ[4], const C *xr, bool off,
                                         int ra, int cb, C cacc[4], C *__restrict__ slot) {
@@ -83,8 +98,6 @@ __device__ __forceinline__ void do_tile(const C t[16], const C xJ[4], const C *x
     for (int j = 0; j < 4; ++j) a = cfma(t[4 * i + j], xJ[j], a);
     rs[i] = a;
   }
-  // column sums skip the diagonal tile (its lower half is the conjugate of
-  // the upper half, already counted by the row sums)
   if (off) {
     C xI[4];
 #pragma unroll
@@ -147,9 +160,11 @@ __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ til
   if (wv >= nunits) return;
   const int lane = threadIdx.x & 63, ra = lane >> 3, cb = lane & 7;
   const int4 d0 = units[2 * wv], d1 = units[2 * wv + 1];
-  const int64_t tile = (int64_t)(uint32_t)d0.x | ((int64_t)d0.y << 32);
+  const int64_t ent = (int64_t)(uint32_t)d0.x | ((int64_t)d0.y << 32);
+  // a one-tile segment is a diagonal tile; of two, the first is off-diagonal
   const bool two = d1.w & 1, off0 = d1.w & 2, off1 = d1.w & 4;
-  const C *tp = tiles + tile * 1024 + lane;
+  const bool upper = ra <= cb, strict = ra < cb;
+  const C *tp = tiles + ent;
   C t0[16], t1[16], xJ[4], cacc[4];
   // x first: loads complete in order, so the LDS staging below waits for x
   // only, not for the tiles
@@ -163,15 +178,20 @@ __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ til
     cacc[j].x = 0;
     cacc[j].y = 0;
   }
-  load_tile(tp, t0);
-  load_tile(tp + (two ? 1024 : 0), t1);  // a one-tile segment re-reads its tile (cache hit)
+  const int ds = upper ? diag_slot(ra, cb) : 0;
+  if (off0) load_tile(tp + lane, t0);
+  else load_diag(tp + ds, upper, t0);
+  if (two) {
+    if (off1) load_tile(tp + kTileFull + lane, t1);
+    else load_diag(tp + kTileFull + ds, upper, t1);
+  }
   C *xw = xs[wave];
   xw[lane] = v;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  do_tile(t0, xJ, xw, off0, ra, cb, cacc, part + d1.x);
-  if (two) do_tile(t1, xJ, xw + 32, off1, ra, cb, cacc, part + d1.x + d1.y);
+  do_tile(t0, xJ, xw, off0 || strict, ra, cb, cacc, part + d1.x);
+  if (two) do_tile(t1, xJ, xw + 32, off1 || strict, ra, cb, cacc, part + d1.x + d1.y);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     cacc[j] = cadd(cacc[j], shfl_xor_c(cacc[j], 8));
@@ -182,7 +202,9 @@ __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ til
 }
 
 // Half a wave per (block, tile row I): y_loc rows of I = column sums of the
-// segments of tile column I + row sums of tiles (I, J >= I).
+// segments of tile column I + row sums of tiles (I, J >= I).  The slots are
+// independent loads: eight are in flight per lane (a row of a 24-tile block
+// sums 25 slots), summed in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rows(const int2 *__restrict__ rows, int64_t nrows,
                                               const int32_t *__restrict__ bn,
@@ -192,20 +214,38 @@ __global__ __launch_bounds__(256) void k_rows(const int2 *__restrict__ rows, int
                                               const cplx_t<T> *__restrict__ part,
                                               cplx_t<T> *__restrict__ yl) {
   using C = cplx_t<T>;
+  constexpr int U = 8;
   const int64_t hw = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 5;
   if (hw >= nrows) return;
   const int r = threadIdx.x & 31;
   const int2 bi = rows[hw];
   const int nt = (bn[bi.x] + 31) >> 5, I = bi.y;
-  C acc;
-  acc.x = 0;
-  acc.y = 0;
   const C *cp = part + cp_off[bi.x] + colbase(I) + r;
-  const int nseg = (I + kSeg) / kSeg;
-  for (int q = 0; q < nseg; ++q) acc = cadd(acc, cp[q * 32]);
   const C *rp = part + rp_off[bi.x] + row_slot(nt, I, I) + r;
-  for (int q = 0; q < nt - I; ++q) acc = cadd(acc, rp[q * 32]);
-  yl[loc_off[bi.x] + 32 * I + r] = acc;
+  const int nseg = (I + kSeg) / kSeg, tot = nseg + nt - I;
+  C acc[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    acc[u].x = 0;
+    acc[u].y = 0;
+  }
+  for (int q0 = 0; q0 < tot; q0 += U) {
+    C v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + u;
+      v[u].x = 0;
+      v[u].y = 0;
+      if (q < tot) v[u] = q < nseg ? cp[q * 32] : rp[(q - nseg) * 32];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = cadd(acc[u], v[u]);
+  }
+#pragma unroll
+  for (int w = U / 2; w >= 1; w /= 2)
+#pragma unroll
+    for (int u = 0; u < w; ++u) acc[u] = cadd(acc[u], acc[u + w]);
+  yl[loc_off[bi.x] + 32 * I + r] = acc[0];
 }
 
 template <typename T, int MODE>
@@ -229,6 +269,7 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t nvec, const int32_t *__
 
 __global__ __launch_bounds__(256) void k_pack(const int4 *__restrict__ tdesc, int64_t tile0,
                                               const int32_t *__restrict__ bn,
+                                              const int64_t *__restrict__ ent_off,
                                               const double2 *__restrict__ src,
                                               const int64_t *__restrict__ src_off,
                                               const int32_t *__restrict__ ld,
@@ -239,17 +280,20 @@ __global__ __launch_bounds__(256) void k_pack(const int4 *__restrict__ tdesc, in
   const int4 td = tdesc[t];
   const int b = td.x, I = td.y, J = td.z, n = bn[b];
   const int64_t mo = map_off ? map_off[b] : -1;
-  for (int e = threadIdx.x; e < 1024; e += 256) {
-    const int k = e >> 6, lane = e & 63;
-    const int ri = 4 * (lane >> 3) + (k >> 2), cj = 4 * (lane & 7) + (k & 3);
+  const int64_t t0 = ent_off[b] + tile_entry(I, J);
+  for (int e = threadIdx.x; e < kTileFull; e += 256) {
+    const int k = e >> 6, lane = e & 63, ra = lane >> 3, cb = lane & 7;
+    if (I == J && ra > cb) continue;   // below the diagonal of a diagonal tile
+    const int64_t dst = t0 + (I == J ? k * kDiagSlots + diag_slot(ra, cb) : e);
+    const int ri = 4 * ra + (k >> 2), cj = 4 * cb + (k & 3);
     const int row = 32 * I + ri, col = 32 * J + cj;
     double2 v = mk(0.0, 0.0);
     if (row < n && col < n) {
       const int64_t mr = mo >= 0 ? map[mo + row] : row, mc = mo >= 0 ? map[mo + col] : col;
       v = src[src_off[b] + mr + mc * (int64_t)ld[b]];
     }
-    if (t64) t64[t * 1024 + e] = v;
-    if (t32) t32[t * 1024 + e] = mkf((float)v.x, (float)v.y);
+    if (t64) t64[dst] = v;
+    if (t32) t32[dst] = mkf((float)v.x, (float)v.y);
   }
 }
 
@@ -260,8 +304,9 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
   nblk = (int)sizes.size();
   nvec = nvec_;
   n_h = sizes;
-  std::vector<int64_t> toff(nblk), cpo(nblk), rpo(nblk), loff(nblk);
+  std::vector<int64_t> toff(nblk), eoff(nblk), cpo(nblk), rpo(nblk), loff(nblk);
   int64_t t = 0, p = 0, lo = 0, ii = 0;
+  nent = 0;
   packed = 0;
   full = 0;
   std::vector<int4> un;
@@ -271,6 +316,8 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
   for (int b = 0; b < nblk; ++b) {
     const int n = sizes[b], nt = (n + 31) / 32;
     toff[b] = t;
+    eoff[b] = nent;
+    nent += tile_entry(0, nt);
     cpo[b] = p;
     p += colbase(nt);
     rpo[b] = p;
@@ -299,15 +346,15 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
   nunits = (int64_t)un.size();
   if (npart >= (1LL << 31) || nloc >= (1LL << 31))
     throw DpgError(-1, "HermSet: partial or local vectors beyond 32-bit offsets");
-  // unit descriptors: {tile index lo, hi, x offset of tile row I0, of tile
-  // column J}, {row-partial slot of (I0, J), step to the slot of (I0 + 1, J),
+  // unit descriptors: {entry offset of tile (I0, J) lo, hi, x offset of tile
+  // row I0, of tile column J}, {row-partial slot of (I0, J), step to the slot of (I0 + 1, J),
   // column-partial slot, flags: 1 two tiles, 2 first tile off-diagonal, 4
   // second tile off-diagonal}
   std::vector<int4> ud(2 * un.size());
   for (size_t k = 0; k < un.size(); ++k) {
     const int b = un[k].x, J = un[k].y, I0 = un[k].z, seg = un[k].w;
     const int nt = (sizes[b] + 31) / 32;
-    const int64_t tile = toff[b] + (int64_t)J * (J + 1) / 2 + I0;
+    const int64_t tile = eoff[b] + tile_entry(I0, J);
     const int64_t r0 = rpo[b] + row_slot(nt, I0, J);
     const int64_t rd = I0 + 1 <= J ? row_slot(nt, I0 + 1, J) - row_slot(nt, I0, J) : 0;
     const int64_t cs = cpo[b] + colbase(J) + seg * 32;
@@ -318,6 +365,7 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
   }
   nrows = (int64_t)rw.size();
   tile_off_h = toff;
+  ent_off_h = eoff;
   // reduction lists: for every vector entry, the local rows holding it
   std::vector<int32_t> cnt(nvec + 1, 0);
   for (int32_t v : gi) {
@@ -330,7 +378,7 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
   for (int64_t k = 0; k < (int64_t)gi.size(); ++k)
     if (gi[k] >= 0) ent[fill[gi[k]]++] = (int32_t)k;
   bn.upload(sizes, bud, s);
-  tile_off.upload(toff, bud, s);
+  ent_off.upload(eoff, bud, s);
   cp_off.upload(cpo, bud, s);
   rp_off.upload(rpo, bud, s);
   loc_off.upload(loff, bud, s);
@@ -341,13 +389,13 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
   red_ptr.upload(cnt, bud, s);
   red_ent.upload(ent, bud, s);
   if (fp64) {
-    t64.alloc(ntiles * 1024, bud);
+    t64.alloc(nent, bud);
     p64.alloc(npart, bud);
     xl64.alloc(nloc, bud);
     yl64.alloc(nloc, bud);
   }
   if (fp32) {
-    t32.alloc(ntiles * 1024, bud);
+    t32.alloc(nent, bud);
     p32.alloc(npart, bud);
     xl32.alloc(nloc, bud);
     yl32.alloc(nloc, bud);
@@ -360,7 +408,8 @@ void HermSet::pack(const double2 *src, const int64_t *src_off_dev, const int32_t
                    int64_t tile0, int64_t count) {
   if (count < 0) count = ntiles - tile0;
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_pack, dim3((unsigned)count), dim3(256), 0, s, tdesc.p, tile0, bn.p, src,
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)count), dim3(256), 0, s, tdesc.p, tile0, bn.p,
+                     ent_off.p, src,
                      src_off_dev, ld_dev, map_off_dev, map_dev, t64.p, t32.p);
   LAUNCH_OK();
 }

@@ -4,10 +4,12 @@
 // "V-cycle and smoother") and the coarsest-level inverse.
 //
 // Storage: only the upper triangle of 32x32 tiles of each block, tiles of
-// block b ordered by tile column J then tile row I <= J; diagonal tiles are
-// stored whole.  Inside a tile, entry (r, c) sits at [k][lane] with
-// lane = 8 (r/4) + c/4 and k = 4 (r%4) + c%4, so that one wave reads a tile
-// with 16 fully coalesced 64-lane loads and every lane holds a 4x4 sub-block.
+// block b ordered by tile column J then tile row I <= J.  Inside a tile,
+// entry (r, c) sits at [k][lane] with lane = 8 (r/4) + c/4 and
+// k = 4 (r%4) + c%4, so that one wave reads a tile with 16 fully coalesced
+// 64-lane loads and every lane holds a 4x4 sub-block.  A diagonal tile keeps
+// only the sub-blocks on and above its diagonal (36 of 64, the diagonal 4x4
+// sub-blocks whole): [k][slot] with 36 slots, 576 entries instead of 1024.
 //
 // Apply (four kernels, deterministic):
 //  1. gather:  x_loc[b] = R_b x, zero-padded to 32 nt_b entries;
@@ -26,15 +28,31 @@ namespace dpg {
 
 enum { RED_SET = 0, RED_RESID = 1, RED_AXPY = 2, RED_SET_SCALED = 3 };
 
+constexpr int kTileFull = 1024, kTileDiag = 576, kDiagSlots = 36;
+
+// Entry offset of tile (I, J), I <= J, inside its block: the tile columns
+// before J hold J (J - 1) / 2 full tiles and J diagonal tiles, and the tiles
+// of column J come in order I = 0..J.
+__host__ __device__ __forceinline__ int64_t tile_entry(int I, int J) {
+  return (int64_t)kTileFull * ((int64_t)J * (J - 1) / 2 + I) + (int64_t)kTileDiag * J;
+}
+
+// Slot of sub-block (ra, cb), ra <= cb, in a diagonal tile: row-major order
+// of the upper triangle of the 8 x 8 sub-block grid.
+__host__ __device__ __forceinline__ int diag_slot(int ra, int cb) {
+  return ra * 8 - ra * (ra - 1) / 2 + (cb - ra);
+}
+
 struct HermSet {
   int nblk = 0;
   int64_t nvec = 0;          // length of the target vector
   int64_t ntiles = 0, npart = 0, nunits = 0, nrows = 0, nloc = 0, packed = 0;
+  int64_t nent = 0;          // stored tile entries
   int64_t full = 0;          // sum of n_b^2 (entries of the full blocks)
   std::vector<int32_t> n_h;  // block sizes (host)
-  std::vector<int64_t> tile_off_h;
+  std::vector<int64_t> tile_off_h, ent_off_h;   // per block: first tile index, first entry
   DevBuf<int32_t> bn;
-  DevBuf<int64_t> tile_off, cp_off, rp_off, loc_off;
+  DevBuf<int64_t> ent_off, cp_off, rp_off, loc_off;
   DevBuf<int32_t> gidx;      // [nloc] vector index of each padded local row, -1 = padding
   DevBuf<int4> units;        // two int4 descriptors per (block, J, tile-row pair), longest first
   DevBuf<int2> rows;         // (block, I)
@@ -46,8 +64,8 @@ struct HermSet {
   DevBuf<double2> p64, xl64, yl64;   // partials and local vectors
   DevBuf<float2> p32, xl32, yl32;
   Prof *prof = nullptr;      // kernel timing of the owning context
-  int64_t bytes_fp64() const { return ntiles * 1024 * 16; }
-  int64_t bytes_fp32() const { return ntiles * 1024 * 8; }
+  int64_t bytes_fp64() const { return nent * 16; }
+  int64_t bytes_fp32() const { return nent * 8; }
   // algorithmic entries: packed Hermitian n(n+1)/2 per block
   int64_t packed_entries() const { return packed; }
 
