@@ -64,9 +64,22 @@ template <typename C> __device__ __forceinline__ C rowsum_scatter(const C rs[4],
   return cadd(k, dpp_c<kDppXor1>(k));
 }
 
+// Tile entries are read once per application: non-temporal loads keep them
+// from displacing the x entries and partials in the caches.
+__device__ __forceinline__ double2 ld_nt(const double2 *p) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ld_nt(const float2 *p) {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+  return make_float2(v.x, v.y);
+}
+
 template <typename C> __device__ __forceinline__ void load_tile(const C *__restrict__ tp, C t[16]) {
 #pragma unroll
-  for (int k = 0; k < 16; ++k) t[k] = tp[k * 64];
+  for (int k = 0; k < 16; ++k) t[k] = ld_nt(tp + k * 64);
 }
 
 // Diagonal tile: lanes of stored sub-blocks (on) read their slot, the others
@@ -77,7 +90,7 @@ __device__ __forceinline__ void load_diag(const C *__restrict__ tp, bool on, C t
   for (int k = 0; k < 16; ++k) {
     t[k].x = 0;
     t[k].y = 0;
-    if (on) t[k] = tp[k * kDiagSlots];
+    if (on) t[k] = ld_nt(tp + k * kDiagSlots);
   }
 }
 
