@@ -70,19 +70,26 @@ __device__ __forceinline__ void xcd_remap(int &bx, int &by) {
 }
 
 // One k-slice of op(A) (64 x 16) and op(B) (16 x 64), four entries of each per
-// thread, zero outside m x k and k x n.
+// thread.  Every load is issued (entries outside m x k and k x n read the
+// nearest entry inside, which exists because the tile is not empty), and the
+// returned mask marks the entries inside; store_slice writes zeros for the
+// others and conjugates an OP_C operand.  Loads guarded by a branch, or
+// conjugated as they arrive, made the compiler wait for each load of the
+// prefetch before issuing the next.
 template <int OPA, int OPB>
-__device__ __forceinline__ void load_slice(int m, int n, int k, int k0, int r0, int c0,
-                                           const double2 *A, int lda, const double2 *B, int ldb,
-                                           double2 ra[4], double2 rb[4]) {
+__device__ __forceinline__ unsigned load_slice(int m, int n, int k, int k0, int r0, int c0,
+                                               const double2 *A, int lda, const double2 *B,
+                                               int ldb, double2 ra[4], double2 rb[4]) {
   const int tid = threadIdx.x;
+  unsigned ok = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int e = tid + NT * q;
     int rr, kk;
     if (OPA == OP_N) { rr = e % TM; kk = e / TM; } else { kk = e % TK; rr = e / TK; }
     const int r = r0 + rr, kg = k0 + kk;
-    ra[q] = (r < m && kg < k) ? ld_op<OPA>(A, lda, r, kg) : mk(0.0, 0.0);
+    ok |= (unsigned)(r < m && kg < k) << q;
+    ra[q] = ld_op<OPA == OP_C ? OP_T : OPA>(A, lda, min(r, m - 1), min(kg, k - 1));
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -90,12 +97,14 @@ __device__ __forceinline__ void load_slice(int m, int n, int k, int k0, int r0, 
     int kk, cc;
     if (OPB == OP_N) { kk = e % TK; cc = e / TK; } else { cc = e % TN; kk = e / TN; }
     const int c = c0 + cc, kg = k0 + kk;
-    rb[q] = (c < n && kg < k) ? ld_op<OPB>(B, ldb, kg, c) : mk(0.0, 0.0);
+    ok |= (unsigned)(c < n && kg < k) << (4 + q);
+    rb[q] = ld_op<OPB == OP_C ? OP_T : OPB>(B, ldb, min(kg, k - 1), min(c, n - 1));
   }
+  return ok;
 }
 
 template <int OPA, int OPB>
-__device__ __forceinline__ void store_slice(const double2 ra[4], const double2 rb[4],
+__device__ __forceinline__ void store_slice(const double2 ra[4], const double2 rb[4], unsigned ok,
                                             GemmSmem &sm) {
   const int tid = threadIdx.x;
 #pragma unroll
@@ -103,14 +112,16 @@ __device__ __forceinline__ void store_slice(const double2 ra[4], const double2 r
     const int e = tid + NT * q;
     int rr, kk;
     if (OPA == OP_N) { rr = e % TM; kk = e / TM; } else { kk = e % TK; rr = e / TK; }
-    sm.As[rr][kk] = ra[q];
+    const double2 v = OPA == OP_C ? cconj(ra[q]) : ra[q];
+    sm.As[rr][kk] = ((ok >> q) & 1) ? v : mk(0.0, 0.0);
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int e = tid + NT * q;
     int kk, cc;
     if (OPB == OP_N) { kk = e % TK; cc = e / TK; } else { cc = e % TN; kk = e / TN; }
-    sm.Bs[kk][cc] = rb[q];
+    const double2 v = OPB == OP_C ? cconj(rb[q]) : rb[q];
+    sm.Bs[kk][cc] = ((ok >> (4 + q)) & 1) ? v : mk(0.0, 0.0);
   }
 }
 
@@ -145,12 +156,13 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int 
   // The next k-slice is fetched into registers while the current one is
   // multiplied from LDS, so global latency hides behind the matrix cores.
   double2 ra[4], rb[4];
-  if (k_begin < k) load_slice<OPA, OPB>(m, n, k, k_begin, r0, c0, A, lda, B, ldb, ra, rb);
+  unsigned ok = 0;
+  if (k_begin < k) ok = load_slice<OPA, OPB>(m, n, k, k_begin, r0, c0, A, lda, B, ldb, ra, rb);
 #pragma unroll 1
   for (int k0 = k_begin; k0 < k; k0 += TK) {
-    store_slice<OPA, OPB>(ra, rb, sm);
+    store_slice<OPA, OPB>(ra, rb, ok, sm);
     __syncthreads();
-    if (k0 + TK < k) load_slice<OPA, OPB>(m, n, k, k0 + TK, r0, c0, A, lda, B, ldb, ra, rb);
+    if (k0 + TK < k) ok = load_slice<OPA, OPB>(m, n, k, k0 + TK, r0, c0, A, lda, B, ldb, ra, rb);
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 4) {
       double2 a[2], b[2];
@@ -181,22 +193,35 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int 
     }
     __syncthreads();
   }
+  // The C entries of a row block (eight per lane) are loaded together, from
+  // the nearest entry inside m x n where outside (the value is then unused),
+  // before any is combined and stored.
   const bool use_beta = beta.x != 0.0 || beta.y != 0.0;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2; ++i) {
+    double2 cv[2][4];
+    if (use_beta) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + wr + 16 * i + lk + 4 * e, c = c0 + wc + 16 * j + li;
+          cv[j][e] = C[min(r, m - 1) + (int64_t)min(c, n - 1) * ldc];
+        }
+    }
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int r = r0 + wr + 16 * i + lk + 4 * e, c = c0 + wc + 16 * j + li;
         if (r < m && c < n && (!lower_only || c <= r)) {
-          double2 *p = &C[r + (int64_t)c * ldc];
           double2 v = cmul(alpha, mk(acc_re[i][j][e], acc_im[i][j][e]));
-          if (use_beta) v = cfma(beta, *p, v);
-          *p = v;
+          if (use_beta) v = cfma(beta, cv[j][e], v);
+          C[r + (int64_t)c * ldc] = v;
           if (mirror) C[c + (int64_t)r * ldc] = cconj(v);
         }
       }
+  }
 }
 
 // ---- diagonal blocks -------------------------------------------------------------
@@ -435,12 +460,21 @@ __global__ __launch_bounds__(NTB, 2) void k_potrf_diag(double2 *base, const Potr
   if (kb <= 0 || info[blockIdx.x] != 0) return;
   double2 *A = base + it.a + k0 + (int64_t)k0 * lda;
   const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += NTB) {
-    const int i = e % NB, j = e / NB;
+  // all sixteen loads of a thread are issued before the LDS stores (entries
+  // outside the kb x kb block read the nearest one inside and are replaced
+  // by the identity padding)
+  constexpr int kLd = NB * NB / NTB;
+  double2 v[kLd];
+#pragma unroll
+  for (int q = 0; q < kLd; ++q) {
+    const int e = tid + NTB * q, i = e % NB, j = e / NB;
+    v[q] = A[min(i, kb - 1) + (int64_t)min(j, kb - 1) * lda];
+  }
+#pragma unroll
+  for (int q = 0; q < kLd; ++q) {
+    const int e = tid + NTB * q, i = e % NB, j = e / NB;
     if (i < j) continue;
-    double2 v = mk(i == j ? 1.0 : 0.0, 0.0);
-    if (i < kb && j < kb) v = A[i + (int64_t)j * lda];
-    sm.L[pk(i, j)] = v;
+    sm.L[pk(i, j)] = (i < kb && j < kb) ? v[q] : mk(i == j ? 1.0 : 0.0, 0.0);
     sm.X[pk(i, j)] = mk(0.0, 0.0);
   }
   if (tid == 0) sm.fail = 0;

@@ -21,15 +21,22 @@ __global__ __launch_bounds__(256) void k_macro_assemble(const double2 *__restric
   if (r >= nT) return;
   const int Nc = N / 2, b = b0 + blockIdx.z;
   const int ci = b % Nc, cj = (b / Nc) % Nc, ck = b / (Nc * Nc);
-  double2 acc = mk(0.0, 0.0);
+  // all eight loads are issued before any is used (a child without the
+  // entry reads its entry (0, 0), in range, and contributes zero); the sum
+  // runs over the children in order
+  double2 v[8];
+  bool on[8];
 #pragma unroll
   for (int ch = 0; ch < 8; ++ch) {
     const int lr = child_inv[ch * nT + r], lc = child_inv[ch * nT + c];
-    if (lr >= 0 && lc >= 0) {
-      const int e = (2 * ci + (ch & 1)) + N * ((2 * cj + ((ch >> 1) & 1)) + N * (2 * ck + (ch >> 2)));
-      acc = cadd(acc, E[(int64_t)e * n_tr * n_tr + lr + (int64_t)lc * n_tr]);
-    }
+    const int e = (2 * ci + (ch & 1)) + N * ((2 * cj + ((ch >> 1) & 1)) + N * (2 * ck + (ch >> 2)));
+    on[ch] = lr >= 0 && lc >= 0;
+    v[ch] = E[(int64_t)e * n_tr * n_tr + (on[ch] ? lr + (int64_t)lc * n_tr : 0)];
   }
+  double2 acc = mk(0.0, 0.0);
+#pragma unroll
+  for (int ch = 0; ch < 8; ++ch)
+    if (on[ch]) acc = cadd(acc, v[ch]);
   T[(int64_t)blockIdx.z * nT * nT + r + (int64_t)c * nT] = acc;
 }
 
@@ -68,12 +75,20 @@ __global__ __launch_bounds__(256) void k_patch_gather(const double2 *__restrict_
   for (int64_t k = (int64_t)blockIdx.y * 2048 + threadIdx.x; k < kend; k += 256) {
     const int i = (int)(k % n), j = (int)(k / n);
     if (j > i) continue;   // the Cholesky that follows reads the lower triangle only
-    double2 acc = mk(0.0, 0.0);
+    // all eight loads are issued before any is used (an absent cell or slot
+    // reads entry (0, 0) of block 0, in range, and contributes zero)
+    double2 v[8];
+    bool on[8];
+#pragma unroll
     for (int c = 0; c < 8; ++c) {
-      if (blk[c] < 0) continue;
       const int si = sl[i * 8 + c], sj = sl[j * 8 + c];
-      if (si >= 0 && sj >= 0) acc = cadd(acc, Mfull[blk[c] * nb2 + si + (int64_t)sj * nBf]);
+      on[c] = blk[c] >= 0 && si >= 0 && sj >= 0;
+      v[c] = Mfull[on[c] ? blk[c] * nb2 + si + (int64_t)sj * nBf : 0];
     }
+    double2 acc = mk(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (on[c]) acc = cadd(acc, v[c]);
     Sv[k] = acc;
   }
 }
