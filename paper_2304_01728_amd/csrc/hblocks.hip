@@ -82,15 +82,21 @@ template <typename C> __device__ __forceinline__ void load_tile(const C *__restr
   for (int k = 0; k < 16; ++k) t[k] = ld_nt(tp + k * 64);
 }
 
-// Diagonal tile: lanes of stored sub-blocks (on) read their slot, the others
-// (below the diagonal) hold zeros.
+// A tile by its lane's first entry and the stride between its 16 entries: 64
+// for a full tile, 36 for a diagonal one, whose lanes below the diagonal
+// read slot 0 (in range) and are zeroed by mask_lower once the data is
+// needed.  One code path for both kinds: behind a branch, the compiler made
+// the loads of either kind wait for those of the other.
 template <typename C>
-__device__ __forceinline__ void load_diag(const C *__restrict__ tp, bool on, C t[16]) {
+__device__ __forceinline__ void load_strided(const C *__restrict__ tp, int st, C t[16]) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) t[k] = ld_nt(tp + k * st);
+}
+template <typename C> __device__ __forceinline__ void mask_lower(bool keep, C t[16]) {
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    t[k].x = 0;
-    t[k].y = 0;
-    if (on) t[k] = ld_nt(tp + k * kDiagSlots);
+    t[k].x = keep ? t[k].x : 0;
+    t[k].y = keep ? t[k].y : 0;
   }
 }
 
@@ -157,9 +163,12 @@ __global__ __launch_bounds__(256) void k_gather_x(int64_t nloc, const int32_t *_
 
 // One wave per (block, tile column J, pair of tile rows I0, I0 + 1 <= J).  The
 // unit's descriptor (two int4, see HermSet::build) holds every address the
-// wave needs, so the tile loads follow a single descriptor load.  The x
-// entries of the two tile rows are staged in LDS (wave-private), which keeps
-// registers for the tiles and the vector memory queue for tile data.
+// wave needs and is read with scalar loads (the wave index is made uniform),
+// so the tile loads follow it at once and the x loads come after them (with
+// x first, the compiler waited for x, and a vector-loaded descriptor, before
+// issuing the tiles).  The x entries of the two tile rows are staged in LDS
+// (wave-private), which keeps registers for the tiles and the vector memory
+// queue for tile data.
 template <typename T>
 __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ tiles,
                                                const int4 *__restrict__ units, int64_t nunits,
@@ -168,7 +177,7 @@ __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ til
   static_assert(kSeg == 2, "k_units handles segments of two tile rows");
   using C = cplx_t<T>;
   __shared__ C xs[4][kSeg * 32];
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t wv = (int64_t)blockIdx.x * 4 + wave;
   if (wv >= nunits) return;
   const int lane = threadIdx.x & 63, ra = lane >> 3, cb = lane & 7;
@@ -179,30 +188,29 @@ __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ til
   const bool upper = ra <= cb, strict = ra < cb;
   const C *tp = tiles + ent;
   C t0[16], t1[16], xJ[4], cacc[4];
-  // x first: loads complete in order, so the LDS staging below waits for x
-  // only, not for the tiles
-  C v;
-  v.x = 0;
-  v.y = 0;
-  if (lane < 32 * (1 + two)) v = xloc[d0.z + lane];
+  // tiles first, then x (lanes past the unit's rows read its last row); all
+  // of them arrive before any arithmetic
+  const int ds = upper ? diag_slot(ra, cb) : 0;
+  load_strided(tp + (off0 ? lane : ds), off0 ? 64 : kDiagSlots, t0);
+  if (two) load_strided(tp + kTileFull + (off1 ? lane : ds), off1 ? 64 : kDiagSlots, t1);
+  const int nx = 32 * (1 + two);
+  const C v = xloc[d0.z + min(lane, nx - 1)];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     xJ[j] = xloc[d0.w + 4 * cb + j];
     cacc[j].x = 0;
     cacc[j].y = 0;
   }
-  const int ds = upper ? diag_slot(ra, cb) : 0;
-  if (off0) load_tile(tp + lane, t0);
-  else load_diag(tp + ds, upper, t0);
-  if (two) {
-    if (off1) load_tile(tp + kTileFull + lane, t1);
-    else load_diag(tp + kTileFull + ds, upper, t1);
-  }
   C *xw = xs[wave];
-  xw[lane] = v;
+  C w;
+  w.x = lane < nx ? v.x : 0;
+  w.y = lane < nx ? v.y : 0;
+  xw[lane] = w;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (!off0) mask_lower(upper, t0);
+  if (two && !off1) mask_lower(upper, t1);
   do_tile(t0, xJ, xw, off0 || strict, ra, cb, cacc, part + d1.x);
   if (two) do_tile(t1, xJ, xw + 32, off1 || strict, ra, cb, cacc, part + d1.x + d1.y);
 #pragma unroll
