@@ -223,15 +223,12 @@ __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ til
 }
 
 // Half a wave per (block, tile row I): y_loc rows of I = column sums of the
-// segments of tile column I + row sums of tiles (I, J >= I).  The slots are
-// independent loads: eight are in flight per lane (a row of a 24-tile block
-// sums 25 slots), summed in a fixed order.
+// segments of tile column I + row sums of tiles (I, J >= I).  The row's
+// descriptor (rowd, see HermSet::build) gives both partial bases and counts
+// with one load.  The slots are independent loads: eight are in flight per
+// lane (a row of a 24-tile block sums 25 slots), summed in a fixed order.
 template <typename T>
-__global__ __launch_bounds__(256) void k_rows(const int2 *__restrict__ rows, int64_t nrows,
-                                              const int32_t *__restrict__ bn,
-                                              const int64_t *__restrict__ cp_off,
-                                              const int64_t *__restrict__ rp_off,
-                                              const int64_t *__restrict__ loc_off,
+__global__ __launch_bounds__(256) void k_rows(const int4 *__restrict__ rowd, int64_t nrows,
                                               const cplx_t<T> *__restrict__ part,
                                               cplx_t<T> *__restrict__ yl) {
   using C = cplx_t<T>;
@@ -239,11 +236,10 @@ __global__ __launch_bounds__(256) void k_rows(const int2 *__restrict__ rows, int
   const int64_t hw = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 5;
   if (hw >= nrows) return;
   const int r = threadIdx.x & 31;
-  const int2 bi = rows[hw];
-  const int nt = (bn[bi.x] + 31) >> 5, I = bi.y;
-  const C *cp = part + cp_off[bi.x] + colbase(I) + r;
-  const C *rp = part + rp_off[bi.x] + row_slot(nt, I, I) + r;
-  const int nseg = (I + kSeg) / kSeg, tot = nseg + nt - I;
+  const int4 d = rowd[hw];
+  const C *cp = part + d.x + r;
+  const C *rp = part + d.y + r;
+  const int nseg = d.z & 0xffff, tot = nseg + (d.z >> 16);
   C acc[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -266,7 +262,7 @@ __global__ __launch_bounds__(256) void k_rows(const int2 *__restrict__ rows, int
   for (int w = U / 2; w >= 1; w /= 2)
 #pragma unroll
     for (int u = 0; u < w; ++u) acc[u] = cadd(acc[u], acc[u + w]);
-  yl[loc_off[bi.x] + 32 * I + r] = acc[0];
+  yl[d.w + r] = acc[0];
 }
 
 template <typename T, int MODE>
@@ -385,6 +381,14 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
     ud[2 * k + 1] = make_int4((int)r0, (int)rd, (int)cs, flags);
   }
   nrows = (int64_t)rw.size();
+  std::vector<int4> rd(rw.size());
+  for (size_t k = 0; k < rw.size(); ++k) {
+    const int b = rw[k].x, I = rw[k].y, nt = (sizes[b] + 31) / 32;
+    const int nseg = (I + kSeg) / kSeg, nrw = nt - I;
+    if (nseg > 0xffff || nrw > 0x7fff) throw DpgError(-1, "HermSet: block too large for row descriptors");
+    rd[k] = make_int4((int)(cpo[b] + colbase(I)), (int)(rpo[b] + row_slot(nt, I, I)),
+                      nseg | (nrw << 16), (int)(loff[b] + 32 * I));
+  }
   tile_off_h = toff;
   ent_off_h = eoff;
   // reduction lists: for every vector entry, the local rows holding it
@@ -406,6 +410,7 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
   gidx.upload(gi, bud, s);
   units.upload(ud, bud, s);
   rows.upload(rw, bud, s);
+  rowd.upload(rd, bud, s);
   tdesc.upload(td, bud, s);
   red_ptr.upload(cnt, bud, s);
   red_ent.upload(ent, bud, s);
@@ -466,8 +471,8 @@ void herm_apply(HermSet &H, const cplx_t<T> *x, cplx_t<T> *y, const cplx_t<T> *r
     LAUNCH_OK();
   }
   ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
-  hipLaunchKernelGGL((k_rows<T>), dim3(cdiv(H.nrows, 8)), dim3(256), 0, s, H.rows.p, H.nrows,
-                     H.bn.p, H.cp_off.p, H.rp_off.p, H.loc_off.p, part, yl);
+  hipLaunchKernelGGL((k_rows<T>), dim3(cdiv(H.nrows, 8)), dim3(256), 0, s, H.rowd.p, H.nrows,
+                     part, yl);
   LAUNCH_OK();
   const dim3 g(cdiv(H.nvec, 256));
   switch (mode) {

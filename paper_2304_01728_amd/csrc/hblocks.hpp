@@ -56,6 +56,8 @@ struct HermSet {
   DevBuf<int32_t> gidx;      // [nloc] vector index of each padded local row, -1 = padding
   DevBuf<int4> units;        // two int4 descriptors per (block, J, tile-row pair), longest first
   DevBuf<int2> rows;         // (block, I)
+  DevBuf<int4> rowd;         // per (block, I): column-partial base, row-partial base,
+                             // segment count | (row-partial count << 16), local offset
   DevBuf<int4> tdesc;        // (block, I, J, 0) per stored tile (packing)
   DevBuf<int32_t> red_ptr;   // CSR over vector entries
   DevBuf<int32_t> red_ent;   // offsets into the local vectors

@@ -13,31 +13,57 @@ constexpr int kMaxB = 2048, kMaxI = 1024;
 // covers 256 rows of one column, so the column's child indices are uniform.
 // Every entry is written once and the grid spreads over (rows, columns,
 // blocks), so a level with few blocks still fills the GPU.
+// One workgroup per (block, kAsmCols columns); the threads take the rows.
+// Whether child ch holds column c is the same for the whole column, so the
+// children without it are skipped by a uniform branch and each entry loads
+// only from the children that hold its column (about 1.5 on average); the
+// child slots of the thread's rows are loaded once for all its columns.
+// The children are summed in order.
+constexpr int kAsmCols = 32, kAsmRows = 8;   // rows per thread: nT <= 2048
 __global__ __launch_bounds__(256) void k_macro_assemble(const double2 *__restrict__ E, int n_tr,
                                                         const int32_t *__restrict__ child_inv,
                                                         int N, int b0, int nT,
                                                         double2 *__restrict__ T) {
-  const int r = blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
-  if (r >= nT) return;
-  const int Nc = N / 2, b = b0 + blockIdx.z;
+  const int c0 = blockIdx.x * kAsmCols, b = b0 + blockIdx.y;
+  const int Nc = N / 2;
   const int ci = b % Nc, cj = (b / Nc) % Nc, ck = b / (Nc * Nc);
-  // all eight loads are issued before any is used (a child without the
-  // entry reads its entry (0, 0), in range, and contributes zero); the sum
-  // runs over the children in order
-  double2 v[8];
-  bool on[8];
+  const int64_t n2 = (int64_t)n_tr * n_tr;
+  const double2 *Ech[8];
 #pragma unroll
   for (int ch = 0; ch < 8; ++ch) {
-    const int lr = child_inv[ch * nT + r], lc = child_inv[ch * nT + c];
     const int e = (2 * ci + (ch & 1)) + N * ((2 * cj + ((ch >> 1) & 1)) + N * (2 * ck + (ch >> 2)));
-    on[ch] = lr >= 0 && lc >= 0;
-    v[ch] = E[(int64_t)e * n_tr * n_tr + (on[ch] ? lr + (int64_t)lc * n_tr : 0)];
+    Ech[ch] = E + (int64_t)e * n2;
   }
-  double2 acc = mk(0.0, 0.0);
+  int lr[kAsmRows][8];
 #pragma unroll
-  for (int ch = 0; ch < 8; ++ch)
-    if (on[ch]) acc = cadd(acc, v[ch]);
-  T[(int64_t)blockIdx.z * nT * nT + r + (int64_t)c * nT] = acc;
+  for (int q = 0; q < kAsmRows; ++q) {
+    const int r = threadIdx.x + 256 * q;
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) lr[q][ch] = r < nT ? child_inv[ch * nT + r] : -1;
+  }
+  double2 *Tb = T + (int64_t)blockIdx.y * nT * nT;
+  const int cend = min(c0 + kAsmCols, nT);
+  for (int c = c0; c < cend; ++c) {
+    int lc[8];
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) lc[ch] = child_inv[ch * nT + c];
+#pragma unroll
+    for (int q = 0; q < kAsmRows; ++q) {
+      const int r = threadIdx.x + 256 * q;
+      if (256 * q >= nT) break;
+      double2 v[8];
+#pragma unroll
+      for (int ch = 0; ch < 8; ++ch) {
+        v[ch] = mk(0.0, 0.0);
+        if (lc[ch] >= 0) v[ch] = Ech[ch][max(lr[q][ch], 0) + (int64_t)lc[ch] * n_tr];
+      }
+      double2 acc = mk(0.0, 0.0);
+#pragma unroll
+      for (int ch = 0; ch < 8; ++ch)
+        if (lc[ch] >= 0 && lr[q][ch] >= 0) acc = cadd(acc, v[ch]);
+      if (r < nT) Tb[r + (int64_t)c * nT] = acc;
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_copy_sub(const double2 *__restrict__ src,
@@ -51,45 +77,54 @@ __global__ __launch_bounds__(256) void k_copy_sub(const double2 *__restrict__ sr
       src[blockIdx.y * src_stride + (r0 + i) + (int64_t)(c0 + j) * lds];
 }
 
+// One workgroup per (patch, kGatCols columns j); the threads take the rows
+// i >= j (the Cholesky that follows reads the lower triangle only).  Whether
+// cell c holds column j is the same for the whole column, so the cells
+// without it are skipped by a uniform branch and each entry loads only from
+// the cells that hold its column.  Cells are summed in order.
+constexpr int kGatCols = 8;
 __global__ __launch_bounds__(256) void k_patch_gather(const double2 *__restrict__ Mfull, int nBf,
                                                       int Nc, const int64_t *__restrict__ pptr,
                                                       const int32_t *__restrict__ pslot, int v0,
                                                       const int64_t *__restrict__ dst_off,
                                                       double2 *__restrict__ S) {
-  __shared__ int blk[8];
   const int v = v0 + blockIdx.x;
+  const int64_t p0 = pptr[v];
+  const int n = (int)(pptr[v + 1] - p0);
+  const int jb = blockIdx.y * kGatCols;
+  if (jb >= n) return;
   const int vx = v % (Nc + 1), vy = (v / (Nc + 1)) % (Nc + 1), vz = v / ((Nc + 1) * (Nc + 1));
-  if (threadIdx.x < 8) {
-    const int c = threadIdx.x;
+  int blk[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
     const int ci = vx - 1 + (c & 1), cj = vy - 1 + ((c >> 1) & 1), ck = vz - 1 + (c >> 2);
     blk[c] = (ci >= 0 && cj >= 0 && ck >= 0 && ci < Nc && cj < Nc && ck < Nc)
                  ? ci + Nc * (cj + Nc * ck) : -1;
   }
-  __syncthreads();
-  const int64_t p0 = pptr[v];
-  const int n = (int)(pptr[v + 1] - p0);
   const int32_t *sl = pslot + p0 * 8;
   double2 *Sv = S + dst_off[blockIdx.x];
   const int64_t nb2 = (int64_t)nBf * nBf;
-  const int64_t kend = min((int64_t)n * n, (int64_t)(blockIdx.y + 1) * 2048);
-  for (int64_t k = (int64_t)blockIdx.y * 2048 + threadIdx.x; k < kend; k += 256) {
-    const int i = (int)(k % n), j = (int)(k / n);
-    if (j > i) continue;   // the Cholesky that follows reads the lower triangle only
-    // all eight loads are issued before any is used (an absent cell or slot
-    // reads entry (0, 0) of block 0, in range, and contributes zero)
-    double2 v[8];
-    bool on[8];
+  const int jend = min(jb + kGatCols, n);
+  for (int j = jb; j < jend; ++j) {
+    int sj[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int si = sl[i * 8 + c], sj = sl[j * 8 + c];
-      on[c] = blk[c] >= 0 && si >= 0 && sj >= 0;
-      v[c] = Mfull[on[c] ? blk[c] * nb2 + si + (int64_t)sj * nBf : 0];
+    for (int c = 0; c < 8; ++c) sj[c] = blk[c] >= 0 ? sl[j * 8 + c] : -1;
+    for (int i = j + threadIdx.x; i < n; i += 256) {
+      const int4 s0 = *reinterpret_cast<const int4 *>(sl + (int64_t)i * 8);
+      const int4 s1 = *reinterpret_cast<const int4 *>(sl + (int64_t)i * 8 + 4);
+      const int si[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+      double2 w[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        w[c] = mk(0.0, 0.0);
+        if (sj[c] >= 0) w[c] = Mfull[blk[c] * nb2 + max(si[c], 0) + (int64_t)sj[c] * nBf];
+      }
+      double2 acc = mk(0.0, 0.0);
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (sj[c] >= 0 && si[c] >= 0) acc = cadd(acc, w[c]);
+      Sv[i + (int64_t)j * n] = acc;
     }
-    double2 acc = mk(0.0, 0.0);
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-      if (on[c]) acc = cadd(acc, v[c]);
-    Sv[k] = acc;
   }
 }
 
@@ -399,8 +434,8 @@ __global__ __launch_bounds__(256) void k_update_p(int64_t n, double2 *__restrict
 void launch_macro_assemble(const double2 *E, int n_tr, const int32_t *child_inv, int N, int b0,
                            int count, int nT, double2 *T, hipStream_t s) {
   if (count <= 0) return;
-  if (count > 65535 || nT > 65535) throw DpgError(-1, "macro assembly grid too large");
-  hipLaunchKernelGGL(k_macro_assemble, dim3(cdiv(nT, 256), nT, count), dim3(256), 0, s, E, n_tr,
+  if (count > 65535 || nT > 256 * kAsmRows) throw DpgError(-1, "macro assembly grid too large");
+  hipLaunchKernelGGL(k_macro_assemble, dim3(cdiv(nT, kAsmCols), count), dim3(256), 0, s, E, n_tr,
                      child_inv, N, b0, nT, T);
   LAUNCH_OK();
 }
@@ -418,8 +453,8 @@ void launch_patch_gather(const double2 *Mfull, int nBf, int Nc, const int64_t *p
                          const int32_t *patch_slot, int v0, int count, int nmax,
                          const int64_t *dst_off, double2 *S, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_patch_gather, dim3(count, cdiv((int64_t)nmax * nmax, 2048)), dim3(256), 0, s,
-                     Mfull, nBf, Nc, patch_ptr, patch_slot, v0, dst_off, S);
+  hipLaunchKernelGGL(k_patch_gather, dim3(count, cdiv(nmax, kGatCols)), dim3(256), 0, s, Mfull,
+                     nBf, Nc, patch_ptr, patch_slot, v0, dst_off, S);
   LAUNCH_OK();
 }
 
