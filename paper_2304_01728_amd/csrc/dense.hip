@@ -43,7 +43,8 @@ template <int OP> __device__ inline double2 ld_op(const double2 *X, int ldx, int
 // are launched as exactly these tiles: workgroups that exit at once still
 // cost dispatch time.
 __device__ __forceinline__ void tri_index(int t, int &lo, int &hi) {
-  int h = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  // single-precision estimate (t < 2^21 here), corrected by the two loops
+  int h = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
   while ((h + 1) * (h + 2) / 2 <= t) ++h;
   while (h * (h + 1) / 2 > t) --h;
   hi = h;
@@ -55,14 +56,16 @@ __device__ __forceinline__ void tri_index(int t, int &lo, int &hi) {
 // tiles of item 8 g + x run on XCD x, which keeps the operand panels an item's
 // tiles share in one L2 while items stay interleaved over the XCDs.  Items of
 // a last incomplete group of 8 keep the plain order.
+// 32-bit unsigned arithmetic: the tiled launches here have gridDim.x *
+// gridDim.y < 2^32 (at most a few thousand tiles times 65535 items).
 __device__ __forceinline__ void xcd_remap(int &bx, int &by) {
-  const int gx = gridDim.x;
-  const int64_t L = blockIdx.x + (int64_t)blockIdx.y * gx;
-  const int64_t grp = 8LL * gx, full = (int64_t)(gridDim.y / 8) * grp;
+  const uint32_t gx = gridDim.x;
+  const uint32_t L = blockIdx.x + blockIdx.y * gx;
+  const uint32_t grp = 8u * gx, full = (gridDim.y / 8u) * grp;
   if (L < full) {
-    const int64_t g = L / grp, w = L % grp;
-    bx = (int)(w / 8);
-    by = (int)(8 * g + w % 8);
+    const uint32_t g = L / grp, w = L - g * grp;
+    bx = (int)(w / 8u);
+    by = (int)(8u * g + (w & 7u));
   } else {
     bx = (int)(L % gx);
     by = (int)(L / gx);
