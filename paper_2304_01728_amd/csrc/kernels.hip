@@ -19,7 +19,9 @@ constexpr int kMaxB = 2048, kMaxI = 1024;
 // only from the children that hold its column (about 1.5 on average); the
 // child slots of the thread's rows are loaded once for all its columns.
 // The children are summed in order.
-constexpr int kAsmCols = 32, kAsmRows = 8;   // rows per thread: nT <= 2048
+// ROWS rows per thread: nT <= 256 ROWS (instances for 4, 8 and 12).
+constexpr int kAsmCols = 32;
+template <int ROWS>
 __global__ __launch_bounds__(256) void k_macro_assemble(const double2 *__restrict__ E, int n_tr,
                                                         const int32_t *__restrict__ child_inv,
                                                         int N, int b0, int nT,
@@ -34,9 +36,9 @@ __global__ __launch_bounds__(256) void k_macro_assemble(const double2 *__restric
     const int e = (2 * ci + (ch & 1)) + N * ((2 * cj + ((ch >> 1) & 1)) + N * (2 * ck + (ch >> 2)));
     Ech[ch] = E + (int64_t)e * n2;
   }
-  int lr[kAsmRows][8];
+  int lr[ROWS][8];
 #pragma unroll
-  for (int q = 0; q < kAsmRows; ++q) {
+  for (int q = 0; q < ROWS; ++q) {
     const int r = threadIdx.x + 256 * q;
 #pragma unroll
     for (int ch = 0; ch < 8; ++ch) lr[q][ch] = r < nT ? child_inv[ch * nT + r] : -1;
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(256) void k_macro_assemble(const double2 *__restric
 #pragma unroll
     for (int ch = 0; ch < 8; ++ch) lc[ch] = child_inv[ch * nT + c];
 #pragma unroll
-    for (int q = 0; q < kAsmRows; ++q) {
+    for (int q = 0; q < ROWS; ++q) {
       const int r = threadIdx.x + 256 * q;
       if (256 * q >= nT) break;
       double2 v[8];
@@ -434,9 +436,14 @@ __global__ __launch_bounds__(256) void k_update_p(int64_t n, double2 *__restrict
 void launch_macro_assemble(const double2 *E, int n_tr, const int32_t *child_inv, int N, int b0,
                            int count, int nT, double2 *T, hipStream_t s) {
   if (count <= 0) return;
-  if (count > 65535 || nT > 256 * kAsmRows) throw DpgError(-1, "macro assembly grid too large");
-  hipLaunchKernelGGL(k_macro_assemble, dim3(cdiv(nT, kAsmCols), count), dim3(256), 0, s, E, n_tr,
-                     child_inv, N, b0, nT, T);
+  if (count > 65535 || nT > 256 * 12) throw DpgError(-1, "macro assembly grid too large");
+  const dim3 g(cdiv(nT, kAsmCols), count);
+  if (nT <= 256 * 4)
+    hipLaunchKernelGGL(k_macro_assemble<4>, g, dim3(256), 0, s, E, n_tr, child_inv, N, b0, nT, T);
+  else if (nT <= 256 * 8)
+    hipLaunchKernelGGL(k_macro_assemble<8>, g, dim3(256), 0, s, E, n_tr, child_inv, N, b0, nT, T);
+  else
+    hipLaunchKernelGGL(k_macro_assemble<12>, g, dim3(256), 0, s, E, n_tr, child_inv, N, b0, nT, T);
   LAUNCH_OK();
 }
 
