@@ -97,12 +97,16 @@ void plan_elements(dpg_ctx *c) {
   if (P.mp == mp) return;
   const int nel = c->lv[c->L].nel;
   const int64_t per = 16LL * ((int64_t)nt * nt + (int64_t)nt * mp + (int64_t)mp * mp);
-  // an even number of about equal chunks, so that both streams get the same work
+  // a multiple of NS about equal chunks, so that every stream gets the same
+  // work; element stage at 16^3 / p = 3 over two streams 38.4 ms, three 37.8,
+  // four 37.2
+  const int NS = 4;
   const int64_t cmax = std::max<int64_t>(1, std::min<int64_t>(2500000000LL / per, 65535));
-  const int64_t pairs = (nel + 2 * cmax - 1) / (2 * cmax);
-  const int C = (int)std::max<int64_t>(1, (nel + 2 * pairs - 1) / (2 * pairs));
+  const int64_t groups = (nel + NS * cmax - 1) / (NS * cmax);
+  const int C = (int)std::max<int64_t>(1, (nel + NS * groups - 1) / (NS * groups));
+  P.ns = NS;
   Budget *bd = &c->bud;
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < NS; ++k) {
     P.G[k].ensure((int64_t)C * nt * nt, bd);
     P.BL[k].ensure((int64_t)C * nt * mp, bd);
     P.K[k].ensure((int64_t)C * mp * mp, bd);
@@ -135,7 +139,7 @@ void plan_elements(dpg_ctx *c) {
 
 // Per element (Sec. 1.2): Gram matrix G and [B | l]; G = L L^H;
 // W = L^-1 [B | l]; K = W^H W; static condensation of the field block of K.
-// Chunks of elements alternate between the context's two streams.
+// Chunks of elements are dealt round-robin to four streams.
 void element_stage(dpg_ctx *c, bool write_matrices) {
   plan_elements(c);
   ElemPlan &P = c->ep;
@@ -143,10 +147,13 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
   const int nt = c->n_test, nf = c->n_field, ntr = c->n_tr, m = c->m, nr = c->nrhs;
   const int mp = m + nr, C = P.C, nel = f.nel;
   ElemGeom g{c->N, c->side / c->N, c->omega, 1.0, {c->org[0], c->org[1], c->org[2]}};
-  stream_wait(c->stream, c->aux, c->ev_fork);
+  const int NS = P.ns;
+  const hipStream_t xs[4] = {c->stream, c->aux, c->paux[0], c->paux[1]};
+  const hipEvent_t xj[4] = {nullptr, c->ev_join, c->ev_pjoin[0], c->ev_pjoin[1]};
+  for (int k = 1; k < NS; ++k) stream_wait(c->stream, xs[k], c->ev_fork);
   for (int e0 = 0, k = 0; e0 < nel; e0 += C, ++k) {
-    const int cnt = std::min(C, nel - e0), u = k & 1;
-    const hipStream_t s = u ? c->aux : c->stream;
+    const int cnt = std::min(C, nel - e0), u = k % NS;
+    const hipStream_t s = xs[u];
     double2 *G = P.G[u].p, *BL = P.BL[u].p, *K = P.K[u].p, *wk = P.wk[u].p;
     {
       ProfScope ps(&c->prof, DPG_K_GRAM, 0, s);
@@ -201,7 +208,7 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
                       s);
     }
   }
-  stream_wait(c->aux, c->stream, c->ev_join);
+  for (int k = 1; k < NS; ++k) stream_wait(xs[k], c->stream, xj[k]);
   // assembled loads
   for (int r = 0; r < nr; ++r)
     launch_assemble_vec(f.num.n, c->asm_ptr.p, c->asm_ent.p, c->s_elem.p + (int64_t)r * nel * ntr,
@@ -372,11 +379,12 @@ void build_macro_level(dpg_ctx *c, int l) {
   f.Mset.pack(f.Mfull.p, P.soff.p, P.sld.p, P.moff.p, P.map.p, s);
 }
 
-// Share of each level's patch work on the second stream.  Equal halves
-// measured best (0.4: +1.2 ms, 0.6: +3.8 ms, 0.7: +5.4 ms of hierarchy time
-// at 16^3 / p = 3): the second stream's large patch kernels slow down the
-// small kernels of the coarse-level chain on the main stream.
-constexpr double kAuxPatchShare = 0.5;
+// Each level's patch work is cut into this many parts of equal factorisation
+// work, each on a stream of its own (three extra streams and the main one), so
+// that the latency-bound diagonal-block steps of one part overlap the
+// matrix-core updates of the others.  Hierarchy time at 16^3 / p = 3: two
+// parts 50.8 ms, three 50.4, four 49.5.
+constexpr int kPatchParts = 4;
 
 void plan_patches(dpg_ctx *c, int l) {
   LevelData &f = c->lv[l];
@@ -393,19 +401,30 @@ void plan_patches(dpg_ctx *c, int l) {
     nv_max = std::max(nv_max, (int)nv[v]);
     maxent = std::max<int64_t>(maxent, (int64_t)nv[v] * nv[v]);
   }
-  // two parts by factorisation work (sum n^3), one per stream, each cut into
-  // batches that fit its workspaces (S and X: 3 GB each)
+  // parts of equal factorisation work (sum n^3), one per stream, each cut
+  // into batches that fit its workspaces (S and X: 3 GB each)
   const int64_t ws = std::max<int64_t>(3000000000LL / 16, maxent);
+  const int NP = kPatchParts;
   double tot = 0.0;
   for (int v = 0; v < np; ++v) tot += (double)nv[v] * nv[v] * nv[v];
-  int vsplit = 0;
-  for (double acc = 0.0; vsplit < np && acc < kAuxPatchShare * tot; ++vsplit)
-    acc += (double)nv[vsplit] * nv[vsplit] * nv[vsplit];
+  std::vector<int> vcut(NP + 1, np);
+  vcut[0] = 0;
+  {
+    int v = 0;
+    double acc = 0.0;
+    for (int k = 1; k < NP; ++k) {
+      while (v < np && acc < tot * k / NP) {
+        acc += (double)nv[v] * nv[v] * nv[v];
+        ++v;
+      }
+      vcut[k] = v;
+    }
+  }
   std::vector<int64_t> soff_all(np, 0);
-  int maxcnt[2] = {0, 0};
-  for (int half = 0; half < 2; ++half) {
-    int v0 = half ? vsplit : 0;
-    const int vend = half ? np : vsplit;
+  int maxcnt[4] = {0, 0, 0, 0};
+  for (int half = 0; half < NP; ++half) {
+    int v0 = vcut[half];
+    const int vend = vcut[half + 1];
     while (v0 < vend) {
       int cnt = 0;
       int64_t used = 0;
@@ -453,7 +472,7 @@ void plan_patches(dpg_ctx *c, int l) {
   P.soff_all.upload(soff_all, bd, s);
   P.ld_all.upload(nv, bd, s);
   P.info.ensure(np, bd);
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < NP; ++h) {
     if (!maxcnt[h]) continue;
     if (c->pS[h].n < ws) c->pS[h].alloc(ws, bd);
     if (c->pX[h].n < ws) c->pX[h].alloc(ws, bd);
@@ -535,11 +554,11 @@ void build_coarsest(dpg_ctx *c) {
 }
 
 // The whole hierarchy: macro levels one after the other on the main stream;
-// the patches of level l need only that level's macro blocks.  Half of them
-// (by work) run on the second stream as soon as the level's blocks exist,
-// overlapping the coarser levels; the other half on the main stream after the
-// coarsest level, so that the latency-bound steps of one half overlap the
-// matrix-core updates of the other.
+// the patches of level l need only that level's macro blocks.  Three quarters
+// of them (by work) run on the three extra streams as soon as the level's
+// blocks exist, overlapping the coarser levels; the last quarter on the main
+// stream after the coarsest level, so that the latency-bound steps of one part
+// overlap the matrix-core updates of the others.
 void build_hierarchy(dpg_ctx *c) {
   for (int l = c->L; l >= 1; --l) {
     plan_macro(c, l);
@@ -553,15 +572,20 @@ void build_hierarchy(dpg_ctx *c) {
       c->ev_level.push_back(e);
     }
   }
-  stream_wait(c->stream, c->aux, c->ev_fork);
+  const int NX = kPatchParts - 1;   // parts on the extra streams
+  hipStream_t xs[3] = {c->aux, c->paux[0], c->paux[1]};
+  hipEvent_t xj[3] = {c->ev_join, c->ev_pjoin[0], c->ev_pjoin[1]};
+  for (int k = 0; k < NX; ++k) stream_wait(c->stream, xs[k], c->ev_fork);
   for (int l = c->L; l >= 1; --l) {
     build_macro_level(c, l);
-    stream_wait(c->stream, c->aux, c->ev_level[l]);
-    build_patches(c, l, 0, c->aux);
+    for (int k = 0; k < NX; ++k) {
+      stream_wait(c->stream, xs[k], c->ev_level[l]);
+      build_patches(c, l, k, xs[k]);
+    }
   }
   build_coarsest(c);
-  for (int l = c->L; l >= 1; --l) build_patches(c, l, 1, c->stream);
-  stream_wait(c->aux, c->stream, c->ev_join);
+  for (int l = c->L; l >= 1; --l) build_patches(c, l, NX, c->stream);
+  for (int k = 0; k < NX; ++k) stream_wait(xs[k], c->stream, xj[k]);
   for (int l = c->L; l >= 1; --l) {
     check_infos(c->lv[l].mp.info.p, c->lv[l].nblk, c->stream, "interior block of coarse element");
     check_infos(c->lv[l].pp.info.p, (int64_t)c->lv[l].mc.patch_ptr.size() - 1, c->stream,
@@ -1034,6 +1058,10 @@ int dpg_setup(const dpg_mesh *mesh, int p, int dp, double omega, const dpg_mater
     HIP_OK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
     HIP_OK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    for (int k = 0; k + 2 < kPatchParts; ++k) {
+      HIP_OK(hipStreamCreateWithFlags(&c->paux[k], hipStreamNonBlocking));
+      HIP_OK(hipEventCreateWithFlags(&c->ev_pjoin[k], hipEventDisableTiming));
+    }
     c->bud.limit = c->opt.hbm_budget;
     c->N = mesh->n;
     c->p = p;
@@ -1243,6 +1271,8 @@ int dpg_release_setup(dpg_ctx *c) {
     if (c->stage < 3) throw DpgError(DPG_ESTATE, "dpg_build_hierarchy first");
     HIP_OK(hipStreamSynchronize(c->stream));
     HIP_OK(hipStreamSynchronize(c->aux));
+    for (hipStream_t x : c->paux)
+      if (x) HIP_OK(hipStreamSynchronize(x));
     for (LevelData &f : c->lv) {
       f.E.release();
       f.Mfull.release();
@@ -1252,6 +1282,8 @@ int dpg_release_setup(dpg_ctx *c) {
       c->mLinv[k].release();
       c->mX[k].release();
       c->mwk[k].release();
+    }
+    for (int k = 0; k < 4; ++k) {
       c->pS[k].release();
       c->pX[k].release();
       c->pwk[k].release();
@@ -1563,7 +1595,12 @@ void dpg_destroy(dpg_ctx *c) {
     (void)hipStreamSynchronize(c->aux);
     (void)hipStreamDestroy(c->aux);
   }
-  for (hipEvent_t e : {c->ev_fork, c->ev_join})
+  for (hipStream_t x : c->paux)
+    if (x) {
+      (void)hipStreamSynchronize(x);
+      (void)hipStreamDestroy(x);
+    }
+  for (hipEvent_t e : {c->ev_fork, c->ev_join, c->ev_pjoin[0], c->ev_pjoin[1]})
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->ev_level) (void)hipEventDestroy(e);
   if (c->own_stream) {

@@ -18,11 +18,11 @@ namespace dpg {
 // Prepared once per mesh (and per number of loads): item tables on the device
 // and fixed workspaces, so that the setup phases only queue kernels.
 
-// Element stage: chunks of C elements alternate between two streams, each
-// with its own G, [B l], K and diagonal-block-inverse buffers.
+// Element stage: chunks of C elements are dealt to ns streams, each with its
+// own G, [B l], K and diagonal-block-inverse buffers.
 struct ElemPlan {
-  int C = 0, mp = -1;
-  DevBuf<double2> G[2], BL[2], K[2], wk[2];
+  int C = 0, mp = -1, ns = 2;
+  DevBuf<double2> G[4], BL[4], K[4], wk[4];   // one set per stream
   DevBuf<PotrfItem> pG, pK;
   DevBuf<TrsmItem> tG, tK;
   DevBuf<GemmItem> gK, gS;
@@ -46,7 +46,8 @@ struct MacroPlan {
 // Patch factors and inverses of one level, in batches that fit the patch
 // workspaces.
 struct PatchBatch {
-  int half = 0;                      // 0: second stream, 1: main stream (own workspaces)
+  int half = 0;                      // part: 0 .. 2 on the extra streams, 3 on the main
+                                     // stream (each part with its own workspaces)
   int v0 = 0, cnt = 0, nmax = 0;
   int64_t t0 = 0, t1 = 0;
   double fp = 0, ft = 0, fg = 0;
@@ -115,6 +116,8 @@ struct dpg_ctx {
   hipStream_t stream = nullptr;
   hipStream_t own_stream = nullptr;  // created when the options give no stream
   hipStream_t aux = nullptr;         // second stream of the setup phases
+  hipStream_t paux[2] = {nullptr, nullptr};   // third and fourth setup streams
+  hipEvent_t ev_pjoin[2] = {nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<hipEvent_t> ev_level;  // per level: macro blocks ready for the patches
   dpg::Budget bud;
@@ -142,7 +145,7 @@ struct dpg_ctx {
   // setup-phase plans and workspaces
   dpg::ElemPlan ep;
   dpg::DevBuf<double2> mT[2], mLinv[2], mX[2], mwk[2];   // macro levels, one set per stream
-  dpg::DevBuf<double2> pS[2], pX[2], pwk[2];       // patches, one set per half
+  dpg::DevBuf<double2> pS[4], pX[4], pwk[4];       // patches, one set per part
   dpg::DevBuf<double2> zF, zLi, zTi, zwk;          // coarsest
   dpg::DevBuf<dpg::PotrfItem> zpi;
   dpg::DevBuf<dpg::TrsmItem> zti;
