@@ -383,15 +383,22 @@ __device__ __forceinline__ double recip(double d) {
 
 // Wave 0: sub-block (o, o) -> L_oo in place, L_oo^-1 into X.  Lane (i, g)
 // holds row i, columns 4g..4g+3 of the full Hermitian sub-block and of the
-// identity.  Step k eliminates column k below the pivot with multipliers
-// m_i = a_ik / a_kk (a_ik = conj(a_ki)); columns j > k of a and j <= k of the
-// identity take the update, so that a keeps a_ij at step j and the identity
-// becomes the inverse of the unit factor.  The only exchange per step is the
-// pivot row, through LDS; each lane keeps the pivots it needs.
+// identity.  Step k subtracts m_i times the pivot row from every row i > k,
+// m_i = a_ik / a_kk (a_ik = conj(a_ki)), in all columns of both: the
+// sub-block becomes U = D Lu^H (Lu unit lower, zeros below the diagonal) and
+// the identity Lu^-1 (row k of the identity part is zero right of column k,
+// so those columns take no change).  Updating every column keeps the step
+// free of per-column selects.  The only exchange per step is the pivot row,
+// through LDS.
+// a - m r as four fused multiply-adds
+__device__ __forceinline__ double2 cfms(double2 m, double2 r, double2 a) {
+  return mk(fma(-m.x, r.x, fma(m.y, r.y, a.x)), fma(-m.x, r.y, fma(-m.y, r.x, a.y)));
+}
+
 __device__ void factor_sub(DiagSmem &sm, int o) {
   const int lane = threadIdx.x, i = lane & 15, g = lane >> 4;
   double2 a[4], x[4];
-  double di = 1.0, dj[4] = {1.0, 1.0, 1.0, 1.0};
+  double di = 1.0;
   int fail = 0;
 #pragma unroll
   for (int jj = 0; jj < 4; ++jj) {
@@ -419,18 +426,14 @@ __device__ void factor_sub(DiagSmem &sm, int o) {
     }
     const bool ok = d > 0.0;
     if (!ok && fail == 0) fail = k + 1;
-    const double inv = ok ? recip(d) : 0.0;
+    const double r = recip(d);
+    const double inv = ok && i > k ? r : 0.0;
     if (i == k) di = d;
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj)
-      if (4 * g + jj == k) dj[jj] = d;
-    const double2 m = cscale(cconj(ri), i > k ? inv : 0.0);
+    const double2 m = cscale(cconj(ri), inv);
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
-      const int j = 4 * g + jj;
-      const double2 ma = j > k ? m : mk(0.0, 0.0), mx = j > k ? mk(0.0, 0.0) : m;
-      a[jj] = csub(a[jj], cmul(ma, ra[jj]));
-      x[jj] = csub(x[jj], cmul(mx, rx[jj]));
+      a[jj] = cfms(m, ra[jj], a[jj]);
+      x[jj] = cfms(m, rx[jj], x[jj]);
     }
     wave_sync();
   }
@@ -438,14 +441,14 @@ __device__ void factor_sub(DiagSmem &sm, int o) {
     if (lane == 0 && sm.fail == 0) sm.fail = o + fail;
     return;
   }
-  // L_ij = a_ij / sqrt(d_j) below the diagonal, L_ii = sqrt(d_i);
-  // (L^-1)_ij = x_ij / sqrt(d_i)
+  // with d_i = U_ii: L = Lu D^(1/2), so L_ji = conj(U_ij) / sqrt(d_i) below
+  // the diagonal, L_ii = sqrt(d_i), and (L^-1)_ij = (Lu^-1)_ij / sqrt(d_i)
   const double si = sqrt(di), rsi = 1.0 / si;
 #pragma unroll
   for (int jj = 0; jj < 4; ++jj) {
     const int j = 4 * g + jj;
-    if (i > j) sm.L[pk(o + i, o + j)] = cscale(a[jj], 1.0 / sqrt(dj[jj]));
-    else if (i == j) sm.L[pk(o + i, o + i)] = mk(si, 0.0);
+    if (j > i) sm.L[pk(o + j, o + i)] = cscale(cconj(a[jj]), rsi);
+    else if (j == i) sm.L[pk(o + i, o + i)] = mk(si, 0.0);
     if (i >= j) sm.X[pk(o + i, o + j)] = cscale(x[jj], rsi);
   }
 }
