@@ -493,93 +493,102 @@ __global__ __launch_bounds__(NTB, 2) void k_potrf_diag(double2 *base, const Potr
     if (tid < 64) factor_sub(sm, o);
     __syncthreads();
     if (sm.fail) break;
-    // (a) sub-blocks below: L_rs = A_rs L_ss^-H (X_ss lower: terms t <= j),
-    //     threads [0, 4 prow): one row and four columns each;
-    // (b) X_st = X_ss Y_st for t < s (X_ss lower: terms k <= i), threads
-    //     [4 prow, 192): one row and four columns of one block each
-    double2 pv[4];
+    // (a) sub-blocks below: L_rs = A_rs L_ss^-H (X_ss lower: terms t <= j);
+    // (b) X_st = X_ss Y_st for t < s (X_ss lower: terms k <= i).  One 16 x 16
+    // tile per wave on the FP64 matrix cores; a wave reads and then overwrites
+    // only its own tile (and reads X_ss), so the tiles need no barrier between.
+    {
+      const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+      const int nb = prow / DB;
+      for (int tt = wave; tt < nb + s; tt += NTB / 64) {
+        v4d cre = {0.0, 0.0, 0.0, 0.0}, cim = {0.0, 0.0, 0.0, 0.0};
+        if (tt < nb) {
+          const int ri = r0 + DB * tt;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) pv[c] = mk(0.0, 0.0);
-    const int npan = prow * 4;
-    const bool pon = tid < npan, xon = tid >= npan && tid < npan + 64 * s;
-    const int pi = r0 + tid % max(prow, 1), pj = 4 * (tid / max(prow, 1));
-    const int xu = tid - npan, xt = DB * (xu / 64), xi = xu % DB, xj = 4 * ((xu / DB) % 4);
-    if (pon) {
-#pragma unroll 4
-      for (int t = 0; t < DB; ++t) {
-        const double2 av = sm.L[pk(pi, o + t)];
+          for (int ks = 0; ks < DB; ks += 4) {
+            const int k = ks + lk;
+            const double2 av = sm.L[pk(ri + li, o + k)];
+            const double2 xv = sm.X[pk(o + li, o + min(k, li))];
+            const double2 bv = k <= li ? xv : mk(0.0, 0.0);
+            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, cim, 0, 0, 0);
+            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.y, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.x, bv.y, cim, 0, 0, 0);
+          }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int j = pj + c;
-          const double2 xv = sm.X[pk(o + j, o + min(t, j))];
-          pv[c] = cfmaconj(t <= j ? xv : mk(0.0, 0.0), av, pv[c]);
+          for (int v = 0; v < 4; ++v) sm.L[pk(ri + 4 * v + lk, o + li)] = mk(cre[v], cim[v]);
+        } else {
+          const int tc = DB * (tt - nb);
+#pragma unroll
+          for (int ks = 0; ks < DB; ks += 4) {
+            const int k = ks + lk;
+            const double2 xv = sm.X[pk(o + li, o + min(k, li))];
+            const double2 av = k <= li ? xv : mk(0.0, 0.0);
+            const double2 bv = sm.X[pk(o + k, tc + li)];
+            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, cim, 0, 0, 0);
+            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv.y, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, cim, 0, 0, 0);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) sm.X[pk(o + 4 * v + lk, tc + li)] = mk(cre[v], cim[v]);
         }
       }
-    } else if (xon) {
-#pragma unroll 4
-      for (int k = 0; k < DB; ++k) {
-        const double2 xr = sm.X[pk(o + xi, o + min(k, xi))];
-        const double2 xm = k <= xi ? xr : mk(0.0, 0.0);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) pv[c] = cfma(xm, sm.X[pk(o + k, xt + xj + c)], pv[c]);
-      }
-    }
-    __syncthreads();
-    if (pon) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) sm.L[pk(pi, o + pj + c)] = pv[c];
-    } else if (xon) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) sm.X[pk(o + xi, xt + xj + c)] = pv[c];
     }
     __syncthreads();
     if (prow == 0) break;
-    // (c) trailing lower triangle: A_ij -= sum_t L_it conj(L_jt), 2 x 2 entries
-    //     per item; (d) Y_rt -= L_rs X_st for r > s, t <= s, one row and four
-    //     columns per item (X_ss lower: terms k >= j).  Neither reads what the
-    //     other writes.
-    const int m2 = prow / 2, ntr = m2 * m2, nt1 = s + 1;
-    for (int b = tid; b < ntr + 64 * nt1 * (3 - s); b += NTB) {
-      if (b < ntr) {
-        const int hi = b % m2, lo = b / m2;
-        if (hi < lo) continue;
-        const int i0 = r0 + 2 * hi, j0 = r0 + 2 * lo;
-        double2 c00 = mk(0.0, 0.0), c01 = c00, c10 = c00, c11 = c00;
-#pragma unroll 4
-        for (int t = 0; t < DB; ++t) {
-          const int c = o + t;
-          const double2 li0 = sm.L[pk(i0, c)], li1 = sm.L[pk(i0 + 1, c)];
-          const double2 lj0 = sm.L[pk(j0, c)], lj1 = sm.L[pk(j0 + 1, c)];
-          c00 = cfmaconj(lj0, li0, c00);
-          c01 = cfmaconj(lj1, li0, c01);
-          c10 = cfmaconj(lj0, li1, c10);
-          c11 = cfmaconj(lj1, li1, c11);
-        }
-        sm.L[pk(i0, j0)] = csub(sm.L[pk(i0, j0)], c00);
-        sm.L[pk(i0 + 1, j0)] = csub(sm.L[pk(i0 + 1, j0)], c10);
-        sm.L[pk(i0 + 1, j0 + 1)] = csub(sm.L[pk(i0 + 1, j0 + 1)], c11);
-        if (hi != lo) sm.L[pk(i0, j0 + 1)] = csub(sm.L[pk(i0, j0 + 1)], c01);
-      } else {
-        const int u = b - ntr, blk = u / 64;
-        const int rr = DB * (s + 1 + blk / nt1), tt = DB * (blk % nt1);
-        const int i = u % DB, j0 = 4 * ((u / DB) % 4);
-        double2 acc[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = mk(0.0, 0.0);
-#pragma unroll 4
-        for (int k = 0; k < DB; ++k) {
-          const double2 lv = sm.L[pk(rr + i, o + k)];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const int j = tt + j0 + c;
-            const double2 xv = sm.X[pk(max(o + k, j), j)];
-            acc[c] = cfma(lv, o + k >= j ? xv : mk(0.0, 0.0), acc[c]);
+    // (c) trailing lower triangle: A_ij -= sum_t L_it conj(L_jt); (d) Y_rt -=
+    // L_rs X_st for r > s, t <= s (X_ss lower: terms k >= j).  Both as 16 x 16
+    // tiles on the FP64 matrix cores (k = 16 in four steps of 4, four real
+    // products per complex one), one wave per tile; neither reads what the
+    // other writes.
+    {
+      const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+      const int nb = prow / DB, ntc = nb * (nb + 1) / 2, ntd = nb * (s + 1);
+      for (int tt = wave; tt < ntc + ntd; tt += NTB / 64) {
+        v4d cre = {0.0, 0.0, 0.0, 0.0}, cim = {0.0, 0.0, 0.0, 0.0};
+        if (tt < ntc) {
+          int bi = 0, bj = tt;   // lower tile number tt, row by row
+          while (bj > bi) {
+            bj -= bi + 1;
+            ++bi;
           }
-        }
+          const int ri = r0 + DB * bi, rj = r0 + DB * bj;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int q = pk(rr + i, tt + j0 + c);
-          sm.X[q] = csub(sm.X[q], acc[c]);
+          for (int ks = 0; ks < DB; ks += 4) {
+            const int c = o + ks + lk;
+            const double2 av = sm.L[pk(ri + li, c)], bv = sm.L[pk(rj + li, c)];
+            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, cim, 0, 0, 0);
+            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.y, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.x, bv.y, cim, 0, 0, 0);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int R = ri + 4 * v + lk, Cc = rj + li;
+            if (bi != bj || R >= Cc) {
+              const int q = pk(R, Cc);
+              sm.L[q] = csub(sm.L[q], mk(cre[v], cim[v]));
+            }
+          }
+        } else {
+          const int u = tt - ntc, rr = r0 + DB * (u / (s + 1)), tc = DB * (u % (s + 1));
+#pragma unroll
+          for (int ks = 0; ks < DB; ks += 4) {
+            const int kr = o + ks + lk, cc = tc + li;
+            const double2 av = sm.L[pk(rr + li, kr)];
+            const double2 xv = sm.X[pk(max(kr, cc), cc)];
+            const double2 bv = kr >= cc ? xv : mk(0.0, 0.0);
+            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, cim, 0, 0, 0);
+            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv.y, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, cim, 0, 0, 0);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int q = pk(rr + 4 * v + lk, tc + li);
+            sm.X[q] = csub(sm.X[q], mk(cre[v], cim[v]));
+          }
         }
       }
     }
