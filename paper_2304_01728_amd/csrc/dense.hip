@@ -403,7 +403,8 @@ __device__ void factor_sub(DiagSmem &sm, int o) {
 #pragma unroll
   for (int jj = 0; jj < 4; ++jj) {
     const int j = 4 * g + jj;
-    a[jj] = i >= j ? sm.L[pk(o + i, o + j)] : cconj(sm.L[pk(o + j, o + i)]);
+    const double2 v = sm.L[pk(o + max(i, j), o + min(i, j))];
+    a[jj] = mk(v.x, i >= j ? v.y : -v.y);
     x[jj] = mk(i == j ? 1.0 : 0.0, 0.0);
   }
 #pragma unroll 1
@@ -468,13 +469,15 @@ __global__ __launch_bounds__(NTB, 2) void k_potrf_diag(double2 *base, const Potr
   const int tid = threadIdx.x;
   // all sixteen loads of a thread are issued before the LDS stores (entries
   // outside the kb x kb block read the nearest one inside and are replaced
-  // by the identity padding)
+  // by the identity padding; entries above the diagonal, which are not used,
+  // read the diagonal entry of their column, so that only the lines of the
+  // lower triangle are fetched)
   constexpr int kLd = NB * NB / NTB;
   double2 v[kLd];
 #pragma unroll
   for (int q = 0; q < kLd; ++q) {
     const int e = tid + NTB * q, i = e % NB, j = e / NB;
-    v[q] = A[min(i, kb - 1) + (int64_t)min(j, kb - 1) * lda];
+    v[q] = A[min(max(i, j), kb - 1) + (int64_t)min(j, kb - 1) * lda];
   }
 #pragma unroll
   for (int q = 0; q < kLd; ++q) {
