@@ -103,14 +103,18 @@ __global__ __launch_bounds__(256) void k_gram(const ElemTables *__restrict__ tb,
                                               const int4 *__restrict__ test, int nt, ElemGeom g,
                                               const double *__restrict__ kappa, int e0,
                                               double2 *__restrict__ G) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)nt * nt) return;
+  // one wave per column j, its lanes over the rows i >= j (Hermitian: the
+  // Cholesky that follows reads the lower triangle only)
+  const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (j >= nt) return;
   const int e = e0 + blockIdx.y;
-  const int i = (int)(idx % nt), j = (int)(idx / nt);
-  if (i < j) return;   // Hermitian: the Cholesky that follows reads the lower triangle only
-  const int4 ti = test[i], tj = test[j];
+  const int4 tj = test[j];
   const double hh = 0.5 * g.h, w = g.omega, kap = kappa ? kappa[e] : 1.0;
-  const int a[3] = {ti.y, ti.z, ti.w}, b[3] = {tj.y, tj.z, tj.w};
+  const int b[3] = {tj.y, tj.z, tj.w};
+  double2 *Gc = G + (int64_t)blockIdx.y * nt * nt + (int64_t)j * nt;
+  for (int i = j + (threadIdx.x & 63); i < nt; i += 64) {
+  const int4 ti = test[i];
+  const int a[3] = {ti.y, ti.z, ti.w};
   const bool dl[3] = {a[0] == b[0], a[1] == b[1], a[2] == b[2]};
   double re = 0.0, im = 0.0;
   if (ti.x == 0 && tj.x == 0) {
@@ -137,7 +141,8 @@ __global__ __launch_bounds__(256) void k_gram(const ElemTables *__restrict__ tb,
       if (dl[f]) re = hh * tb->DM[b[d] * kMX + a[d]] * tb->DM[a[ei] * kMX + b[ei]];
     }
   }
-  G[(int64_t)blockIdx.y * nt * nt + idx] = mk(re, im);
+  Gc[i] = mk(re, im);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_bmat(const ElemTables *__restrict__ tb,
@@ -146,15 +151,18 @@ __global__ __launch_bounds__(256) void k_bmat(const ElemTables *__restrict__ tb,
                                               ElemGeom g, const double *__restrict__ kappa,
                                               const double *__restrict__ Zel, int e0,
                                               double2 *__restrict__ BL, int64_t strideBL) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)nt * m) return;
+  // one wave per trial function j, its lanes over the test functions i
+  const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (j >= m) return;
   const int e = e0 + blockIdx.y;
-  const int i = (int)(idx % nt), j = (int)(idx / nt);
-  const int4 ti = test[i], tr = trial[j];
+  const int4 tr = trial[j];
   const double hh = 0.5 * g.h, w = g.omega, kap = kappa ? kappa[e] : 1.0;
   const double Z = Zel ? Zel[e] : 1.0;
   int cell[3];
   elem_cell(e, g.N, cell);
+  double2 *Bc = BL + (int64_t)blockIdx.y * strideBL + (int64_t)j * nt;
+  for (int i = threadIdx.x & 63; i < nt; i += 64) {
+  const int4 ti = test[i];
   const int a[3] = {ti.y, ti.z, ti.w};
   const int isq = ti.x == 0, ev = ti.x - 1;   // ev = component of v (if not q)
   double re = 0.0, im = 0.0;
@@ -201,7 +209,8 @@ __global__ __launch_bounds__(256) void k_bmat(const ElemTables *__restrict__ tb,
            tb->fM[a[f2] * kMX + tr.z];
     }
   }
-  BL[(int64_t)blockIdx.y * strideBL + i + (int64_t)j * nt] = mk(re, im);
+  Bc[i] = mk(re, im);
+  }
 }
 
 constexpr int LX = 8, LQ = 12;
@@ -317,7 +326,7 @@ __global__ __launch_bounds__(256) void k_load(const ElemTables *__restrict__ tb,
 
 void launch_gram(const ElemTables *tb, const int4 *test, int nt, ElemGeom g, const double *kappa,
                  int e0, int count, double2 *G, hipStream_t s) {
-  hipLaunchKernelGGL(k_gram, dim3(cdiv((int64_t)nt * nt, 256), count), dim3(256), 0, s, tb, test,
+  hipLaunchKernelGGL(k_gram, dim3(cdiv(nt, 4), count), dim3(256), 0, s, tb, test,
                      nt, g, kappa, e0, G);
   LAUNCH_OK();
 }
@@ -325,7 +334,7 @@ void launch_gram(const ElemTables *tb, const int4 *test, int nt, ElemGeom g, con
 void launch_bmat(const ElemTables *tb, const int4 *test, const int4 *trial, int nt, int m,
                  ElemGeom g, const double *kappa, const double *Zel, int e0, int count,
                  double2 *BL, int64_t strideBL, hipStream_t s) {
-  hipLaunchKernelGGL(k_bmat, dim3(cdiv((int64_t)nt * m, 256), count), dim3(256), 0, s, tb, test,
+  hipLaunchKernelGGL(k_bmat, dim3(cdiv(m, 4), count), dim3(256), 0, s, tb, test,
                      trial, nt, m, g, kappa, Zel, e0, BL, strideBL);
   LAUNCH_OK();
 }
