@@ -72,11 +72,12 @@ __global__ __launch_bounds__(256) void k_copy_sub(const double2 *__restrict__ sr
                                                   int64_t src_stride, int lds, int r0, int c0,
                                                   int rows, int cols, double2 *__restrict__ dst,
                                                   int64_t dst_stride, int ldd) {
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k >= (int64_t)rows * cols) return;
-  const int i = (int)(k % rows), j = (int)(k / rows);
-  dst[blockIdx.y * dst_stride + i + (int64_t)j * ldd] =
-      src[blockIdx.y * src_stride + (r0 + i) + (int64_t)(c0 + j) * lds];
+  // one wave per column, its lanes over the rows
+  const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (j >= cols) return;
+  const double2 *sc = src + blockIdx.y * src_stride + r0 + (int64_t)(c0 + j) * lds;
+  double2 *dc = dst + blockIdx.y * dst_stride + (int64_t)j * ldd;
+  for (int i = threadIdx.x & 63; i < rows; i += 64) dc[i] = sc[i];
 }
 
 // One workgroup per (patch, kGatCols columns j); the threads take the rows
@@ -133,10 +134,12 @@ __global__ __launch_bounds__(256) void k_patch_gather(const double2 *__restrict_
 __global__ __launch_bounds__(256) void k_identity(const int64_t *__restrict__ off,
                                                   const int32_t *__restrict__ nn,
                                                   double2 *__restrict__ X) {
+  // one wave per column, its lanes over the rows
   const int n = nn[blockIdx.y];
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k >= (int64_t)n * n) return;
-  X[off[blockIdx.y] + k] = mk((k % n) == (k / n) ? 1.0 : 0.0, 0.0);
+  const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (j >= n) return;
+  double2 *xc = X + off[blockIdx.y] + (int64_t)j * n;
+  for (int i = threadIdx.x & 63; i < n; i += 64) xc[i] = mk(i == j ? 1.0 : 0.0, 0.0);
 }
 
 __global__ __launch_bounds__(256) void k_assemble_dense(const double2 *__restrict__ E, int n_tr,
@@ -451,7 +454,7 @@ void launch_copy_sub(const double2 *src, int64_t src_stride, int lds, int r0, in
                      int cols, double2 *dst, int64_t dst_stride, int ldd, int count,
                      hipStream_t s) {
   if (count <= 0 || rows <= 0 || cols <= 0) return;
-  hipLaunchKernelGGL(k_copy_sub, dim3(cdiv((int64_t)rows * cols, 256), count), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_copy_sub, dim3(cdiv(cols, 4), count), dim3(256), 0, s,
                      src, src_stride, lds, r0, c0, rows, cols, dst, dst_stride, ldd);
   LAUNCH_OK();
 }
@@ -468,7 +471,7 @@ void launch_patch_gather(const double2 *Mfull, int nBf, int Nc, const int64_t *p
 void launch_identity(const int64_t *off, const int32_t *n, int count, int nmax, double2 *X,
                      hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_identity, dim3(cdiv((int64_t)nmax * nmax, 256), count), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_identity, dim3(cdiv(nmax, 4), count), dim3(256), 0, s,
                      off, n, X);
   LAUNCH_OK();
 }
