@@ -1058,7 +1058,7 @@ int dpg_setup(const dpg_mesh *mesh, int p, int dp, double omega, const dpg_mater
     HIP_OK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
     HIP_OK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-    for (int k = 0; k + 2 < kPatchParts; ++k) {
+    for (int k = 0; k < 2; ++k) {   // third and fourth setup streams (elements, patches)
       HIP_OK(hipStreamCreateWithFlags(&c->paux[k], hipStreamNonBlocking));
       HIP_OK(hipEventCreateWithFlags(&c->ev_pjoin[k], hipEventDisableTiming));
     }
