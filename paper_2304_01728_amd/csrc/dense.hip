@@ -601,9 +601,9 @@ __global__ __launch_bounds__(NTB, 2) void k_potrf_diag(double2 *base, const Potr
     if (tid == 0) info[blockIdx.x] = k0 + sm.fail;
     return;
   }
-  for (int e = tid; e < kb * kb; e += NTB) {
-    const int i = e % kb, j = e / kb;
-    if (i >= j) A[i + (int64_t)j * lda] = sm.L[pk(i, j)];
+  for (int e = tid; e < NB * NB; e += NTB) {
+    const int i = e % NB, j = e / NB;
+    if (i >= j && i < kb) A[i + (int64_t)j * lda] = sm.L[pk(i, j)];
   }
   double2 *w = work + ((int64_t)blockIdx.x * wslots + k0 / NB) * NB * NB;
   for (int e = tid; e < NB * NB; e += NTB) {
