@@ -99,8 +99,9 @@ def lib():
             getattr(L, name).restype = C.c_int
         L.dpg_load_rhs.argtypes = [vp, C.POINTER(dpg_load), C.c_int, vp]
         L.dpg_load_rhs.restype = C.c_int
-        L.dpg_solve.argtypes = [vp, vp, C.c_int, C.c_double, vp, vp, vp]
-        L.dpg_solve.restype = C.c_int
+        for name in ("dpg_solve",):
+            getattr(L, name).argtypes = [vp, vp, C.c_int, C.c_double, vp, vp, vp]
+            getattr(L, name).restype = C.c_int
         L.dpg_get_fields.argtypes = [vp, vp, C.c_int, vp]
         L.dpg_get_fields.restype = C.c_int
         L.dpg_info.argtypes = [vp, C.POINTER(dpg_info_t)]
@@ -151,10 +152,11 @@ def _loads(loads):
 
 
 class Context:
-    """Owner of a dpg_ctx handle."""
+    """Owner of a dpg_ctx handle (flags: the dpg_options.flags it was set up with)."""
 
-    def __init__(self, handle):
+    def __init__(self, handle, flags=0):
         self.h = handle
+        self.flags = flags
 
     def close(self):
         if self.h:
@@ -184,7 +186,7 @@ def dpg_setup(n, p, omega, loads, dp=1, side=1.0, origin=(0.0, 0.0, 0.0), c=None
     del keep, keepc
     if code != DPG_OK:
         raise DPGError(code, "dpg_setup failed")
-    return Context(h.value)
+    return Context(h.value, int(opt.flags))
 
 
 def dpg_assemble(ctx):
@@ -214,27 +216,51 @@ def dpg_load_rhs(ctx, loads, want=True):
     return out
 
 
+def _device_arg(t, n, name):
+    """Checks a torch tensor passed as a device pointer: complex128, contiguous,
+    on a GPU, at least n entries.  Returns its address."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor with device=True")
+    if t.dtype != torch.complex128 or not t.is_contiguous() or t.device.type != "cuda":
+        raise ValueError(f"{name}: need a contiguous complex128 tensor on a GPU, got "
+                         f"{t.dtype} on {t.device} (contiguous={t.is_contiguous()})")
+    if t.numel() < n:
+        raise ValueError(f"{name}: {t.numel()} entries, need nrhs x n_trace = {n}")
+    return t.data_ptr()
+
+
+def _solve(fn, ctx, rhs, nrhs, tol, x_out, device):
+    nT = dpg_info(ctx).n_trace
+    iters = np.zeros(nrhs, dtype=np.int32)
+    rel = np.zeros(nrhs, dtype=np.float64)
+    if device:
+        if not ctx.flags & DPG_DEVICE_PTRS:
+            raise ValueError("device=True needs a context set up with DPG_DEVICE_PTRS")
+        rp = _device_arg(rhs, nrhs * nT, "rhs") if rhs is not None else None
+        xp = _device_arg(x_out, nrhs * nT, "x_out") if x_out is not None else None
+        x = x_out
+    else:
+        if ctx.flags & DPG_DEVICE_PTRS:
+            raise ValueError("the context takes device pointers: pass device=True")
+        if rhs is not None:
+            rhs = np.ascontiguousarray(np.asarray(rhs, dtype=np.complex128).reshape(nrhs, nT))
+        x = np.zeros((nrhs, nT), dtype=np.complex128) if x_out is None else x_out
+        if x.dtype != np.complex128 or not x.flags.c_contiguous or x.size < nrhs * nT:
+            raise ValueError("x_out: need a contiguous complex128 array of nrhs x n_trace")
+        rp = rhs.ctypes.data if rhs is not None else None
+        xp = x.ctypes.data
+    code = fn(ctx.h, rp, nrhs, tol, xp, iters.ctypes.data, rel.ctypes.data)
+    _check(ctx.h, code, allow=(DPG_ENOCONV,))
+    return x, iters, rel, code
+
+
 def dpg_solve(ctx, rhs=None, nrhs=1, tol=1e-8, x_out=None, device=False):
     """Solve; rhs: [nrhs, n_trace] complex128 (host) or None for the assembled
     loads.  With device=True, rhs / x_out are torch device tensors (complex128,
     contiguous) and the context must have been set up with DPG_DEVICE_PTRS.
     Returns (x, iters, relres, status)."""
-    nT = dpg_info(ctx).n_trace
-    iters = np.zeros(nrhs, dtype=np.int32)
-    rel = np.zeros(nrhs, dtype=np.float64)
-    if device:
-        rp = rhs.data_ptr() if rhs is not None else None
-        xp = x_out.data_ptr() if x_out is not None else None
-        x = x_out
-    else:
-        if rhs is not None:
-            rhs = np.ascontiguousarray(np.asarray(rhs, dtype=np.complex128).reshape(nrhs, nT))
-        x = np.zeros((nrhs, nT), dtype=np.complex128) if x_out is None else x_out
-        rp = rhs.ctypes.data if rhs is not None else None
-        xp = x.ctypes.data
-    code = lib().dpg_solve(ctx.h, rp, nrhs, tol, xp, iters.ctypes.data, rel.ctypes.data)
-    _check(ctx.h, code, allow=(DPG_ENOCONV,))
-    return x, iters, rel, code
+    return _solve(lib().dpg_solve, ctx, rhs, nrhs, tol, x_out, device)
 
 
 def dpg_get_fields(ctx, x):

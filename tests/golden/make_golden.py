@@ -1,11 +1,21 @@
-"""Writes the stored expected values of the full-size parity tests.
+"""Writes the stored expected values of the GPU parity tests.
 
-Runs only the oracle (no GPU code): the plane-wave workload on the 16^3 mesh
-of order 3 (omega = 8 pi, V(2,2), theta = 1/5), solved by the oracle's PCG to
-1e-8 and to 1e-12.  Stores the iteration counts and the solution at 256
-seeded sample positions of the canonical trace vector.
+Runs only the oracle (no GPU code).  Each case is a workload the oracle
+cannot finish inside a test's time limit on one core:
 
-    python tests/golden/make_golden.py      # takes a few minutes
+  plane_wave_16   16^3, p = 3, omega = 8 pi, V(2,2), theta = 1/5: oracle PCG
+                  iteration counts at 1e-8 and 1e-12, the solution at 1e-12
+                  (whole vector, plane_wave_16_x12.npy) and 256 sampled
+                  entries of it and of the assembled load (plane_wave_16.json)
+  plane_wave_8_p4 8^3, p = 4, omega = 4 pi (4 elements per wavelength, as on
+                  the 32^3 mesh at 16 pi), three levels, V(2,2): iteration
+                  counts at 1e-8 and 1e-10, solution at 1e-12
+  point_sources_6_p3
+                  6^3, p = 3, omega = 3 pi, 32 Gaussian sources (width 0.02,
+                  centres from seed 3), homogeneous impedance data, V(2,2):
+                  per-column iteration counts at 1e-8, solutions at 1e-12
+
+    python tests/golden/make_golden.py [case ...]     # all cases by default
 """
 import json
 import os
@@ -20,12 +30,16 @@ from oracle import dpg, multigrid  # noqa: E402
 from paper_2304_01728_amd import workloads  # noqa: E402
 
 
-def main():
+def _condensed(pr):
     from threadpoolctl import threadpool_limits
-    w = workloads.plane_wave_16()
     with threadpool_limits(1):
-        pr = dpg.Problem(w.N, w.p, w.omega, [dict(u0=dpg.plane_wave_u0(w.omega, w.direction))])
-        S, s, _ = pr.condensed()
+        return pr.condensed()
+
+
+def plane_wave_16():
+    w = workloads.plane_wave_16()
+    pr = dpg.Problem(w.N, w.p, w.omega, [dict(u0=dpg.plane_wave_u0(w.omega, w.direction))])
+    S, s, _ = _condensed(pr)
     rhs = dpg.assemble_vector(pr.edofs, s, pr.num.n)[:, 0]
     H = multigrid.Hierarchy(w.N, w.p, S, theta=w.theta, nu_pre=w.nu_pre, nu_post=w.nu_post)
     x8, it8, rr8 = H.solve(rhs, 1e-8)
@@ -47,7 +61,51 @@ def main():
     }
     with open(os.path.join(HERE, "plane_wave_16.json"), "w") as f:
         json.dump(out, f, indent=1)
-    print("iterations", it8, it12)
+    np.save(os.path.join(HERE, "plane_wave_16_x12.npy"), x12.astype(np.complex128))
+    print("plane_wave_16 iterations", it8, it12)
+
+
+def plane_wave_8_p4():
+    N, p, omega = 8, 4, 4 * np.pi
+    d = workloads.plane_wave_direction(2)
+    pr = dpg.Problem(N, p, omega, [dict(u0=dpg.plane_wave_u0(omega, d))])
+    S, s, _ = _condensed(pr)
+    rhs = dpg.assemble_vector(pr.edofs, s, pr.num.n)[:, 0]
+    H = multigrid.Hierarchy(N, p, S, nu_pre=2, nu_post=2)
+    _, it8, _ = H.solve(rhs, 1e-8)
+    _, it10, _ = H.solve(rhs, 1e-10)
+    x12, it12, _ = H.solve(rhs, 1e-12)
+    np.savez(os.path.join(HERE, "plane_wave_8_p4.npz"), x12=x12, iters=np.array([it8, it10, it12]),
+             N=N, p=p, omega=omega, direction=d, seed=2)
+    print("plane_wave_8_p4 iterations", it8, it10, it12)
+
+
+def point_sources_6_p3():
+    N, p, omega, sigma = 6, 3, 3 * np.pi, 0.02
+    cen = workloads.source_centres(3, 32)
+    pr = dpg.Problem(N, p, omega, [dict(f=dpg.gaussian_sources([c], sigma, [1.0])) for c in cen])
+    S, s, _ = _condensed(pr)
+    rhs = dpg.assemble_vector(pr.edofs, s, pr.num.n)
+    H = multigrid.Hierarchy(N, p, S, nu_pre=2, nu_post=2)
+    its, xs = [], []
+    for k in range(32):
+        _, it8, _ = H.solve(rhs[:, k], 1e-8)
+        x12, _, _ = H.solve(rhs[:, k], 1e-12)
+        its.append(it8)
+        xs.append(x12)
+    np.savez(os.path.join(HERE, "point_sources_6_p3.npz"), x12=np.array(xs), iters=np.array(its),
+             N=N, p=p, omega=omega, sigma=sigma, centres=cen, seed=3)
+    print("point_sources_6_p3 iterations", its)
+
+
+CASES = {"plane_wave_16": plane_wave_16, "plane_wave_8_p4": plane_wave_8_p4,
+         "point_sources_6_p3": point_sources_6_p3}
+
+
+def main():
+    names = sys.argv[1:] or list(CASES)
+    for n in names:
+        CASES[n]()
 
 
 if __name__ == "__main__":

@@ -293,10 +293,10 @@ def test_load_rhs_replaces_loads(two_level):
 
 
 def test_full_size_workload_against_stored_oracle_values():
-    """16^3, p = 3, omega = 8 pi, V(2,2): the launch configuration bench.py
-    times.  Iteration counts and sampled solution entries against values the
-    oracle wrote (tests/golden/make_golden.py); topology bit-exact against the
-    oracle computed here; sampled element matrices against the oracle."""
+    """16^3, p = 3, omega = 8 pi, V(2,2), FP64.  Iteration counts, sampled
+    entries and the whole solution vector against values the oracle wrote
+    (tests/golden/make_golden.py); topology bit-exact against the oracle
+    computed here; sampled element matrices against the oracle."""
     D = _D()
     path = os.path.join(HERE, "golden", "plane_wave_16.json")
     g = json.load(open(path))
@@ -313,6 +313,10 @@ def test_full_size_workload_against_stored_oracle_values():
     pos = np.array(g["sample_pos"])
     ref = np.array(g["x12_sample_re"]) + 1j * np.array(g["x12_sample_im"])
     assert np.abs(x12[0][pos] - ref).max() <= 1e-10 * g["x_inf_norm"]
+    # the whole solution vector
+    xo = np.load(os.path.join(HERE, "golden", "plane_wave_16_x12.npy"))
+    assert xo.shape == x12[0].shape
+    assert np.linalg.norm(x12[0] - xo) <= 1e-10 * np.linalg.norm(xo)
     sref = np.array(g["s_sample_re"]) + 1j * np.array(g["s_sample_im"])
     sa = D.dpg_export(ctx, D.X_ASM_RHS)
     assert np.abs(sa[pos] - sref).max() <= elem_tol(w.p, w.omega, 1.0 / w.N) * np.abs(sa).max()
