@@ -137,6 +137,15 @@ int dpg_build_hierarchy(dpg_ctx *ctx);
  * n_trace x nrhs, if s_out is not NULL. */
 int dpg_load_rhs(dpg_ctx *ctx, const dpg_load *loads, int nrhs, double *s_out);
 
+/* Frees what only dpg_assemble and dpg_build_hierarchy use: the element and
+ * coarse element matrices, the full condensed macro blocks, the dense
+ * coarsest operator and the setup work areas.  Solves, dpg_load_rhs and
+ * dpg_get_fields keep working; dpg_assemble, dpg_build_hierarchy and the
+ * exports of the freed matrices return DPG_ESTATE afterwards.  For callers
+ * that keep many hierarchies resident (a solve server).  Requires a built
+ * hierarchy (DPG_ESTATE otherwise). */
+int dpg_release_setup(dpg_ctx *ctx);
+
 /* Solves T x = rhs for nrhs right-hand sides (rhs: n_trace x nrhs trace
  * vectors; NULL: the assembled loads).  PCG on the macro grid with one
  * V(nu_pre, nu_post) cycle per iteration, x0 = 0, stop at
@@ -150,17 +159,25 @@ int dpg_load_rhs(dpg_ctx *ctx, const dpg_load *loads, int nrhs, double *s_out);
  * per-column CG scalars; a converged column stops updating while the others
  * continue); DPG_COLUMNWISE in the options' flags solves them one by one
  * instead.  Both give each column the same iterates up to rounding. */
-/* Frees what only dpg_assemble and dpg_build_hierarchy use: the element and
- * coarse element matrices, the full condensed macro blocks, the dense
- * coarsest operator and the setup work areas.  Solves, dpg_load_rhs and
- * dpg_get_fields keep working; dpg_assemble, dpg_build_hierarchy and the
- * exports of the freed matrices return DPG_ESTATE afterwards.  For callers
- * that keep many hierarchies resident (a solve server).  Requires a built
- * hierarchy (DPG_ESTATE otherwise). */
-int dpg_release_setup(dpg_ctx *ctx);
-
 int dpg_solve(dpg_ctx *ctx, const double *rhs, int nrhs, double tol, double *x_out,
               int32_t *iters_out, double *relres_out);
+
+/* For callers that cannot allocate device memory: code run under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and errors as dpg_solve with DPG_COLUMNWISE (columns
+ * solved one after the other, each with the same iterates as dpg_solve gives
+ * it), but the call allocates nothing: no hipMalloc or hipFree, no HIP graph
+ * instantiation (every kernel is launched directly on the context's stream),
+ * no library routine that allocates.  The CG reduction partials and scalars
+ * live in a static device array of the library (8,256 bytes per GPU, held
+ * until the process ends) instead of the context's buffers; the vectors are
+ * the ones dpg_setup allocated.  Every size the context accepts fits, since
+ * the array holds one column's reductions.  All calls on one GPU share that
+ * array: calls that overlap on one GPU (contexts on different streams, or
+ * different host threads) race and must be serialised by the caller.
+ * DPG_ESTATE while kernel profiling is on (dpg_profile creates events). */
+int dpg_solve_noalloc(dpg_ctx *ctx, const double *rhs, int nrhs, double tol, double *x_out,
+                      int32_t *iters_out, double *relres_out);
 
 /* Field coefficients of the element-interior unknowns for trace solutions x
  * (n_trace x nrhs): x_f = K_ff^-1 (b_f - K_ft x_t) per element, output

@@ -4,9 +4,39 @@
 #include <cmath>
 #include <cstring>
 
+#include <mutex>
+
 #include "ctx.hpp"
 
 using namespace dpg;
+
+// Scratch of dpg_solve_noalloc: the reduction partials (2 kDotBlocks doubles)
+// and the eight CG scalars of the column being solved.  Each GPU the library
+// runs on holds one copy until the process ends.  Host code never uses this
+// name as an address: dpg_setup looks up the device address once per device
+// (scratch_device_ptr) and the kernels receive that pointer.
+constexpr int kScratchDoubles = 2 * kDotBlocks + 8;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, which must be the current device
+// on the first call for it.
+double *scratch_device_ptr(int dev, bool resolve) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) throw DpgError(DPG_EDEVICE, "device index out of range");
+  if (!g_scratch[dev] && resolve) {
+    void *ptr = nullptr;
+    HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw DpgError(DPG_EDEVICE, "no device address for the solve scratch");
+    g_scratch[dev] = static_cast<double *>(ptr);
+  }
+  return g_scratch[dev];
+}
+}  // namespace
 
 namespace {
 
@@ -682,8 +712,8 @@ void precondition(dpg_ctx *c, const double2 *r, double2 *z) {
   }
 }
 
-void read_sc(dpg_ctx *c) {
-  HIP_OK(hipMemcpyAsync(c->host_sc, c->sc.p, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+void read_sc(dpg_ctx *c, const double *sc) {
+  HIP_OK(hipMemcpyAsync(c->host_sc, sc, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_OK(hipStreamSynchronize(c->stream));
 }
 
@@ -717,19 +747,22 @@ template <class F> hipGraphExec_t capture(hipStream_t s, F &&f) {
 
 // PCG on the finest macro grid for one trace right-hand side s (device);
 // full trace solution into xout (device).  Returns DPG_OK / ENOCONV.
+// partial (2 kDotBlocks doubles) and sc (8 doubles) hold the reduction
+// partials and the CG scalars; graphs: replay the iteration as HIP graphs
+// (instantiated per call) instead of launching every kernel.
 int solve_one(dpg_ctx *c, const double2 *sv, double tol, double2 *xout, int32_t *iters,
-              double *relres) {
+              double *relres, double *partial, double *sc, bool graphs) {
   LevelData &top = c->lv[c->L];
   const hipStream_t s = c->stream;
   const int64_t nM = top.nM;
   launch_condense_local<double>(top.WH.p, top.nI, top.nBf, top.blkI.p, top.nblk, sv, top.c64.p, s);
   launch_condense_reduce<double>(nM, top.macroB.p, top.cred_ptr.p, top.cred_ent.p, sv, top.c64.p,
                                  c->b.p, s);
-  HIP_OK(hipMemsetAsync(c->sc.p, 0, 8 * sizeof(double), s));
-  dot_re(nM, c->b.p, c->b.p, c->partial.p, c->sc.p + 5, s);
-  HIP_OK(hipMemsetAsync(c->x.p, 0, nM * 16, s));
+  launch_zero(4, reinterpret_cast<double2 *>(sc), s);   // the 8 scalars
+  dot_re(nM, c->b.p, c->b.p, partial, sc + 5, s);
+  launch_zero(nM, c->x.p, s);
   HIP_OK(hipMemcpyAsync(c->r.p, c->b.p, nM * 16, hipMemcpyDeviceToDevice, s));
-  read_sc(c);
+  read_sc(c, sc);
   const double bb = c->host_sc[5];
   int it = 0;
   double rr = 0.0;
@@ -738,7 +771,7 @@ int solve_one(dpg_ctx *c, const double2 *sv, double tol, double2 *xout, int32_t 
   if (bb > 0.0) {
     double2 *z = c->z.p, *zo = c->zo.p;
     precondition(c, c->r.p, z);
-    dot_re(nM, c->r.p, z, c->partial.p, c->sc.p + 0, s);
+    dot_re(nM, c->r.p, z, partial, sc + 0, s);
     HIP_OK(hipMemcpyAsync(c->pv.p, z, nM * 16, hipMemcpyDeviceToDevice, s));
     rr = 1.0;
     // One iteration is two fixed launch sequences around the host's
@@ -749,17 +782,17 @@ int solve_one(dpg_ctx *c, const double2 *sv, double tol, double2 *xout, int32_t 
     auto part_a = [&]() {
       herm_apply<double>(top.Mset, c->pv.p, c->q.p, nullptr, RED_SET, 1.0, s);
       PROF(DPG_K_CG, 0);
-      cg_alpha(nM, c->pv.p, c->q.p, c->partial.p, c->sc.p, s);
-      cg_update_xr(nM, c->x.p, c->r.p, c->pv.p, c->q.p, c->partial.p, c->sc.p, s);
+      cg_alpha(nM, c->pv.p, c->q.p, partial, sc, s);
+      cg_update_xr(nM, c->x.p, c->r.p, c->pv.p, c->q.p, partial, sc, s);
     };
     auto part_b = [&](double2 *zn, double2 *zp) {
       precondition(c, c->r.p, zn);
       PROF(DPG_K_CG, 0);
-      cg_beta(nM, c->r.p, zn, zp, c->partial.p, c->sc.p, s);
-      cg_update_p(nM, c->pv.p, zn, c->sc.p, s);
+      cg_beta(nM, c->r.p, zn, zp, partial, sc, s);
+      cg_update_p(nM, c->pv.p, zn, sc, s);
     };
     GraphSet gs;
-    const bool graphs = !c->prof.on;
+    graphs = graphs && !c->prof.on;
     if (graphs) {
       gs.a = capture(s, part_a);
       gs.b[0] = capture(s, [&]() { part_b(c->zo.p, c->z.p); });   // odd iterations
@@ -769,7 +802,7 @@ int solve_one(dpg_ctx *c, const double2 *sv, double tol, double2 *xout, int32_t 
       if (graphs) HIP_OK(hipGraphLaunch(gs.a, s));
       else part_a();
       ++it;
-      read_sc(c);
+      read_sc(c, sc);
       if (c->host_sc[6] != 0.0)
         throw DpgError(DPG_EBREAKDOWN, "CG breakdown at iteration " + std::to_string(it) +
                                            " (p^H M p = " + std::to_string(c->host_sc[1]) + ")");
@@ -787,6 +820,38 @@ int solve_one(dpg_ctx *c, const double2 *sv, double tol, double2 *xout, int32_t 
   HIP_OK(hipStreamSynchronize(s));
   if (iters) *iters = it;
   if (relres) *relres = rr;
+  return status;
+}
+
+// Columns solved one after the other (solve_one), rhs / x_out staged through
+// the context's trace vectors when they are host memory.
+int solve_columns(dpg_ctx *c, const double *rhs, int nrhs, double tol, double *x_out,
+                  int32_t *iters_out, double *relres_out, double *partial, double *sc,
+                  bool graphs) {
+  const int64_t nT = c->lv[c->L].num.n;
+  const bool dev = c->opt.flags & DPG_DEVICE_PTRS;
+  int status = DPG_OK;
+  for (int k = 0; k < nrhs; ++k) {
+    const double2 *sv;
+    if (rhs) {
+      HIP_OK(hipMemcpyAsync(c->sB.p, rhs + 2 * nT * k, nT * 16,
+                            dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+      sv = c->sB.p;
+    } else {
+      sv = c->s_asm.p + nT * k;
+    }
+    int32_t it = 0;
+    double rr = 0;
+    const int st = solve_one(c, sv, tol, c->xfull.p, &it, &rr, partial, sc, graphs);
+    if (st != DPG_OK) status = st;
+    if (iters_out) iters_out[k] = it;
+    if (relres_out) relres_out[k] = rr;
+    if (x_out) {
+      HIP_OK(hipMemcpyAsync(x_out + 2 * nT * k, c->xfull.p, nT * 16,
+                            dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+      HIP_OK(hipStreamSynchronize(c->stream));
+    }
+  }
   return status;
 }
 
@@ -1047,6 +1112,8 @@ int dpg_setup(const dpg_mesh *mesh, int p, int dp, double omega, const dpg_mater
       throw DpgError(DPG_EINVAL, "bad smoothing counts or maxit");
     if (c->opt.precision != DPG_FP64 && c->opt.precision != DPG_MIXED)
       throw DpgError(DPG_EINVAL, "unknown precision mode");
+    HIP_OK(hipGetDevice(&c->device));
+    (void)scratch_device_ptr(c->device, true);   // once per device, with it current
     c->stream = (hipStream_t)c->opt.stream;
     if (!c->stream) {
       // an own stream (blocking, so ordered with the caller's null-stream
@@ -1362,29 +1429,34 @@ int dpg_solve(dpg_ctx *c, const double *rhs, int nrhs, double tol, double *x_out
         }
       }
     } else {
-      for (int k = 0; k < nrhs; ++k) {
-        const double2 *sv;
-        if (rhs) {
-          HIP_OK(hipMemcpyAsync(c->sB.p, rhs + 2 * nT * k, nT * 16,
-                                dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
-          sv = c->sB.p;
-        } else {
-          sv = c->s_asm.p + nT * k;
-        }
-        int32_t it = 0;
-        double rr = 0;
-        const int st = solve_one(c, sv, tol, c->xfull.p, &it, &rr);
-        if (st != DPG_OK) status = st;
-        if (iters_out) iters_out[k] = it;
-        if (relres_out) relres_out[k] = rr;
-        if (x_out) {
-          HIP_OK(hipMemcpyAsync(x_out + 2 * nT * k, c->xfull.p, nT * 16,
-                                dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
-          HIP_OK(hipStreamSynchronize(c->stream));
-        }
-      }
+      status = solve_columns(c, rhs, nrhs, tol, x_out, iters_out, relres_out, c->partial.p,
+                             c->sc.p, true);
     }
     c->prof.flush();
+    c->ms[3] = ms_since(t0);
+    if (status == DPG_ENOCONV) c->err = "maximum number of iterations reached";
+    return status;
+  });
+}
+
+int dpg_solve_noalloc(dpg_ctx *c, const double *rhs, int nrhs, double tol, double *x_out,
+                      int32_t *iters_out, double *relres_out) {
+  if (!c) return DPG_EINVAL;
+  return guarded(c, [&]() {
+    if (c->stage < 3) throw DpgError(DPG_ESTATE, "dpg_build_hierarchy first");
+    if (nrhs < 1 || !(tol >= 0.0)) throw DpgError(DPG_EINVAL, "bad nrhs or tol");
+    if (!rhs && nrhs > c->nrhs) throw DpgError(DPG_EINVAL, "more columns than assembled loads");
+    if (c->prof.on)
+      throw DpgError(DPG_ESTATE, "kernel profiling creates events: switch it off for this call");
+    // The scratch holds the reductions of one column; columns are solved one
+    // after the other, so every size the context accepts fits.
+    static_assert(2 * kDotBlocks + 8 <= kScratchDoubles, "solve scratch too small");
+    double *sp = scratch_device_ptr(c->device, false);
+    if (!sp) throw DpgError(DPG_ESTATE, "solve scratch not set up on this device");
+    auto t0 = clk::now();
+    const int status =
+        solve_columns(c, rhs, nrhs, tol, x_out, iters_out, relres_out, sp, sp + 2 * kDotBlocks,
+                      false);
     c->ms[3] = ms_since(t0);
     if (status == DPG_ENOCONV) c->err = "maximum number of iterations reached";
     return status;

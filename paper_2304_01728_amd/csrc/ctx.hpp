@@ -113,6 +113,7 @@ struct dpg_ctx {
   int N = 0, p = 0, dp = 1, nrhs = 0;
   double omega = 0, side = 1, org[3] = {0, 0, 0};
   dpg_options opt{};
+  int device = 0;                    // the device current at dpg_setup
   hipStream_t stream = nullptr;
   hipStream_t own_stream = nullptr;  // created when the options give no stream
   hipStream_t aux = nullptr;         // second stream of the setup phases

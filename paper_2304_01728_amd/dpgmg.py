@@ -26,7 +26,7 @@ _DOUBLE_EXPORTS = {X_PROLONG_VAL}
 SYMBOLS = ["dpg_default_options", "dpg_setup", "dpg_assemble", "dpg_build_hierarchy",
            "dpg_load_rhs", "dpg_solve", "dpg_get_fields", "dpg_info", "dpg_export",
            "dpg_profile", "dpg_kernel_stats", "dpg_last_error", "dpg_destroy",
-           "dpg_release_setup"]
+           "dpg_release_setup", "dpg_solve_noalloc"]
 
 
 class dpg_mesh(C.Structure):
@@ -99,7 +99,7 @@ def lib():
             getattr(L, name).restype = C.c_int
         L.dpg_load_rhs.argtypes = [vp, C.POINTER(dpg_load), C.c_int, vp]
         L.dpg_load_rhs.restype = C.c_int
-        for name in ("dpg_solve",):
+        for name in ("dpg_solve", "dpg_solve_noalloc"):
             getattr(L, name).argtypes = [vp, vp, C.c_int, C.c_double, vp, vp, vp]
             getattr(L, name).restype = C.c_int
         L.dpg_get_fields.argtypes = [vp, vp, C.c_int, vp]
@@ -261,6 +261,12 @@ def dpg_solve(ctx, rhs=None, nrhs=1, tol=1e-8, x_out=None, device=False):
     contiguous) and the context must have been set up with DPG_DEVICE_PTRS.
     Returns (x, iters, relres, status)."""
     return _solve(lib().dpg_solve, ctx, rhs, nrhs, tol, x_out, device)
+
+
+def dpg_solve_noalloc(ctx, rhs=None, nrhs=1, tol=1e-8, x_out=None, device=False):
+    """dpg_solve column by column without any device allocation in the call
+    (arguments and results as dpg_solve)."""
+    return _solve(lib().dpg_solve_noalloc, ctx, rhs, nrhs, tol, x_out, device)
 
 
 def dpg_get_fields(ctx, x):
