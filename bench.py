@@ -154,6 +154,47 @@ def compare_precision(workload):
     print(json.dumps(out), flush=True)
 
 
+def store_vs_restrict(workload, omegas_over_pi=(2.0, 4.0, 8.0, 12.0)):
+    """The paper's comparison of coarse operators (Sec. 4.2): PCG iterations
+    and time to tolerance with Galerkin restriction and with operators stored
+    (assembled directly on each coarser mesh), on the workload's mesh and
+    order across frequencies."""
+    import dataclasses
+    import torch
+    from paper_2304_01728_amd import dpgmg as D
+    from paper_2304_01728_amd import workloads as W
+    base = W.ALL[workload]()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for om in omegas_over_pi:
+        w = dataclasses.replace(base, omega=om * np.pi)
+        row = {"omega_over_pi": om, "elements_per_wavelength": 2 * w.N / om}
+        for name, flags in (("restrict", 0), ("store", D.DPG_STORE_COARSE)):
+            opt = make_options(D, w, torch_stream=stream.cuda_stream)
+            opt.flags |= flags
+            ctx = D.dpg_setup(w.N, w.p, w.omega, loads_of(w), dp=w.dp, options=opt)
+            nT = D.dpg_info(ctx).n_trace
+            x = torch.zeros((w.nrhs, nT), dtype=torch.complex128, device="cuda:0")
+            D.dpg_assemble(ctx)
+            D.dpg_build_hierarchy(ctx)
+            D.dpg_solve(ctx, nrhs=w.nrhs, tol=w.tol, x_out=x, device=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, it, rr, code = D.dpg_solve(ctx, nrhs=w.nrhs, tol=w.tol, x_out=x, device=True)
+            torch.cuda.synchronize()
+            row[name] = {"iterations": int(np.max(it)), "time_to_tol_ms":
+                         1e3 * (time.perf_counter() - t0), "status": int(code)}
+            ctx.close()
+            del x
+            torch.cuda.empty_cache()
+        print(f"[store-vs-restrict] omega = {om} pi: restrict {row['restrict']['iterations']}, "
+              f"store {row['store']['iterations']}", file=sys.stderr, flush=True)
+        rows.append(row)
+    print(json.dumps({"comparison": "coarse operators: restrict vs store", "workload": base.name,
+                      "tol": base.tol, "rows": rows}), flush=True)
+
+
 def calibrate_copy():
     """A plain device copy of known size, for scaling HBM counters."""
     import torch
@@ -366,6 +407,9 @@ def main():
     ap.add_argument("--compare-precision", action="store_true",
                     help="solve the workload in FP64 and in mixed precision; report times "
                          "to tolerance and the mixed solution's error against the FP64 one")
+    ap.add_argument("--store-vs-restrict", action="store_true",
+                    help="iterations and time to tolerance with restricted and with stored "
+                         "coarse operators across frequencies, on the workload's mesh")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device copy (for HBM counter calibration)")
     ap.add_argument("--serving", action="store_true",
@@ -385,6 +429,9 @@ def main():
         return
     if args.compare_precision:
         compare_precision(args.workload)
+        return
+    if args.store_vs_restrict:
+        store_vs_restrict(args.workload)
         return
     if args.serving:
         serving_stream(args.requests, args.seed, args.max_active, args.load_factor)

@@ -62,7 +62,14 @@ enum {
 
 enum { DPG_FP64 = 0, DPG_MIXED = 1 };       /* dpg_options.precision          */
 enum { DPG_DEVICE_PTRS = 1,                 /* dpg_options.flags              */
-       DPG_COLUMNWISE = 2 };                 /* solve nrhs > 1 column by column */
+       DPG_COLUMNWISE = 2,                   /* solve nrhs > 1 column by column */
+       DPG_STORE_COARSE = 4 };               /* coarse operators assembled on
+                                                their own meshes ("store", the
+                                                alternative of Sec. 3 and the
+                                                comparison of Sec. 4.2) instead
+                                                of Galerkin P^T M P; needs a
+                                                wave speed constant on every
+                                                coarse element                 */
 
 /* Uniform mesh of the cube [origin, origin + side]^3 into n^3 equal boxes;
  * element e = i + n (j + n k). */
@@ -77,17 +84,22 @@ typedef struct {
   const double *c;
 } dpg_material;
 
-/* One right-hand side (Sec. 2 load l, eq. helmholtz data):
+/* One right-hand side (Sec. 2 load l = <u0, q>_Gamma + (f, q), eq. helmholtz
+ * data); the parts below are summed:
  *  - impedance data of a plane wave p = A exp(-i w d.x), u = d p, i.e.
- *    u0 = (Z^-1 - d.n) A exp(-i w d.x) on Gamma (A = amp; A = 0: u0 = 0);
+ *    u0 = (Z^-1 - d.n) A exp(-i w d.x) on Gamma (A = amp; A = 0: none);
  *  - nsrc Gaussian point sources in the first equation,
  *    f = sum a_s (2 pi s^2)^(-3/2) exp(-|x - x_s|^2 / (2 s^2)), given as
- *    src[6*k .. 6*k+5] = (x, y, z, sigma, re a, im a). */
+ *    src[6*k .. 6*k+5] = (x, y, z, sigma, re a, im a);
+ *  - general impedance data u0 given by its values at the boundary load
+ *    points (complex, interleaved; the points and their order are those of
+ *    dpg_boundary_points), or NULL. */
 typedef struct {
   double dir[3];
   double amp[2];
   int32_t nsrc;
   const double *src;
+  const double *u0_qp;
 } dpg_load;
 
 typedef struct {
@@ -98,7 +110,7 @@ typedef struct {
   int32_t nu_post;
   int32_t nlevels;    /* 0: halve while n is even and n > 2 (n = 2: once)    */
   int32_t maxit;      /* outer CG iteration cap                              */
-  int32_t flags;      /* DPG_DEVICE_PTRS | DPG_COLUMNWISE                    */
+  int32_t flags;      /* DPG_DEVICE_PTRS | DPG_COLUMNWISE | DPG_STORE_COARSE */
   double theta;       /* smoother damping; must be < 1/4                     */
   int64_t hbm_budget; /* bytes the context may allocate; 0 = no limit        */
   void *stream;       /* hipStream_t to launch on; NULL: a stream the context
@@ -118,6 +130,16 @@ void dpg_default_options(dpg_options *opt);
 int dpg_setup(const dpg_mesh *mesh, int p, int dp, double omega, const dpg_material *mat,
               const dpg_load *loads, int nrhs, const dpg_options *opt, dpg_ctx **out);
 
+/* The boundary load points where dpg_load.u0_qp gives the impedance data
+ * u0 (Sec. 2, eq. helmholtz): the Gauss rule of the load integrals, p + dp + 5
+ * points per direction, on every face of Gamma.  Faces in the order axis
+ * d = 0, 1, 2 (x, y, z), side low then high (outward normal -e_d, +e_d),
+ * cells (c1, c2) along the two other axes in ascending axis order, c1
+ * fastest; on each face the points with the first in-plane coordinate
+ * fastest.  Writes min(cap, count) points as (x, y, z) triples to xyz (may
+ * be NULL) and returns count = 6 n^2 (p + dp + 5)^2, or a negative error. */
+int64_t dpg_boundary_points(const dpg_ctx *ctx, double *xyz, int64_t cap);
+
 /* Element DPG work on the GPU, all in FP64 (Sec. 2 and Sec. 1.2): Gram
  * matrix G of the adjoint graph norm, B and loads l; Cholesky G = L L^H;
  * W = L^-1 [B l]; K = W^H W; static condensation of the fields,
@@ -127,9 +149,11 @@ int dpg_assemble(dpg_ctx *ctx);
 
 /* Multigrid hierarchy on the GPU (Sec. 3), FP64: per level, macro
  * condensation of the 8 children of every coarse element, Galerkin coarse
- * element matrices P^T M P, vertex-patch blocks factored and inverted (the
- * inverse kept in FP64, plus an FP32 copy in mixed mode); dense Cholesky of
- * the coarsest operator. */
+ * element matrices P^T M P (with DPG_STORE_COARSE: the element DPG matrices
+ * of the coarser mesh itself, by the element stage of dpg_assemble at that
+ * mesh size), vertex-patch blocks factored and inverted (the inverse kept in
+ * FP64, plus an FP32 copy in mixed mode); dense Cholesky of the coarsest
+ * operator.  Errors: DPG_ENOTPD names the coarse element, patch or level. */
 int dpg_build_hierarchy(dpg_ctx *ctx);
 
 /* Replaces the assembled loads by new right-hand sides for the same operator
@@ -184,6 +208,18 @@ int dpg_solve_noalloc(dpg_ctx *ctx, const double *rhs, int nrhs, double tol, dou
  * [nrhs][n^3][4 p^3] in the order (p, u_x, u_y, u_z), each a Legendre
  * tensor product with x-degree fastest.  Requires the assembled loads. */
 int dpg_get_fields(dpg_ctx *ctx, const double *x, int nrhs, double *fields_out);
+
+/* DPG residual error indicator (Sec. 1.2, the method's built-in error
+ * estimate; Sec. 3, first paragraph: it drives the refinements that produce
+ * the mesh hierarchy): for trace solutions x (n_trace x nrhs, as from
+ * dpg_solve for the context's first nrhs loads), per element K
+ *     eta_K^2 = r^H G_K^-1 r,   r = l_K - B_K [x_f; x_t],
+ * the residual of the element equations in the dual test norm, with the
+ * fields x_f recovered from the traces.  Output [nrhs][n^3] doubles.
+ * Re-runs the FP64 element stage (Gram and B, both Cholesky factors) on the
+ * GPU and allocates a staging copy when the pointers are host memory.
+ * sum_K eta_K^2 is the quantity the DPG solution minimises. */
+int dpg_error_indicator(dpg_ctx *ctx, const double *x, int nrhs, double *eta2_out);
 
 typedef struct {
   int64_t n_trace;          /* trace unknowns of the finest mesh          */

@@ -125,6 +125,21 @@ class Problem:
         G, B, _ = self._operator(e)
         return optimal_test_product(G, B, self.element_load(e))
 
+    def condensed_operator(self):
+        """Per-element condensed matrices S [nel, n_tr, n_tr] without loads: the
+        operator of this mesh assembled directly (used for the "store" coarse
+        operators of the multigrid hierarchy)."""
+        S = np.zeros((self.nel, self.n_tr, self.n_tr), dtype=np.complex128)
+        scache = {}
+        for e in range(self.nel):
+            G, B, cG = self._operator(e)
+            key = id(cG)
+            if key not in scache:
+                K, _ = optimal_test_product(G, B, np.zeros((G.shape[0], 1)))
+                scache[key] = condense(K, np.zeros((K.shape[0], 1)), self.n_field)[0]
+            S[e] = scache[key]
+        return S
+
     def condensed(self, elements=None):
         """Per-element S [nel, n_tr, n_tr], s [nel, n_tr, nrhs], recovery data.
 
@@ -190,3 +205,22 @@ def recover_fields(rec, edofs, x):
         xt[d >= 0] = x[d[d >= 0]]
         out.append(sla.cho_solve(c, bf - Kft @ xt))
     return np.array(out)
+
+
+def error_indicator(pr, x, rec):
+    """DPG residual error indicator of every element (Sec. 1.2, the built-in
+    error estimate; Sec. 3, first paragraph): the residual of the element
+    equations in the dual test norm, eta_K^2 = r^H G^-1 r with
+    r = l_K - B_K [x_f; x_t], for the trace solution x [n_trace, nrhs] and the
+    fields recovered from it.  Returns eta^2 [nel, nrhs]."""
+    fields = recover_fields(rec, pr.edofs, x)
+    out = np.zeros((pr.nel, x.shape[1]))
+    for e in range(pr.nel):
+        G, B, cG = pr._operator(e)
+        d = pr.edofs[e]
+        xt = np.zeros((d.size, x.shape[1]), dtype=np.complex128)
+        xt[d >= 0] = x[d[d >= 0]]
+        r = pr.element_load(e) - B @ np.vstack([fields[e], xt])
+        out[e] = np.real(np.sum(r.conj() * sla.cho_solve(cG, r), axis=0))
+    return out
+

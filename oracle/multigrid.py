@@ -8,7 +8,9 @@ Sec. 3 of the paper, restated:
     then the natural inclusion P_l maps the trace unknowns of mesh l-1 onto
     the macro-grid unknowns.
   * Coarse operators by restriction ("Alternative construction"):
-    T_{l-1} = P_l^T M_l P_l, formed coarse element by coarse element.
+    T_{l-1} = P_l^T M_l P_l, formed coarse element by coarse element; or,
+    for the comparison the paper makes (Sec. 3 and 4.2), assembled directly
+    on the coarse mesh from its own element DPG matrices ("store").
   * Smoother ("V-cycle and smoother"): additive Schwarz over the macro-grid
     unknowns supported in each coarse-grid vertex patch, damped by theta.
     CG and smoothing both act on the macro grid.
@@ -128,7 +130,10 @@ def build_patches(lv):
 class Hierarchy:
     """All levels, finest last: levels[0] is the coarsest mesh."""
 
-    def __init__(self, N, p, S_fine, theta=0.2, nu_pre=1, nu_post=1, nlevels=0):
+    def __init__(self, N, p, S_fine, theta=0.2, nu_pre=1, nu_post=1, nlevels=0, coarse=None):
+        """coarse: None for coarse operators by restriction (Galerkin P^T M P);
+        else a function n -> element matrices of the n^3 mesh assembled
+        directly ("store", the approach the paper compares against)."""
         sizes = level_sizes(N)
         if nlevels > 0:
             sizes = sizes[:nlevels]
@@ -144,7 +149,10 @@ class Hierarchy:
             coarse_num = topology.Numbering(sizes[L - l + 1], p)
             lv.P = topology.prolongation(lv.macro, coarse_num)
             build_patches(lv)
-            E = galerkin(lv, coarse_num, topology.element_dofs(coarse_num))
+            if coarse is None:
+                E = galerkin(lv, coarse_num, topology.element_dofs(coarse_num))
+            else:
+                E = coarse(sizes[L - l + 1])
             levels[l] = lv
         lv0 = Level(sizes[L], p, E)
         lv0.T = dpg.assemble(lv0.edofs, E, lv0.n).toarray()

@@ -77,12 +77,29 @@ std::vector<int> level_sizes(int N, int nlevels) {
   return s;
 }
 
+// Boundary load points of the finest mesh: 6 N^2 faces of nql^2 points.
+int64_t boundary_points(const dpg_ctx *c) {
+  return 6LL * c->N * c->N * c->tables_h.nql * c->tables_h.nql;
+}
+
 void set_loads(dpg_ctx *c, const dpg_load *loads, int nrhs) {
   c->nrhs = nrhs;
   c->ld_h.assign(nrhs, LoadDesc{});
   c->src_h.clear();
+  std::vector<double2> u0;
+  const int64_t nbp = boundary_points(c);
   for (int r = 0; r < nrhs; ++r) {
     LoadDesc &d = c->ld_h[r];
+    d.u0_off = -1;
+    if (loads[r].u0_qp) {
+      d.u0_off = (int64_t)u0.size();
+      for (int64_t k = 0; k < nbp; ++k) {
+        const double2 v = mk(loads[r].u0_qp[2 * k], loads[r].u0_qp[2 * k + 1]);
+        if (!std::isfinite(v.x) || !std::isfinite(v.y))
+          throw DpgError(DPG_EINVAL, "impedance data at the boundary points is not finite");
+        u0.push_back(v);
+      }
+    }
     for (int k = 0; k < 3; ++k) d.dir[k] = loads[r].dir[k];
     d.amp[0] = loads[r].amp[0];
     d.amp[1] = loads[r].amp[1];
@@ -94,6 +111,8 @@ void set_loads(dpg_ctx *c, const dpg_load *loads, int nrhs) {
       if (!(loads[r].src[6 * k + 3] > 0.0)) throw DpgError(DPG_EINVAL, "source width must be > 0");
   }
   c->ld.upload(c->ld_h, &c->bud, c->stream);
+  if (u0.empty()) c->u0q.release();
+  else c->u0q.upload(u0, &c->bud, c->stream);
   if (c->src_h.empty()) c->src_h.push_back(0.0);
   c->src.upload(c->src_h, &c->bud, c->stream);
   HIP_OK(hipStreamSynchronize(c->stream));
@@ -121,11 +140,17 @@ void stream_wait(hipStream_t a, hipStream_t b, hipEvent_t ev) {
 
 // ---- element stage -----------------------------------------------------------------
 
-void plan_elements(dpg_ctx *c) {
+// Grow-only device buffer: reallocated only when more room is needed, so
+// that plans for meshes of different sizes share the largest allocation.
+template <typename T> void grow(DevBuf<T> &b, int64_t n, Budget *bd) {
+  if (b.n < n) b.alloc(n, bd);
+}
+
+// Element-stage plan for nel elements with nr load columns.
+void plan_elements(dpg_ctx *c, int nel, int nr) {
   ElemPlan &P = c->ep;
-  const int nt = c->n_test, nf = c->n_field, mp = c->m + c->nrhs;
-  if (P.mp == mp) return;
-  const int nel = c->lv[c->L].nel;
+  const int nt = c->n_test, nf = c->n_field, mp = c->m + nr;
+  if (P.mp == mp && P.nel == nel) return;
   const int64_t per = 16LL * ((int64_t)nt * nt + (int64_t)nt * mp + (int64_t)mp * mp);
   // a multiple of NS about equal chunks, so that every stream gets the same
   // work; element stage at 16^3 / p = 3 over two streams 38.4 ms, three 37.8,
@@ -137,10 +162,10 @@ void plan_elements(dpg_ctx *c) {
   P.ns = NS;
   Budget *bd = &c->bud;
   for (int k = 0; k < NS; ++k) {
-    P.G[k].ensure((int64_t)C * nt * nt, bd);
-    P.BL[k].ensure((int64_t)C * nt * mp, bd);
-    P.K[k].ensure((int64_t)C * mp * mp, bd);
-    P.wk[k].ensure(dense_work_size(C, nt), bd);
+    grow(P.G[k], (int64_t)C * nt * nt, bd);
+    grow(P.BL[k], (int64_t)C * nt * mp, bd);
+    grow(P.K[k], (int64_t)C * mp * mp, bd);
+    grow(P.wk[k], dense_work_size(C, nt), bd);
   }
   std::vector<PotrfItem> pG(C), pK(C);
   std::vector<TrsmItem> tG(C), tK(C);
@@ -161,22 +186,56 @@ void plan_elements(dpg_ctx *c) {
   P.tK.upload(tK, bd, c->stream);
   P.gK.upload(gK, bd, c->stream);
   P.gS.upload(gS, bd, c->stream);
-  P.info.ensure(2LL * nel, bd);
+  grow(P.info, 2LL * nel, bd);
   HIP_OK(hipStreamSynchronize(c->stream));
   P.C = C;
   P.mp = mp;
+  P.nel = nel;
 }
+
+// Error-indicator pass of the element stage: trace solutions x (nr <= the
+// context's loads columns of n_trace entries, device) and the output
+// eta2 [nr][nel] (device).
+struct IndicatorArgs {
+  const double2 *x;
+  int nr;
+  double *eta2;
+};
 
 // Per element (Sec. 1.2): Gram matrix G and [B | l]; G = L L^H;
 // W = L^-1 [B | l]; K = W^H W; static condensation of the field block of K.
-// Chunks of elements are dealt round-robin to four streams.
-void element_stage(dpg_ctx *c, bool write_matrices) {
-  plan_elements(c);
+// Chunks of elements are dealt round-robin to four streams.  Level L (the
+// finest mesh) with the context's loads; a coarser level l < L (the "store"
+// coarse operators) with no loads, writing only its element matrices.
+// With ind (finest level only), the pass computes the DPG residual error
+// indicator instead of condensing: after K_ff = L_f L_f^H and
+// Y = L_f^-1 [K_ft | b], the unknowns [x_f; x_t] of every element
+// (x_f = L_f^-H (Y_b - Y_t x_t)), the residual W_l - W_B [x_f; x_t] =
+// L^-1 (l - B [x_f; x_t]), and eta^2 = its squared norm = r^H G^-1 r.
+void element_stage(dpg_ctx *c, int l, bool write_matrices, const IndicatorArgs *ind = nullptr) {
+  const bool fine = l == c->L;
+  LevelData &f = c->lv[l];
+  const int nr = fine ? c->nrhs : 0;
+  plan_elements(c, f.nel, nr);
   ElemPlan &P = c->ep;
-  LevelData &f = c->lv[c->L];
-  const int nt = c->n_test, nf = c->n_field, ntr = c->n_tr, m = c->m, nr = c->nrhs;
+  const int nt = c->n_test, nf = c->n_field, ntr = c->n_tr, m = c->m;
   const int mp = m + nr, C = P.C, nel = f.nel;
-  ElemGeom g{c->N, c->side / c->N, c->omega, 1.0, {c->org[0], c->org[1], c->org[2]}};
+  if (ind) {
+    if (!fine || ind->nr < 1 || ind->nr > nr) throw DpgError(DPG_EINVAL, "bad indicator columns");
+    for (int k = 0; k < P.ns; ++k) grow(P.X[k], (int64_t)C * m * ind->nr, &c->bud);
+    if (P.gR_nr != ind->nr || P.gR_C != C) {
+      std::vector<GemmItem> gR(C);
+      for (int i = 0; i < C; ++i)
+        gR[i] = {(int64_t)i * nt * mp, (int64_t)i * m * ind->nr, (int64_t)i * nt * mp + (int64_t)m * nt,
+                 nt, ind->nr, m, nt, m, nt};
+      P.gR.upload(gR, &c->bud, c->stream);
+      HIP_OK(hipStreamSynchronize(c->stream));
+      P.gR_nr = ind->nr;
+      P.gR_C = C;
+    }
+  }
+  const double *kap = fine ? c->kappa.p : f.kappa.p, *Zel = fine ? c->Zel.p : f.Zel.p;
+  ElemGeom g{f.N, c->side / f.N, c->omega, 1.0, {c->org[0], c->org[1], c->org[2]}};
   const int NS = P.ns;
   const hipStream_t xs[4] = {c->stream, c->aux, c->paux[0], c->paux[1]};
   const hipEvent_t xj[4] = {nullptr, c->ev_join, c->ev_pjoin[0], c->ev_pjoin[1]};
@@ -187,16 +246,16 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
     double2 *G = P.G[u].p, *BL = P.BL[u].p, *K = P.K[u].p, *wk = P.wk[u].p;
     {
       ProfScope ps(&c->prof, DPG_K_GRAM, 0, s);
-      launch_gram(c->tables.p, c->testd.p, nt, g, c->kappa.p, e0, cnt, G, s);
+      launch_gram(c->tables.p, c->testd.p, nt, g, kap, e0, cnt, G, s);
     }
     {
       ProfScope ps(&c->prof, DPG_K_BMAT, 0, s);
-      launch_bmat(c->tables.p, c->testd.p, c->triald.p, nt, m, g, c->kappa.p, c->Zel.p, e0, cnt,
+      launch_bmat(c->tables.p, c->testd.p, c->triald.p, nt, m, g, kap, Zel, e0, cnt,
                   BL, (int64_t)nt * mp, s);
     }
-    {
+    if (nr > 0) {
       ProfScope ps(&c->prof, DPG_K_LOAD, 0, s);
-      launch_load(c->tables.p, nt, m, g, c->Zel.p, c->ld.p, c->src.p, nr, e0, cnt, BL,
+      launch_load(c->tables.p, nt, m, g, Zel, c->ld.p, c->src.p, c->u0q.p, nr, e0, cnt, BL,
                   (int64_t)nt * mp, s);
     }
     {
@@ -219,6 +278,22 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
       ProfScope ps(&c->prof, DPG_K_TRSM, cnt * f_trsm(nf, mp - nf), s);
       trsm_batched(K, K, P.tK.p, cnt, nf, mp - nf, false, wk, true, s);
     }
+    if (ind) {
+      const int q = ind->nr;
+      const int64_t nT = f.num.n;
+      {
+        ProfScope ps(&c->prof, DPG_K_OTHER, 0, s);
+        launch_indicator_x(K, (int64_t)mp * mp, mp, nf, ntr, q, f.edofs.p + (int64_t)e0 * ntr, cnt,
+                           ind->x, nT, P.X[u].p, s);
+      }
+      {
+        ProfScope ps(&c->prof, DPG_K_GEMM, cnt * f_gemm(nt, q, m), s);
+        gemm_batched(OP_N, OP_N, mk(-1, 0), BL, P.X[u].p, mk(1, 0), BL, P.gR.p, cnt, nt, q, s);
+      }
+      ProfScope ps(&c->prof, DPG_K_OTHER, 0, s);
+      launch_colnorm2(BL, (int64_t)nt * mp, nt, nt, m, q, e0, cnt, nel, ind->eta2, s);
+      continue;
+    }
     {
       ProfScope ps(&c->prof, DPG_K_GEMM, cnt * f_herk(mp - nf, nf), s);
       gemm_batched(OP_C, OP_N, mk(-1, 0), K, K, mk(1, 0), K, P.gS.p, cnt, mp - nf, mp - nf, s,
@@ -230,7 +305,7 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
     for (int r = 0; r < nr; ++r)
       launch_copy_sub(K, (int64_t)mp * mp, mp, nf, m + r, ntr, 1,
                       c->s_elem.p + ((int64_t)r * nel + e0) * ntr, ntr, ntr, cnt, s);
-    if (c->keep_recovery) {
+    if (fine && c->keep_recovery) {
       launch_copy_sub(K, (int64_t)mp * mp, mp, 0, 0, nf, nf, c->rec_L.p + (int64_t)e0 * nf * nf,
                       (int64_t)nf * nf, nf, cnt, s);
       launch_copy_sub(K, (int64_t)mp * mp, mp, 0, nf, nf, mp - nf,
@@ -239,6 +314,11 @@ void element_stage(dpg_ctx *c, bool write_matrices) {
     }
   }
   for (int k = 1; k < NS; ++k) stream_wait(xs[k], c->stream, xj[k]);
+  if (!fine || ind) {
+    check_infos(P.info.p, nel, c->stream, "coarse-mesh element Gram matrix");
+    check_infos(P.info.p + nel, nel, c->stream, "coarse-mesh element field block");
+    return;
+  }
   // assembled loads
   for (int r = 0; r < nr; ++r)
     launch_assemble_vec(f.num.n, c->asm_ptr.p, c->asm_ent.p, c->s_elem.p + (int64_t)r * nel * ntr,
@@ -339,7 +419,8 @@ void plan_macro(dpg_ctx *c, int l) {
   P.ready = true;
 }
 
-// Macro condensation of level l (Sec. 3) and the Galerkin element matrices of
+// Macro condensation of level l (Sec. 3) and, unless the coarse operators are
+// stored (assembled on their own meshes), the Galerkin element matrices of
 // level l - 1.  Chunks of coarse elements alternate between the two streams
 // (each with its own workspaces); on return the main stream has everything.
 void build_macro_level(dpg_ctx *c, int l) {
@@ -392,7 +473,7 @@ void build_macro_level(dpg_ctx *c, int l) {
       launch_copy_sub(T, (int64_t)nT * nT, nT, 0, 0, nBf, nBf, f.Mfull.p + (int64_t)b0 * nBf * nBf,
                       (int64_t)nBf * nBf, nBf, cnt, s);
     }
-    {
+    if (!(c->opt.flags & DPG_STORE_COARSE)) {
       ProfScope ps(&c->prof, DPG_K_GEMM, cnt * (f_gemm(nBf, ntr, nBf) + f_gemm(ntr, ntr, nBf)), s);
       gemm_batched(OP_N, OP_N, mk(1, 0), T, P.Ploc.p, mk(0, 0), X, P.gX.p, cnt, nBf, ntr, s);
       gemm_batched(OP_T, OP_N, mk(1, 0), P.Ploc.p, X, mk(0, 0), cl.E.p + (int64_t)b0 * ntr * ntr,
@@ -595,6 +676,8 @@ void build_hierarchy(dpg_ctx *c) {
     plan_patches(c, l);
   }
   plan_coarsest(c);
+  if (c->opt.flags & DPG_STORE_COARSE)   // coarse operators assembled on their own meshes
+    for (int l = c->L - 1; l >= 0; --l) element_stage(c, l, true);
   if ((int)c->ev_level.size() < c->L + 1) {
     for (int l = (int)c->ev_level.size(); l <= c->L; ++l) {
       hipEvent_t e;
@@ -1248,6 +1331,34 @@ int dpg_setup(const dpg_mesh *mesh, int p, int dp, double omega, const dpg_mater
       }
       if (!mixed || l == c->L) f.c64.alloc((int64_t)f.nblk * f.nBf, &c->bud);
     }
+    if (c->opt.flags & DPG_STORE_COARSE) {
+      // "store" coarse operators (Sec. 3, alternative construction): each
+      // coarser mesh gets its own element material, which must be uniform
+      // over the fine elements a coarse element covers
+      for (int l = 0; l < c->L; ++l) {
+        LevelData &f = c->lv[l];
+        const int r = c->N / f.N;
+        std::vector<double> kl(f.nel), zl(f.nel);
+        for (int e = 0; e < f.nel; ++e) {
+          const int i = e % f.N, j = (e / f.N) % f.N, k = e / (f.N * f.N);
+          const double c0 = c->c_h[(int64_t)i * r + (int64_t)c->N * (j * r + (int64_t)c->N * k * r)];
+          for (int a = 0; a < r; ++a)
+            for (int b = 0; b < r; ++b)
+              for (int d = 0; d < r; ++d) {
+                const int64_t fe = (int64_t)(i * r + a) +
+                                   (int64_t)c->N * ((j * r + b) + (int64_t)c->N * (k * r + d));
+                if (c->c_h[fe] != c0)
+                  throw DpgError(DPG_EINVAL,
+                                 "stored coarse operators need a wave speed that is constant on "
+                                 "every element of every coarser mesh");
+              }
+          kl[e] = 1.0 / (c0 * c0);
+          zl[e] = c0;
+        }
+        f.kappa.upload(kl, &c->bud, s);
+        f.Zel.upload(zl, &c->bud, s);
+      }
+    }
     {
       const int64_t n0 = c->lv[0].num.n;
       std::vector<int32_t> sz{(int32_t)n0}, id(n0);
@@ -1310,7 +1421,7 @@ int dpg_assemble(dpg_ctx *c) {
       c->rec_L.ensure((int64_t)top.nel * c->n_field * c->n_field, &c->bud);
       c->rec_Y.ensure((int64_t)top.nel * c->n_field * (c->n_tr + c->nrhs), &c->bud);
     }
-    element_stage(c, true);
+    element_stage(c, c->L, true);
     c->prof.flush();
     c->ms[1] = ms_since(t0);
     c->stage = 2;
@@ -1378,7 +1489,7 @@ int dpg_load_rhs(dpg_ctx *c, const dpg_load *loads, int nrhs, double *s_out) {
       c->rec_L.ensure((int64_t)top.nel * c->n_field * c->n_field, &c->bud);
       c->rec_Y.ensure((int64_t)top.nel * c->n_field * (c->n_tr + c->nrhs), &c->bud);
     }
-    element_stage(c, false);
+    element_stage(c, c->L, false);
     c->prof.flush();
     if (s_out) {
       const bool dev = c->opt.flags & DPG_DEVICE_PTRS;
@@ -1486,6 +1597,68 @@ int dpg_get_fields(dpg_ctx *c, const double *x, int nrhs, double *fields_out) {
     }
     return DPG_OK;
   });
+}
+
+int dpg_error_indicator(dpg_ctx *c, const double *x, int nrhs, double *eta2_out) {
+  if (!c) return DPG_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (c->stage < 2) throw DpgError(DPG_ESTATE, "dpg_assemble first");
+    if (!x || !eta2_out || nrhs < 1 || nrhs > c->nrhs)
+      throw DpgError(DPG_EINVAL, "need x and eta2_out, 1 <= nrhs <= assembled loads");
+    LevelData &top = c->lv[c->L];
+    const int64_t nT = top.num.n, nel = top.nel;
+    const bool dev = c->opt.flags & DPG_DEVICE_PTRS;
+    DevBuf<double2> xs;
+    DevBuf<double> eta;
+    const double2 *xd = reinterpret_cast<const double2 *>(x);
+    double *ed = eta2_out;
+    if (!dev) {
+      xs.alloc(nT * nrhs, &c->bud);
+      HIP_OK(hipMemcpyAsync(xs.p, x, (size_t)nT * nrhs * 16, hipMemcpyHostToDevice, c->stream));
+      eta.alloc(nel * nrhs, &c->bud);
+      xd = xs.p;
+      ed = eta.p;
+    }
+    IndicatorArgs ia{xd, nrhs, ed};
+    element_stage(c, c->L, false, &ia);
+    if (!dev)
+      HIP_OK(hipMemcpyAsync(eta2_out, eta.p, (size_t)nel * nrhs * 8, hipMemcpyDeviceToHost,
+                            c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->prof.flush();
+    return DPG_OK;
+  });
+}
+
+int64_t dpg_boundary_points(const dpg_ctx *cc, double *xyz, int64_t cap) {
+  dpg_ctx *c = const_cast<dpg_ctx *>(cc);
+  if (!c) return DPG_EINVAL;
+  if (c->stage < 1) return DPG_ESTATE;
+  int64_t rc = 0;
+  const int st = guarded(c, [&]() -> int {
+    const int N = c->N, nq = c->tables_h.nql;
+    const double h = c->side / N;
+    rc = boundary_points(c);
+    if (!xyz || cap <= 0) return DPG_OK;
+    int64_t k = 0;
+    for (int d = 0; d < 3; ++d)
+      for (int s = 0; s < 2; ++s) {
+        const int f1 = d == 0 ? 1 : 0, f2 = d == 2 ? 1 : 2;
+        for (int c2 = 0; c2 < N; ++c2)
+          for (int c1 = 0; c1 < N; ++c1)
+            for (int p2 = 0; p2 < nq; ++p2)
+              for (int p1 = 0; p1 < nq; ++p1, ++k) {
+                if (k >= cap) return DPG_OK;
+                double X[3];
+                X[d] = c->org[d] + (s ? c->side : 0.0);
+                X[f1] = c->org[f1] + h * c1 + (c->tables_h.xq[p1] + 1.0) * 0.5 * h;
+                X[f2] = c->org[f2] + h * c2 + (c->tables_h.xq[p2] + 1.0) * 0.5 * h;
+                for (int a = 0; a < 3; ++a) xyz[3 * k + a] = X[a];
+              }
+      }
+    return DPG_OK;
+  });
+  return st == DPG_OK ? rc : st;
 }
 
 int dpg_info(const dpg_ctx *c, dpg_info_t *info) {

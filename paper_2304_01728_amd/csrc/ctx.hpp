@@ -21,12 +21,17 @@ namespace dpg {
 // Element stage: chunks of C elements are dealt to ns streams, each with its
 // own G, [B l], K and diagonal-block-inverse buffers.
 struct ElemPlan {
-  int C = 0, mp = -1, ns = 2;
+  int C = 0, mp = -1, nel = -1, ns = 2;
   DevBuf<double2> G[4], BL[4], K[4], wk[4];   // one set per stream
   DevBuf<PotrfItem> pG, pK;
   DevBuf<TrsmItem> tG, tK;
   DevBuf<GemmItem> gK, gS;
   DevBuf<int> info;    // [2 nel]: Gram factor, then field block, per element
+  // error-indicator pass: per-stream element unknowns [C][nr][m] and the
+  // residual products' items (for gR_nr columns, chunks of gR_C)
+  DevBuf<double2> X[4];
+  DevBuf<GemmItem> gR;
+  int gR_nr = 0, gR_C = 0;
 };
 
 // Macro condensation and Galerkin step of one level (workspaces shared by
@@ -72,6 +77,8 @@ struct LevelData {
   std::vector<int32_t> edofs_h;
   DevBuf<int32_t> edofs;
   DevBuf<double2> E;                 // element matrices [nel][n_tr^2]
+  DevBuf<double> kappa, Zel;         // per element c^-2 and Z on a coarser mesh whose
+                                     // operator is assembled directly ("store")
   // macro grid (levels >= 1)
   bool macro = false;
   MacroLevel mc;
@@ -133,6 +140,7 @@ struct dpg_ctx {
   std::vector<double> src_h;
   dpg::DevBuf<dpg::LoadDesc> ld;
   dpg::DevBuf<double> src;
+  dpg::DevBuf<double2> u0q;          // impedance data at the boundary load points, all loads
   std::vector<dpg::LevelData> lv;
   int L = 0;
   bool keep_recovery = false;

@@ -218,7 +218,8 @@ constexpr int LX = 8, LQ = 12;
 __global__ __launch_bounds__(256) void k_load(const ElemTables *__restrict__ tb, int nt, int m,
                                               ElemGeom g, const double *__restrict__ Zel,
                                               const LoadDesc *__restrict__ ld,
-                                              const double *__restrict__ src, int e0,
+                                              const double *__restrict__ src,
+                                              const double2 *__restrict__ u0q, int e0,
                                               double2 *__restrict__ BL, int64_t strideBL) {
   __shared__ double2 buf1[LQ * LQ * LQ];   // point values, then second contraction
   __shared__ double2 buf2[LX * LQ * LQ];   // first contraction
@@ -278,7 +279,8 @@ __global__ __launch_bounds__(256) void k_load(const ElemTables *__restrict__ tb,
     }
     __syncthreads();
   }
-  if (L.amp[0] != 0.0 || L.amp[1] != 0.0) {
+  const bool pw = L.amp[0] != 0.0 || L.amp[1] != 0.0;
+  if (pw || L.u0_off >= 0) {
     const double Z = Zel ? Zel[e] : 1.0;
     for (int d = 0; d < 3; ++d)
       for (int s = 0; s < 2; ++s) {
@@ -287,17 +289,26 @@ __global__ __launch_bounds__(256) void k_load(const ElemTables *__restrict__ tb,
         const int f1 = d == 0 ? 1 : 0, f2 = d == 2 ? 1 : 2;
         const double nd = s ? 1.0 : -1.0;          // outward normal = nd e_d
         const double fac = 1.0 / Z - L.dir[d] * nd;
+        const double2 *uq =
+            L.u0_off >= 0
+                ? u0q + L.u0_off + boundary_face(d, s, cell[f1], cell[f2], g.N) * nq * nq
+                : nullptr;
         for (int k = tid; k < nq * nq; k += 256) {
           const int p1 = k % nq, p2 = k / nq;
-          double X[3];
-          X[d] = x0[d] + (s ? g.h : 0.0);
-          X[f1] = x0[f1] + (tb->xq[p1] + 1.0) * hh;
-          X[f2] = x0[f2] + (tb->xq[p2] + 1.0) * hh;
-          const double th = -g.omega * (L.dir[0] * X[0] + L.dir[1] * X[1] + L.dir[2] * X[2]);
-          double sn, cs;
-          sincos(th, &sn, &cs);
-          const double wt = fac * tb->wq[p1] * tb->wq[p2];
-          buf1[k] = mk(wt * (L.amp[0] * cs - L.amp[1] * sn), wt * (L.amp[0] * sn + L.amp[1] * cs));
+          double2 u = mk(0.0, 0.0);
+          if (pw) {   // plane wave: u0 = (Z^-1 - d.n) A exp(-i w d.x)
+            double X[3];
+            X[d] = x0[d] + (s ? g.h : 0.0);
+            X[f1] = x0[f1] + (tb->xq[p1] + 1.0) * hh;
+            X[f2] = x0[f2] + (tb->xq[p2] + 1.0) * hh;
+            const double th = -g.omega * (L.dir[0] * X[0] + L.dir[1] * X[1] + L.dir[2] * X[2]);
+            double sn, cs;
+            sincos(th, &sn, &cs);
+            u = mk(fac * (L.amp[0] * cs - L.amp[1] * sn), fac * (L.amp[0] * sn + L.amp[1] * cs));
+          }
+          if (uq) u = cadd(u, uq[k]);
+          const double wt = tb->wq[p1] * tb->wq[p2];
+          buf1[k] = mk(wt * u.x, wt * u.y);
         }
         __syncthreads();
         // C1[a1][p2] = sum_p1 Lq[a1][p1] F[p2][p1]
@@ -340,11 +351,11 @@ void launch_bmat(const ElemTables *tb, const int4 *test, const int4 *trial, int 
 }
 
 void launch_load(const ElemTables *tb, int nt, int m, ElemGeom g, const double *Zel,
-                 const LoadDesc *ld, const double *src, int nrhs, int e0, int count, double2 *BL,
-                 int64_t strideBL, hipStream_t s) {
+                 const LoadDesc *ld, const double *src, const double2 *u0q, int nrhs, int e0,
+                 int count, double2 *BL, int64_t strideBL, hipStream_t s) {
   if (nrhs <= 0) return;
-  hipLaunchKernelGGL(k_load, dim3(count, nrhs), dim3(256), 0, s, tb, nt, m, g, Zel, ld, src, e0,
-                     BL, strideBL);
+  hipLaunchKernelGGL(k_load, dim3(count, nrhs), dim3(256), 0, s, tb, nt, m, g, Zel, ld, src, u0q,
+                     e0, BL, strideBL);
   LAUNCH_OK();
 }
 

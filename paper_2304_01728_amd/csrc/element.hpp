@@ -34,7 +34,17 @@ struct LoadDesc {
   double dir[3];
   double amp[2];
   int src0, nsrc;         // sources src[6*src0 ...]
+  int64_t u0_off;         // impedance data at the boundary load points: u0q[u0_off ...]
+                          // (canonical boundary point order), -1 = none
 };
+
+// Boundary load points of an N^3 mesh: faces of Gamma in the order axis d,
+// side s (low, high), cell coordinates (c1, c2) along the two other axes in
+// ascending order, c1 fastest; nql x nql Gauss points per face, the first
+// in-plane axis fastest.  Face index ((2 d + s) N + c2) N + c1.
+__host__ __device__ inline int64_t boundary_face(int d, int s, int c1, int c2, int N) {
+  return ((int64_t)(2 * d + s) * N + c2) * N + c1;
+}
 
 struct ElemGeom {
   int N;
@@ -57,8 +67,10 @@ void launch_bmat(const ElemTables *tb, const int4 *test, const int4 *trial, int 
                  ElemGeom g, const double *kappa, const double *Zel, int e0, int count,
                  double2 *BL, int64_t strideBL, hipStream_t s);
 // load columns m .. m+nrhs-1 of BL[e].
+// u0q: impedance data at the boundary load points (complex, indexed by the
+// loads' u0_off), may be null when no load uses it.
 void launch_load(const ElemTables *tb, int nt, int m, ElemGeom g, const double *Zel,
-                 const LoadDesc *ld, const double *src, int nrhs, int e0, int count, double2 *BL,
-                 int64_t strideBL, hipStream_t s);
+                 const LoadDesc *ld, const double *src, const double2 *u0q, int nrhs, int e0,
+                 int count, double2 *BL, int64_t strideBL, hipStream_t s);
 
 }  // namespace dpg

@@ -319,6 +319,64 @@ __global__ __launch_bounds__(256) void k_fields(const double2 *__restrict__ recL
   for (int i = threadIdx.x; i < nf; i += 256) out[(int64_t)e * nf + i] = v[i];
 }
 
+// Error indicator, step 1: the unknowns [x_f; x_t] of element e0 + blockIdx.x
+// for load column blockIdx.y.  K holds, per element (stride ks, leading
+// dimension ld), the factor L of K_ff in its first nf columns and
+// Y = L^-1 [K_ft | b] in the columns after: x_f = L^-H (Y_b - Y_t x_t).
+// X[i] is m x nr (leading dimension m = nf + ntr), x_t gathered from x
+// (column r at x + r nvec) through the element map (-1: absent, zero).
+__global__ __launch_bounds__(256) void k_indicator_x(const double2 *__restrict__ K, int64_t ks,
+                                                     int ld, int nf, int ntr, int nr,
+                                                     const int32_t *__restrict__ edofs,
+                                                     const double2 *__restrict__ x, int64_t nvec,
+                                                     double2 *__restrict__ X) {
+  __shared__ double2 v[kMaxI];
+  __shared__ double2 xt[kMaxB];
+  const int e = blockIdx.x, r = blockIdx.y, m = nf + ntr;
+  const double2 *xr = x + (int64_t)r * nvec;
+  double2 *Xe = X + ((int64_t)e * nr + r) * m;
+  for (int j = threadIdx.x; j < ntr; j += 256) {
+    const int32_t t = edofs[(int64_t)e * ntr + j];
+    xt[j] = t >= 0 ? xr[t] : mk(0.0, 0.0);
+    Xe[nf + j] = xt[j];
+  }
+  __syncthreads();
+  const double2 *Ke = K + (int64_t)e * ks;
+  for (int i = threadIdx.x; i < nf; i += 256) {
+    double2 acc = Ke[i + (int64_t)(m + r) * ld];
+    for (int j = 0; j < ntr; ++j) acc = csub(acc, cmul(Ke[i + (int64_t)(nf + j) * ld], xt[j]));
+    v[i] = acc;
+  }
+  __syncthreads();
+  for (int i = nf - 1; i >= 0; --i) {   // L^H u = v from the last unknown
+    if (threadIdx.x == 0) v[i] = cscale(v[i], 1.0 / Ke[i + (int64_t)i * ld].x);
+    __syncthreads();
+    for (int k = threadIdx.x; k < i; k += 256)
+      v[k] = csub(v[k], cmul(cconj(Ke[i + (int64_t)k * ld]), v[i]));
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < nf; i += 256) Xe[i] = v[i];
+}
+
+// Error indicator, step 3: out[r * nel_out + e0 + e] = || W[e](:, c0 + r) ||^2
+// over n rows (W per element at stride ws, leading dimension ld).
+__global__ __launch_bounds__(256) void k_colnorm2(const double2 *__restrict__ W, int64_t ws,
+                                                  int ld, int n, int c0, int e0, int64_t nel_out,
+                                                  double *__restrict__ out) {
+  __shared__ double red[256];
+  const int e = blockIdx.x, r = blockIdx.y;
+  const double2 *w = W + (int64_t)e * ws + (int64_t)(c0 + r) * ld;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += w[i].x * w[i].x + w[i].y * w[i].y;
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[(int64_t)r * nel_out + e0 + e] = red[0];
+}
+
 template <typename C> __global__ void k_zero(int64_t n, C *a) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) {
@@ -534,6 +592,24 @@ void launch_fields(const double2 *recL, const double2 *recY, int nf, int ntr, in
   if (nf > kMaxI || ntr > kMaxB) throw DpgError(-1, "element too large for field recovery");
   hipLaunchKernelGGL(k_fields, dim3(nel), dim3(256), 0, s, recL, recY, nf, ntr, nrhs, col, edofs,
                      x, out);
+  LAUNCH_OK();
+}
+
+void launch_indicator_x(const double2 *K, int64_t ks, int ld, int nf, int ntr, int nr,
+                        const int32_t *edofs, int count, const double2 *x, int64_t nvec,
+                        double2 *X, hipStream_t s) {
+  if (nf > kMaxI || ntr > kMaxB) throw DpgError(-1, "element too large for the error indicator");
+  if (count <= 0 || nr <= 0) return;
+  hipLaunchKernelGGL(k_indicator_x, dim3(count, nr), dim3(256), 0, s, K, ks, ld, nf, ntr, nr,
+                     edofs, x, nvec, X);
+  LAUNCH_OK();
+}
+
+void launch_colnorm2(const double2 *W, int64_t ws, int ld, int n, int c0, int ncols, int e0,
+                     int count, int64_t nel_out, double *out, hipStream_t s) {
+  if (count <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL(k_colnorm2, dim3(count, ncols), dim3(256), 0, s, W, ws, ld, n, c0, e0,
+                     nel_out, out);
   LAUNCH_OK();
 }
 

@@ -69,6 +69,19 @@ void launch_assemble_vec(int64_t n, const int32_t *ptr, const int32_t *ent, cons
 void launch_fields(const double2 *recL, const double2 *recY, int nf, int ntr, int nrhs, int col,
                    const int32_t *edofs, int nel, const double2 *x, double2 *out, hipStream_t s);
 
+// DPG residual error indicator (Sec. 1.2): per element and load column r,
+// X(:, r) = [x_f; x_t] with x_t gathered from x + r nvec through edofs and
+// x_f = L^-H (Y_b - Y_t x_t), where K (stride ks, leading dimension ld) holds
+// L = chol(K_ff) in its first nf columns and Y = L^-1 [K_ft | b] after them.
+// X: [count][nr][m], m = nf + ntr.
+void launch_indicator_x(const double2 *K, int64_t ks, int ld, int nf, int ntr, int nr,
+                        const int32_t *edofs, int count, const double2 *x, int64_t nvec,
+                        double2 *X, hipStream_t s);
+// out[r nel_out + e0 + e] = sum_i |W[e](i, c0 + r)|^2, i < n, for e < count,
+// r < ncols (W per element at stride ws, leading dimension ld).
+void launch_colnorm2(const double2 *W, int64_t ws, int ld, int n, int c0, int ncols, int e0,
+                     int count, int64_t nel_out, double *out, hipStream_t s);
+
 // a[0..n) = 0 (a kernel, not a memset: safe inside captured graphs).
 template <typename C> void launch_zero(int64_t n, C *a, hipStream_t s);
 

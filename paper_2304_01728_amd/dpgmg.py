@@ -17,6 +17,7 @@ DPG_OK, DPG_EINVAL, DPG_ENOMEM, DPG_ENOTPD, DPG_ENOCONV, DPG_EBREAKDOWN, DPG_EST
 DPG_FP64, DPG_MIXED = 0, 1
 DPG_DEVICE_PTRS = 1
 DPG_COLUMNWISE = 2
+DPG_STORE_COARSE = 4
 (X_ELEM_DOFS, X_MACRO_B, X_BLOCK_B, X_BLOCK_I, X_PATCHES, X_PROLONG, X_ELEM_S, X_ELEM_RHS,
  X_MACRO_M, X_COARSE_E, X_PATCH_INV, X_COARSEST, X_PROLONG_VAL, X_ASM_RHS) = range(1, 15)
 
@@ -26,7 +27,8 @@ _DOUBLE_EXPORTS = {X_PROLONG_VAL}
 SYMBOLS = ["dpg_default_options", "dpg_setup", "dpg_assemble", "dpg_build_hierarchy",
            "dpg_load_rhs", "dpg_solve", "dpg_get_fields", "dpg_info", "dpg_export",
            "dpg_profile", "dpg_kernel_stats", "dpg_last_error", "dpg_destroy",
-           "dpg_release_setup", "dpg_solve_noalloc"]
+           "dpg_release_setup", "dpg_solve_noalloc", "dpg_error_indicator",
+           "dpg_boundary_points"]
 
 
 class dpg_mesh(C.Structure):
@@ -39,7 +41,7 @@ class dpg_material(C.Structure):
 
 class dpg_load(C.Structure):
     _fields_ = [("dir", C.c_double * 3), ("amp", C.c_double * 2), ("nsrc", C.c_int32),
-                ("src", C.POINTER(C.c_double))]
+                ("src", C.POINTER(C.c_double)), ("u0_qp", C.POINTER(C.c_double))]
 
 
 class dpg_options(C.Structure):
@@ -104,10 +106,14 @@ def lib():
             getattr(L, name).restype = C.c_int
         L.dpg_get_fields.argtypes = [vp, vp, C.c_int, vp]
         L.dpg_get_fields.restype = C.c_int
+        L.dpg_error_indicator.argtypes = [vp, vp, C.c_int, vp]
+        L.dpg_error_indicator.restype = C.c_int
         L.dpg_info.argtypes = [vp, C.POINTER(dpg_info_t)]
         L.dpg_info.restype = C.c_int
         L.dpg_export.argtypes = [vp, C.c_int, C.c_int, vp, C.c_int64]
         L.dpg_export.restype = C.c_int64
+        L.dpg_boundary_points.argtypes = [vp, vp, C.c_int64]
+        L.dpg_boundary_points.restype = C.c_int64
         L.dpg_profile.argtypes = [vp, C.c_int]
         L.dpg_profile.restype = C.c_int
         L.dpg_kernel_stats.argtypes = [vp, C.c_int, C.POINTER(dpg_kstat)]
@@ -136,7 +142,8 @@ def dpg_default_options(**kw):
 
 
 def _loads(loads):
-    """list of dicts {dir, amp, sources: [[x,y,z,sigma,re,im], ...]} -> ctypes array."""
+    """list of dicts {dir, amp, sources: [[x,y,z,sigma,re,im], ...], u0_qp: complex
+    values at dpg_boundary_points} -> ctypes array."""
     arr = (dpg_load * max(1, len(loads)))()
     keep = []
     for i, ld in enumerate(loads):
@@ -148,6 +155,10 @@ def _loads(loads):
         if src.size:
             keep.append(src)
             arr[i].src = src.ctypes.data_as(C.POINTER(C.c_double))
+        if ld.get("u0_qp") is not None:
+            u0 = np.ascontiguousarray(np.asarray(ld["u0_qp"], dtype=np.complex128))
+            keep.append(u0)
+            arr[i].u0_qp = u0.ctypes.data_as(C.POINTER(C.c_double))
     return arr, keep
 
 
@@ -276,6 +287,34 @@ def dpg_get_fields(ctx, x):
     nel = info.level_n[0] ** 3
     out = np.zeros((x.shape[0], nel, info.n_field), dtype=np.complex128)
     _check(ctx.h, lib().dpg_get_fields(ctx.h, x.ctypes.data, x.shape[0], out.ctypes.data))
+    return out
+
+
+def dpg_error_indicator(ctx, x):
+    """eta_K^2 per element for trace solutions x [nrhs, n_trace] (host):
+    returns [nrhs, n^3]."""
+    if ctx.flags & DPG_DEVICE_PTRS:
+        raise ValueError("the context takes device pointers; this wrapper passes host arrays")
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+    x = x.reshape(-1, x.shape[-1])
+    info = dpg_info(ctx)
+    if x.shape[1] != info.n_trace:
+        raise ValueError(f"x has {x.shape[1]} entries per column, need {info.n_trace}")
+    nel = info.level_n[0] ** 3
+    out = np.zeros((x.shape[0], nel), dtype=np.float64)
+    _check(ctx.h, lib().dpg_error_indicator(ctx.h, x.ctypes.data, x.shape[0], out.ctypes.data))
+    return out
+
+
+def dpg_boundary_points(ctx):
+    """[count, 3] coordinates of the boundary load points (the order u0_qp uses)."""
+    n = lib().dpg_boundary_points(ctx.h, None, 0)
+    if n < 0:
+        _check(ctx.h, int(n))
+    out = np.zeros((n, 3), dtype=np.float64)
+    m = lib().dpg_boundary_points(ctx.h, out.ctypes.data, n)
+    if m < 0:
+        _check(ctx.h, int(m))
     return out
 
 

@@ -338,3 +338,93 @@ def test_full_size_workload_against_stored_oracle_values():
     tol = elem_tol(w.p, w.omega, 1.0 / w.N)
     for e in sample:
         assert rel(Sg[e].T, S[e]) <= tol
+
+
+# ---- DPG residual error indicator (Sec. 1.2) -------------------------------------------------
+
+def test_error_indicator_matches_oracle(two_level):
+    """eta_K^2 of every element for the GPU solution, against the oracle's
+    residual of the same solution.  The residual l - Bx cancels, so the bound
+    is relative to the largest eta_K^2."""
+    c = two_level
+    D = c.D
+    x, _, _, _ = D.dpg_solve(c.ctx, tol=1e-12)
+    eta2 = D.dpg_error_indicator(c.ctx, x)
+    ref = dpg.error_indicator(c.pr, x[0][:, None], c.rec)[:, 0]
+    assert np.abs(eta2[0] - ref).max() <= 1e-9 * ref.max()
+
+
+def test_error_indicator_several_loads_and_falls_with_h():
+    D = _D()
+    N, p, omega = 4, 2, 3 * np.pi
+    cen = workloads.source_centres(3, 2)
+    loads = [dict(dir=(0, 0, 1), amp=0.0, sources=[[*c0, 0.08, 1.0, 0.5]]) for c0 in cen]
+    ctx = D.dpg_setup(N, p, omega, loads)
+    D.dpg_assemble(ctx)
+    D.dpg_build_hierarchy(ctx)
+    x, _, _, _ = D.dpg_solve(ctx, nrhs=2, tol=1e-12)
+    eta2 = D.dpg_error_indicator(ctx, x)
+    pr = dpg.Problem(N, p, omega, [dict(f=dpg.gaussian_sources([c0], 0.08, [1.0 + 0.5j]))
+                                   for c0 in cen])
+    _, _, rec = pr.condensed()
+    ref = dpg.error_indicator(pr, x.T, rec)
+    for k in range(2):
+        assert np.abs(eta2[k] - ref[:, k]).max() <= 1e-9 * ref[:, k].max()
+    ctx.close()
+    # plane waves: the total falls with h
+    d = workloads.plane_wave_direction(4)
+    tot = []
+    for N in (4, 8):
+        ctx = D.dpg_setup(N, 2, 2 * np.pi, [dict(dir=d, amp=1.0)])
+        D.dpg_assemble(ctx)
+        D.dpg_build_hierarchy(ctx)
+        x, _, _, _ = D.dpg_solve(ctx, tol=1e-10)
+        tot.append(D.dpg_error_indicator(ctx, x).sum())
+        ctx.close()
+    assert tot[1] < 0.25 * tot[0]
+
+
+# ---- impedance data given at the boundary load points (Sec. 2, eq. helmholtz) ---------------
+
+def _boundary_normals(count, N, nq):
+    face = np.arange(count) // (nq * nq)
+    d = face // (2 * N * N)
+    s = (face // (N * N)) % 2
+    n = np.zeros((count, 3))
+    n[np.arange(count), d] = np.where(s == 1, 1.0, -1.0)
+    return n
+
+
+def test_impedance_data_at_boundary_points():
+    D = _D()
+    N, p, omega = 4, 2, 2 * np.pi
+    dvec = workloads.plane_wave_direction(0)
+    ctx0 = D.dpg_setup(N, p, omega, [dict(dir=dvec, amp=1.0)])
+    X = D.dpg_boundary_points(ctx0)
+    nq = p + 1 + 5
+    assert X.shape == (6 * N * N * nq * nq, 3)
+    nrm = _boundary_normals(X.shape[0], N, nq)
+    assert np.all(np.abs(np.sum(X * np.abs(nrm), axis=1) - (nrm.sum(axis=1) > 0)) == 0)
+    pw = (1.0 - nrm @ dvec) * np.exp(-1j * omega * (X @ dvec))
+    # the plane wave given point by point equals the built-in plane-wave load
+    ctx1 = D.dpg_setup(N, p, omega, [dict(amp=0.0, u0_qp=pw)])
+    for ctx in (ctx0, ctx1):
+        D.dpg_assemble(ctx)
+    s0, s1 = D.dpg_export(ctx0, D.X_ASM_RHS), D.dpg_export(ctx1, D.X_ASM_RHS)
+    assert rel(s1, s0) <= 1e-13
+    # general data (plus half a plane wave, summed) against the oracle
+    g = lambda X, n: (X[:, 0] + 2j * X[:, 1] - X[:, 2] ** 2) * (1.0 + n @ np.array([0.3, 0.5, 0.7]))
+    ctx2 = D.dpg_setup(N, p, omega, [dict(dir=dvec, amp=0.5, u0_qp=g(X, nrm))])
+    D.dpg_assemble(ctx2)
+    D.dpg_build_hierarchy(ctx2)
+    u0pw = dpg.plane_wave_u0(omega, dvec, amp=0.5)
+    pr = dpg.Problem(N, p, omega, [dict(u0=lambda Y, n: g(Y, n[None, :].repeat(len(Y), 0))
+                                        + u0pw(Y, n))])
+    S, s, _ = pr.condensed()
+    rhs = dpg.assemble_vector(pr.edofs, s, pr.num.n)[:, 0]
+    assert rel(D.dpg_export(ctx2, D.X_ASM_RHS), rhs) <= elem_tol(p, omega, 1.0 / N)
+    x, _, _, _ = D.dpg_solve(ctx2, tol=1e-12)
+    xo, _, _ = multigrid.Hierarchy(N, p, S).solve(rhs, 1e-12)
+    assert np.linalg.norm(x[0] - xo) <= 1e-10 * np.linalg.norm(xo)
+    for ctx in (ctx0, ctx1, ctx2):
+        ctx.close()

@@ -10,6 +10,7 @@
 """
 import numpy as np
 import pytest
+import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
@@ -153,3 +154,62 @@ def test_condensed_element_matrices_hermitian_positive_semidefinite():
         ev = np.linalg.eigvalsh(S[e][np.ix_(ok, ok)])
         assert ev.min() > 0
         assert np.all(S[e][~ok] == 0) and np.all(S[e][:, ~ok] == 0)
+
+
+# ---- the DPG residual error indicator (Sec. 1.2; Sec. 3, first paragraph) ----------------------
+
+def test_error_indicator_vanishes_for_reproduced_polynomials():
+    """A solution in the trial space satisfies every element equation exactly,
+    so its residual -- and the indicator of every element -- is zero."""
+    N, p, omega, kappa, Z = 2, 2, 3.0, 0.7, 1.3
+    rng = np.random.default_rng(5)
+    cp = rng.standard_normal((p, p, p)) + 1j * rng.standard_normal((p, p, p))
+    cu = rng.standard_normal((3, p, p, p)) + 1j * rng.standard_normal((3, p, p, p))
+    P = lambda X: _monomial_field(cp, p, X)
+    U = lambda X: np.stack([_monomial_field(cu[d], p, X) for d in range(3)], axis=1)
+    f = lambda X: 1j * omega * kappa * P(X) + sum(_monomial_field(cu[d], p, X, d) for d in range(3))
+    g = lambda X: 1j * omega * U(X) + np.stack([_monomial_field(cp, p, X, d) for d in range(3)], 1)
+    u0 = lambda X, n: P(X) / Z - U(X) @ n
+    pr = dpg.Problem(N, p, omega, [dict(f=f, g=g, u0=u0)], kappa=np.full(8, kappa),
+                     Zel=np.full(8, Z))
+    S, s, rec = pr.condensed()
+    T = dpg.assemble(pr.edofs, S, pr.num.n)
+    x = dpg.direct_solve(T, dpg.assemble_vector(pr.edofs, s, pr.num.n))
+    eta2 = dpg.error_indicator(pr, x, rec)
+    # scale: the load in the same dual norm
+    lnorm = sum(np.real(np.vdot(l, sla.cho_solve(pr._operator(e)[2], l)))
+                for e, l in ((e, pr.element_load(e)[:, 0]) for e in range(8)))
+    assert eta2.max() <= 1e-20 * lnorm
+
+
+def test_error_indicator_is_the_minimised_residual():
+    """The DPG solution minimises the residual sum_K eta_K^2 over the trial
+    space, so moving the traces by d (fields re-recovered) raises it by exactly
+    d^H T d, T the condensed operator: the cross term vanishes at the optimum."""
+    N, p, omega = 2, 2, 2 * np.pi
+    d = np.array([0.48, 0.6, 0.64])
+    pr = dpg.Problem(N, p, omega, [dict(u0=dpg.plane_wave_u0(omega, d))])
+    S, s, rec = pr.condensed()
+    T = dpg.assemble(pr.edofs, S, pr.num.n)
+    x = dpg.direct_solve(T, dpg.assemble_vector(pr.edofs, s, pr.num.n))
+    J0 = dpg.error_indicator(pr, x, rec).sum()
+    rng = np.random.default_rng(2)
+    dx = 1e-3 * (rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape))
+    J1 = dpg.error_indicator(pr, x + dx, rec).sum()
+    quad = np.real(np.vdot(dx[:, 0], T @ dx[:, 0]))
+    assert J0 > 0
+    assert abs((J1 - J0) - quad) <= 1e-8 * quad
+
+
+def test_error_indicator_falls_with_h_on_plane_waves():
+    omega, p = np.pi, 2
+    d = np.array([1.0, 2.0, 2.0]) / 3.0
+    tot = []
+    for N in (1, 2, 4):
+        pr = dpg.Problem(N, p, omega, [dict(u0=dpg.plane_wave_u0(omega, d))])
+        S, s, rec = pr.condensed()
+        T = dpg.assemble(pr.edofs, S, pr.num.n)
+        x = dpg.direct_solve(T, dpg.assemble_vector(pr.edofs, s, pr.num.n))
+        tot.append(dpg.error_indicator(pr, x, rec).sum())
+    assert tot[0] > tot[1] > tot[2]
+    assert np.log2(np.sqrt(tot[1] / tot[2])) > p - 0.5

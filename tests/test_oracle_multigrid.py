@@ -111,3 +111,58 @@ def test_pcg_zero_rhs_and_iteration_cap(two_level):
     assert it == 0 and np.all(x == 0)
     x, it, rr = H.solve(rhs, 0.0, maxit=3)
     assert it == 3 and rr > 0
+
+
+# ---- "store" coarse operators (Sec. 3, alternative construction; Sec. 4.2) ----------------------
+
+def _store(p, omega):
+    return lambda n: dpg.Problem(n, p, omega, []).condensed_operator()
+
+
+def test_store_coarse_operator_is_the_coarse_mesh_dpg_operator(two_level):
+    """With store, the coarse operator is the DPG trace operator of the coarse
+    mesh itself (the 2^3 problem's own condensed matrix): Hermitian positive
+    definite, and different from the Galerkin operator P^T M P."""
+    pr, S, _, rhs, H = two_level
+    Hs = multigrid.Hierarchy(4, 2, S, coarse=_store(2, 2 * np.pi))
+    Ts, Tr = Hs.levels[0].T, H.levels[0].T
+    assert np.abs(Ts - Ts.conj().T).max() <= 1e-13 * np.abs(Ts).max()
+    assert np.linalg.eigvalsh(Ts).min() > 0
+    assert np.abs(Ts - Tr).max() > 1e-3 * np.abs(Tr).max()
+    # the coarse mesh's own solve: the 2^3 problem of the same data
+    pc = dpg.Problem(2, 2, 2 * np.pi, pr.loads)
+    Sc, sc, _ = pc.condensed()
+    assert np.abs(dpg.assemble(pc.edofs, Sc, pc.num.n).toarray() - Ts).max() <= \
+        1e-13 * np.abs(Ts).max()
+
+
+def test_store_vcycle_hermitian_positive_definite_and_pcg_exact(two_level):
+    pr, S, T, rhs, H = two_level
+    Hs = multigrid.Hierarchy(4, 2, S, coarse=_store(2, 2 * np.pi))
+    V = _vcycle_matrix(Hs)
+    assert np.abs(V - V.conj().T).max() <= 1e-12 * np.abs(V).max()
+    assert np.linalg.eigvals(V @ Hs.levels[Hs.L].M.toarray()).real.min() > 0
+    xd = spla.spsolve(T.tocsc(), rhs)
+    x, it, rr = Hs.solve(rhs, 1e-12)
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+
+
+@pytest.mark.slow
+def test_restrict_beats_store_and_the_gap_grows_with_frequency():
+    """The paper's comparison (Sec. 4.2, uniform h-refinements): coarse
+    operators by restriction need fewer PCG iterations than stored (directly
+    assembled) ones, increasingly so as omega grows.  8^3, p = 2, V(2,2)."""
+    d = np.array([2.0, -1.0, 2.0]) / 3.0
+    gaps = []
+    for omega in (2 * np.pi, 8 * np.pi):
+        pr = dpg.Problem(8, 2, omega, [dict(u0=dpg.plane_wave_u0(omega, d))])
+        S, s, _ = pr.condensed()
+        rhs = dpg.assemble_vector(pr.edofs, s, pr.num.n)[:, 0]
+        Hr = multigrid.Hierarchy(8, 2, S, nu_pre=2, nu_post=2)
+        Hs = multigrid.Hierarchy(8, 2, S, nu_pre=2, nu_post=2, coarse=_store(2, omega))
+        xr, itr, _ = Hr.solve(rhs, 1e-10)
+        xs, its, _ = Hs.solve(rhs, 1e-10)
+        assert np.linalg.norm(xr - xs) <= 1e-8 * np.linalg.norm(xr)
+        assert itr < its
+        gaps.append(its - itr)
+    assert gaps[1] > gaps[0]
