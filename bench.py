@@ -29,11 +29,12 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 matrix (= vector) peak
 FP32_PEAK_TFLOPS = 157.3
 
 
-def make_options(D, w, torch_stream=None, device_ptrs=True, columnwise=False):
+def make_options(D, w, torch_stream=None, device_ptrs=True, columnwise=False, recompute=False):
     return D.dpg_default_options(
         nu_pre=w.nu_pre, nu_post=w.nu_post, theta=w.theta,
         precision=D.DPG_MIXED if w.precision == "mixed" else D.DPG_FP64,
-        flags=(D.DPG_DEVICE_PTRS if device_ptrs else 0) | (D.DPG_COLUMNWISE if columnwise else 0),
+        flags=(D.DPG_DEVICE_PTRS if device_ptrs else 0) | (D.DPG_COLUMNWISE if columnwise else 0)
+        | (D.DPG_RECOMPUTE_PATCHES if recompute else 0),
         stream=torch_stream)
 
 
@@ -52,10 +53,21 @@ DENSE = ("potrf", "trsm", "gemm")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def source_digest(path):
+def source_digest(path, symbol=None):
+    """SHA-256 prefix of a kernel's source: the text of the __global__
+    function `symbol` (from its template line to its closing brace at column
+    0), or of the whole file when symbol is None."""
     import hashlib
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    import re
+    with open(path) as f:
+        text = f.read()
+    if symbol:
+        base = symbol.split("<")[0]
+        m = re.search(r"(template <[^\n]*>\n)?__global__[^\n]*\b" + re.escape(base) + r"\(", text)
+        if m:
+            end = text.find("\n}\n", m.start())
+            text = text[m.start():end + 3]
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def measured_traffic(symbol, workload):
@@ -68,7 +80,7 @@ def measured_traffic(symbol, workload):
         return None
     if not rec or rec.get("workload") != workload:
         return None
-    if source_digest(os.path.join(ROOT, rec["source"])) != rec["source_sha256_16"]:
+    if source_digest(os.path.join(ROOT, rec["source"]), symbol) != rec["source_sha256_16"]:
         return None
     return rec["bytes_per_launch"]
 
@@ -297,14 +309,19 @@ def serving_stream(n_req, seed, max_active, load_factor):
     for op in ops:
         print(f"[serving] calibrate op {op.key}: N={op.N} p={op.p} omega={op.omega:.2f}",
               file=sys.stderr, flush=True)
-        ctx = op.build()
+        ctx = op.build(batch_slots=1)
         cen = probe.uniform(0.1, 0.9, size=(8, 3))
         src = np.column_stack([cen, np.full(8, 0.02), np.ones(8), np.zeros(8)])
         ld = [dict(dir=(0.0, 0.0, 1.0), amp=0.0, sources=src)]
-        t0 = time.perf_counter()
-        D.dpg_load_rhs(ctx, ld, want=False)
-        D.dpg_solve(ctx, nrhs=1, tol=op.tol)
-        service.append(time.perf_counter() - t0)
+        for rep in range(2):   # the first run captures the graphs of the batch
+            t0 = time.perf_counter()
+            D.dpg_load_rhs(ctx, ld, want=False)
+            k = D.dpg_batch_add(ctx, None, load_col=0, tol=op.tol)
+            while not D.dpg_batch_step(ctx, 100):
+                pass
+            D.dpg_batch_take(ctx, k)
+            t = time.perf_counter() - t0
+        service.append(t)
         ctx.close()
     capacity = 1.0 / float(np.mean(service))
     rate = load_factor * capacity
@@ -336,6 +353,10 @@ def serving_stream(n_req, seed, max_active, load_factor):
         "requests": n_req, "wall_s": wall, "arrival_rate": rate,
         "single_request_capacity": capacity, "load_factor": load_factor,
         "mean_batch": float(np.mean(batches)), "max_batch": int(np.max(batches)),
+        "joined_running_batch": int(sum(r.joined_running for r in reqs)),
+        "batch_note": ("batch = most columns a request's operator batch ran while the request "
+                       "was in it; joined_running_batch = requests admitted into a block solve "
+                       "already part-way through"),
         "builds_during_stream": srv.builds - builds0,
         "evictions_during_stream": srv.evictions - evict0,
         "hbm_budget_GB": budget / 1e9,
@@ -400,6 +421,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="plane_wave_32_mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--recompute-patches", action="store_true",
+                    help="smooth with patch inverses recomputed in every application (FP64 "
+                         "workloads; no stored inverses)")
+    ap.add_argument("--no-kernel-stats", action="store_true",
+                    help="skip the extra step timed kernel by kernel with HIP events (for runs "
+                         "under a hardware-counter profiler)")
     ap.add_argument("--no-fp64-twin", action="store_true",
                     help="skip the FP64 solve of a mixed-precision workload")
     ap.add_argument("--columnwise", action="store_true",
@@ -445,7 +472,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    opt = make_options(D, w, torch_stream=stream.cuda_stream, columnwise=args.columnwise)
+    opt = make_options(D, w, torch_stream=stream.cuda_stream, columnwise=args.columnwise,
+                       recompute=args.recompute_patches)
     print(f"[bench] {w.name}: setup", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     ctx = D.dpg_setup(w.N, w.p, w.omega, loads_of(w), dp=w.dp, options=opt)
@@ -485,11 +513,13 @@ def main():
     print(f"[bench] {args.steps} timed steps done ({elapsed:.2f} s)", file=sys.stderr, flush=True)
     # one more step with per-kernel HIP events for the kernel statistics (the
     # events serialise the launches, so the timed steps above run without them)
-    D.dpg_profile(ctx, True)
-    step()
-    torch.cuda.synchronize()
-    stats = D.dpg_kernel_stats(ctx)
-    D.dpg_profile(ctx, False)
+    stats = {}
+    if not args.no_kernel_stats:
+        D.dpg_profile(ctx, True)
+        step()
+        torch.cuda.synchronize()
+        stats = D.dpg_kernel_stats(ctx)
+        D.dpg_profile(ctx, False)
     resident = D.dpg_info(ctx).resident_bytes
     D.dpg_release_setup(ctx)
     resident_solve = D.dpg_info(ctx).resident_bytes
@@ -515,7 +545,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if w.precision == "fp64" else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "N": w.N, "p": w.p, "dp": w.dp, "omega": w.omega,
+        "config": {"workload": w.name + (" recomputed patches" if args.recompute_patches else ""),
+                   "N": w.N, "p": w.p, "dp": w.dp, "omega": w.omega,
                    "nu": [w.nu_pre, w.nu_post], "theta": w.theta, "tol": w.tol,
                    "precision": w.precision, "nrhs": w.nrhs, "n_trace": nT,
                    "n_macro": info.n_macro, "levels": list(info.level_n)[:info.nlevels]},
@@ -535,7 +566,7 @@ def main():
         "setup_topology_ms": 1e3 * setup_s,
         "resident_GB": resident / 1e9,
         "resident_after_release_GB": resident_solve / 1e9,
-        "roofline": roofline_for(stats, w.name),
+        "roofline": roofline_for(stats, w.name) if stats else None,
         "roofline_setup": roofline_setup(stats),
         "kernels": {k: {"launches": n, "ms": ms, "work": wk} for k, (n, ms, wk) in stats.items()},
         "kernels_note": "per-kernel HIP events over one extra profiled step",

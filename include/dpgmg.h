@@ -63,13 +63,20 @@ enum {
 enum { DPG_FP64 = 0, DPG_MIXED = 1 };       /* dpg_options.precision          */
 enum { DPG_DEVICE_PTRS = 1,                 /* dpg_options.flags              */
        DPG_COLUMNWISE = 2,                   /* solve nrhs > 1 column by column */
-       DPG_STORE_COARSE = 4 };               /* coarse operators assembled on
+       DPG_STORE_COARSE = 4,                 /* coarse operators assembled on
                                                 their own meshes ("store", the
                                                 alternative of Sec. 3 and the
                                                 comparison of Sec. 4.2) instead
                                                 of Galerkin P^T M P; needs a
                                                 wave speed constant on every
                                                 coarse element                 */
+       DPG_RECOMPUTE_PATCHES = 8 };          /* no stored patch inverses: every
+                                                smoothing step refactors the
+                                                patch blocks from the macro
+                                                blocks (Sec. 5 and Sec. 6: a
+                                                GPU code that recomputes the
+                                                patches); FP64, one column at a
+                                                time (no batches)              */
 
 /* Uniform mesh of the cube [origin, origin + side]^3 into n^3 equal boxes;
  * element e = i + n (j + n k). */
@@ -110,7 +117,8 @@ typedef struct {
   int32_t nu_post;
   int32_t nlevels;    /* 0: halve while n is even and n > 2 (n = 2: once)    */
   int32_t maxit;      /* outer CG iteration cap                              */
-  int32_t flags;      /* DPG_DEVICE_PTRS | DPG_COLUMNWISE | DPG_STORE_COARSE */
+  int32_t flags;      /* DPG_DEVICE_PTRS | DPG_COLUMNWISE | DPG_STORE_COARSE
+                         | DPG_RECOMPUTE_PATCHES                              */
   double theta;       /* smoother damping; must be < 1/4                     */
   int64_t hbm_budget; /* bytes the context may allocate; 0 = no limit        */
   void *stream;       /* hipStream_t to launch on; NULL: a stream the context
@@ -185,6 +193,34 @@ int dpg_release_setup(dpg_ctx *ctx);
  * instead.  Both give each column the same iterates up to rounding. */
 int dpg_solve(dpg_ctx *ctx, const double *rhs, int nrhs, double tol, double *x_out,
               int32_t *iters_out, double *relres_out);
+
+/* Continuous batching (a block solve whose columns join and leave while it
+ * runs): the multi-right-hand-side forms of dpg_solve over a batch of up to
+ * max_slots <= 32 columns, each with its own CG recurrence and tolerance.
+ * dpg_batch_add puts a right-hand side (rhs: n_trace trace vector, host or
+ * device per DPG_DEVICE_PTRS; NULL: column load_col of the loads of
+ * dpg_assemble / dpg_load_rhs, copied at the call) into the lowest free slot,
+ * also while other columns are part-way through; its first iteration is the
+ * first step of PCG from x0 = 0.  dpg_batch_step runs up to max_iters
+ * iterations of the running columns (one V-cycle and one block matvec each,
+ * every stored block streamed once for all columns, launched as HIP graphs
+ * captured per batch width), stopping after the first iteration in which a
+ * column finishes; done_out (max_slots entries) receives every finished slot
+ * not taken yet, ndone_out their number.  dpg_batch_take writes the full
+ * trace solution of a finished slot to x_out (n_trace) with its iteration
+ * count and relative residual, frees the slot, and returns DPG_OK,
+ * DPG_ENOCONV (maxit reached) or DPG_EBREAKDOWN for that column.  The
+ * columns are independent: a column gets the same iterates (up to rounding)
+ * whether it runs alone or beside others, joined early or late.  Requires a
+ * built hierarchy; dpg_solve with nrhs > 1 uses the same machinery and
+ * returns DPG_ESTATE while a batch is open.  dpg_batch_open closes a batch
+ * already open; dpg_destroy closes it. */
+int dpg_batch_open(dpg_ctx *ctx, int max_slots);
+int dpg_batch_add(dpg_ctx *ctx, const double *rhs, int load_col, double tol, int32_t *slot_out);
+int dpg_batch_step(dpg_ctx *ctx, int max_iters, int32_t *done_out, int32_t *ndone_out);
+int dpg_batch_take(dpg_ctx *ctx, int slot, double *x_out, int32_t *iters_out,
+                   double *relres_out);
+int dpg_batch_close(dpg_ctx *ctx);
 
 /* For callers that cannot allocate device memory: code run under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  Same

@@ -118,6 +118,46 @@ void set_loads(dpg_ctx *c, const dpg_load *loads, int nrhs) {
   HIP_OK(hipStreamSynchronize(c->stream));
 }
 
+// Elements that a new set of loads needs.  Returns true (all elements) unless
+// every load consists of Gaussian point sources only; then list receives the
+// elements whose box comes within 8 sigma of some source (ascending).  Beyond
+// 8 sigma the density is below exp(-32) = 1.3e-14 of its peak and the mass
+// outside that ball below 1e-13 of the total, so the omitted element loads are
+// below the rounding of the kept ones.  Also true when the list would cover
+// most of the mesh.
+bool source_elements(const dpg_ctx *c, std::vector<int32_t> &list) {
+  list.clear();
+  for (const LoadDesc &d : c->ld_h)
+    if (d.amp[0] != 0.0 || d.amp[1] != 0.0 || d.u0_off >= 0) return true;
+  const int N = c->N;
+  const double h = c->side / N;
+  std::vector<char> mark((size_t)N * N * N, 0);
+  for (size_t k = 0; 6 * k + 5 < c->src_h.size(); ++k) {
+    const double *S = c->src_h.data() + 6 * k;   // (x, y, z, sigma > 0, re a, im a)
+    const double R = 8.0 * S[3];
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::max(0, (int)std::floor((S[d] - R - c->org[d]) / h));
+      hi[d] = std::min(N - 1, (int)std::floor((S[d] + R - c->org[d]) / h));
+    }
+    for (int kz = lo[2]; kz <= hi[2]; ++kz)
+      for (int jy = lo[1]; jy <= hi[1]; ++jy)
+        for (int ix = lo[0]; ix <= hi[0]; ++ix) {
+          const int cell[3] = {ix, jy, kz};
+          double d2 = 0.0;   // squared distance from the centre to the element box
+          for (int d = 0; d < 3; ++d) {
+            const double a = c->org[d] + h * cell[d], b = a + h;
+            const double t = S[d] < a ? a - S[d] : S[d] > b ? S[d] - b : 0.0;
+            d2 += t * t;
+          }
+          if (d2 <= R * R) mark[ix + (size_t)N * (jy + (size_t)N * kz)] = 1;
+        }
+  }
+  for (size_t e = 0; e < mark.size(); ++e)
+    if (mark[e]) list.push_back((int32_t)e);
+  return 4 * list.size() > 3 * mark.size();
+}
+
 // Throws DPG_ENOTPD for the first item whose Cholesky met a non-positive
 // pivot (info[i] = j + 1 for pivot j of item i).
 void check_infos(const int *info, int64_t count, hipStream_t s, const char *what) {
@@ -212,7 +252,11 @@ struct IndicatorArgs {
 // Y = L_f^-1 [K_ft | b], the unknowns [x_f; x_t] of every element
 // (x_f = L_f^-H (Y_b - Y_t x_t)), the residual W_l - W_B [x_f; x_t] =
 // L^-1 (l - B [x_f; x_t]), and eta^2 = its squared norm = r^H G^-1 r.
-void element_stage(dpg_ctx *c, int l, bool write_matrices, const IndicatorArgs *ind = nullptr) {
+// With elist (device, nlist entries; finest level, loads only), the pass
+// covers only the listed elements and writes their condensed loads (the
+// caller zeroes the others).
+void element_stage(dpg_ctx *c, int l, bool write_matrices, const IndicatorArgs *ind = nullptr,
+                   const int32_t *elist = nullptr, int nlist = 0) {
   const bool fine = l == c->L;
   LevelData &f = c->lv[l];
   const int nr = fine ? c->nrhs : 0;
@@ -220,6 +264,9 @@ void element_stage(dpg_ctx *c, int l, bool write_matrices, const IndicatorArgs *
   ElemPlan &P = c->ep;
   const int nt = c->n_test, nf = c->n_field, ntr = c->n_tr, m = c->m;
   const int mp = m + nr, C = P.C, nel = f.nel;
+  if (elist && (!fine || ind || write_matrices))
+    throw DpgError(DPG_EINVAL, "element lists are for load updates only");
+  const int total = elist ? nlist : nel;
   if (ind) {
     if (!fine || ind->nr < 1 || ind->nr > nr) throw DpgError(DPG_EINVAL, "bad indicator columns");
     for (int k = 0; k < P.ns; ++k) grow(P.X[k], (int64_t)C * m * ind->nr, &c->bud);
@@ -235,13 +282,13 @@ void element_stage(dpg_ctx *c, int l, bool write_matrices, const IndicatorArgs *
     }
   }
   const double *kap = fine ? c->kappa.p : f.kappa.p, *Zel = fine ? c->Zel.p : f.Zel.p;
-  ElemGeom g{f.N, c->side / f.N, c->omega, 1.0, {c->org[0], c->org[1], c->org[2]}};
+  ElemGeom g{f.N, c->side / f.N, c->omega, 1.0, {c->org[0], c->org[1], c->org[2]}, elist};
   const int NS = P.ns;
   const hipStream_t xs[4] = {c->stream, c->aux, c->paux[0], c->paux[1]};
   const hipEvent_t xj[4] = {nullptr, c->ev_join, c->ev_pjoin[0], c->ev_pjoin[1]};
   for (int k = 1; k < NS; ++k) stream_wait(c->stream, xs[k], c->ev_fork);
-  for (int e0 = 0, k = 0; e0 < nel; e0 += C, ++k) {
-    const int cnt = std::min(C, nel - e0), u = k % NS;
+  for (int e0 = 0, k = 0; e0 < total; e0 += C, ++k) {
+    const int cnt = std::min(C, total - e0), u = k % NS;
     const hipStream_t s = xs[u];
     double2 *G = P.G[u].p, *BL = P.BL[u].p, *K = P.K[u].p, *wk = P.wk[u].p;
     {
@@ -302,29 +349,35 @@ void element_stage(dpg_ctx *c, int l, bool write_matrices, const IndicatorArgs *
     if (write_matrices)
       launch_copy_sub(K, (int64_t)mp * mp, mp, nf, nf, ntr, ntr, f.E.p + (int64_t)e0 * ntr * ntr,
                       (int64_t)ntr * ntr, ntr, cnt, s);
+    const int32_t *dl = elist ? elist + e0 : nullptr;   // destination elements
+    const int64_t eo = elist ? 0 : e0;
     for (int r = 0; r < nr; ++r)
       launch_copy_sub(K, (int64_t)mp * mp, mp, nf, m + r, ntr, 1,
-                      c->s_elem.p + ((int64_t)r * nel + e0) * ntr, ntr, ntr, cnt, s);
+                      c->s_elem.p + ((int64_t)r * nel + eo) * ntr, ntr, ntr, cnt, s, dl);
     if (fine && c->keep_recovery) {
-      launch_copy_sub(K, (int64_t)mp * mp, mp, 0, 0, nf, nf, c->rec_L.p + (int64_t)e0 * nf * nf,
-                      (int64_t)nf * nf, nf, cnt, s);
-      launch_copy_sub(K, (int64_t)mp * mp, mp, 0, nf, nf, mp - nf,
-                      c->rec_Y.p + (int64_t)e0 * nf * (mp - nf), (int64_t)nf * (mp - nf), nf, cnt,
-                      s);
+      if (write_matrices) {   // L = chol(K_ff) and Y_t = L^-1 K_ft (load independent)
+        launch_copy_sub(K, (int64_t)mp * mp, mp, 0, 0, nf, nf, c->rec_L.p + eo * nf * nf,
+                        (int64_t)nf * nf, nf, cnt, s);
+        launch_copy_sub(K, (int64_t)mp * mp, mp, 0, nf, nf, ntr, c->rec_Y.p + eo * nf * ntr,
+                        (int64_t)nf * ntr, nf, cnt, s);
+      }
+      if (nr > 0)             // Y_b = L^-1 b_f
+        launch_copy_sub(K, (int64_t)mp * mp, mp, 0, m, nf, nr, c->rec_Yb.p + eo * nf * nr,
+                        (int64_t)nf * nr, nf, cnt, s, dl);
     }
   }
   for (int k = 1; k < NS; ++k) stream_wait(xs[k], c->stream, xj[k]);
   if (!fine || ind) {
-    check_infos(P.info.p, nel, c->stream, "coarse-mesh element Gram matrix");
-    check_infos(P.info.p + nel, nel, c->stream, "coarse-mesh element field block");
+    check_infos(P.info.p, nel, c->stream, fine ? "element Gram matrix" : "coarse-mesh element Gram matrix");
+    check_infos(P.info.p + nel, nel, c->stream, fine ? "element field block" : "coarse-mesh element field block");
     return;
   }
   // assembled loads
   for (int r = 0; r < nr; ++r)
     launch_assemble_vec(f.num.n, c->asm_ptr.p, c->asm_ent.p, c->s_elem.p + (int64_t)r * nel * ntr,
                         0, c->s_asm.p + (int64_t)r * f.num.n, c->stream);
-  check_infos(P.info.p, nel, c->stream, "element Gram matrix");
-  check_infos(P.info.p + nel, nel, c->stream, "element field block");
+  check_infos(P.info.p, total, c->stream, elist ? "listed element (Gram matrix)" : "element Gram matrix");
+  check_infos(P.info.p + nel, total, c->stream, elist ? "listed element (field block)" : "element field block");
 }
 
 // ---- hierarchy -------------------------------------------------------------------------
@@ -513,9 +566,12 @@ void plan_patches(dpg_ctx *c, int l) {
     maxent = std::max<int64_t>(maxent, (int64_t)nv[v] * nv[v]);
   }
   // parts of equal factorisation work (sum n^3), one per stream, each cut
-  // into batches that fit its workspaces (S and X: 3 GB each)
-  const int64_t ws = std::max<int64_t>(3000000000LL / 16, maxent);
-  const int NP = kPatchParts;
+  // into batches that fit its workspaces (S and X: 3 GB each).  With the
+  // inverses recomputed in every smoothing step, one part on the main stream
+  // and workspaces of 0.5 GB.
+  const bool rec = c->opt.flags & DPG_RECOMPUTE_PATCHES;
+  const int64_t ws = std::max<int64_t>((rec ? 500000000LL : 3000000000LL) / 16, maxent);
+  const int NP = rec ? 1 : kPatchParts;
   double tot = 0.0;
   for (int v = 0; v < np; ++v) tot += (double)nv[v] * nv[v] * nv[v];
   std::vector<int> vcut(NP + 1, np);
@@ -533,6 +589,7 @@ void plan_patches(dpg_ctx *c, int l) {
   }
   std::vector<int64_t> soff_all(np, 0);
   int maxcnt[4] = {0, 0, 0, 0};
+  int64_t maxuse[4] = {0, 0, 0, 0};   // largest batch footprint of each part (entries)
   for (int half = 0; half < NP; ++half) {
     int v0 = vcut[half];
     const int vend = vcut[half + 1];
@@ -573,9 +630,21 @@ void plan_patches(dpg_ctx *c, int l) {
       B.pi.upload(pi, bd, s);
       B.ti.upload(ti, bd, s);
       B.gi.upload(gi, bd, s);
+      if (rec) {   // t_v = X_v x_v, y_v = X_v^H t_v on the local vectors of the patch set
+        std::vector<GemmItem> gy(cnt), gz(cnt);
+        for (int i = 0; i < cnt; ++i) {
+          const int n = nn[i];
+          const int64_t lo = f.Sset.loc_off_h[v0 + i];
+          gy[i] = {off[i], lo, lo, n, 1, n, n, n, n};
+          gz[i] = {off[i], lo, lo, n, 1, n, n, n, n};
+        }
+        B.gy.upload(gy, bd, s);
+        B.gz.upload(gz, bd, s);
+      }
       B.t0 = f.Sset.tile_off_h[v0];
       B.t1 = (v0 + cnt < np) ? f.Sset.tile_off_h[v0 + cnt] : f.Sset.ntiles;
       maxcnt[half] = std::max(maxcnt[half], cnt);
+      maxuse[half] = std::max(maxuse[half], used);
       P.batches.push_back(std::move(B));
       v0 += cnt;
     }
@@ -583,10 +652,11 @@ void plan_patches(dpg_ctx *c, int l) {
   P.soff_all.upload(soff_all, bd, s);
   P.ld_all.upload(nv, bd, s);
   P.info.ensure(np, bd);
+  if (rec) grow(c->ptmp, f.Sset.nloc, bd);
   for (int h = 0; h < NP; ++h) {
     if (!maxcnt[h]) continue;
-    if (c->pS[h].n < ws) c->pS[h].alloc(ws, bd);
-    if (c->pX[h].n < ws) c->pX[h].alloc(ws, bd);
+    if (c->pS[h].n < maxuse[h]) c->pS[h].alloc(maxuse[h], bd);
+    if (c->pX[h].n < maxuse[h]) c->pX[h].alloc(maxuse[h], bd);
     if (c->pwk[h].n < dense_work_size(maxcnt[h], nv_max))
       c->pwk[h].alloc(dense_work_size(maxcnt[h], nv_max), bd);
   }
@@ -626,6 +696,63 @@ void build_patches(dpg_ctx *c, int l, int half, hipStream_t s) {
     }
     f.Sset.pack(S, P.soff_all.p, P.ld_all.p, nullptr, nullptr, s, B.t0, B.t1 - B.t0);
   }
+}
+
+// Patch factors of level l without keeping them: gather and Cholesky of every
+// patch block, to report a non-positive pivot at build time (DPG_ENOTPD) when
+// the smoother recomputes its inverses in every application.
+void check_patches(dpg_ctx *c, int l) {
+  LevelData &f = c->lv[l];
+  PatchPlan &P = f.pp;
+  const hipStream_t s = c->stream;
+  for (PatchBatch &B : P.batches) {
+    double2 *S = c->pS[B.half].p, *wk = c->pwk[B.half].p;
+    launch_patch_gather_tiles(f.Mset.t64.p, f.Mset.ent_off.p, f.mpidx.p, f.nBf, f.mc.Nc,
+                              f.patch_ptr.p, f.patch_slot.p, B.v0, B.cnt, B.nmax, B.off.p, S, s);
+    potrf_batched(S, B.pi.p, B.cnt, P.info.p + B.v0, B.nmax, wk, s);
+  }
+}
+
+// The smoother of level l with its patch inverses recomputed from the macro
+// blocks (DPG_RECOMPUTE_PATCHES; none is stored): y <- epilogue(sum_v R_v^T
+// S_v^-1 R_v x) batch by batch -- gather S_v from the packed macro-block
+// tiles the matvec streams anyway, S_v = L L^H, X = L^-1, then S_v^-1 x_v =
+// X^H (X x_v).  The same operator as the stored inverses, rounded
+// differently; HBM traffic and memory traded for matrix-core work.
+void smooth_recompute(dpg_ctx *c, int l, const double2 *x, double2 *y, const double2 *r, int mode,
+                      double theta) {
+  LevelData &f = c->lv[l];
+  PatchPlan &P = f.pp;
+  HermSet &H = f.Sset;
+  const hipStream_t s = c->stream;
+  herm_gather(H, x, H.xl64.p, s);
+  for (PatchBatch &B : P.batches) {
+    double2 *S = c->pS[B.half].p, *X = c->pX[B.half].p, *wk = c->pwk[B.half].p;
+    {
+      PROF(DPG_K_PATCH_GATHER, 0);
+      launch_patch_gather_tiles(f.Mset.t64.p, f.Mset.ent_off.p, f.mpidx.p, f.nBf, f.mc.Nc,
+                                f.patch_ptr.p, f.patch_slot.p, B.v0, B.cnt, B.nmax, B.off.p, S,
+                                s);
+    }
+    {
+      PROF(DPG_K_POTRF, B.fp);
+      potrf_batched(S, B.pi.p, B.cnt, P.info.p + B.v0, B.nmax, wk, s);
+    }
+    {
+      PROF(DPG_K_OTHER, 0);
+      launch_identity(B.off.p, B.nn.p, B.cnt, B.nmax, X, s);
+    }
+    {
+      PROF(DPG_K_TRSM, B.ft);
+      trsm_batched(S, X, B.ti.p, B.cnt, B.nmax, B.nmax, true, wk, true, s);
+    }
+    PROF(DPG_K_GEMM, 0);
+    gemm_batched(OP_N, OP_N, mk(1, 0), X, H.xl64.p, mk(0, 0), c->ptmp.p, B.gy.p, B.cnt, B.nmax, 1,
+                 s);
+    gemm_batched(OP_C, OP_N, mk(1, 0), X, c->ptmp.p, mk(0, 0), H.yl64.p, B.gz.p, B.cnt, B.nmax,
+                 1, s);
+  }
+  herm_scatter(H, H.yl64.p, y, r, mode, theta, s);
 }
 
 void plan_coarsest(dpg_ctx *c) {
@@ -688,17 +815,25 @@ void build_hierarchy(dpg_ctx *c) {
   const int NX = kPatchParts - 1;   // parts on the extra streams
   hipStream_t xs[3] = {c->aux, c->paux[0], c->paux[1]};
   hipEvent_t xj[3] = {c->ev_join, c->ev_pjoin[0], c->ev_pjoin[1]};
-  for (int k = 0; k < NX; ++k) stream_wait(c->stream, xs[k], c->ev_fork);
-  for (int l = c->L; l >= 1; --l) {
-    build_macro_level(c, l);
-    for (int k = 0; k < NX; ++k) {
-      stream_wait(c->stream, xs[k], c->ev_level[l]);
-      build_patches(c, l, k, xs[k]);
+  if (c->opt.flags & DPG_RECOMPUTE_PATCHES) {   // no stored inverses: check the factors only
+    for (int l = c->L; l >= 1; --l) {
+      build_macro_level(c, l);
+      check_patches(c, l);
     }
+    build_coarsest(c);
+  } else {
+    for (int k = 0; k < NX; ++k) stream_wait(c->stream, xs[k], c->ev_fork);
+    for (int l = c->L; l >= 1; --l) {
+      build_macro_level(c, l);
+      for (int k = 0; k < NX; ++k) {
+        stream_wait(c->stream, xs[k], c->ev_level[l]);
+        build_patches(c, l, k, xs[k]);
+      }
+    }
+    build_coarsest(c);
+    for (int l = c->L; l >= 1; --l) build_patches(c, l, NX, c->stream);
+    for (int k = 0; k < NX; ++k) stream_wait(xs[k], c->stream, xj[k]);
   }
-  build_coarsest(c);
-  for (int l = c->L; l >= 1; --l) build_patches(c, l, NX, c->stream);
-  for (int k = 0; k < NX; ++k) stream_wait(xs[k], c->stream, xj[k]);
   for (int l = c->L; l >= 1; --l) {
     check_infos(c->lv[l].mp.info.p, c->lv[l].nblk, c->stream, "interior block of coarse element");
     check_infos(c->lv[l].pp.info.p, (int64_t)c->lv[l].mc.patch_ptr.size() - 1, c->stream,
@@ -735,6 +870,18 @@ template <> struct LB<float> {
   static const float *Ptv(LevelData &f) { return f.Ptval32.p; }
 };
 
+// The smoother's patch sum on level l: stored inverses, or recomputed ones.
+template <typename T>
+void smooth_apply(dpg_ctx *c, int l, const cplx_t<T> *x, cplx_t<T> *y, int mode, T theta) {
+  if constexpr (sizeof(T) == 8) {
+    if (c->opt.flags & DPG_RECOMPUTE_PATCHES) {
+      smooth_recompute(c, l, x, y, nullptr, mode, theta);
+      return;
+    }
+  }
+  herm_apply<T>(c->lv[l].Sset, x, y, nullptr, mode, theta, c->stream);
+}
+
 template <typename T> void vcycle(dpg_ctx *c, int l) {
   using B = LB<T>;
   LevelData &f = c->lv[l];
@@ -744,10 +891,10 @@ template <typename T> void vcycle(dpg_ctx *c, int l) {
   if (c->opt.nu_pre == 0) launch_zero(f.nM, x, s);
   for (int k = 0; k < c->opt.nu_pre; ++k) {
     if (k == 0) {
-      herm_apply<T>(f.Sset, r, x, nullptr, RED_SET_SCALED, th, s);
+      smooth_apply<T>(c, l, r, x, RED_SET_SCALED, th);
     } else {
       herm_apply<T>(f.Mset, x, res, r, RED_RESID, (T)0, s);
-      herm_apply<T>(f.Sset, res, x, nullptr, RED_AXPY, th, s);
+      smooth_apply<T>(c, l, res, x, RED_AXPY, th);
     }
   }
   herm_apply<T>(f.Mset, x, res, r, RED_RESID, (T)0, s);
@@ -776,7 +923,7 @@ template <typename T> void vcycle(dpg_ctx *c, int l) {
   }
   for (int k = 0; k < c->opt.nu_post; ++k) {
     herm_apply<T>(f.Mset, x, res, r, RED_RESID, (T)0, s);
-    herm_apply<T>(f.Sset, res, x, nullptr, RED_AXPY, th, s);
+    smooth_apply<T>(c, l, res, x, RED_AXPY, th);
   }
 }
 
@@ -799,15 +946,6 @@ void read_sc(dpg_ctx *c, const double *sc) {
   HIP_OK(hipMemcpyAsync(c->host_sc, sc, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_OK(hipStreamSynchronize(c->stream));
 }
-
-// Instantiated HIP graphs of one solve, destroyed with the object.
-struct GraphSet {
-  hipGraphExec_t a = nullptr, b[2] = {nullptr, nullptr};
-  ~GraphSet() {
-    for (hipGraphExec_t g : {a, b[0], b[1]})
-      if (g) (void)hipGraphExecDestroy(g);
-  }
-};
 
 // Capture the launches of f on stream s into an executable graph.  A capture
 // that fails is ended and discarded, so the stream is never left capturing.
@@ -1061,92 +1199,285 @@ void precondition_blk(dpg_ctx *c, const double2 *r, double2 *z, int nr) {
   }
 }
 
-// PCG for nr <= kMaxCols right-hand sides at once: sv_cols holds the trace
-// loads column by column ([nr][n_trace], device); the full trace solutions go
-// to xcols likewise.  Each column runs its own CG recurrence (its own alpha
-// and beta); the operator and the V-cycle are applied to all columns of the
-// block together, and a column that reached tol keeps its iterate.
-int solve_block(dpg_ctx *c, const double2 *sv_cols, int nr, double tol, double2 *xcols,
-                int32_t *iters, double *relres) {
-  ensure_block(c, nr);
+// ---- block PCG with columns that join and leave (continuous batching) -----------------
+//
+// The block vectors (trace right-hand sides bsv, and x, r, p, z, z_old on the
+// finest macro grid) hold the session's width w columns interleaved.  Each
+// column runs its own CG recurrence (its own alpha and beta; a finished
+// column is frozen: alpha = beta = 0).  One iteration is (B) the V-cycle on
+// all columns, beta and the search directions, then (A) the block matvec,
+// alpha and the x / r updates; a column that joins starts with x = p = z =
+// z_old = 0, r = b and rz = 1, so that its first (B) sets p = z and
+// rz = r^H z -- the first step of PCG -- while the other columns go on.
+
+void batch_close(dpg_ctx *c) {
+  BatchSession &S = c->bs;
+  S.graphs.reset();
+  S.gw = 0;
+  S.open = false;
+  S.max = S.w = 0;
+}
+
+void batch_open(dpg_ctx *c, int max_slots) {
+  if (max_slots < 1 || max_slots > kMaxCols)
+    throw DpgError(DPG_EINVAL, "a batch holds 1 to 32 columns");
+  if (c->opt.flags & DPG_RECOMPUTE_PATCHES)
+    throw DpgError(DPG_EINVAL, "recomputed patch inverses solve one column at a time");
+  batch_close(c);
+  ensure_block(c, max_slots);
+  BatchSession &S = c->bs;
+  LevelData &top = c->lv[c->L];
+  const hipStream_t s = c->stream;
+  for (auto *v : {&c->bx, &c->br, &c->bp, &c->bz, &c->bzo}) launch_zero(top.nM * max_slots, v->p, s);
+  launch_zero(top.num.n * max_slots, c->bsv.p, s);
+  launch_zero(4 * kMaxCols, reinterpret_cast<double2 *>(c->bsc.p), s);
+  for (int k = 0; k < kMaxCols; ++k) {
+    S.state[k] = 0;
+    S.iters[k] = 0;
+    S.bb[k] = S.rr[k] = 0.0;
+    S.tol[k] = 0.0;
+    c->host_bact[k] = 0;
+  }
+  S.act_dirty = true;
+  S.max = max_slots;
+  S.w = 1;
+  S.cur = 0;
+  S.open = true;
+}
+
+// Width w_new (columns beyond it must be free): the block vectors are laid
+// out again through the matvec output, which holds nothing between steps.
+void batch_width(dpg_ctx *c, int w_new) {
+  BatchSession &S = c->bs;
+  if (w_new == S.w) return;
   LevelData &top = c->lv[c->L];
   const hipStream_t s = c->stream;
   const int64_t nM = top.nM, nT = top.num.n;
-  double *S = c->host_bsc;
+  for (auto *v : {&c->bx, &c->br, &c->bp, &c->bz, &c->bzo}) {
+    HIP_OK(hipMemcpyAsync(c->bq.p, v->p, nM * S.w * 16, hipMemcpyDeviceToDevice, s));
+    launch_rewidth(nM, S.w, w_new, c->bq.p, v->p, s);
+  }
+  HIP_OK(hipMemcpyAsync(c->bxf.p, c->bsv.p, nT * S.w * 16, hipMemcpyDeviceToDevice, s));
+  launch_rewidth(nT, S.w, w_new, c->bxf.p, c->bsv.p, s);
+  S.w = w_new;
+}
+
+// A right-hand side sv (trace vector, device) joins in the lowest free slot.
+int batch_add(dpg_ctx *c, const double2 *sv, double tol) {
+  BatchSession &S = c->bs;
+  int k = 0;
+  while (k < S.max && S.state[k] != 0) ++k;
+  if (k == S.max) throw DpgError(DPG_EINVAL, "every slot of the batch is in use");
+  if (k >= S.w) {
+    int w = 1;
+    while (w <= k) w *= 2;
+    batch_width(c, std::min(w, S.max));
+  }
+  LevelData &top = c->lv[c->L];
+  const hipStream_t s = c->stream;
+  const int64_t nM = top.nM, nT = top.num.n;
+  launch_set_col(nT, S.w, k, sv, c->bsv.p, s);
+  launch_condense_local<double>(top.WH.p, top.nI, top.nBf, top.blkI.p, top.nblk, sv, top.c64.p, s);
+  launch_condense_reduce<double>(nM, top.macroB.p, top.cred_ptr.p, top.cred_ent.p, sv, top.c64.p,
+                                 c->b.p, s);
+  launch_zero(4, reinterpret_cast<double2 *>(c->sc.p), s);
+  dot_re(nM, c->b.p, c->b.p, c->partial.p, c->sc.p + 5, s);
+  launch_set_col(nM, S.w, k, c->b.p, c->br.p, s);
+  for (auto *v : {&c->bx, &c->bp, &c->bz, &c->bzo}) launch_set_col(nM, S.w, k, nullptr, v->p, s);
+  cgb_reset_col(c->bsc.p, k, s);
+  read_sc(c, c->sc.p);
+  const double bb = c->host_sc[5];
+  if (!std::isfinite(bb)) throw DpgError(DPG_EINVAL, "right-hand side is not finite");
+  S.bb[k] = bb;
+  S.tol[k] = tol;
+  S.iters[k] = 0;
+  if (bb > 0.0) {
+    S.state[k] = 1;
+    S.rr[k] = 1.0;
+    c->host_bact[k] = 1;
+    S.act_dirty = true;
+  } else {            // zero right-hand side: x = 0 after no iteration
+    S.state[k] = 2;
+    S.rr[k] = 0.0;
+    S.done.push_back(k);
+  }
+  return k;
+}
+
+// Iterations of the running columns until one of them finishes or max_iters
+// have run; appends the slots that finished to S.done.
+void batch_step(dpg_ctx *c, int max_iters) {
+  BatchSession &S = c->bs;
+  LevelData &top = c->lv[c->L];
+  const hipStream_t s = c->stream;
+  const int64_t nM = top.nM;
+  double *Sc = c->host_bsc;
   int *act = c->host_bact;
+  const size_t done0 = S.done.size();
+  for (int it = 0; it < max_iters && S.done.size() == done0; ++it) {
+    int running = 0;
+    for (int k = 0; k < S.w; ++k) running += S.state[k] == 1;
+    if (!running) break;
+    if (S.act_dirty) {
+      HIP_OK(hipMemcpyAsync(c->bact.p, act, kMaxCols * sizeof(int), hipMemcpyHostToDevice, s));
+      S.act_dirty = false;
+    }
+    const int w = S.w;
+    auto part_a = [&]() {
+      herm_apply_blk<double>(top.Mset, top.Mb, c->bp.p, c->bq.p, nullptr, RED_SET, 1.0, w, s);
+      PROF(DPG_K_CG, 0);
+      cgb_alpha(nM, w, c->bp.p, c->bq.p, c->bpartial.p, c->bsc.p, c->bact.p, s);
+      cgb_update_xr(nM, w, c->bx.p, c->br.p, c->bp.p, c->bq.p, c->bpartial.p, c->bsc.p, s);
+    };
+    auto part_b = [&](double2 *zn, double2 *zp) {
+      precondition_blk(c, c->br.p, zn, w);
+      PROF(DPG_K_CG, 0);
+      cgb_beta(nM, w, c->br.p, zn, zp, c->bpartial.p, c->bsc.p, c->bact.p, s);
+      cgb_update_p(nM, w, c->bp.p, zn, c->bsc.p, s);
+    };
+    double2 *zb[2] = {c->bz.p, c->bzo.p};
+    // HIP graphs of the three launch sequences, captured once per width
+    // (B in two versions: z and z_old swap every iteration)
+    const bool graphs = !c->prof.on;
+    if (graphs && S.gw != w) {
+      S.graphs.reset(new GraphSet());
+      S.graphs->a = capture(s, part_a);
+      S.graphs->b[0] = capture(s, [&]() { part_b(zb[0], zb[1]); });
+      S.graphs->b[1] = capture(s, [&]() { part_b(zb[1], zb[0]); });
+      S.gw = w;
+    }
+    S.cur ^= 1;
+    if (graphs) {
+      HIP_OK(hipGraphLaunch(S.graphs->b[S.cur], s));
+      HIP_OK(hipGraphLaunch(S.graphs->a, s));
+    } else {
+      part_b(zb[S.cur], zb[S.cur ^ 1]);
+      part_a();
+    }
+    HIP_OK(hipMemcpyAsync(Sc, c->bsc.p, 8 * kMaxCols * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (int k = 0; k < w; ++k) {
+      if (S.state[k] != 1) continue;
+      ++S.iters[k];
+      const double rr = std::sqrt(Sc[4 * kMaxCols + k] / S.bb[k]);
+      if (Sc[6 * kMaxCols + k] != 0.0 || !std::isfinite(rr)) {
+        S.state[k] = 4;                      // breakdown (p^H M p <= 0 or not finite)
+      } else {
+        S.rr[k] = rr;
+        if (rr <= S.tol[k]) S.state[k] = 2;
+        else if (S.iters[k] >= c->opt.maxit) S.state[k] = 3;
+      }
+      if (S.state[k] != 1) {
+        act[k] = 0;
+        S.act_dirty = true;
+        S.done.push_back(k);
+      }
+    }
+  }
+}
+
+// Solution of a finished slot: its macro-grid column expanded to the full
+// trace vector (recovery of the condensed unknowns) into xout (device); the
+// slot becomes free and the width shrinks while its upper half is free.
+int batch_take(dpg_ctx *c, int k, double2 *xout, int32_t *iters, double *relres) {
+  BatchSession &S = c->bs;
+  if (k < 0 || k >= S.max || S.state[k] < 2)
+    throw DpgError(DPG_ESTATE, "slot " + std::to_string(k) + " holds no finished solve");
+  LevelData &top = c->lv[c->L];
+  const hipStream_t s = c->stream;
+  const int64_t nM = top.nM, nT = top.num.n;
+  launch_get_col(nM, S.w, k, c->bx.p, c->x.p, s);
+  launch_get_col(nT, S.w, k, c->bsv.p, c->sB.p, s);
+  launch_expand<double>(top.WH.p, top.Tinv.p, top.nI, top.nBf, top.blkI.p, top.blkBm.p, top.nblk,
+                        c->sB.p, c->x.p, nM, top.macroB.p, xout, s);
+  if (iters) *iters = S.iters[k];
+  if (relres) *relres = S.rr[k];
+  const int st = S.state[k] == 2 ? DPG_OK : S.state[k] == 3 ? DPG_ENOCONV : DPG_EBREAKDOWN;
+  S.state[k] = 0;
+  for (size_t i = 0; i < S.done.size(); ++i)
+    if (S.done[i] == k) {
+      S.done.erase(S.done.begin() + i);
+      break;
+    }
+  int w = S.w;
+  while (w > 1) {
+    bool upper_free = true;
+    for (int j = w / 2; j < w; ++j) upper_free = upper_free && S.state[j] == 0;
+    if (!upper_free) break;
+    w /= 2;
+  }
+  batch_width(c, w);
+  return st;
+}
+
+// All nr columns of a freshly opened batch at once ([nr][n_trace], device): the block
+// condensation and one reduction for every column, one host sync.
+void batch_add_all(dpg_ctx *c, const double2 *sv_cols, int nr, double tol) {
+  BatchSession &S = c->bs;
+  LevelData &top = c->lv[c->L];
+  const hipStream_t s = c->stream;
+  const int64_t nM = top.nM, nT = top.num.n;
+  S.w = nr;   // the vectors of a freshly opened batch are zero in every layout
   launch_interleave(nT, nr, sv_cols, c->bsv.p, s);
   launch_condense_blk<double>(top.WH.p, top.nI, top.nBf, top.blkI.p, top.nblk, nM, top.macroB.p,
-                              top.cred_ptr.p, top.cred_ent.p, c->bsv.p, top.bc64.p, c->bb.p, nr,
+                              top.cred_ptr.p, top.cred_ent.p, c->bsv.p, top.bc64.p, c->br.p, nr,
                               s);
-  HIP_OK(hipMemsetAsync(c->bsc.p, 0, 8 * kMaxCols * sizeof(double), s));
-  cgb_dot(nM, nr, c->bb.p, c->bb.p, c->bpartial.p, c->bsc.p, 5, s);
-  HIP_OK(hipMemsetAsync(c->bx.p, 0, nM * nr * 16, s));
-  HIP_OK(hipMemcpyAsync(c->br.p, c->bb.p, nM * nr * 16, hipMemcpyDeviceToDevice, s));
-  auto read_bsc = [&]() {
-    HIP_OK(hipMemcpyAsync(S, c->bsc.p, 8 * kMaxCols * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-  };
-  read_bsc();
-  std::vector<double> bb(nr), rr(nr, 0.0);
-  int nact = 0;
+  for (int k = 0; k < nr; ++k) cgb_reset_col(c->bsc.p, k, s);
+  cgb_dot(nM, nr, c->br.p, c->br.p, c->bpartial.p, c->bsc.p, 5, s);
+  HIP_OK(hipMemcpyAsync(c->host_bsc, c->bsc.p, 8 * kMaxCols * sizeof(double),
+                        hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
   for (int k = 0; k < nr; ++k) {
-    bb[k] = S[5 * kMaxCols + k];
-    if (!std::isfinite(bb[k])) throw DpgError(DPG_EINVAL, "right-hand side is not finite");
-    act[k] = bb[k] > 0.0;
-    nact += act[k];
-    iters[k] = 0;
-    rr[k] = act[k] ? 1.0 : 0.0;
-  }
-  for (int k = nr; k < kMaxCols; ++k) act[k] = 0;
-  auto push_act = [&]() {
-    HIP_OK(hipMemcpyAsync(c->bact.p, act, kMaxCols * sizeof(int), hipMemcpyHostToDevice, s));
-  };
-  push_act();
-  int it = 0, status = DPG_OK;
-  if (nact > 0) {
-    double2 *z = c->bz.p, *zo = c->bzo.p;
-    precondition_blk(c, c->br.p, z, nr);
-    cgb_dot(nM, nr, c->br.p, z, c->bpartial.p, c->bsc.p, 0, s);
-    HIP_OK(hipMemcpyAsync(c->bp.p, z, nM * nr * 16, hipMemcpyDeviceToDevice, s));
-    while (it < c->opt.maxit) {
-      herm_apply_blk<double>(top.Mset, top.Mb, c->bp.p, c->bq.p, nullptr, RED_SET, 1.0, nr, s);
-      {
-        PROF(DPG_K_CG, 0);
-        cgb_alpha(nM, nr, c->bp.p, c->bq.p, c->bpartial.p, c->bsc.p, c->bact.p, s);
-        cgb_update_xr(nM, nr, c->bx.p, c->br.p, c->bp.p, c->bq.p, c->bpartial.p, c->bsc.p, s);
-      }
-      ++it;
-      read_bsc();
-      bool changed = false;
-      for (int k = 0; k < nr; ++k) {
-        if (!act[k]) continue;
-        if (S[6 * kMaxCols + k] != 0.0)
-          throw DpgError(DPG_EBREAKDOWN, "CG breakdown in column " + std::to_string(k) +
-                                             " at iteration " + std::to_string(it));
-        rr[k] = std::sqrt(S[4 * kMaxCols + k] / bb[k]);
-        if (!std::isfinite(rr[k])) throw DpgError(DPG_EBREAKDOWN, "residual is not finite");
-        iters[k] = it;
-        if (rr[k] <= tol) {
-          act[k] = 0;
-          --nact;
-          changed = true;
-        }
-      }
-      if (nact == 0) break;
-      if (changed) push_act();
-      std::swap(z, zo);
-      precondition_blk(c, c->br.p, z, nr);
-      PROF(DPG_K_CG, 0);
-      cgb_beta(nM, nr, c->br.p, z, zo, c->bpartial.p, c->bsc.p, c->bact.p, s);
-      cgb_update_p(nM, nr, c->bp.p, z, c->bsc.p, s);
+    const double bb = c->host_bsc[5 * kMaxCols + k];
+    if (!std::isfinite(bb)) throw DpgError(DPG_EINVAL, "right-hand side is not finite");
+    S.bb[k] = bb;
+    S.tol[k] = tol;
+    S.iters[k] = 0;
+    if (bb > 0.0) {
+      S.state[k] = 1;
+      S.rr[k] = 1.0;
+      c->host_bact[k] = 1;
+    } else {
+      S.state[k] = 2;
+      S.rr[k] = 0.0;
+      S.done.push_back(k);
     }
-    if (nact > 0) status = DPG_ENOCONV;
+  }
+  S.act_dirty = true;
+}
+
+// dpg_solve's block path: nr <= kMaxCols loads sv_cols ([nr][n_trace],
+// device) through one batch, full trace solutions to xcols likewise (block
+// expansion of all columns).
+int solve_block(dpg_ctx *c, const double2 *sv_cols, int nr, double tol, double2 *xcols,
+                int32_t *iters, double *relres) {
+  batch_open(c, nr);
+  batch_add_all(c, sv_cols, nr, tol);
+  BatchSession &S = c->bs;
+  LevelData &top = c->lv[c->L];
+  const int64_t nT = top.num.n, nM = top.nM;
+  int status = DPG_OK;
+  for (;;) {
+    int running = 0;
+    for (int k = 0; k < S.w; ++k) running += S.state[k] == 1;
+    if (!running) break;
+    batch_step(c, c->opt.maxit);
+    for (int k = 0; k < S.w; ++k)
+      if (S.state[k] == 4)
+        throw DpgError(DPG_EBREAKDOWN, "CG breakdown in column " + std::to_string(k) +
+                                           " at iteration " + std::to_string(S.iters[k]));
   }
   launch_expand_blk<double>(top.WH.p, top.Tinv.p, top.nI, top.nBf, top.blkI.p, top.blkBm.p,
-                            top.nblk, c->bsv.p, c->bx.p, nM, top.macroB.p, c->bxf.p, nr, s);
-  launch_deinterleave(nT, nr, c->bxf.p, xcols, s);
-  HIP_OK(hipStreamSynchronize(s));
-  for (int k = 0; k < nr; ++k) relres[k] = rr[k];
+                            top.nblk, c->bsv.p, c->bx.p, nM, top.macroB.p, c->bxf.p, nr,
+                            c->stream);
+  launch_deinterleave(nT, nr, c->bxf.p, xcols, c->stream);
+  for (int k = 0; k < nr; ++k) {
+    iters[k] = S.iters[k];
+    relres[k] = S.rr[k];
+    if (S.state[k] == 3) status = DPG_ENOCONV;
+  }
+  HIP_OK(hipStreamSynchronize(c->stream));
+  batch_close(c);
   return status;
 }
 
@@ -1195,6 +1526,8 @@ int dpg_setup(const dpg_mesh *mesh, int p, int dp, double omega, const dpg_mater
       throw DpgError(DPG_EINVAL, "bad smoothing counts or maxit");
     if (c->opt.precision != DPG_FP64 && c->opt.precision != DPG_MIXED)
       throw DpgError(DPG_EINVAL, "unknown precision mode");
+    if ((c->opt.flags & DPG_RECOMPUTE_PATCHES) && c->opt.precision != DPG_FP64)
+      throw DpgError(DPG_EINVAL, "recomputed patch inverses are an FP64 path");
     HIP_OK(hipGetDevice(&c->device));
     (void)scratch_device_ptr(c->device, true);   // once per device, with it current
     c->stream = (hipStream_t)c->opt.stream;
@@ -1310,7 +1643,18 @@ int dpg_setup(const dpg_mesh *mesh, int p, int dp, double omega, const dpg_mater
       const int np = (int)f.mc.patch_ptr.size() - 1;
       std::vector<int32_t> psz(np);
       for (int v = 0; v < np; ++v) psz[v] = (int32_t)(f.mc.patch_ptr[v + 1] - f.mc.patch_ptr[v]);
-      f.Sset.build(psz, f.mc.patch_idx, f.nM, !mixed, mixed, &c->bud, s);
+      if (c->opt.flags & DPG_RECOMPUTE_PATCHES) {   // no tiles: the inverses are recomputed
+        std::vector<int32_t> pidx((size_t)f.nblk * f.nBf, -1);   // slot -> packed position
+        for (int b = 0; b < f.nblk; ++b)
+          for (int64_t k = f.mc.blkB_ptr[b]; k < f.mc.blkB_ptr[b + 1]; ++k)
+            pidx[(size_t)b * f.nBf + f.mc.blkB_present[k]] = (int32_t)(k - f.mc.blkB_ptr[b]);
+        f.mpidx.upload(pidx, &c->bud, s);
+        f.Sset.build(psz, f.mc.patch_idx, f.nM, false, false, &c->bud, s);
+        f.Sset.xl64.alloc(f.Sset.nloc, &c->bud);
+        f.Sset.yl64.alloc(f.Sset.nloc, &c->bud);
+      } else {
+        f.Sset.build(psz, f.mc.patch_idx, f.nM, !mixed, mixed, &c->bud, s);
+      }
       f.Mset.prof = &c->prof;
       f.Sset.prof = &c->prof;
       // work vectors
@@ -1419,7 +1763,8 @@ int dpg_assemble(dpg_ctx *c) {
     c->s_asm.ensure(std::max<int64_t>(1, (int64_t)c->nrhs * top.num.n), &c->bud);
     if (c->keep_recovery) {
       c->rec_L.ensure((int64_t)top.nel * c->n_field * c->n_field, &c->bud);
-      c->rec_Y.ensure((int64_t)top.nel * c->n_field * (c->n_tr + c->nrhs), &c->bud);
+      c->rec_Y.ensure((int64_t)top.nel * c->n_field * c->n_tr, &c->bud);
+      c->rec_Yb.ensure(std::max<int64_t>(1, (int64_t)top.nel * c->n_field * c->nrhs), &c->bud);
     }
     element_stage(c, c->L, true);
     c->prof.flush();
@@ -1451,6 +1796,8 @@ int dpg_release_setup(dpg_ctx *c) {
     HIP_OK(hipStreamSynchronize(c->aux));
     for (hipStream_t x : c->paux)
       if (x) HIP_OK(hipStreamSynchronize(x));
+    const bool rec = c->opt.flags & DPG_RECOMPUTE_PATCHES;   // the smoother needs the
+                                                             // patch work areas
     for (LevelData &f : c->lv) {
       f.E.release();
       f.Mfull.release();
@@ -1461,7 +1808,7 @@ int dpg_release_setup(dpg_ctx *c) {
       c->mX[k].release();
       c->mwk[k].release();
     }
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 4 && !rec; ++k) {
       c->pS[k].release();
       c->pX[k].release();
       c->pwk[k].release();
@@ -1485,11 +1832,23 @@ int dpg_load_rhs(dpg_ctx *c, const dpg_load *loads, int nrhs, double *s_out) {
     set_loads(c, loads, nrhs);
     c->s_elem.ensure((int64_t)nrhs * top.nel * c->n_tr, &c->bud);
     c->s_asm.ensure((int64_t)nrhs * top.num.n, &c->bud);
-    if (c->keep_recovery) {
-      c->rec_L.ensure((int64_t)top.nel * c->n_field * c->n_field, &c->bud);
-      c->rec_Y.ensure((int64_t)top.nel * c->n_field * (c->n_tr + c->nrhs), &c->bud);
+    if (c->keep_recovery)
+      c->rec_Yb.ensure((int64_t)top.nel * c->n_field * c->nrhs, &c->bud);
+    std::vector<int32_t> list;
+    if (source_elements(c, list)) {
+      element_stage(c, c->L, false);
+    } else {
+      // point sources only: the elements near a source carry the whole load
+      const hipStream_t s = c->stream;
+      launch_zero(c->s_elem.n, c->s_elem.p, s);
+      if (c->keep_recovery) launch_zero(c->rec_Yb.n, c->rec_Yb.p, s);
+      grow(c->elist, std::max<int64_t>(1, (int64_t)list.size()), &c->bud);
+      if (!list.empty())
+        HIP_OK(hipMemcpyAsync(c->elist.p, list.data(), list.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
+      HIP_OK(hipStreamSynchronize(s));
+      element_stage(c, c->L, false, nullptr, c->elist.p, (int)list.size());
     }
-    element_stage(c, c->L, false);
     c->prof.flush();
     if (s_out) {
       const bool dev = c->opt.flags & DPG_DEVICE_PTRS;
@@ -1513,7 +1872,8 @@ int dpg_solve(dpg_ctx *c, const double *rhs, int nrhs, double tol, double *x_out
     const int64_t nT = top.num.n;
     const bool dev = c->opt.flags & DPG_DEVICE_PTRS;
     int status = DPG_OK;
-    if (nrhs > 1 && !(c->opt.flags & DPG_COLUMNWISE)) {
+    if (nrhs > 1 && !(c->opt.flags & (DPG_COLUMNWISE | DPG_RECOMPUTE_PATCHES))) {
+      if (c->bs.open) throw DpgError(DPG_ESTATE, "a batch is open (dpg_batch_close first)");
       for (int k0 = 0; k0 < nrhs; k0 += kMaxCols) {
         const int nr = std::min(kMaxCols, nrhs - k0);
         ensure_block(c, nr);
@@ -1589,12 +1949,88 @@ int dpg_get_fields(dpg_ctx *c, const double *x, int nrhs, double *fields_out) {
     for (int k = 0; k < nrhs; ++k) {
       HIP_OK(hipMemcpyAsync(c->sB.p, x + 2 * nT * k, nT * 16,
                             dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
-      launch_fields(c->rec_L.p, c->rec_Y.p, c->n_field, c->n_tr, c->nrhs, k, top.edofs.p,
+      launch_fields(c->rec_L.p, c->rec_Y.p, c->rec_Yb.p, c->n_field, c->n_tr, c->nrhs, k, top.edofs.p,
                     top.nel, c->sB.p, out.p, c->stream);
       HIP_OK(hipMemcpyAsync(fields_out + 2 * nfe * k, out.p, nfe * 16,
                             dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
       HIP_OK(hipStreamSynchronize(c->stream));
     }
+    return DPG_OK;
+  });
+}
+
+int dpg_batch_open(dpg_ctx *c, int max_slots) {
+  if (!c) return DPG_EINVAL;
+  return guarded(c, [&]() {
+    if (c->stage < 3) throw DpgError(DPG_ESTATE, "dpg_build_hierarchy first");
+    batch_open(c, max_slots);
+    return DPG_OK;
+  });
+}
+
+int dpg_batch_add(dpg_ctx *c, const double *rhs, int load_col, double tol, int32_t *slot_out) {
+  if (!c) return DPG_EINVAL;
+  return guarded(c, [&]() {
+    if (!c->bs.open) throw DpgError(DPG_ESTATE, "dpg_batch_open first");
+    if (!(tol >= 0.0)) throw DpgError(DPG_EINVAL, "bad tol");
+    const int64_t nT = c->lv[c->L].num.n;
+    const double2 *sv;
+    if (rhs) {
+      const bool dev = c->opt.flags & DPG_DEVICE_PTRS;
+      HIP_OK(hipMemcpyAsync(c->sB.p, rhs, nT * 16,
+                            dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+      sv = c->sB.p;
+    } else {
+      if (load_col < 0 || load_col >= c->nrhs)
+        throw DpgError(DPG_EINVAL, "load column out of range");
+      sv = c->s_asm.p + nT * load_col;
+    }
+    const int k = batch_add(c, sv, tol);
+    if (slot_out) *slot_out = k;
+    return DPG_OK;
+  });
+}
+
+int dpg_batch_step(dpg_ctx *c, int max_iters, int32_t *done_out, int32_t *ndone_out) {
+  if (!c) return DPG_EINVAL;
+  return guarded(c, [&]() {
+    if (!c->bs.open) throw DpgError(DPG_ESTATE, "dpg_batch_open first");
+    if (max_iters < 0) throw DpgError(DPG_EINVAL, "bad max_iters");
+    auto t0 = clk::now();
+    batch_step(c, max_iters);
+    c->prof.flush();
+    c->ms[3] = ms_since(t0);
+    const BatchSession &S = c->bs;
+    if (done_out)
+      for (size_t i = 0; i < S.done.size(); ++i) done_out[i] = S.done[i];
+    if (ndone_out) *ndone_out = (int32_t)S.done.size();
+    return DPG_OK;
+  });
+}
+
+int dpg_batch_take(dpg_ctx *c, int slot, double *x_out, int32_t *iters_out, double *relres_out) {
+  if (!c) return DPG_EINVAL;
+  return guarded(c, [&]() {
+    if (!c->bs.open) throw DpgError(DPG_ESTATE, "dpg_batch_open first");
+    const int64_t nT = c->lv[c->L].num.n;
+    const int st = batch_take(c, slot, c->xfull.p, iters_out, relres_out);
+    if (x_out) {
+      const bool dev = c->opt.flags & DPG_DEVICE_PTRS;
+      HIP_OK(hipMemcpyAsync(x_out, c->xfull.p, nT * 16,
+                            dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    }
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (st == DPG_ENOCONV) c->err = "maximum number of iterations reached";
+    if (st == DPG_EBREAKDOWN) c->err = "CG breakdown in slot " + std::to_string(slot);
+    return st;
+  });
+}
+
+int dpg_batch_close(dpg_ctx *c) {
+  if (!c) return DPG_EINVAL;
+  return guarded(c, [&]() {
+    HIP_OK(hipStreamSynchronize(c->stream));
+    batch_close(c);
     return DPG_OK;
   });
 }
@@ -1790,6 +2226,8 @@ int64_t dpg_export(const dpg_ctx *cc, int what, int level, void *out, int64_t ca
         need_macro();
         if (c->stage < 3) throw DpgError(DPG_ESTATE, "dpg_build_hierarchy first");
         HermSet &H = f.Sset;
+        if (!H.t64.p && !H.t32.p)
+          throw DpgError(DPG_ESTATE, "patch inverses are not stored (DPG_RECOMPUTE_PATCHES)");
         std::vector<double2> t;
         if (H.t64.p) t = H.t64.download(s);
         else {
@@ -1835,6 +2273,8 @@ int64_t dpg_export(const dpg_ctx *cc, int what, int level, void *out, int64_t ca
 
 void dpg_destroy(dpg_ctx *c) {
   if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  batch_close(c);
   if (c->host_sc) (void)hipHostFree(c->host_sc);
   if (c->aux) {
     (void)hipStreamSynchronize(c->aux);

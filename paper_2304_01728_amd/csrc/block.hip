@@ -476,6 +476,35 @@ __global__ __launch_bounds__(256) void k_interleave(int64_t n, int nr, const dou
   else blk[(int64_t)k * n + d] = cols[e];
 }
 
+// Column k of an interleaved block of width w: set from a plain vector (or
+// zero), or copied out.
+__global__ __launch_bounds__(256) void k_col(int64_t n, int w, int k, const double2 *__restrict__ src,
+                                             double2 *__restrict__ dst, int dir) {
+  const int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (d >= n) return;
+  if (dir == 0) dst[d * w + k] = src ? src[d] : mk(0.0, 0.0);
+  else dst[d] = src[d * w + k];
+}
+
+// dst (width w_new) <- src (width w_old): columns k < min(w_old, w_new) kept,
+// new columns zero.
+__global__ __launch_bounds__(256) void k_rewidth(int64_t n, int w_old, int w_new,
+                                                 const double2 *__restrict__ src,
+                                                 double2 *__restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * w_new) return;
+  const int64_t d = e / w_new;
+  const int k = (int)(e % w_new);
+  dst[e] = k < w_old ? src[d * w_old + k] : mk(0.0, 0.0);
+}
+
+// A column joining a block solve: rz = 1 (so that its first flexible beta is
+// finite; it multiplies a zero search direction), every other scalar 0.
+__global__ void k_col_reset(double *sc, int k) {
+  const int q = threadIdx.x;
+  if (q < 8) sc[q * kMaxCols + k] = q == 0 ? 1.0 : 0.0;
+}
+
 // ---- per-column CG --------------------------------------------------------------------
 
 // Per workgroup and column: sums of Re(a^H b) (and Re(a^H c) when c).
@@ -599,6 +628,10 @@ template <typename T>
 void herm_apply_blk(HermSet &H, HermBlockBufs &W, const cplx_t<T> *X, cplx_t<T> *Y,
                     const cplx_t<T> *R, int mode, T theta, int nr, hipStream_t s) {
   if (nr < 1 || nr > kMaxCols || nr > W.cap) throw DpgError(-1, "block apply: bad column count");
+  if (nr == 1) {   // one column: the HBM-bound single-vector apply (same layout)
+    herm_apply<T>(H, X, Y, R, mode, theta, s);
+    return;
+  }
   const cplx_t<T> *tiles;
   cplx_t<T> *xl, *yl;
   if constexpr (sizeof(T) == 8) {
@@ -701,6 +734,28 @@ void launch_interleave(int64_t n, int nr, const double2 *cols, double2 *blk, hip
 }
 void launch_deinterleave(int64_t n, int nr, const double2 *blk, double2 *cols, hipStream_t s) {
   hipLaunchKernelGGL(k_interleave, dim3(cdiv(n * nr, 256)), dim3(256), 0, s, n, nr, blk, cols, 1);
+  LAUNCH_OK();
+}
+
+void launch_set_col(int64_t n, int w, int k, const double2 *src, double2 *blk, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_col, dim3(cdiv(n, 256)), dim3(256), 0, s, n, w, k, src, blk, 0);
+  LAUNCH_OK();
+}
+void launch_get_col(int64_t n, int w, int k, const double2 *blk, double2 *dst, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_col, dim3(cdiv(n, 256)), dim3(256), 0, s, n, w, k, blk, dst, 1);
+  LAUNCH_OK();
+}
+void launch_rewidth(int64_t n, int w_old, int w_new, const double2 *src, double2 *dst,
+                    hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_rewidth, dim3(cdiv(n * w_new, 256)), dim3(256), 0, s, n, w_old, w_new,
+                     src, dst);
+  LAUNCH_OK();
+}
+void cgb_reset_col(double *sc, int k, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_reset, dim3(1), dim3(64), 0, s, sc, k);
   LAUNCH_OK();
 }
 

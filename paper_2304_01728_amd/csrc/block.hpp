@@ -50,6 +50,14 @@ void launch_expand_blk(const cplx_t<T> *WH, const cplx_t<T> *Tinv, int nI, int n
 void launch_interleave(int64_t n, int nr, const double2 *cols, double2 *blk, hipStream_t s);
 void launch_deinterleave(int64_t n, int nr, const double2 *blk, double2 *cols, hipStream_t s);
 
+// Column k of an interleaved block of width w: blk[:, k] = src (zero when src
+// is null), or dst = blk[:, k].
+void launch_set_col(int64_t n, int w, int k, const double2 *src, double2 *blk, hipStream_t s);
+void launch_get_col(int64_t n, int w, int k, const double2 *blk, double2 *dst, hipStream_t s);
+// dst (n x w_new) <- src (n x w_old), columns beyond w_old zero (dst != src).
+void launch_rewidth(int64_t n, int w_old, int w_new, const double2 *src, double2 *dst,
+                    hipStream_t s);
+
 // ---- per-column CG on interleaved FP64 blocks ----------------------------------------
 // Device scalars sc[q * kMaxCols + k] for column k: q = 0 rz, 1 pq, 2 alpha,
 // 3 beta, 4 ||r||^2, 5 ||b||^2, 6 breakdown flag, 7 r^H z_old.  act[k] != 0
@@ -66,5 +74,9 @@ void cgb_beta(int64_t n, int nr, const double2 *r, const double2 *z, const doubl
               double *partial, double *sc, const int *act, hipStream_t s);
 void cgb_update_p(int64_t n, int nr, double2 *p, const double2 *z, const double *sc,
                   hipStream_t s);
+// Scalars of a column that joins a running block solve (its x, p, z and z_old
+// columns zero, r = b): rz = 1, the others 0, so that its first beta step
+// sets p = z and rz = r^H z.
+void cgb_reset_col(double *sc, int k, hipStream_t s);
 
 }  // namespace dpg

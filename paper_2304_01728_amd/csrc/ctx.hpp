@@ -1,6 +1,7 @@
 // Internal context of libdpgmg.
 #pragma once
 #include <chrono>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -61,6 +62,7 @@ struct PatchBatch {
   DevBuf<PotrfItem> pi;
   DevBuf<TrsmItem> ti;
   DevBuf<GemmItem> gi;
+  DevBuf<GemmItem> gy, gz;           // recomputed inverses: t = X x_v, y_v = X^H t
 };
 struct PatchPlan {
   bool ready = false;
@@ -93,6 +95,8 @@ struct LevelData {
   DevBuf<int32_t> cred_ptr, cred_ent;
   DevBuf<int64_t> patch_ptr;
   DevBuf<int32_t> patch_slot;
+  DevBuf<int32_t> mpidx;             // [nblk][nBf] packed position of each macro-block slot
+                                     // (recomputed patch inverses)
   HermSet Mset, Sset;
   DevBuf<int64_t> Pptr, Ptptr;
   DevBuf<int32_t> Pcol, Ptcol;
@@ -109,6 +113,36 @@ struct LevelData {
   HermBlockBufs Mb, Sb;
   MacroPlan mp;
   PatchPlan pp;
+};
+
+// Instantiated HIP graphs of the PCG iteration: (A) matvec, alpha, x and r;
+// (B) V-cycle, beta, search direction, in two versions (z and z_old swap
+// every iteration).  Destroyed with the object.
+struct GraphSet {
+  hipGraphExec_t a = nullptr, b[2] = {nullptr, nullptr};
+  GraphSet() = default;
+  GraphSet(const GraphSet &) = delete;
+  GraphSet &operator=(const GraphSet &) = delete;
+  ~GraphSet() {
+    for (hipGraphExec_t g : {a, b[0], b[1]})
+      if (g) (void)hipGraphExecDestroy(g);
+  }
+};
+
+// A block PCG whose columns join and leave while it runs (continuous
+// batching; dpg_batch_* and the block path of dpg_solve).  Slot k is column
+// k of the interleaved block vectors of the context (width w).
+struct BatchSession {
+  bool open = false;
+  int max = 0, w = 0;                // capacity, current width (a power of two or max)
+  int cur = 0;                       // which of bz / bzo holds z
+  int state[kMaxCols] = {};          // 0 free, 1 running, 2 converged, 3 maxit, 4 breakdown
+  int iters[kMaxCols] = {};
+  double tol[kMaxCols] = {}, bb[kMaxCols] = {}, rr[kMaxCols] = {};
+  bool act_dirty = true;
+  std::vector<int> done;             // finished slots not taken yet, in finishing order
+  std::unique_ptr<GraphSet> graphs;  // captured for width gw
+  int gw = 0;
 };
 
 }  // namespace dpg
@@ -147,7 +181,8 @@ struct dpg_ctx {
   dpg::DevBuf<double2> s_elem;       // [nrhs][nel][n_tr] condensed element loads
   dpg::DevBuf<double2> s_asm;        // [nrhs][n_trace] assembled loads
   dpg::DevBuf<int32_t> asm_ptr, asm_ent;
-  dpg::DevBuf<double2> rec_L, rec_Y; // [nel][nf^2], [nel][nf (n_tr + nrhs)]
+  dpg::DevBuf<double2> rec_L, rec_Y, rec_Yb;  // [nel][nf^2], [nel][nf n_tr], [nel][nrhs nf]
+  dpg::DevBuf<int32_t> elist;        // elements of a point-source load update
   // coarsest mesh
   dpg::DevBuf<double2> T0;
   dpg::HermSet T0set;
@@ -155,6 +190,7 @@ struct dpg_ctx {
   dpg::ElemPlan ep;
   dpg::DevBuf<double2> mT[2], mLinv[2], mX[2], mwk[2];   // macro levels, one set per stream
   dpg::DevBuf<double2> pS[4], pX[4], pwk[4];       // patches, one set per part
+  dpg::DevBuf<double2> ptmp;                       // recomputed inverses: X x_v, local layout
   dpg::DevBuf<double2> zF, zLi, zTi, zwk;          // coarsest
   dpg::DevBuf<dpg::PotrfItem> zpi;
   dpg::DevBuf<dpg::TrsmItem> zti;
@@ -174,6 +210,7 @@ struct dpg_ctx {
   dpg::DevBuf<int> bact;
   double *host_bsc = nullptr;        // pinned, 8 x kMaxCols
   int *host_bact = nullptr;          // pinned, kMaxCols
+  dpg::BatchSession bs;
   double ms[4] = {0, 0, 0, 0};
   dpg::Prof prof;
 };

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_gram(const ElemTables *__restrict__ tb,
   // Cholesky that follows reads the lower triangle only)
   const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (j >= nt) return;
-  const int e = e0 + blockIdx.y;
+  const int e = g.elist ? g.elist[e0 + blockIdx.y] : e0 + blockIdx.y;
   const int4 tj = test[j];
   const double hh = 0.5 * g.h, w = g.omega, kap = kappa ? kappa[e] : 1.0;
   const int b[3] = {tj.y, tj.z, tj.w};
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_bmat(const ElemTables *__restrict__ tb,
   // one wave per trial function j, its lanes over the test functions i
   const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (j >= m) return;
-  const int e = e0 + blockIdx.y;
+  const int e = g.elist ? g.elist[e0 + blockIdx.y] : e0 + blockIdx.y;
   const int4 tr = trial[j];
   const double hh = 0.5 * g.h, w = g.omega, kap = kappa ? kappa[e] : 1.0;
   const double Z = Zel ? Zel[e] : 1.0;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void k_load(const ElemTables *__restrict__ tb,
   __shared__ double2 buf2[LX * LQ * LQ];   // first contraction
   __shared__ double2 lq[LX * LX * LX];     // q-part of the load
   const int tid = threadIdx.x;
-  const int e = e0 + blockIdx.x, r = blockIdx.y;
+  const int e = g.elist ? g.elist[e0 + blockIdx.x] : e0 + blockIdx.x, r = blockIdx.y;
   const LoadDesc L = ld[r];
   const int P1 = tb->P1, nq = tb->nql;
   const double hh = 0.5 * g.h;

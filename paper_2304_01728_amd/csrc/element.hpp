@@ -50,6 +50,8 @@ struct ElemGeom {
   int N;
   double h, omega, alpha;
   double org[3];
+  const int32_t *elist;   // device list of the elements to process (index e0 + i of a
+                          // launch), or null for the elements e0 + i themselves
 };
 
 void build_elem_tables(int p, int dp, ElemTables &t);

@@ -391,6 +391,7 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
   }
   tile_off_h = toff;
   ent_off_h = eoff;
+  loc_off_h = loff;
   // reduction lists: for every vector entry, the local rows holding it
   std::vector<int32_t> cnt(nvec + 1, 0);
   for (int32_t v : gi) {
@@ -475,6 +476,34 @@ void herm_apply(HermSet &H, const cplx_t<T> *x, cplx_t<T> *y, const cplx_t<T> *r
                      part, yl);
   LAUNCH_OK();
   const dim3 g(cdiv(H.nvec, 256));
+  switch (mode) {
+    case RED_SET:
+      hipLaunchKernelGGL((k_scatter<T, RED_SET>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
+      break;
+    case RED_RESID:
+      hipLaunchKernelGGL((k_scatter<T, RED_RESID>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
+      break;
+    case RED_AXPY:
+      hipLaunchKernelGGL((k_scatter<T, RED_AXPY>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
+      break;
+    default:
+      hipLaunchKernelGGL((k_scatter<T, RED_SET_SCALED>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
+  }
+  LAUNCH_OK();
+}
+
+void herm_gather(HermSet &H, const double2 *x, double2 *xl, hipStream_t s) {
+  ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
+  hipLaunchKernelGGL((k_gather_x<double>), dim3(cdiv(H.nloc, 256)), dim3(256), 0, s, H.nloc,
+                     H.gidx.p, x, xl);
+  LAUNCH_OK();
+}
+
+void herm_scatter(HermSet &H, const double2 *yl, double2 *y, const double2 *r, int mode,
+                  double theta, hipStream_t s) {
+  ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
+  const dim3 g(cdiv(H.nvec, 256));
+  using T = double;
   switch (mode) {
     case RED_SET:
       hipLaunchKernelGGL((k_scatter<T, RED_SET>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);

@@ -51,6 +51,7 @@ struct HermSet {
   int64_t full = 0;          // sum of n_b^2 (entries of the full blocks)
   std::vector<int32_t> n_h;  // block sizes (host)
   std::vector<int64_t> tile_off_h, ent_off_h;   // per block: first tile index, first entry
+  std::vector<int64_t> loc_off_h;                // per block: first row of its local vectors
   DevBuf<int32_t> bn;
   DevBuf<int64_t> ent_off, cp_off, rp_off, loc_off;
   DevBuf<int32_t> gidx;      // [nloc] vector index of each padded local row, -1 = padding
@@ -81,6 +82,13 @@ struct HermSet {
             const int64_t *map_off_dev, const int32_t *map_dev, hipStream_t s, int64_t tile0 = 0,
             int64_t ntile_count = -1);
 };
+
+// The first and last phases of herm_apply alone (FP64), for a caller that
+// applies the blocks itself: xl = the local vectors R_b x (block b at
+// loc_off_h[b], 32-padded with zeros); y <- epilogue(sum_b R_b^T yl_b).
+void herm_gather(HermSet &H, const double2 *x, double2 *xl, hipStream_t s);
+void herm_scatter(HermSet &H, const double2 *yl, double2 *y, const double2 *r, int mode,
+                  double theta, hipStream_t s);
 
 // y <- epilogue(sum_b R_b^T A_b R_b x): RED_SET y = Ax; RED_RESID y = r - Ax;
 // RED_AXPY y += theta Ax; RED_SET_SCALED y = theta Ax.

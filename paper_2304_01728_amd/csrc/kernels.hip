@@ -1,6 +1,8 @@
 // Hierarchy-setup and solve-phase kernels (see kernels.hpp).
 #include "kernels.hpp"
 
+#include "hblocks.hpp"
+
 namespace dpg {
 namespace {
 
@@ -71,13 +73,79 @@ __global__ __launch_bounds__(256) void k_macro_assemble(const double2 *__restric
 __global__ __launch_bounds__(256) void k_copy_sub(const double2 *__restrict__ src,
                                                   int64_t src_stride, int lds, int r0, int c0,
                                                   int rows, int cols, double2 *__restrict__ dst,
-                                                  int64_t dst_stride, int ldd) {
+                                                  int64_t dst_stride, int ldd,
+                                                  const int32_t *__restrict__ dlist) {
   // one wave per column, its lanes over the rows
   const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (j >= cols) return;
+  const int64_t db = dlist ? dlist[blockIdx.y] : blockIdx.y;
+  double2 *dc = dst + db * dst_stride + (int64_t)j * ldd;
+  if (!src) {
+    for (int i = threadIdx.x & 63; i < rows; i += 64) dc[i] = mk(0.0, 0.0);
+    return;
+  }
   const double2 *sc = src + blockIdx.y * src_stride + r0 + (int64_t)(c0 + j) * lds;
-  double2 *dc = dst + blockIdx.y * dst_stride + (int64_t)j * ldd;
   for (int i = threadIdx.x & 63; i < rows; i += 64) dc[i] = sc[i];
+}
+
+// Entry (i, j) of a Hermitian block stored as packed upper 32x32 tiles (the
+// layout of a HermSet: tile (I, J <= I) at tile_entry, entry (r, c) of a full
+// tile at [4 (r % 4) + c % 4][8 (r / 4) + c / 4], a diagonal tile by its upper
+// 4x4 sub-blocks); the lower triangle by conjugate transposition.
+__device__ __forceinline__ double2 herm_tile_entry(const double2 *__restrict__ blk, int i, int j) {
+  const bool low = i > j;
+  const int a = low ? j : i, b = low ? i : j;
+  const int I = a >> 5, J = b >> 5, r = a & 31, c = b & 31;
+  const int k = 4 * (r & 3) + (c & 3);
+  const double2 v = I < J ? blk[tile_entry(I, J) + k * 64 + 8 * (r >> 2) + (c >> 2)]
+                          : blk[tile_entry(I, I) + k * kDiagSlots + diag_slot(r >> 2, c >> 2)];
+  return low ? cconj(v) : v;
+}
+
+// The patch gather below with the macro blocks read from their packed tiles
+// (tiles + ent_off[b] per block b) instead of full squares: pidx[b nBf + s]
+// is the packed position of the block's local slot s.
+__global__ __launch_bounds__(256) void k_patch_gather_tiles(
+    const double2 *__restrict__ tiles, const int64_t *__restrict__ ent_off,
+    const int32_t *__restrict__ pidx, int nBf, int Nc, const int64_t *__restrict__ pptr,
+    const int32_t *__restrict__ pslot, int v0, const int64_t *__restrict__ dst_off,
+    double2 *__restrict__ S) {
+  const int v = v0 + blockIdx.x;
+  const int64_t p0 = pptr[v];
+  const int n = (int)(pptr[v + 1] - p0);
+  const int jb = blockIdx.y * 8;
+  if (jb >= n) return;
+  const int vx = v % (Nc + 1), vy = (v / (Nc + 1)) % (Nc + 1), vz = v / ((Nc + 1) * (Nc + 1));
+  int blk[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int ci = vx - 1 + (c & 1), cj = vy - 1 + ((c >> 1) & 1), ck = vz - 1 + (c >> 2);
+    blk[c] = (ci >= 0 && cj >= 0 && ck >= 0 && ci < Nc && cj < Nc && ck < Nc)
+                 ? ci + Nc * (cj + Nc * ck) : -1;
+  }
+  const int32_t *sl = pslot + p0 * 8;
+  double2 *Sv = S + dst_off[blockIdx.x];
+  const int jend = min(jb + 8, n);
+  for (int j = jb; j < jend; ++j) {
+    int pj[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int sj = blk[c] >= 0 ? sl[j * 8 + c] : -1;
+      pj[c] = sj >= 0 ? pidx[(int64_t)blk[c] * nBf + sj] : -1;
+    }
+    for (int i = j + threadIdx.x; i < n; i += 256) {
+      double2 acc = mk(0.0, 0.0);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (pj[c] < 0) continue;
+        const int si = sl[(int64_t)i * 8 + c];
+        if (si < 0) continue;
+        const int pi = pidx[(int64_t)blk[c] * nBf + si];
+        acc = cadd(acc, herm_tile_entry(tiles + ent_off[blk[c]], pi, pj[c]));
+      }
+      Sv[i + (int64_t)j * n] = acc;
+    }
+  }
 }
 
 // One workgroup per (patch, kGatCols columns j); the threads take the rows
@@ -287,8 +355,9 @@ __global__ __launch_bounds__(256) void k_assemble_vec(int64_t n, const int32_t *
 }
 
 __global__ __launch_bounds__(256) void k_fields(const double2 *__restrict__ recL,
-                                                const double2 *__restrict__ recY, int nf, int ntr,
-                                                int nrhs, int col,
+                                                const double2 *__restrict__ recY,
+                                                const double2 *__restrict__ recYb, int nf,
+                                                int ntr, int nrhs, int col,
                                                 const int32_t *__restrict__ edofs,
                                                 const double2 *__restrict__ x,
                                                 double2 *__restrict__ out) {
@@ -300,10 +369,11 @@ __global__ __launch_bounds__(256) void k_fields(const double2 *__restrict__ recL
     xt[j] = t >= 0 ? x[t] : mk(0.0, 0.0);
   }
   __syncthreads();
-  const double2 *Y = recY + (int64_t)e * nf * (ntr + nrhs);
+  const double2 *Y = recY + (int64_t)e * nf * ntr;
+  const double2 *Yb = recYb + ((int64_t)e * nrhs + col) * nf;
   const double2 *L = recL + (int64_t)e * nf * nf;
   for (int i = threadIdx.x; i < nf; i += 256) {
-    double2 acc = Y[i + (int64_t)(ntr + col) * nf];
+    double2 acc = Yb[i];
     for (int j = 0; j < ntr; ++j) acc = csub(acc, cmul(Y[i + (int64_t)j * nf], xt[j]));
     v[i] = acc;
   }
@@ -510,10 +580,20 @@ void launch_macro_assemble(const double2 *E, int n_tr, const int32_t *child_inv,
 
 void launch_copy_sub(const double2 *src, int64_t src_stride, int lds, int r0, int c0, int rows,
                      int cols, double2 *dst, int64_t dst_stride, int ldd, int count,
-                     hipStream_t s) {
+                     hipStream_t s, const int32_t *dlist) {
   if (count <= 0 || rows <= 0 || cols <= 0) return;
   hipLaunchKernelGGL(k_copy_sub, dim3(cdiv(cols, 4), count), dim3(256), 0, s,
-                     src, src_stride, lds, r0, c0, rows, cols, dst, dst_stride, ldd);
+                     src, src_stride, lds, r0, c0, rows, cols, dst, dst_stride, ldd, dlist);
+  LAUNCH_OK();
+}
+
+void launch_patch_gather_tiles(const double2 *tiles, const int64_t *ent_off, const int32_t *pidx,
+                               int nBf, int Nc, const int64_t *patch_ptr,
+                               const int32_t *patch_slot, int v0, int count, int nmax,
+                               const int64_t *dst_off, double2 *S, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_patch_gather_tiles, dim3(count, cdiv(nmax, kGatCols)), dim3(256), 0, s,
+                     tiles, ent_off, pidx, nBf, Nc, patch_ptr, patch_slot, v0, dst_off, S);
   LAUNCH_OK();
 }
 
@@ -587,11 +667,12 @@ void launch_assemble_vec(int64_t n, const int32_t *ptr, const int32_t *ent, cons
   LAUNCH_OK();
 }
 
-void launch_fields(const double2 *recL, const double2 *recY, int nf, int ntr, int nrhs, int col,
-                   const int32_t *edofs, int nel, const double2 *x, double2 *out, hipStream_t s) {
+void launch_fields(const double2 *recL, const double2 *recY, const double2 *recYb, int nf,
+                   int ntr, int nrhs, int col, const int32_t *edofs, int nel, const double2 *x,
+                   double2 *out, hipStream_t s) {
   if (nf > kMaxI || ntr > kMaxB) throw DpgError(-1, "element too large for field recovery");
-  hipLaunchKernelGGL(k_fields, dim3(nel), dim3(256), 0, s, recL, recY, nf, ntr, nrhs, col, edofs,
-                     x, out);
+  hipLaunchKernelGGL(k_fields, dim3(nel), dim3(256), 0, s, recL, recY, recYb, nf, ntr, nrhs, col,
+                     edofs, x, out);
   LAUNCH_OK();
 }
 

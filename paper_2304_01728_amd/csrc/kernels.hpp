@@ -13,10 +13,12 @@ namespace dpg {
 void launch_macro_assemble(const double2 *E, int n_tr, const int32_t *child_inv, int N, int b0,
                            int count, int nT, double2 *T, hipStream_t s);
 
-// dst[b][i + j ldd] = src[b][r0 + i + (c0 + j) lds] for i < rows, j < cols.
+// dst[d(b)][i + j ldd] = src[b][r0 + i + (c0 + j) lds] for i < rows, j < cols,
+// b < count, with d(b) = dlist[b] (or b when dlist is null); zeros when src
+// is null.
 void launch_copy_sub(const double2 *src, int64_t src_stride, int lds, int r0, int c0, int rows,
                      int cols, double2 *dst, int64_t dst_stride, int ldd, int count,
-                     hipStream_t s);
+                     hipStream_t s, const int32_t *dlist = nullptr);
 
 // Lower triangle of the patch block S_v (n_v x n_v) gathered from the macro
 // blocks of the <= 8 coarse cells around vertex v: S[i,j] = sum_c M_c[slot_c(i),
@@ -24,6 +26,14 @@ void launch_copy_sub(const double2 *src, int64_t src_stride, int lds, int r0, in
 void launch_patch_gather(const double2 *Mfull, int nBf, int Nc, const int64_t *patch_ptr,
                          const int32_t *patch_slot, int v0, int count, int nmax,
                          const int64_t *dst_off, double2 *S, hipStream_t s);
+
+// The same lower triangle with the macro blocks read from their packed FP64
+// Hermitian tiles (a HermSet: block b at tiles + ent_off[b]); pidx[b nBf + s]
+// = packed position of local slot s of block b (-1 absent).
+void launch_patch_gather_tiles(const double2 *tiles, const int64_t *ent_off, const int32_t *pidx,
+                               int nBf, int Nc, const int64_t *patch_ptr,
+                               const int32_t *patch_slot, int v0, int count, int nmax,
+                               const int64_t *dst_off, double2 *S, hipStream_t s);
 
 // X[b] = identity of size n[b] (column-major, leading dimension n[b]).
 void launch_identity(const int64_t *off, const int32_t *n, int count, int nmax, double2 *X,
@@ -64,10 +74,12 @@ void launch_assemble_vec(int64_t n, const int32_t *ptr, const int32_t *ent, cons
                          int64_t se_stride, double2 *out, hipStream_t s);
 
 // Field recovery (Sec. 1.2, static condensation undone): per element,
-// x_f = K_ff^-1 (b_f - K_ft x_t) = L^-H (Y_b - Y_t x_t) with L = chol(K_ff) and
-// Y = L^-1 [K_ft | b_f] kept from the element stage.  out[e][nf].
-void launch_fields(const double2 *recL, const double2 *recY, int nf, int ntr, int nrhs, int col,
-                   const int32_t *edofs, int nel, const double2 *x, double2 *out, hipStream_t s);
+// x_f = K_ff^-1 (b_f - K_ft x_t) = L^-H (Y_b - Y_t x_t) with L = chol(K_ff),
+// Y_t = L^-1 K_ft ([nel][nf][ntr]) and Y_b = L^-1 b_f ([nel][nrhs][nf]) kept
+// from the element stage; load column col.  out[e][nf].
+void launch_fields(const double2 *recL, const double2 *recY, const double2 *recYb, int nf,
+                   int ntr, int nrhs, int col, const int32_t *edofs, int nel, const double2 *x,
+                   double2 *out, hipStream_t s);
 
 // DPG residual error indicator (Sec. 1.2): per element and load column r,
 // X(:, r) = [x_f; x_t] with x_t gathered from x + r nvec through edofs and

@@ -18,6 +18,7 @@ DPG_FP64, DPG_MIXED = 0, 1
 DPG_DEVICE_PTRS = 1
 DPG_COLUMNWISE = 2
 DPG_STORE_COARSE = 4
+DPG_RECOMPUTE_PATCHES = 8
 (X_ELEM_DOFS, X_MACRO_B, X_BLOCK_B, X_BLOCK_I, X_PATCHES, X_PROLONG, X_ELEM_S, X_ELEM_RHS,
  X_MACRO_M, X_COARSE_E, X_PATCH_INV, X_COARSEST, X_PROLONG_VAL, X_ASM_RHS) = range(1, 15)
 
@@ -28,7 +29,8 @@ SYMBOLS = ["dpg_default_options", "dpg_setup", "dpg_assemble", "dpg_build_hierar
            "dpg_load_rhs", "dpg_solve", "dpg_get_fields", "dpg_info", "dpg_export",
            "dpg_profile", "dpg_kernel_stats", "dpg_last_error", "dpg_destroy",
            "dpg_release_setup", "dpg_solve_noalloc", "dpg_error_indicator",
-           "dpg_boundary_points"]
+           "dpg_boundary_points", "dpg_batch_open", "dpg_batch_add", "dpg_batch_step",
+           "dpg_batch_take", "dpg_batch_close"]
 
 
 class dpg_mesh(C.Structure):
@@ -114,6 +116,14 @@ def lib():
         L.dpg_export.restype = C.c_int64
         L.dpg_boundary_points.argtypes = [vp, vp, C.c_int64]
         L.dpg_boundary_points.restype = C.c_int64
+        L.dpg_batch_open.argtypes = [vp, C.c_int]
+        L.dpg_batch_add.argtypes = [vp, vp, C.c_int, C.c_double, vp]
+        L.dpg_batch_step.argtypes = [vp, C.c_int, vp, vp]
+        L.dpg_batch_take.argtypes = [vp, C.c_int, vp, vp, vp]
+        L.dpg_batch_close.argtypes = [vp]
+        for name in ("dpg_batch_open", "dpg_batch_add", "dpg_batch_step", "dpg_batch_take",
+                     "dpg_batch_close"):
+            getattr(L, name).restype = C.c_int
         L.dpg_profile.argtypes = [vp, C.c_int]
         L.dpg_profile.restype = C.c_int
         L.dpg_kernel_stats.argtypes = [vp, C.c_int, C.POINTER(dpg_kstat)]
@@ -316,6 +326,58 @@ def dpg_boundary_points(ctx):
     if m < 0:
         _check(ctx.h, int(m))
     return out
+
+
+def dpg_batch_open(ctx, max_slots):
+    _check(ctx.h, lib().dpg_batch_open(ctx.h, max_slots))
+    ctx.batch_slots = max_slots
+
+
+def dpg_batch_add(ctx, rhs=None, load_col=0, tol=1e-8):
+    """Adds a right-hand side (host trace vector, or None for column load_col
+    of the context's loads); returns its slot."""
+    slot = C.c_int32()
+    if rhs is not None:
+        if ctx.flags & DPG_DEVICE_PTRS:
+            rp = _device_arg(rhs, dpg_info(ctx).n_trace, "rhs")
+        else:
+            rhs = np.ascontiguousarray(np.asarray(rhs, dtype=np.complex128))
+            if rhs.size != dpg_info(ctx).n_trace:
+                raise ValueError("rhs must have n_trace entries")
+            rp = rhs.ctypes.data
+    else:
+        rp = None
+    _check(ctx.h, lib().dpg_batch_add(ctx.h, rp, load_col, tol, C.byref(slot)))
+    return slot.value
+
+
+def dpg_batch_step(ctx, max_iters):
+    """Runs up to max_iters iterations; returns the finished slots not taken yet."""
+    done = np.zeros(32, dtype=np.int32)
+    nd = C.c_int32()
+    _check(ctx.h, lib().dpg_batch_step(ctx.h, max_iters, done.ctypes.data, C.byref(nd)))
+    return [int(v) for v in done[:nd.value]]
+
+
+def dpg_batch_take(ctx, slot, x_out=None):
+    """(x, iterations, relres, status) of a finished slot; frees it.  x is a
+    host array unless the context takes device pointers (then x_out, a device
+    tensor of n_trace complex128 entries, is required)."""
+    it = C.c_int32()
+    rr = C.c_double()
+    if ctx.flags & DPG_DEVICE_PTRS:
+        xp = _device_arg(x_out, dpg_info(ctx).n_trace, "x_out")
+        x = x_out
+    else:
+        x = np.zeros(dpg_info(ctx).n_trace, dtype=np.complex128) if x_out is None else x_out
+        xp = x.ctypes.data
+    code = lib().dpg_batch_take(ctx.h, slot, xp, C.byref(it), C.byref(rr))
+    _check(ctx.h, code, allow=(DPG_ENOCONV, DPG_EBREAKDOWN))
+    return x, it.value, rr.value, code
+
+
+def dpg_batch_close(ctx):
+    _check(ctx.h, lib().dpg_batch_close(ctx.h))
 
 
 def dpg_export(ctx, what, level=0):

@@ -10,9 +10,12 @@ speed) and carries one to sixteen Gaussian point sources.  The server
 * gives each resident operator a host worker thread and the context its own
   stream, so that solves of different operators overlap on the device (the
   library releases the interpreter lock inside its calls);
-* batches every request of an operator that is waiting when its worker
-  becomes free into one multi-right-hand-side solve (up to 32 columns),
-  so requests that arrive while others run join the next batch.
+* runs every operator's solves as one continuous batch (dpg_batch_*): a
+  request that arrives while others are being solved joins the running
+  block solve at the next iteration, in a free column slot (up to 32), and
+  leaves it as soon as its own column converges, so no request waits for a
+  whole batch to finish.  Each column keeps its own CG recurrence, so a
+  request's result is the same alone and in the mix.
 
 Latency is measured from a request's arrival to its result on the host.
 Every step of a solve runs in the library's kernels; this module only
@@ -27,7 +30,7 @@ import numpy as np
 
 from . import dpgmg as D
 
-MAX_BATCH = 32
+MAX_BATCH = 32      # column slots of a batch in the library
 
 
 class Operator:
@@ -39,7 +42,9 @@ class Operator:
         self.c = None if c is None else np.ascontiguousarray(np.asarray(c, dtype=float))
         self.precision, self.tol = precision, tol
 
-    def build(self):
+    def build(self, batch_slots=0):
+        """Context with its hierarchy; with batch_slots > 0 a batch of that many
+        column slots is opened on it (its buffers count in the footprint)."""
         opt = D.dpg_default_options(
             precision=D.DPG_MIXED if self.precision == "mixed" else D.DPG_FP64)
         ctx = D.dpg_setup(self.N, self.p, self.omega, [dict(dir=(0.0, 0.0, 1.0), amp=0.0)],
@@ -47,6 +52,8 @@ class Operator:
         D.dpg_assemble(ctx)
         D.dpg_build_hierarchy(ctx)
         D.dpg_release_setup(ctx)   # keep only what solves and new loads need
+        if batch_slots > 0:
+            D.dpg_batch_open(ctx, batch_slots)
         return ctx
 
 
@@ -68,7 +75,8 @@ class Request:
         self.relres = None
         self.status = None
         self.t_done = None
-        self.batch = 0
+        self.batch = 0               # most columns its batch ran while it was in it
+        self.joined_running = False  # admitted while other requests were part-way through
         self.error = None
         self.done = threading.Event()
 
@@ -88,12 +96,15 @@ class _Resident:
 
 class Server:
     """budget_bytes: device memory the resident contexts may hold together.
-    max_active: solves allowed on the device at once."""
+    max_active: operators whose batches step on the device at once.
+    max_batch: column slots of each operator's batch.  step_iters: block PCG
+    iterations between two looks at the queue (admissions happen there)."""
 
-    def __init__(self, operators, budget_bytes, max_active=4, max_batch=MAX_BATCH):
+    def __init__(self, operators, budget_bytes, max_active=4, max_batch=8, step_iters=1):
         self.ops = {op.key: op for op in operators}
         self.budget = budget_bytes
         self.max_batch = max_batch
+        self.step_iters = step_iters
         self.cv = threading.Condition()
         self.slots = threading.Semaphore(max_active)
         self.resident = {}
@@ -173,7 +184,7 @@ class Server:
             if admit is None:
                 continue
             try:
-                ctx = op.build()
+                ctx = op.build(self.max_batch)
                 nbytes = D.dpg_info(ctx).resident_bytes
             except Exception as exc:          # reported on every request of this operator
                 with self.cv:
@@ -201,36 +212,52 @@ class Server:
         self.cv.notify_all()
 
     def _worker(self, res):
+        ctx = res.ctx                  # built with a batch of max_batch slots open
+        slots = {}                     # batch slot -> request being solved
         while True:
             with self.cv:
-                while not res.stop and not res.pending:
+                while not res.stop and not res.pending and not slots:
                     self.cv.wait()
-                if res.stop and not res.pending:
-                    ctx, res.ctx = res.ctx, None
+                if res.stop and not res.pending and not slots:
                     break
-                batch = [res.pending.popleft() for _ in range(min(self.max_batch, len(res.pending)))]
+                free = self.max_batch - len(slots)
+                new = [res.pending.popleft() for _ in range(min(free, len(res.pending)))]
                 res.busy = True
+            finished = []
             self.slots.acquire()
             try:
-                D.dpg_load_rhs(res.ctx, [r.load() for r in batch], want=False)
-                x, it, rel, code = D.dpg_solve(res.ctx, nrhs=len(batch), tol=res.op.tol)
-                err = None
-            except Exception as exc:
-                err = exc
+                if new:
+                    # the loads of the newcomers, then each joins the running batch
+                    D.dpg_load_rhs(ctx, [r.load() for r in new], want=False)
+                    running = bool(slots)
+                    for j, r in enumerate(new):
+                        r.joined_running = running
+                        slots[D.dpg_batch_add(ctx, None, load_col=j, tol=res.op.tol)] = r
+                for r in slots.values():
+                    r.batch = max(r.batch, len(slots))
+                for k in D.dpg_batch_step(ctx, self.step_iters):
+                    x, it, rel, code = D.dpg_batch_take(ctx, k)
+                    finished.append((slots.pop(k), x.copy(), it, rel, code, None))
+            except Exception as exc:   # reported on every request of the batch
+                finished += [(r, None, None, None, None, exc) for r in slots.values()]
+                slots.clear()
+                D.dpg_batch_open(ctx, self.max_batch)
             finally:
                 self.slots.release()
             t = time.perf_counter()
             with self.cv:
-                for k, r in enumerate(batch):
+                for r, x, it, rel, code, err in finished:
                     if err is None:
-                        r.x, r.iters, r.relres, r.status = x[k], int(it[k]), float(rel[k]), code
+                        r.x, r.iters, r.relres, r.status = x, int(it), float(rel), code
                     else:
                         r.error = err
-                    r.t_done, r.batch = t, len(batch)
+                    r.t_done = t
                     r.done.set()
-                res.busy = False
+                res.busy = bool(slots)
                 res.last_used = t
                 self.cv.notify_all()
+        D.dpg_batch_close(ctx)
+        res.ctx = None
         ctx.close()
 
     def close(self):

@@ -1,0 +1,141 @@
+"""Continuous batching through the C ABI (dpg_batch_*): columns that join a
+running block solve, early or late, in fresh or reused slots, get the same
+result as solved alone (iteration counts +-1; solutions within 1e-10 in FP64,
+1e-8 in mixed precision, the bounds of those paths against the oracle); and
+point-source load updates, which only visit the elements near a source,
+against the oracle's loads over every element.
+"""
+import numpy as np
+import pytest
+
+from oracle import dpg
+from paper_2304_01728_amd import workloads
+
+from test_gpu_parity import elem_tol, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _D():
+    from paper_2304_01728_amd import dpgmg as D
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return D
+
+
+def _sources(seed, count, sigma):
+    cen = workloads.source_centres(seed, count)
+    amps = [complex(1.0 - 0.1 * k, 0.3 + 0.2 * k) for k in range(count)]
+    loads = [dict(dir=(0, 0, 1), amp=0.0, sources=[[*c0, sigma, a.real, a.imag]])
+             for c0, a in zip(cen, amps)]
+    fs = [dict(f=dpg.gaussian_sources([c0], sigma, [a])) for c0, a in zip(cen, amps)]
+    return loads, fs
+
+
+def _ctx(D, N, p, omega, loads, precision="fp64", nu=(2, 2)):
+    opt = D.dpg_default_options(nu_pre=nu[0], nu_post=nu[1],
+                                precision=D.DPG_MIXED if precision == "mixed" else D.DPG_FP64)
+    print(f"[batch] N={N} p={p} nrhs={len(loads)} {precision}", flush=True)
+    ctx = D.dpg_setup(N, p, omega, loads, options=opt)
+    D.dpg_assemble(ctx)
+    D.dpg_build_hierarchy(ctx)
+    return ctx
+
+
+def _relerr(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-8)])
+def test_late_joins_equal_solves_alone(precision, bar):
+    D = _D()
+    loads, _ = _sources(9, 4, 0.05)
+    ctx = _ctx(D, 8, 2, 4 * np.pi, loads, precision)
+    nT = D.dpg_info(ctx).n_trace
+    rhs = D.dpg_export(ctx, D.X_ASM_RHS).reshape(4, nT)
+    tol = 1e-10
+    alone = [D.dpg_solve(ctx, rhs=rhs[k][None, :], tol=tol) for k in range(4)]
+    D.dpg_batch_open(ctx, 4)
+    col_of = {}
+    col_of[D.dpg_batch_add(ctx, None, load_col=0, tol=tol)] = 0
+    assert D.dpg_batch_step(ctx, 3) == []            # column 0 is 3 iterations in
+    col_of[D.dpg_batch_add(ctx, None, load_col=1, tol=tol)] = 1
+    assert D.dpg_batch_step(ctx, 2) == []
+    col_of[D.dpg_batch_add(ctx, rhs[2], tol=tol)] = 2  # an explicit right-hand side
+    assert sorted(col_of) == [0, 1, 2]
+    got = {}
+    added_last = False
+    while len(got) < 4:
+        for k in D.dpg_batch_step(ctx, 200):
+            x, it, rr, code = D.dpg_batch_take(ctx, k)
+            assert code == D.DPG_OK and rr <= tol
+            got[col_of.pop(k)] = (x.copy(), it)
+            if not added_last:                        # the freed slot is reused at once
+                kk = D.dpg_batch_add(ctx, None, load_col=3, tol=tol)
+                assert kk == k
+                col_of[kk] = 3
+                added_last = True
+    D.dpg_batch_close(ctx)
+    for j in range(4):
+        xa, ita, rra, ca = alone[j]
+        assert ca == D.DPG_OK
+        assert abs(got[j][1] - int(ita[0])) <= 1, (j, got[j][1], ita[0])
+        assert _relerr(got[j][0], xa[0]) <= bar, (j, _relerr(got[j][0], xa[0]))
+    ctx.close()
+
+
+def test_batch_zero_rhs_errors_and_dpg_solve_after_close():
+    D = _D()
+    loads, _ = _sources(2, 2, 0.05)
+    ctx = _ctx(D, 4, 2, 3 * np.pi, loads, nu=(1, 1))
+    nT = D.dpg_info(ctx).n_trace
+    D.dpg_batch_open(ctx, 2)
+    k0 = D.dpg_batch_add(ctx, np.zeros(nT), tol=1e-8)
+    k1 = D.dpg_batch_add(ctx, None, load_col=1, tol=1e-8)
+    with pytest.raises(D.DPGError) as e:              # both slots in use
+        D.dpg_batch_add(ctx, None, load_col=0)
+    assert e.value.code == D.DPG_EINVAL
+    with pytest.raises(D.DPGError) as e:              # still running
+        D.dpg_batch_take(ctx, k1)
+    assert e.value.code == D.DPG_ESTATE
+    with pytest.raises(D.DPGError) as e:              # the block path shares the batch
+        D.dpg_solve(ctx, nrhs=2, tol=1e-8)
+    assert e.value.code == D.DPG_ESTATE
+    assert k0 in D.dpg_batch_step(ctx, 0)             # a zero load is done at once
+    x0, it0, rr0, c0 = D.dpg_batch_take(ctx, k0)
+    assert it0 == 0 and c0 == D.DPG_OK and np.all(x0 == 0)
+    while True:
+        done = D.dpg_batch_step(ctx, 50)
+        if done:
+            break
+    x1, it1, rr1, c1 = D.dpg_batch_take(ctx, k1)
+    D.dpg_batch_close(ctx)
+    xs, its, _, _ = D.dpg_solve(ctx, nrhs=2, tol=1e-8)
+    assert abs(int(its[1]) - it1) <= 1 and _relerr(x1, xs[1]) <= 1e-8
+    ctx.close()
+
+
+def test_point_source_load_update_visits_nearby_elements_only():
+    """dpg_load_rhs with point sources of width 0.02 on an 8^3 mesh computes
+    the loads of the elements within 8 sigma of a source only; the condensed
+    loads, the solution and the recovered fields match the oracle's, which
+    integrates every element."""
+    D = _D()
+    N, p, omega = 8, 2, 4 * np.pi
+    ctx = _ctx(D, N, p, omega, [dict(dir=workloads.plane_wave_direction(3), amp=1.0)], nu=(1, 1))
+    loads, fs = _sources(6, 2, 0.02)
+    s_new = D.dpg_load_rhs(ctx, loads)
+    pr = dpg.Problem(N, p, omega, fs)
+    S, s, rec = pr.condensed()
+    ref = dpg.assemble_vector(pr.edofs, s, pr.num.n)
+    assert rel(s_new, ref.T) <= elem_tol(p, omega, 1.0 / N)
+    x, it, rr, code = D.dpg_solve(ctx, nrhs=2, tol=1e-12)
+    from oracle import multigrid
+    H = multigrid.Hierarchy(N, p, S)
+    for k in range(2):
+        xo, _, _ = H.solve(ref[:, k], 1e-12)
+        assert _relerr(x[k], xo) <= 1e-10
+    f = D.dpg_get_fields(ctx, x)
+    fo = dpg.recover_fields(rec, pr.edofs, x.T)
+    assert rel(f, fo.transpose(2, 0, 1)) <= 1e-10
+    ctx.close()

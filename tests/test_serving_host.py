@@ -1,8 +1,9 @@
 """Scheduling logic of the serving loop on the CPU, with the library replaced
 by a stand-in whose "solution" is a known function of each request's sources:
-every request gets its own result, requests that wait together share a batch,
-the resident footprint never exceeds the budget, idle operators are evicted
-least recently used first, and a context is destroyed before the next one is
+every request gets its own result, requests that arrive while others are
+being solved join the running batch (continuous batching), the resident
+footprint never exceeds the budget, idle operators are evicted least
+recently used first, and a context is destroyed before the next one is
 built.  No GPU and no library calls."""
 import threading
 import time
@@ -24,7 +25,8 @@ class FakeLib:
         self.events = []
         self.per = nbytes_per_element
         self.solve_s = solve_s
-        self.batches = []
+        self.batches = []         # running columns at every batch iteration
+        self.adds = 0
         self.next_id = 0
 
     # --- the calls the server makes ---
@@ -61,12 +63,43 @@ class FakeLib:
     def dpg_load_rhs(self, ctx, loads, want=True):
         ctx.loads = loads
 
-    def dpg_solve(self, ctx, nrhs=1, tol=1e-8):
-        time.sleep(self.solve_s)
+    # a batch: slot -> [load, iterations left]; each step is one iteration
+    def dpg_batch_open(self, ctx, slots):
+        ctx.nslots, ctx.cols, ctx.done = slots, {}, []
+
+    def dpg_batch_add(self, ctx, rhs=None, load_col=0, tol=1e-8):
+        k = min(set(range(ctx.nslots)) - set(ctx.cols))
+        ld = ctx.loads[load_col]
+        ctx.cols[k] = [ld, 3 + int(ld["sources"].shape[0])]
         with self.lock:
-            self.batches.append(nrhs)
-        x = np.array([[ld["sources"].sum() + ctx.N] for ld in ctx.loads[:nrhs]])
-        return x, np.full(nrhs, 5), np.full(nrhs, tol / 2), 0
+            self.adds += 1
+        return k
+
+    def dpg_batch_step(self, ctx, max_iters):
+        for _ in range(max_iters):
+            running = [k for k, c in ctx.cols.items() if c[1] > 0]
+            if not running:
+                break
+            time.sleep(self.solve_s / 5)
+            with self.lock:
+                self.batches.append(len(running))
+            fin = []
+            for k in running:
+                ctx.cols[k][1] -= 1
+                if ctx.cols[k][1] == 0:
+                    fin.append(k)
+            ctx.done += fin
+            if fin:
+                break
+        return list(ctx.done)
+
+    def dpg_batch_take(self, ctx, k):
+        ld, _ = ctx.cols.pop(k)
+        ctx.done.remove(k)
+        return np.array([ld["sources"].sum() + ctx.N]), 5, 1e-9, 0
+
+    def dpg_batch_close(self, ctx):
+        ctx.cols = {}
 
 
 def _ops():
@@ -98,10 +131,28 @@ def test_every_request_gets_its_own_result(fake):
     for r in reqs:
         assert r.x[0] == pytest.approx(r.sources.sum() + N[r.op_key])
     assert len(lat) == 40 and np.all(lat > 0)
-    assert max(fake.batches) > 1                  # requests that waited were batched
-    assert sum(fake.batches) == 40
+    assert max(fake.batches) > 1                  # requests joined running batches
+    assert fake.adds == 40
     assert srv.builds == 3 and srv.evictions == 0
     assert not fake.live                          # every context destroyed on close
+
+
+def test_late_request_joins_the_running_batch(fake):
+    """One operator: the second request arrives while the first is part-way
+    through its iterations and joins it; it finishes before a solve that waited
+    for the whole batch could have started."""
+    ops = _ops()[:1]
+    srv = serving.Server(ops, budget_bytes=1 << 40, max_active=1)
+    src = np.ones((12, 6))
+    a = serving.Request(0, 0, src, 0.0)             # 15 iterations of solve_s / 5
+    b = serving.Request(1, 0, src[:1], 0.012)       # 4 iterations, arrives mid-way
+    try:
+        serving.run_stream(srv, [a, b])
+    finally:
+        srv.close()
+    assert b.batch == 2 and a.batch == 2
+    assert b.t_done < a.t_done                      # left the batch before the first
+    assert b.x[0] == pytest.approx(src[:1].sum() + ops[0].N)
 
 
 def test_budget_is_respected_with_eviction(fake):
