@@ -18,6 +18,12 @@ Sec. 3 of the paper, restated:
   * Outer iteration: CG preconditioned by one V(nu_pre, nu_post) cycle, zero
     initial guess, stopped at relative l2 residual <= tol (Sec. 4 parameters).
 
+Order levels (Sec. 4.2, uniform p-refinements): optionally the order is
+lowered on the finest mesh before the mesh is coarsened; between two orders
+on one mesh the prolongation is the inclusion of the lower-order traces
+(hierarchical bases: an injection), nothing is condensed, and the patches
+are the vertex patches of the mesh itself.
+
 Readings where the paper is silent: damping theta = 1/5.  Colouring the
 coarse vertices by index parity gives 8 classes of pairwise M-orthogonal
 patches, so lambda_max(S M) <= 8, and the bound is attained by unknowns on a
@@ -31,6 +37,16 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from . import dpg, topology
+
+
+def level_plan(N, p, p_min=None, nlevels=0):
+    """(mesh size, order) of every level, finest first: with p_min < p the
+    order is lowered on the finest mesh one step at a time down to p_min (the
+    uniform p-refinements of Sec. 4.2 read from coarse to fine), then the mesh
+    is halved as in level_sizes."""
+    p_min = p if p_min is None else p_min
+    plan = [(N, q) for q in range(p, p_min, -1)] + [(n, p_min) for n in level_sizes(N)]
+    return plan[:nlevels] if nlevels > 0 else plan
 
 
 def level_sizes(N):
@@ -83,6 +99,22 @@ def assemble_macro(mc, blocks, Mblocks):
                          shape=(mc.nM, mc.nM)).tocsr()
 
 
+def order_blocks(lv):
+    """An order level (mesh unchanged below it): the macro grid is the whole
+    trace space, its blocks are the element matrices (unknowns in ascending
+    canonical order), nothing is condensed."""
+    mc = topology.OrderLevel(lv.num)
+    lv.macro = mc
+    lv.Mblocks = []
+    for e in range(len(mc.children)):
+        d = lv.edofs[e]
+        loc = np.nonzero(d >= 0)[0]
+        loc = loc[np.argsort(d[loc])]
+        lv.Mblocks.append(lv.E[e][np.ix_(loc, loc)])
+    lv.TII, lv.TIB = None, None
+    lv.M = assemble_macro(mc, range(len(mc.children)), lv.Mblocks)
+
+
 def macro_condense(lv):
     """Macro condensation of every coarse element of the level."""
     mc = topology.MacroLevel(lv.num)
@@ -130,31 +162,41 @@ def build_patches(lv):
 class Hierarchy:
     """All levels, finest last: levels[0] is the coarsest mesh."""
 
-    def __init__(self, N, p, S_fine, theta=0.2, nu_pre=1, nu_post=1, nlevels=0, coarse=None):
+    def __init__(self, N, p, S_fine, theta=0.2, nu_pre=1, nu_post=1, nlevels=0, coarse=None,
+                 p_min=None):
         """coarse: None for coarse operators by restriction (Galerkin P^T M P);
         else a function n -> element matrices of the n^3 mesh assembled
-        directly ("store", the approach the paper compares against)."""
-        sizes = level_sizes(N)
-        if nlevels > 0:
-            sizes = sizes[:nlevels]
+        directly ("store", the approach the paper compares against).
+        p_min: lowest order of the order levels above the mesh levels
+        (level_plan); None = no order levels."""
+        plan = level_plan(N, p, p_min, nlevels)
+        if coarse is not None and plan[0][1] != plan[-1][1]:
+            raise ValueError("stored coarse operators are for mesh levels only")
         self.theta, self.nu_pre, self.nu_post = theta, nu_pre, nu_post
         self.p = p
-        L = len(sizes) - 1
+        self.plan = plan
+        L = len(plan) - 1
         self.L = L
         levels = [None] * (L + 1)
         E = S_fine
         for l in range(L, 0, -1):
-            lv = Level(sizes[L - l], p, E)
-            macro_condense(lv)
-            coarse_num = topology.Numbering(sizes[L - l + 1], p)
-            lv.P = topology.prolongation(lv.macro, coarse_num)
+            (Nl, ql), (Nc, qc) = plan[L - l], plan[L - l + 1]
+            lv = Level(Nl, ql, E)
+            coarse_num = topology.Numbering(Nc, qc)
+            lv.order_level = Nc == Nl
+            if lv.order_level:
+                order_blocks(lv)
+                lv.P = topology.order_injection(lv.num, coarse_num)
+            else:
+                macro_condense(lv)
+                lv.P = topology.prolongation(lv.macro, coarse_num)
             build_patches(lv)
             if coarse is None:
                 E = galerkin(lv, coarse_num, topology.element_dofs(coarse_num))
             else:
-                E = coarse(sizes[L - l + 1])
+                E = coarse(Nc)
             levels[l] = lv
-        lv0 = Level(sizes[L], p, E)
+        lv0 = Level(*plan[L], E)
         lv0.T = dpg.assemble(lv0.edofs, E, lv0.n).toarray()
         lv0.chol = sla.cho_factor(lv0.T, lower=True)
         levels[0] = lv0
@@ -171,6 +213,8 @@ class Hierarchy:
 
     def condense_rhs(self, lv, rc):
         """Macro right-hand side r_B - sum_K T_BI T_II^-1 r_I of a trace vector."""
+        if getattr(lv, 'order_level', False):
+            return rc.copy()
         mc = lv.macro
         rB = rc[mc.B].copy()
         for kc in range(len(mc.children)):
@@ -180,6 +224,8 @@ class Hierarchy:
 
     def expand(self, lv, rc, eB):
         """Trace vector with B part eB and I part T_II^-1 (r_I - T_IB e_B)."""
+        if getattr(lv, 'order_level', False):
+            return eB.copy()
         mc = lv.macro
         e = np.zeros(lv.n, dtype=np.complex128)
         e[mc.B] = eB

@@ -248,3 +248,91 @@ def prolongation(level, coarse_num):
                       shape=(level.nM, coarse_num.n)).tocsr()
     P.eliminate_zeros()
     return P
+
+
+class OrderLevel:
+    """The level of a hierarchy that coarsens the order on one mesh (the
+    uniform p-refinements of Sec. 4.2 read as multigrid levels): mesh N,
+    order q, next coarser level (N, q - 1).
+
+    Every trace unknown of the mesh stays on the coarse skeleton (the meshes
+    coincide), so nothing is condensed: the macro grid is the whole trace
+    space, the blocks are the elements (their unknowns in ascending canonical
+    order) and the vertex patches are those of the mesh itself -- an unknown
+    belongs to the patch of vertex v iff every element its support touches
+    contains v.  Attribute names follow MacroLevel."""
+
+    def __init__(self, num):
+        N, q = num.N, num.p
+        self.num, self.N, self.Nc, self.p = num, N, N, q
+        kind, coord = num.describe()
+        self.kind, self.coord = kind, coord
+        self.B = np.arange(num.n)
+        self.macro_of = np.arange(num.n)
+        self.nM = num.n
+        self.isB = np.ones(num.n, dtype=bool)
+        # support intervals (element index per axis), as in MacroLevel with the
+        # elements in the place of the coarse cells
+        lo = np.zeros((num.n, 3), dtype=np.int64)
+        hi = np.zeros((num.n, 3), dtype=np.int64)
+        hb = kind == 0
+        for a in range(3):
+            X = coord[hb, a]
+            atv = X % q == 0
+            lo[hb, a] = np.where(atv, np.maximum(X // q - 1, 0), X // q)
+            hi[hb, a] = np.where(atv, np.minimum(X // q, N - 1), X // q)
+        for d in range(3):
+            m = kind == d + 1
+            ip = [k for k in range(3) if k != d]
+            lo[m, d] = coord[m, 0] - 1
+            hi[m, d] = coord[m, 0]
+            for a, col in ((ip[0], 1), (ip[1], 2)):
+                lo[m, a] = coord[m, col] // q
+                hi[m, a] = coord[m, col] // q
+        edofs = element_dofs(num)
+        self.edofs = edofs
+        self.children = [[e] for e in range(N ** 3)]
+        self.blocks_B = [np.sort(edofs[e][edofs[e] >= 0]) for e in range(N ** 3)]
+        self.blocks_I = [np.zeros(0, dtype=np.int64) for _ in range(N ** 3)]
+        members = [[] for _ in range((N + 1) ** 3)]
+        for dz in range(2):
+            for dy in range(2):
+                for dx in range(2):
+                    v = hi + np.array([dx, dy, dz])
+                    ok = np.all(v <= lo + 1, axis=1) & np.all(v <= N, axis=1)
+                    vid = (v[:, 2] * (N + 1) + v[:, 1]) * (N + 1) + v[:, 0]
+                    for mi in np.nonzero(ok)[0]:
+                        members[vid[mi]].append(mi)
+        self.patches = [np.array(sorted(m), dtype=np.int64) for m in members]
+
+
+def order_injection(num, coarse_num):
+    """P [n_trace(N, q), n_trace(N, q - 1)]: the natural inclusion of the order
+    q - 1 trace space in the order q one on the same mesh.  The hierarchical
+    H1 functions (vertex hats and integrated Legendre bubbles) and the
+    Legendre flux functions do not depend on the order they belong to, so
+    every coarse function is one fine function: lattice coordinate
+    X' = (q-1) cell + a' goes to q cell + a' (a' = 0 a vertex, else the same
+    bubble), flux in-plane T' = (q-1) cell + m to q cell + m."""
+    q = num.p
+    assert coarse_num.N == num.N and coarse_num.p == q - 1
+    qc = q - 1
+
+    def lat(Xc):
+        return q * (Xc // qc) + Xc % qc
+
+    rows, cols = [], []
+    Zc, Yc, Xc = np.nonzero(coarse_num.h1_index >= 0)
+    rows.append(num.h1_index[lat(Zc), lat(Yc), lat(Xc)])
+    cols.append(coarse_num.h1_index[Zc, Yc, Xc])
+    for d in range(3):
+        for s in range(1, num.N):
+            T2c, T1c = np.meshgrid(np.arange(coarse_num.M), np.arange(coarse_num.M),
+                                   indexing='ij')
+            T1c, T2c = T1c.ravel(), T2c.ravel()
+            rows.append(num.flux(d, s, lat(T1c), lat(T2c)))
+            cols.append(coarse_num.flux(d, s, T1c, T2c))
+    r, c = np.concatenate(rows), np.concatenate(cols)
+    assert np.all(r >= 0)
+    return sp.coo_matrix((np.ones(r.size), (r, c)), shape=(num.n, coarse_num.n)).tocsr()
+

@@ -166,3 +166,106 @@ def test_restrict_beats_store_and_the_gap_grows_with_frequency():
         assert itr < its
         gaps.append(its - itr)
     assert gaps[1] > gaps[0]
+
+
+# ---- order levels (Sec. 4.2, uniform p-refinements read as multigrid levels) -------------------
+
+from oracle import basis1d, element  # noqa: E402
+
+
+def _trace_values(num, x, e, d, s, pts):
+    """The H1 trace and the flux trace given by the coefficient vector x on
+    face (axis d, side s) of element e, at reference points pts [n, 2] of the
+    face (first in-plane axis first), evaluated from the shape functions."""
+    N, q = num.N, num.p
+    ed = topology.element_dofs(num)[e]
+    lat = element.h1_boundary_lattice(q)
+    ip = [a for a in range(3) if a != d]
+    xi = np.zeros((len(pts), 3))
+    xi[:, d] = 1.0 if s else -1.0
+    xi[:, ip[0]], xi[:, ip[1]] = pts[:, 0], pts[:, 1]
+    H = [basis1d.h1(q, xi[:, a]) for a in range(3)]
+    ph = np.zeros(len(pts), dtype=complex)
+    for k, (a, b, c) in enumerate(lat):
+        ph += x[ed[k]] * H[0][a] * H[1][b] * H[2][c]
+    un = np.zeros(len(pts), dtype=complex)
+    c0 = len(lat) + (2 * d + s) * q * q
+    if ed[c0] >= 0:
+        Lm = basis1d.legendre(q, pts[:, 0])
+        Ln = basis1d.legendre(q, pts[:, 1])
+        for n in range(q):
+            for m in range(q):
+                un += x[ed[c0 + n * q + m]] * Lm[m] * Ln[n]
+    return ph, un
+
+
+@pytest.mark.parametrize("N,q", [(2, 2), (2, 3), (3, 4)])
+def test_order_injection_reproduces_lower_order_traces(N, q):
+    """P x is the order-q coefficient vector of the same trace functions as the
+    order-(q-1) vector x: pressure and flux traces agree at random points of
+    every face of every element."""
+    fine, coarse = topology.Numbering(N, q), topology.Numbering(N, q - 1)
+    P = topology.order_injection(fine, coarse)
+    assert P.shape == (fine.n, coarse.n) and np.all(P.sum(axis=0) == 1)
+    rng = np.random.default_rng(N + 10 * q)
+    xc = rng.standard_normal(coarse.n) + 1j * rng.standard_normal(coarse.n)
+    xf = P @ xc
+    pts = rng.uniform(-1, 1, size=(7, 2))
+    for e in range(N ** 3):
+        for d in range(3):
+            for s in range(2):
+                pc, uc = _trace_values(coarse, xc, e, d, s, pts)
+                pf, uf = _trace_values(fine, xf, e, d, s, pts)
+                assert np.abs(pf - pc).max() <= 1e-12 * np.abs(pc).max()
+                assert np.abs(uf - uc).max() <= 1e-12 * max(np.abs(uc).max(), 1.0)
+
+
+def test_order_level_patches_by_definition():
+    """Unknown t is in the patch of vertex v iff every element holding t
+    contains v (the support rule, with the elements as the cells)."""
+    N, q = 3, 2
+    num = topology.Numbering(N, q)
+    ol = topology.OrderLevel(num)
+    ed = topology.element_dofs(num)
+    holders = [set() for _ in range(num.n)]
+    for e in range(N ** 3):
+        for t in ed[e][ed[e] >= 0]:
+            holders[t].add(e)
+    for vz in range(N + 1):
+        for vy in range(N + 1):
+            for vx in range(N + 1):
+                around = {(vx - 1 + a) + N * ((vy - 1 + b) + N * (vz - 1 + c))
+                          for c in range(2) for b in range(2) for a in range(2)
+                          if 0 <= vx - 1 + a < N and 0 <= vy - 1 + b < N and 0 <= vz - 1 + c < N}
+                want = [t for t in range(num.n) if holders[t] <= around]
+                got = ol.patches[(vz * (N + 1) + vy) * (N + 1) + vx]
+                assert list(got) == want
+
+
+@pytest.fixture(scope="module")
+def order_levels():
+    N, p = 2, 3
+    pr = dpg.Problem(N, p, 2 * np.pi, [dict(u0=dpg.plane_wave_u0(2 * np.pi, [0.6, 0.0, 0.8]))])
+    S, s, _ = pr.condensed()
+    T = dpg.assemble(pr.edofs, S, pr.num.n)
+    rhs = dpg.assemble_vector(pr.edofs, s, pr.num.n)[:, 0]
+    return pr, S, T, rhs, multigrid.Hierarchy(N, p, S, nu_pre=2, nu_post=2, p_min=2)
+
+
+def test_order_levels_galerkin_vcycle_and_pcg(order_levels):
+    pr, S, T, rhs, H = order_levels
+    assert H.plan == [(2, 3), (2, 2), (1, 2)]
+    lv, lc = H.levels[H.L], H.levels[H.L - 1]
+    assert lv.order_level and not lc.order_level
+    P = lv.P.toarray()
+    brute = P.T @ lv.M.toarray() @ P
+    assert np.abs(brute - dpg.assemble(lc.edofs, lc.E, lc.n).toarray()).max() <= \
+        1e-13 * np.abs(brute).max()
+    assert np.abs(lv.M.toarray() - T.toarray()).max() <= 1e-14 * np.abs(T).max()
+    V = _vcycle_matrix(H)
+    assert np.abs(V - V.conj().T).max() <= 1e-12 * np.abs(V).max()
+    ev = np.linalg.eigvals(V @ lv.M.toarray()).real
+    assert ev.min() > 0 and ev.max() < 1.0 + 1e-10
+    xd = spla.spsolve(T.tocsc(), rhs)
+    x, it, rr = H.solve(rhs, 1e-12)
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
