@@ -123,11 +123,19 @@ typedef struct {
   int64_t hbm_budget; /* bytes the context may allocate; 0 = no limit        */
   void *stream;       /* hipStream_t to launch on; NULL: a stream the context
                          creates (blocking, i.e. ordered with the null stream) */
+  int32_t p_min;      /* order levels (Sec. 4.2, uniform p-refinements read as
+                         multigrid levels): with 1 <= p_min < p the hierarchy
+                         first lowers the order on the finest mesh one step at
+                         a time (prolongation: the inclusion of the lower-order
+                         traces; nothing condensed; the mesh's own vertex
+                         patches), then halves the mesh at order p_min.
+                         0: no order levels.                                  */
 } dpg_options;
 
 typedef struct dpg_ctx dpg_ctx;
 
-/* Fills opt with the defaults: FP64, V(1,1), theta = 1/5, maxit = 500. */
+/* Fills opt with the defaults: FP64, V(1,1), theta = 1/5, maxit = 500, no
+ * order levels. */
 void dpg_default_options(dpg_options *opt);
 
 /* Builds the mesh topology (canonical numbering, element maps, macro sets,
@@ -267,6 +275,7 @@ typedef struct {
   int64_t resident_bytes;   /* device memory held by the context          */
   int32_t n_test, n_field, n_tr;
   double setup_ms[4];       /* topology, assemble, hierarchy, last solve  */
+  int32_t level_p[16];      /* order per level, finest first              */
 } dpg_info_t;
 
 int dpg_info(const dpg_ctx *ctx, dpg_info_t *info);

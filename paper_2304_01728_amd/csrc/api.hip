@@ -82,6 +82,18 @@ int64_t boundary_points(const dpg_ctx *c) {
   return 6LL * c->N * c->N * c->tables_h.nql * c->tables_h.nql;
 }
 
+// (mesh size, order) of every level, finest first: with 1 <= p_min < p the
+// order is lowered on the finest mesh one step at a time down to p_min
+// (order levels), then the mesh is halved (level_sizes).
+std::vector<std::pair<int, int>> level_plan(int N, int p, int p_min, int nlevels) {
+  std::vector<std::pair<int, int>> plan;
+  const int pm = p_min > 0 ? p_min : p;
+  for (int q = p; q > pm; --q) plan.push_back({N, q});
+  for (int n : level_sizes(N, 0)) plan.push_back({n, pm});
+  if (nlevels > 0 && (int)plan.size() > nlevels) plan.resize(nlevels);
+  return plan;
+}
+
 void set_loads(dpg_ctx *c, const dpg_load *loads, int nrhs) {
   c->nrhs = nrhs;
   c->ld_h.assign(nrhs, LoadDesc{});
@@ -382,9 +394,13 @@ void element_stage(dpg_ctx *c, int l, bool write_matrices, const IndicatorArgs *
 
 // ---- hierarchy -------------------------------------------------------------------------
 
+// The full (nBf x nBf) macro blocks of a level: its element matrices on an
+// order level, the condensed blocks otherwise.
+const double2 *mfull(const LevelData &f) { return f.order ? f.E.p : f.Mfull.p; }
+
 // Chunk size of the macro blocks of a level and the shared workspace sizes.
 int macro_chunk(dpg_ctx *c, const LevelData &f) {
-  const int ntr = c->n_tr, nBf = f.nBf, nI = f.nI, nT = nBf + nI;
+  const int ntr = f.ntr_c, nBf = f.nBf, nI = f.nI, nT = nBf + nI;
   const int64_t per = 16LL * ((int64_t)nT * nT + (int64_t)nI * nI + (int64_t)nBf * ntr);
   const int64_t cmax = std::max<int64_t>(1, std::min<int64_t>(2500000000LL / per, 65535));
   if (f.nblk <= cmax) return f.nblk;
@@ -398,7 +414,9 @@ void plan_macro(dpg_ctx *c, int l) {
   if (P.ready) return;
   const hipStream_t s = c->stream;
   Budget *bd = &c->bud;
-  const int ntr = c->n_tr, nBf = f.nBf, nI = f.nI, nT = nBf + nI, nblk = f.nblk;
+  // ntr: element size of the coarser level (the Galerkin products' output)
+  const int ntr = f.ntr_c, nBf = f.nBf, nI = f.nI, nT = nBf + nI, nblk = f.nblk;
+  const bool ord = f.order;   // order level: the blocks are the element matrices
   const int CB = macro_chunk(c, f);
   std::vector<double2> ploc_h(f.P.local.size());
   for (size_t i = 0; i < ploc_h.size(); ++i) ploc_h[i] = mk(f.P.local[i], 0.0);
@@ -431,15 +449,17 @@ void plan_macro(dpg_ctx *c, int l) {
   P.gA.upload(gA, bd, s);
   P.idoff.upload(idoff, bd, s);
   P.idn.upload(idn, bd, s);
-  std::vector<int32_t> cinv((size_t)8 * nT, -1);
-  for (int ch = 0; ch < 8; ++ch)
-    for (int k = 0; k < ntr; ++k) {
-      const int32_t slot = f.mc.child_map[(size_t)ch * ntr + k];
-      if (slot < 0 || slot >= nT || cinv[(size_t)ch * nT + slot] >= 0)
-        throw DpgError(-1, "child map is not one-to-one");
-      cinv[(size_t)ch * nT + slot] = k;
-    }
-  P.cmap.upload(cinv, bd, s);
+  if (!ord) {
+    std::vector<int32_t> cinv((size_t)8 * nT, -1);
+    for (int ch = 0; ch < 8; ++ch)
+      for (int k = 0; k < f.ntr; ++k) {
+        const int32_t slot = f.mc.child_map[(size_t)ch * f.ntr + k];
+        if (slot < 0 || slot >= nT || cinv[(size_t)ch * nT + slot] >= 0)
+          throw DpgError(-1, "child map is not one-to-one");
+        cinv[(size_t)ch * nT + slot] = k;
+      }
+    P.cmap.upload(cinv, bd, s);
+  }
   std::vector<int64_t> soff(nblk), moff(nblk);
   std::vector<int32_t> sld(nblk, nBf);
   for (int b = 0; b < nblk; ++b) {
@@ -454,15 +474,17 @@ void plan_macro(dpg_ctx *c, int l) {
   // level outputs and the shared workspaces (the finest level has the most blocks)
   LevelData &cl = c->lv[l - 1];
   cl.E.ensure((int64_t)nblk * ntr * ntr, bd);
-  f.Mfull.ensure((int64_t)nblk * nBf * nBf, bd);
-  f.Tinv.ensure((int64_t)nblk * nI * nI, bd);
-  f.WH.ensure((int64_t)nblk * nBf * nI, bd);
-  if (c->opt.precision == DPG_MIXED && l < c->L) {
+  if (!ord) {
+    f.Mfull.ensure((int64_t)nblk * nBf * nBf, bd);
+    f.Tinv.ensure((int64_t)nblk * nI * nI, bd);
+    f.WH.ensure((int64_t)nblk * nBf * nI, bd);
+  }
+  if (c->opt.precision == DPG_MIXED && l < c->L && !ord) {
     f.Tinv32.ensure(f.Tinv.n, bd);
     f.WH32.ensure(f.WH.n, bd);
   }
   for (int h = 0; h < (nblk > CB ? 2 : 1); ++h) {
-    if (c->mT[h].n < (int64_t)CB * nT * nT) c->mT[h].alloc((int64_t)CB * nT * nT, bd);
+    if (!ord && c->mT[h].n < (int64_t)CB * nT * nT) c->mT[h].alloc((int64_t)CB * nT * nT, bd);
     if (c->mLinv[h].n < (int64_t)CB * nI * nI) c->mLinv[h].alloc((int64_t)CB * nI * nI, bd);
     if (c->mX[h].n < (int64_t)CB * nBf * ntr) c->mX[h].alloc((int64_t)CB * nBf * ntr, bd);
     if (c->mwk[h].n < dense_work_size(CB, nI)) c->mwk[h].alloc(dense_work_size(CB, nI), bd);
@@ -480,16 +502,21 @@ void build_macro_level(dpg_ctx *c, int l) {
   LevelData &f = c->lv[l];
   LevelData &cl = c->lv[l - 1];
   MacroPlan &P = f.mp;
-  const int ntr = c->n_tr, nBf = f.nBf, nI = f.nI, nT = nBf + nI, nblk = f.nblk, CB = P.CB;
+  const int ntr = f.ntr_c, nBf = f.nBf, nI = f.nI, nT = nBf + nI, nblk = f.nblk, CB = P.CB;
   const bool two = nblk > CB;
   if (two) stream_wait(c->stream, c->aux, c->ev_fork);
   for (int b0 = 0, k = 0; b0 < nblk; b0 += CB, ++k) {
     const int cnt = std::min(CB, nblk - b0), u = two ? (k & 1) : 0;
     const hipStream_t s = u ? c->aux : c->stream;
     double2 *T = c->mT[u].p, *Linv = c->mLinv[u].p, *X = c->mX[u].p, *wk = c->mwk[u].p;
+    if (f.order) {
+      // order level: the blocks are the element matrices themselves (nothing
+      // condensed); only the Galerkin products below
+      T = f.E.p + (int64_t)b0 * nT * nT;
+    } else {
     {
       ProfScope ps(&c->prof, DPG_K_MACRO_ASM, 0, s);
-      launch_macro_assemble(f.E.p, ntr, P.cmap.p, f.N, b0, cnt, nT, T, s);
+      launch_macro_assemble(f.E.p, f.ntr, P.cmap.p, f.N, b0, cnt, nT, T, s);
     }
     {
       ProfScope ps(&c->prof, DPG_K_POTRF, cnt * f_potrf(nI), s);
@@ -526,6 +553,7 @@ void build_macro_level(dpg_ctx *c, int l) {
       launch_copy_sub(T, (int64_t)nT * nT, nT, 0, 0, nBf, nBf, f.Mfull.p + (int64_t)b0 * nBf * nBf,
                       (int64_t)nBf * nBf, nBf, cnt, s);
     }
+    }
     if (!(c->opt.flags & DPG_STORE_COARSE)) {
       ProfScope ps(&c->prof, DPG_K_GEMM, cnt * (f_gemm(nBf, ntr, nBf) + f_gemm(ntr, ntr, nBf)), s);
       gemm_batched(OP_N, OP_N, mk(1, 0), T, P.Ploc.p, mk(0, 0), X, P.gX.p, cnt, nBf, ntr, s);
@@ -535,12 +563,12 @@ void build_macro_level(dpg_ctx *c, int l) {
   }
   if (two) stream_wait(c->aux, c->stream, c->ev_join);
   const hipStream_t s = c->stream;
-  if (c->opt.precision == DPG_MIXED && l < c->L) {
+  if (c->opt.precision == DPG_MIXED && l < c->L && !f.order) {
     launch_to32(f.Tinv.n, f.Tinv.p, f.Tinv32.p, s);
     launch_to32(f.WH.n, f.WH.p, f.WH32.p, s);
   }
   // macro blocks -> packed tiles (present slots only)
-  f.Mset.pack(f.Mfull.p, P.soff.p, P.sld.p, P.moff.p, P.map.p, s);
+  f.Mset.pack(mfull(f), P.soff.p, P.sld.p, P.moff.p, P.map.p, s);
 }
 
 // Each level's patch work is cut into this many parts of equal factorisation
@@ -674,7 +702,7 @@ void build_patches(dpg_ctx *c, int l, int half, hipStream_t s) {
     if (B.half != half) continue;
     {
       ProfScope ps(&c->prof, DPG_K_PATCH_GATHER, 0, s);
-      launch_patch_gather(f.Mfull.p, f.nBf, f.mc.Nc, f.patch_ptr.p, f.patch_slot.p, B.v0, B.cnt,
+      launch_patch_gather(mfull(f), f.nBf, f.mc.Nc, f.patch_ptr.p, f.patch_slot.p, B.v0, B.cnt,
                           B.nmax, B.off.p, S, s);
     }
     {
@@ -781,7 +809,7 @@ void build_coarsest(dpg_ctx *c) {
   LevelData &z = c->lv[0];
   const hipStream_t s = c->stream;
   const int n0 = (int)z.num.n;
-  launch_assemble_dense(z.E.p, c->n_tr, z.edofs.p, z.nel, n0, c->T0.p, s);
+  launch_assemble_dense(z.E.p, z.ntr, z.edofs.p, z.nel, n0, c->T0.p, s);
   HIP_OK(hipMemcpyAsync(c->zF.p, c->T0.p, (size_t)n0 * n0 * 16, hipMemcpyDeviceToDevice, s));
   potrf_batched(c->zF.p, c->zpi.p, 1, c->zinfo.p, n0, c->zwk.p, s);
   launch_identity(c->zoff.p, c->znn.p, 1, n0, c->zLi.p, s);
@@ -835,7 +863,8 @@ void build_hierarchy(dpg_ctx *c) {
     for (int k = 0; k < NX; ++k) stream_wait(xs[k], c->stream, xj[k]);
   }
   for (int l = c->L; l >= 1; --l) {
-    check_infos(c->lv[l].mp.info.p, c->lv[l].nblk, c->stream, "interior block of coarse element");
+    if (!c->lv[l].order)   // an order level factors no interior block
+      check_infos(c->lv[l].mp.info.p, c->lv[l].nblk, c->stream, "interior block of coarse element");
     check_infos(c->lv[l].pp.info.p, (int64_t)c->lv[l].mc.patch_ptr.size() - 1, c->stream,
                 "vertex patch");
   }
@@ -882,6 +911,41 @@ void smooth_apply(dpg_ctx *c, int l, const cplx_t<T> *x, cplx_t<T> *y, int mode,
   herm_apply<T>(c->lv[l].Sset, x, y, nullptr, mode, theta, c->stream);
 }
 
+// Condensation of the macro-grid interior unknowns of level g (Sec. 3): the
+// macro right-hand side from nr interleaved full trace columns (cc: the
+// per-block partial products).  On an order level nothing is condensed (the
+// macro unknowns are the level's traces, in order): a copy.
+template <typename T>
+void condense_level(const LevelData &g, const cplx_t<T> *WH, const cplx_t<T> *full, cplx_t<T> *cc,
+                    cplx_t<T> *out, int nr, hipStream_t s) {
+  if (g.order) {
+    HIP_OK(hipMemcpyAsync(out, full, g.nM * nr * sizeof(cplx_t<T>), hipMemcpyDeviceToDevice, s));
+  } else if (nr == 1) {
+    launch_condense_local<T>(WH, g.nI, g.nBf, g.blkI.p, g.nblk, full, cc, s);
+    launch_condense_reduce<T>(g.nM, g.macroB.p, g.cred_ptr.p, g.cred_ent.p, full, cc, out, s);
+  } else {
+    launch_condense_blk<T>(WH, g.nI, g.nBf, g.blkI.p, g.nblk, g.nM, g.macroB.p, g.cred_ptr.p,
+                           g.cred_ent.p, full, cc, out, nr, s);
+  }
+}
+
+// Expansion: the full trace columns from the macro solution xm and the
+// loads full (interior recovery); on an order level a copy of xm.
+template <typename T>
+void expand_level(const LevelData &g, const cplx_t<T> *WH, const cplx_t<T> *Ti,
+                  const cplx_t<T> *full, const cplx_t<T> *xm, cplx_t<T> *out, int nr,
+                  hipStream_t s) {
+  if (g.order) {
+    HIP_OK(hipMemcpyAsync(out, xm, g.nM * nr * sizeof(cplx_t<T>), hipMemcpyDeviceToDevice, s));
+  } else if (nr == 1) {
+    launch_expand<T>(WH, Ti, g.nI, g.nBf, g.blkI.p, g.blkBm.p, g.nblk, full, xm, g.nM, g.macroB.p,
+                     out, s);
+  } else {
+    launch_expand_blk<T>(WH, Ti, g.nI, g.nBf, g.blkI.p, g.blkBm.p, g.nblk, full, xm, g.nM,
+                         g.macroB.p, out, nr, s);
+  }
+}
+
 template <typename T> void vcycle(dpg_ctx *c, int l) {
   using B = LB<T>;
   LevelData &f = c->lv[l];
@@ -908,14 +972,11 @@ template <typename T> void vcycle(dpg_ctx *c, int l) {
   } else {
     {
       PROF(DPG_K_CONDENSE, 0);
-      launch_condense_local<T>(B::WH(g), g.nI, g.nBf, g.blkI.p, g.nblk, rc, B::cc(g), s);
-      launch_condense_reduce<T>(g.nM, g.macroB.p, g.cred_ptr.p, g.cred_ent.p, rc, B::cc(g),
-                                B::r(g), s);
+      condense_level<T>(g, B::WH(g), rc, B::cc(g), B::r(g), 1, s);
     }
     vcycle<T>(c, l - 1);
     PROF(DPG_K_EXPAND, 0);
-    launch_expand<T>(B::WH(g), B::Ti(g), g.nI, g.nBf, g.blkI.p, g.blkBm.p, g.nblk, rc, B::x(g),
-                     g.nM, g.macroB.p, ec, s);
+    expand_level<T>(g, B::WH(g), B::Ti(g), rc, B::x(g), ec, 1, s);
   }
   {
     PROF(DPG_K_TRANSFER, 0);
@@ -976,9 +1037,7 @@ int solve_one(dpg_ctx *c, const double2 *sv, double tol, double2 *xout, int32_t 
   LevelData &top = c->lv[c->L];
   const hipStream_t s = c->stream;
   const int64_t nM = top.nM;
-  launch_condense_local<double>(top.WH.p, top.nI, top.nBf, top.blkI.p, top.nblk, sv, top.c64.p, s);
-  launch_condense_reduce<double>(nM, top.macroB.p, top.cred_ptr.p, top.cred_ent.p, sv, top.c64.p,
-                                 c->b.p, s);
+  condense_level<double>(top, top.WH.p, sv, top.c64.p, c->b.p, 1, s);
   launch_zero(4, reinterpret_cast<double2 *>(sc), s);   // the 8 scalars
   dot_re(nM, c->b.p, c->b.p, partial, sc + 5, s);
   launch_zero(nM, c->x.p, s);
@@ -1036,8 +1095,7 @@ int solve_one(dpg_ctx *c, const double2 *sv, double tol, double2 *xout, int32_t 
     }
     if (rr > tol) status = DPG_ENOCONV;
   }
-  launch_expand<double>(top.WH.p, top.Tinv.p, top.nI, top.nBf, top.blkI.p, top.blkBm.p, top.nblk,
-                        sv, c->x.p, nM, top.macroB.p, xout, s);
+  expand_level<double>(top, top.WH.p, top.Tinv.p, sv, c->x.p, xout, 1, s);
   HIP_OK(hipStreamSynchronize(s));
   if (iters) *iters = it;
   if (relres) *relres = rr;
@@ -1166,13 +1224,11 @@ template <typename T> void vcycle_blk(dpg_ctx *c, int l, int nr) {
   } else {
     {
       PROF(DPG_K_CONDENSE, 0);
-      launch_condense_blk<T>(B::WH(g), g.nI, g.nBf, g.blkI.p, g.nblk, g.nM, g.macroB.p,
-                             g.cred_ptr.p, g.cred_ent.p, rc, BB::cc(g), BB::r(g), nr, s);
+      condense_level<T>(g, B::WH(g), rc, BB::cc(g), BB::r(g), nr, s);
     }
     vcycle_blk<T>(c, l - 1, nr);
     PROF(DPG_K_EXPAND, 0);
-    launch_expand_blk<T>(B::WH(g), B::Ti(g), g.nI, g.nBf, g.blkI.p, g.blkBm.p, g.nblk, rc,
-                         BB::x(g), g.nM, g.macroB.p, ec, nr, s);
+    expand_level<T>(g, B::WH(g), B::Ti(g), rc, BB::x(g), ec, nr, s);
   }
   {
     PROF(DPG_K_TRANSFER, 0);
@@ -1277,9 +1333,7 @@ int batch_add(dpg_ctx *c, const double2 *sv, double tol) {
   const hipStream_t s = c->stream;
   const int64_t nM = top.nM, nT = top.num.n;
   launch_set_col(nT, S.w, k, sv, c->bsv.p, s);
-  launch_condense_local<double>(top.WH.p, top.nI, top.nBf, top.blkI.p, top.nblk, sv, top.c64.p, s);
-  launch_condense_reduce<double>(nM, top.macroB.p, top.cred_ptr.p, top.cred_ent.p, sv, top.c64.p,
-                                 c->b.p, s);
+  condense_level<double>(top, top.WH.p, sv, top.c64.p, c->b.p, 1, s);
   launch_zero(4, reinterpret_cast<double2 *>(c->sc.p), s);
   dot_re(nM, c->b.p, c->b.p, c->partial.p, c->sc.p + 5, s);
   launch_set_col(nM, S.w, k, c->b.p, c->br.p, s);
@@ -1388,8 +1442,7 @@ int batch_take(dpg_ctx *c, int k, double2 *xout, int32_t *iters, double *relres)
   const int64_t nM = top.nM, nT = top.num.n;
   launch_get_col(nM, S.w, k, c->bx.p, c->x.p, s);
   launch_get_col(nT, S.w, k, c->bsv.p, c->sB.p, s);
-  launch_expand<double>(top.WH.p, top.Tinv.p, top.nI, top.nBf, top.blkI.p, top.blkBm.p, top.nblk,
-                        c->sB.p, c->x.p, nM, top.macroB.p, xout, s);
+  expand_level<double>(top, top.WH.p, top.Tinv.p, c->sB.p, c->x.p, xout, 1, s);
   if (iters) *iters = S.iters[k];
   if (relres) *relres = S.rr[k];
   const int st = S.state[k] == 2 ? DPG_OK : S.state[k] == 3 ? DPG_ENOCONV : DPG_EBREAKDOWN;
@@ -1419,9 +1472,7 @@ void batch_add_all(dpg_ctx *c, const double2 *sv_cols, int nr, double tol) {
   const int64_t nM = top.nM, nT = top.num.n;
   S.w = nr;   // the vectors of a freshly opened batch are zero in every layout
   launch_interleave(nT, nr, sv_cols, c->bsv.p, s);
-  launch_condense_blk<double>(top.WH.p, top.nI, top.nBf, top.blkI.p, top.nblk, nM, top.macroB.p,
-                              top.cred_ptr.p, top.cred_ent.p, c->bsv.p, top.bc64.p, c->br.p, nr,
-                              s);
+  condense_level<double>(top, top.WH.p, c->bsv.p, top.bc64.p, c->br.p, nr, s);
   for (int k = 0; k < nr; ++k) cgb_reset_col(c->bsc.p, k, s);
   cgb_dot(nM, nr, c->br.p, c->br.p, c->bpartial.p, c->bsc.p, 5, s);
   HIP_OK(hipMemcpyAsync(c->host_bsc, c->bsc.p, 8 * kMaxCols * sizeof(double),
@@ -1455,7 +1506,7 @@ int solve_block(dpg_ctx *c, const double2 *sv_cols, int nr, double tol, double2 
   batch_add_all(c, sv_cols, nr, tol);
   BatchSession &S = c->bs;
   LevelData &top = c->lv[c->L];
-  const int64_t nT = top.num.n, nM = top.nM;
+  const int64_t nT = top.num.n;
   int status = DPG_OK;
   for (;;) {
     int running = 0;
@@ -1467,9 +1518,7 @@ int solve_block(dpg_ctx *c, const double2 *sv_cols, int nr, double tol, double2 
         throw DpgError(DPG_EBREAKDOWN, "CG breakdown in column " + std::to_string(k) +
                                            " at iteration " + std::to_string(S.iters[k]));
   }
-  launch_expand_blk<double>(top.WH.p, top.Tinv.p, top.nI, top.nBf, top.blkI.p, top.blkBm.p,
-                            top.nblk, c->bsv.p, c->bx.p, nM, top.macroB.p, c->bxf.p, nr,
-                            c->stream);
+  expand_level<double>(top, top.WH.p, top.Tinv.p, c->bsv.p, c->bx.p, c->bxf.p, nr, c->stream);
   launch_deinterleave(nT, nr, c->bxf.p, xcols, c->stream);
   for (int k = 0; k < nr; ++k) {
     iters[k] = S.iters[k];
@@ -1579,26 +1628,42 @@ int dpg_setup(const dpg_mesh *mesh, int p, int dp, double omega, const dpg_mater
     c->testd.upload(test, &c->bud, c->stream);
     c->triald.upload(trial, &c->bud, c->stream);
     set_loads(c, loads, nrhs);
-    std::vector<int> sizes = level_sizes(c->N, c->opt.nlevels);
-    if (sizes.size() < 2)
-      throw DpgError(DPG_EINVAL, "the mesh size must be even (at least one coarsening)");
-    c->L = (int)sizes.size() - 1;
+    if (c->opt.p_min < 0 || c->opt.p_min > p)
+      throw DpgError(DPG_EINVAL, "p_min must lie in [1, p] (0: no order levels)");
+    const std::vector<std::pair<int, int>> plan =
+        level_plan(c->N, p, c->opt.p_min, c->opt.nlevels);
+    if (plan.size() < 2)
+      throw DpgError(DPG_EINVAL, "no coarser level (an even mesh size or p_min < p is needed)");
+    if ((c->opt.flags & DPG_STORE_COARSE) && plan.back().second != p)
+      throw DpgError(DPG_EINVAL, "stored coarse operators are for mesh levels only");
+    c->L = (int)plan.size() - 1;
     c->lv.resize(c->L + 1);
     const bool mixed = c->opt.precision == DPG_MIXED;
     const hipStream_t s = c->stream;
     for (int l = 0; l <= c->L; ++l) {
       LevelData &f = c->lv[l];
-      f.N = sizes[c->L - l];
+      f.N = plan[c->L - l].first;
+      f.q = plan[c->L - l].second;
+      f.el.build(f.q);
+      f.ntr = f.el.n_tr;
       f.nel = f.N * f.N * f.N;
-      f.num.build(f.N, p);
-      f.edofs_h = element_dofs(f.num, c->el);
+      f.num.build(f.N, f.q);
+      f.edofs_h = element_dofs(f.num, f.el);
       f.edofs.upload(f.edofs_h, &c->bud, s);
     }
     for (int l = 1; l <= c->L; ++l) {
       LevelData &f = c->lv[l];
+      LevelData &g = c->lv[l - 1];
       f.macro = true;
-      f.mc.build(f.num, c->el);
-      f.P.build(f.mc, f.num, c->lv[l - 1].num, c->el);
+      f.order = g.N == f.N;
+      f.ntr_c = g.ntr;
+      if (f.order) {
+        f.mc.build_order(f.num, f.el);
+        f.P.build_order(f.mc, f.num, g.num, f.el, g.el);
+      } else {
+        f.mc.build(f.num, f.el);
+        f.P.build(f.mc, f.num, g.num, f.el);
+      }
       f.nblk = f.mc.Nc * f.mc.Nc * f.mc.Nc;
       f.nBf = f.mc.nBf;
       f.nI = f.mc.nI;
@@ -2108,6 +2173,7 @@ int dpg_info(const dpg_ctx *c, dpg_info_t *info) {
   for (int k = 0; k <= c->L && k < 16; ++k) {
     const auto &f = c->lv[c->L - k];
     info->level_n[k] = f.N;
+    info->level_p[k] = f.q;
     info->level_ntrace[k] = f.num.n;
     info->level_nmacro[k] = f.nM;
   }
@@ -2210,8 +2276,8 @@ int64_t dpg_export(const dpg_ctx *cc, int what, int level, void *out, int64_t ca
       case DPG_X_MACRO_M: {
         need_macro();
         if (c->released) throw DpgError(DPG_ESTATE, "setup data released");
-        if (!f.Mfull.p) throw DpgError(DPG_ESTATE, "dpg_build_hierarchy first");
-        std::vector<double2> full = f.Mfull.download(s), v;
+        if (!mfull(f)) throw DpgError(DPG_ESTATE, "dpg_build_hierarchy first");
+        std::vector<double2> full = f.order ? f.E.download(s) : f.Mfull.download(s), v;
         for (int b = 0; b < f.nblk; ++b) {
           const int64_t k0 = f.mc.blkB_ptr[b], n = f.mc.blkB_ptr[b + 1] - k0;
           const double2 *Mb = full.data() + (int64_t)b * f.nBf * f.nBf;

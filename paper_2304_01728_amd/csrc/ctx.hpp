@@ -75,6 +75,9 @@ struct PatchPlan {
 // One mesh of the hierarchy.  Level 0 is the coarsest mesh, level L the finest.
 struct LevelData {
   int N = 0, nel = 0;
+  int q = 0, ntr = 0, ntr_c = 0;     // order, element trace size, that of the coarser level
+  bool order = false;                // the coarser level has the same mesh (order q - 1)
+  ElementLayout el;
   Numbering num;
   std::vector<int32_t> edofs_h;
   DevBuf<int32_t> edofs;

@@ -403,8 +403,185 @@ void MacroLevel::build(const Numbering &fine, const ElementLayout &el) {
   }
 }
 
+// Position of lattice point (a, b, c) of [0, p]^3 in an element's local layout.
+static std::vector<int> lattice_positions(const ElementLayout &el) {
+  const int p = el.p;
+  std::vector<int> pos((p + 1) * (p + 1) * (p + 1), -1);
+  for (int k = 0; k < el.n_h1; ++k)
+    pos[(el.lat[3 * k + 2] * (p + 1) + el.lat[3 * k + 1]) * (p + 1) + el.lat[3 * k]] = k;
+  return pos;
+}
+
+void MacroLevel::build_order(const Numbering &num, const ElementLayout &el) {
+  N = num.N;
+  p = num.p;
+  Nc = N;
+  nBf = el.n_tr;
+  nI = 0;
+  nM = num.n;
+  macro_of.resize(num.n);
+  macro_B.resize(num.n);
+  for (int64_t t = 0; t < num.n; ++t) {
+    macro_of[t] = (int32_t)t;
+    macro_B[t] = t;
+  }
+  blkB = element_dofs(num, el);
+  blkI.clear();
+  child_map.clear();
+  bslot_tab.clear();
+  const int64_t nblk = (int64_t)N * N * N;
+  blkB_ptr.assign(nblk + 1, 0);
+  blkB_present.clear();
+  for (int64_t b = 0; b < nblk; ++b) {
+    std::vector<std::pair<int32_t, int32_t>> pres;   // (canonical index, local slot)
+    for (int s = 0; s < nBf; ++s)
+      if (blkB[b * nBf + s] >= 0) pres.push_back({blkB[b * nBf + s], s});
+    std::sort(pres.begin(), pres.end());
+    for (auto &e : pres) blkB_present.push_back(e.second);
+    blkB_ptr[b + 1] = (int64_t)blkB_present.size();
+  }
+  // support intervals of every unknown, in elements per axis
+  const std::vector<int> lpos = lattice_positions(el);
+  const int64_t nv = (int64_t)(N + 1) * (N + 1) * (N + 1);
+  std::vector<int> LO(3 * nM), HI(3 * nM);
+  for (int64_t t = 0; t < nM; ++t) {
+    int kind, c[3];
+    num.describe(t, kind, c);
+    int *lo = &LO[3 * t], *hi = &HI[3 * t];
+    if (kind == 0) {
+      for (int a = 0; a < 3; ++a) {
+        if (c[a] % p == 0) {
+          lo[a] = std::max(c[a] / p - 1, 0);
+          hi[a] = std::min(c[a] / p, N - 1);
+        } else {
+          lo[a] = hi[a] = c[a] / p;
+        }
+      }
+    } else {
+      const int d = kind - 1, a1 = d == 0 ? 1 : 0, a2 = d == 2 ? 1 : 2;
+      lo[d] = c[0] - 1;
+      hi[d] = c[0];
+      lo[a1] = hi[a1] = c[1] / p;
+      lo[a2] = hi[a2] = c[2] / p;
+    }
+  }
+  std::vector<int64_t> cnt(nv + 1, 0);
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int64_t> fill;
+    if (pass == 1) {
+      patch_ptr.assign(nv + 1, 0);
+      for (int64_t v = 0; v < nv; ++v) patch_ptr[v + 1] = patch_ptr[v] + cnt[v];
+      patch_idx.assign(patch_ptr[nv], -1);
+      fill.assign(patch_ptr.begin(), patch_ptr.end() - 1);
+    }
+    for (int64_t m = 0; m < nM; ++m) {
+      const int *lo = &LO[3 * m], *hi = &HI[3 * m];
+      for (int vz = hi[2]; vz <= lo[2] + 1 && vz <= N; ++vz)
+        for (int vy = hi[1]; vy <= lo[1] + 1 && vy <= N; ++vy)
+          for (int vx = hi[0]; vx <= lo[0] + 1 && vx <= N; ++vx) {
+            const int64_t v = ((int64_t)vz * (N + 1) + vy) * (N + 1) + vx;
+            if (pass == 0) cnt[v]++;
+            else patch_idx[fill[v]++] = (int32_t)m;
+          }
+    }
+  }
+  // local slot of unknown t in element (ci, cj, ck), or -1
+  auto local_slot = [&](int64_t t, const int cell[3]) -> int {
+    int kind, c[3];
+    num.describe(t, kind, c);
+    if (kind == 0) {
+      int l[3];
+      for (int a = 0; a < 3; ++a) {
+        l[a] = c[a] - p * cell[a];
+        if (l[a] < 0 || l[a] > p) return -1;
+      }
+      return lpos[(l[2] * (p + 1) + l[1]) * (p + 1) + l[0]];
+    }
+    const int d = kind - 1, a1 = d == 0 ? 1 : 0, a2 = d == 2 ? 1 : 2;
+    int side;
+    if (c[0] == cell[d]) side = 0;
+    else if (c[0] == cell[d] + 1) side = 1;
+    else return -1;
+    const int t1 = c[1] - p * cell[a1], t2 = c[2] - p * cell[a2];
+    if (t1 < 0 || t1 >= p || t2 < 0 || t2 >= p) return -1;
+    return el.n_h1 + (2 * d + side) * p * p + t2 * p + t1;
+  };
+  patch_slot.assign(patch_idx.size() * 8, -1);
+  for (int64_t v = 0; v < nv; ++v) {
+    const int vx = (int)(v % (N + 1)), vy = (int)((v / (N + 1)) % (N + 1)),
+              vz = (int)(v / ((int64_t)(N + 1) * (N + 1)));
+    for (int64_t k = patch_ptr[v]; k < patch_ptr[v + 1]; ++k)
+      for (int c = 0; c < 8; ++c) {
+        const int cell[3] = {vx - 1 + (c & 1), vy - 1 + ((c >> 1) & 1), vz - 1 + ((c >> 2) & 1)};
+        if (cell[0] < 0 || cell[1] < 0 || cell[2] < 0 || cell[0] >= N || cell[1] >= N ||
+            cell[2] >= N)
+          continue;
+        patch_slot[k * 8 + c] = local_slot(patch_idx[k], cell);
+      }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // prolongation
+
+void Prolongation::build_order(const MacroLevel &mc, const Numbering &fine,
+                               const Numbering &coarse, const ElementLayout &el_fine,
+                               const ElementLayout &el_coarse) {
+  const int q = fine.p, qc = coarse.p;
+  if (qc != q - 1 || coarse.N != fine.N) throw std::runtime_error("order level mismatch");
+  // fine 1-D local index of a coarse one: a vertex stays a vertex, bubble a'
+  // is the same function at index a' (the highest fine bubble has no source)
+  auto up = [&](int Xc) { return q * (Xc / qc) + Xc % qc; };
+  ptr.assign(mc.nM + 1, 0);
+  std::vector<int32_t> src(fine.n, -1);   // coarse unknown injected into each fine one
+  for (int64_t tc = 0; tc < coarse.n; ++tc) {
+    int kind, c[3];
+    coarse.describe(tc, kind, c);
+    int64_t t;
+    if (kind == 0) t = fine.h1(up(c[0]), up(c[1]), up(c[2]));
+    else t = fine.flux(kind - 1, c[0], up(c[1]), up(c[2]));
+    if (t < 0) throw std::runtime_error("order injection: no fine unknown");
+    src[t] = (int32_t)tc;
+  }
+  col.clear();
+  val.clear();
+  for (int64_t m = 0; m < mc.nM; ++m) {
+    if (src[m] >= 0) {
+      col.push_back(src[m]);
+      val.push_back(1.0);
+    }
+    ptr[m + 1] = (int64_t)col.size();
+  }
+  tptr.assign(coarse.n + 1, 0);
+  for (int32_t cidx : col) tptr[cidx + 1]++;
+  for (int64_t i = 0; i < coarse.n; ++i) tptr[i + 1] += tptr[i];
+  tcol.assign(col.size(), 0);
+  tval.assign(col.size(), 0.0);
+  std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
+  for (int64_t m = 0; m < mc.nM; ++m)
+    for (int64_t k = ptr[m]; k < ptr[m + 1]; ++k) {
+      const int64_t dst = fill[col[k]]++;
+      tcol[dst] = (int32_t)m;
+      tval[dst] = val[k];
+    }
+  // element-local injection, [n_tr(coarse)] columns of nBf = n_tr(fine) rows
+  const std::vector<int> lpos = lattice_positions(el_fine);
+  local.assign((int64_t)mc.nBf * el_coarse.n_tr, 0.0);
+  auto upl = [&](int a) { return a == qc ? q : a; };
+  for (int k = 0; k < el_coarse.n_h1; ++k) {
+    const int kf = lpos[(upl(el_coarse.lat[3 * k + 2]) * (q + 1) + upl(el_coarse.lat[3 * k + 1])) *
+                            (q + 1) +
+                        upl(el_coarse.lat[3 * k])];
+    local[(int64_t)k * mc.nBf + kf] = 1.0;
+  }
+  for (int f = 0; f < 6; ++f)
+    for (int n = 0; n < qc; ++n)
+      for (int m = 0; m < qc; ++m) {
+        const int kc = el_coarse.n_h1 + f * qc * qc + n * qc + m;
+        const int kf = el_fine.n_h1 + f * q * q + n * q + m;
+        local[(int64_t)kc * mc.nBf + kf] = 1.0;
+      }
+}
 
 void Prolongation::build(const MacroLevel &mc, const Numbering &fine, const Numbering &coarse,
                          const ElementLayout &el) {

@@ -81,6 +81,13 @@ struct MacroLevel {
   std::vector<int32_t> patch_slot;  // [members][8]
   std::vector<int> bslot_tab;       // [(2p+1)^3] block lattice -> B slot or -1
   void build(const Numbering &fine, const ElementLayout &el);
+  // The level of a hierarchy that lowers the order on one mesh (its coarser
+  // level has the same mesh and order p - 1): nothing is condensed (the macro
+  // grid is every trace unknown), the blocks are the elements (slots = the
+  // element-local layout, present ones listed by ascending canonical index),
+  // nI = 0, and the patches are the vertex patches of the mesh itself (cells =
+  // elements, Nc = N).  child_map and bslot_tab stay empty.
+  void build_order(const Numbering &num, const ElementLayout &el);
   // local B slot of canonical unknown t in coarse cell (ci,cj,ck), or -1
   int slot_in_block(const Numbering &fine, int64_t t, int ci, int cj, int ck) const;
 };
@@ -96,6 +103,12 @@ struct Prolongation {
   std::vector<double> local;        // dense [n_tr (coarse element)][nBf] column-major nBf x n_tr
   void build(const MacroLevel &mc, const Numbering &fine, const Numbering &coarse,
              const ElementLayout &el);
+  // Order level (MacroLevel::build_order): the inclusion of the order p - 1
+  // traces of the same mesh, an injection with hierarchical bases (lattice
+  // X' = (p-1) cell + a' -> p cell + a'; flux degrees kept).  local is the
+  // element-local injection [n_tr(p-1)][n_tr(p)].
+  void build_order(const MacroLevel &mc, const Numbering &fine, const Numbering &coarse,
+                   const ElementLayout &el_fine, const ElementLayout &el_coarse);
 };
 
 }  // namespace dpg

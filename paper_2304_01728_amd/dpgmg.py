@@ -49,7 +49,8 @@ class dpg_load(C.Structure):
 class dpg_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
                 ("nlevels", C.c_int32), ("maxit", C.c_int32), ("flags", C.c_int32),
-                ("theta", C.c_double), ("hbm_budget", C.c_int64), ("stream", C.c_void_p)]
+                ("theta", C.c_double), ("hbm_budget", C.c_int64), ("stream", C.c_void_p),
+                ("p_min", C.c_int32)]
 
 
 class dpg_info_t(C.Structure):
@@ -57,7 +58,7 @@ class dpg_info_t(C.Structure):
                 ("level_n", C.c_int32 * 16), ("level_ntrace", C.c_int64 * 16),
                 ("level_nmacro", C.c_int64 * 16), ("resident_bytes", C.c_int64),
                 ("n_test", C.c_int32), ("n_field", C.c_int32), ("n_tr", C.c_int32),
-                ("setup_ms", C.c_double * 4)]
+                ("setup_ms", C.c_double * 4), ("level_p", C.c_int32 * 16)]
 
 
 class dpg_kstat(C.Structure):
@@ -146,7 +147,10 @@ def _check(ctx, code, allow=()):
 def dpg_default_options(**kw):
     o = dpg_options()
     lib().dpg_default_options(C.byref(o))
+    names = {f[0] for f in dpg_options._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"dpg_options has no field {k!r}")
         setattr(o, k, v)
     return o
 

@@ -50,9 +50,10 @@ def test_struct_layouts_match_c(tmp_path):
     from paper_2304_01728_amd import dpgmg
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dpgmg.h"\n'
-                   'int main(){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dpg_options),'
+                   'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dpg_options),'
                    ' sizeof(dpg_load), sizeof(dpg_info_t), sizeof(dpg_mesh), sizeof(dpg_kstat),'
-                   ' offsetof(dpg_options, theta), offsetof(dpg_load, src));}\n')
+                   ' offsetof(dpg_options, theta), offsetof(dpg_load, src),'
+                   ' offsetof(dpg_options, p_min), offsetof(dpg_info_t, level_p));}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
@@ -60,7 +61,8 @@ def test_struct_layouts_match_c(tmp_path):
     c = ctypes
     want = [c.sizeof(dpgmg.dpg_options), c.sizeof(dpgmg.dpg_load), c.sizeof(dpgmg.dpg_info_t),
             c.sizeof(dpgmg.dpg_mesh), c.sizeof(dpgmg.dpg_kstat), dpgmg.dpg_options.theta.offset,
-            dpgmg.dpg_load.src.offset]
+            dpgmg.dpg_load.src.offset, dpgmg.dpg_options.p_min.offset,
+            dpgmg.dpg_info_t.level_p.offset]
     assert got == want
 
 
@@ -68,8 +70,10 @@ def test_default_options_without_device():
     _need_lib()
     from paper_2304_01728_amd import dpgmg
     o = dpgmg.dpg_default_options()
-    assert (o.precision, o.nu_pre, o.nu_post, o.maxit) == (dpgmg.DPG_FP64, 1, 1, 500)
+    assert (o.precision, o.nu_pre, o.nu_post, o.maxit, o.p_min) == (dpgmg.DPG_FP64, 1, 1, 500, 0)
     assert abs(o.theta - 0.2) < 1e-15
+    with pytest.raises(TypeError):
+        dpgmg.dpg_default_options(pmin=1)          # not a field: no silent attribute
 
 
 def test_bad_arguments_rejected_before_any_device_call():
