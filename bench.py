@@ -207,6 +207,61 @@ def store_vs_restrict(workload, omegas_over_pi=(2.0, 4.0, 8.0, 12.0)):
                       "tol": base.tol, "rows": rows}), flush=True)
 
 
+def p_robustness(workload, p_max=4, elements_per_wavelength=(4.0, 2.0)):
+    """The study of uniform p-refinements (Sec. 4.2): on the workload's mesh,
+    with at least two elements per wavelength, the finest order p runs from 2
+    to p_max over order levels down to p = 1 (then the mesh levels at p = 1),
+    against the mesh levels alone at order p.  PCG iterations to the
+    workload's tolerance, time to tolerance and setup time."""
+    import dataclasses
+    import torch
+    from paper_2304_01728_amd import dpgmg as D
+    from paper_2304_01728_amd import workloads as W
+    base = W.ALL[workload]()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for epw in elements_per_wavelength:
+        for p in range(2, p_max + 1):
+            w = dataclasses.replace(base, p=p, omega=2 * np.pi * base.N / epw)
+            row = {"elements_per_wavelength": epw, "omega_over_pi": w.omega / np.pi, "p": p}
+            for name, p_min in (("order_levels", 1), ("mesh_levels", 0)):
+                opt = make_options(D, w, torch_stream=stream.cuda_stream)
+                opt.p_min = p_min
+                ctx = D.dpg_setup(w.N, w.p, w.omega, loads_of(w), dp=w.dp, options=opt)
+                info = D.dpg_info(ctx)
+                nT = info.n_trace
+                x = torch.zeros((w.nrhs, nT), dtype=torch.complex128, device="cuda:0")
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                D.dpg_assemble(ctx)
+                D.dpg_build_hierarchy(ctx)
+                torch.cuda.synchronize()
+                t_setup = time.perf_counter() - t0
+                D.dpg_solve(ctx, nrhs=w.nrhs, tol=w.tol, x_out=x, device=True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, it, rr, code = D.dpg_solve(ctx, nrhs=w.nrhs, tol=w.tol, x_out=x, device=True)
+                torch.cuda.synchronize()
+                row[name] = {"iterations": int(np.max(it)), "status": int(code),
+                             "time_to_tol_ms": 1e3 * (time.perf_counter() - t0),
+                             "setup_ms": 1e3 * t_setup,
+                             "levels": [[int(info.level_n[k]), int(info.level_p[k])]
+                                        for k in range(info.nlevels)],
+                             "resident_gb": D.dpg_info(ctx).resident_bytes / 1e9}
+                row["n_trace"] = int(nT)
+                ctx.close()
+                del x
+                torch.cuda.empty_cache()
+            print(f"[p-robustness] {epw} elements per wavelength, p = {p}: order levels "
+                  f"{row['order_levels']['iterations']}, mesh levels "
+                  f"{row['mesh_levels']['iterations']} iterations", file=sys.stderr, flush=True)
+            rows.append(row)
+    print(json.dumps({"study": "uniform p-refinements: order levels vs mesh levels",
+                      "mesh": base.N, "tol": base.tol, "precision": base.precision,
+                      "smoothing": [base.nu_pre, base.nu_post], "rows": rows}), flush=True)
+
+
 def calibrate_copy():
     """A plain device copy of known size, for scaling HBM counters."""
     import torch
@@ -437,6 +492,9 @@ def main():
     ap.add_argument("--store-vs-restrict", action="store_true",
                     help="iterations and time to tolerance with restricted and with stored "
                          "coarse operators across frequencies, on the workload's mesh")
+    ap.add_argument("--p-robustness", action="store_true",
+                    help="iterations as the finest order grows, with order levels down to "
+                         "p = 1 and with mesh levels only (Sec. 4.2)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device copy (for HBM counter calibration)")
     ap.add_argument("--serving", action="store_true",
@@ -459,6 +517,9 @@ def main():
         return
     if args.store_vs_restrict:
         store_vs_restrict(args.workload)
+        return
+    if args.p_robustness:
+        p_robustness(args.workload)
         return
     if args.serving:
         serving_stream(args.requests, args.seed, args.max_active, args.load_factor)
