@@ -7,6 +7,13 @@
 namespace dpg {
 namespace {
 
+template <typename C> __device__ __forceinline__ C czero() {
+  C r;
+  r.x = 0;
+  r.y = 0;
+  return r;
+}
+
 template <typename C> __device__ inline C shfl_xor_c(C v, int m) {
   C r;
   r.x = __shfl_xor(v.x, m, 64);
@@ -147,6 +154,32 @@ __host__ __device__ __forceinline__ int64_t row_slot(int nt, int I, int J) {
   return ((int64_t)I * nt - (int64_t)I * (I - 1) / 2 + (J - I)) * 32;
 }
 
+// The FP32 apply (k_strips) takes tile columns in pairs, "strips" (J0 = 2 s,
+// J1 = 2 s + 1; the last strip of a block with an odd tile count has one
+// column), whose tile rows 0..J1 are cut into chunks of at most kChunk rows,
+// one wave each.  Per row I the wave loads tiles (I, J0) and (I, J1) and
+// writes their row sums as one 32-vector (slot (I, s)); the column sums of
+// both columns accumulate in registers over the chunk (one slot per column
+// and chunk).  Partials per 1024-entry tile: 16 + 8 entries instead of the
+// 32 + 16 of the segments above (and the x entries of a row once per two
+// tiles), which pays in FP32, where they weigh twice as much against the
+// tiles; FP64 streams its 16 KB tiles faster as segments.
+constexpr int kChunk = 4;
+
+// Row-sum slots of a block with nt tile columns (ns = ceil(nt / 2) strips):
+// row I is covered by the strips s >= I / 2, its slots are contiguous, and
+// rows come in order: slot(I, s) = I ns - floor((I - 1)^2 / 4) + s - I / 2.
+__host__ __device__ __forceinline__ int64_t strip_row_slot(int ns, int I, int s) {
+  return (int64_t)I * ns - (int64_t)(I - 1) * (I - 1) / 4 + s - I / 2;
+}
+__host__ __forceinline__ int64_t strip_row_slots(int nt) {
+  return (int64_t)nt * ((nt + 1) / 2) - (int64_t)(nt - 1) * (nt - 1) / 4;
+}
+__host__ __forceinline__ int strip_rows(int nt, int s) { return std::min(2 * s + 2, nt); }
+__host__ __forceinline__ int strip_chunks(int nt, int s) {
+  return (strip_rows(nt, s) + kChunk - 1) / kChunk;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather_x(int64_t nloc, const int32_t *__restrict__ gidx,
                                                   const cplx_t<T> *__restrict__ x,
@@ -220,6 +253,107 @@ __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ til
     cacc[j] = cadd(cacc[j], shfl_xor_c(cacc[j], 32));
   }
   if (ra < 4) part[d1.z + 4 * cb + ra] = sel4(cacc[0], cacc[1], cacc[2], cacc[3], ra);
+}
+
+// One wave per (block, strip s, chunk of tile rows [Ia, Ib)).  The unit's
+// descriptor (two int4, see HermSet::build) is read with scalar loads (the
+// wave index is made uniform).  Each row step issues the loads of both tiles,
+// then the x entries of the row, before any arithmetic.  A diagonal tile and
+// an absent one (row J1 of column J0, the second column of a one-column
+// strip) are read through the diagonal tile's 36-slot layout at an address
+// inside it, and masked: one load path for every kind (behind branches the
+// compiler made the loads of one kind wait for the other's).
+template <typename T>
+__global__ __launch_bounds__(256) void k_strips(const cplx_t<T> *__restrict__ tiles,
+                                               const int4 *__restrict__ units, int64_t nunits,
+                                               const cplx_t<T> *__restrict__ xloc,
+                                               cplx_t<T> *__restrict__ part) {
+  using C = cplx_t<T>;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t wv = (int64_t)blockIdx.x * 4 + wave;
+  if (wv >= nunits) return;
+  const int lane = threadIdx.x & 63, ra = lane >> 3, cb = lane & 7;
+  const int4 d0 = units[2 * wv], d1 = units[2 * wv + 1];
+  const int64_t ent = (int64_t)(uint32_t)d0.x | ((int64_t)d0.y << 32);
+  const int J0 = d1.x & 0xffff, nt = d1.x >> 16, J1 = J0 + 1;
+  const int Ia = d1.y & 0xffff, Ib = d1.y >> 16;
+  const bool two = J1 < nt;
+  const int ns = (nt + 1) >> 1, s = J0 >> 1;
+  const bool upper = ra <= cb, strict = ra < cb;
+  const int ds = upper ? diag_slot(ra, cb) : 0;
+  const C *t0 = tiles + ent;                                   // tile (0, J0)
+  const C *t1 = two ? t0 + (int64_t)kTileFull * J0 + kTileDiag : t0;   // tile (0, J1)
+  const C *xb = xloc + d0.z;
+  C *rp = part + d0.w;
+  C xJ0[4], xJ1[4], c0[4], c1[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    xJ0[j] = xb[32 * J0 + 4 * cb + j];
+    xJ1[j] = xb[32 * (two ? J1 : J0) + 4 * cb + j];
+    c0[j].x = 0;
+    c0[j].y = 0;
+    c1[j].x = 0;
+    c1[j].y = 0;
+  }
+#pragma unroll 1
+  for (int I = Ia; I < Ib; ++I) {
+    // (I, J0): full for I < J0, diagonal for I == J0, absent for I == J1;
+    // (I, J1): full for I < J1, diagonal for I == J1, absent without J1
+    const bool fa = I < J0, fb = two && I < J1;
+    const bool ka = fa || (I == J0 && upper), kb = fb || (two && I == J1 && upper);
+    const C *pa = fa ? t0 + (int64_t)kTileFull * I + lane : t0 + (int64_t)kTileFull * J0 + ds;
+    const C *pb = fb ? t1 + (int64_t)kTileFull * I + lane
+                     : two ? t1 + (int64_t)kTileFull * J1 + ds : t0 + (int64_t)kTileFull * J0 + ds;
+    C ta[16], tb[16], xI[4];
+    load_strided(pa, fa ? 64 : kDiagSlots, ta);
+    load_strided(pb, fb ? 64 : kDiagSlots, tb);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) xI[i] = xb[32 * I + 4 * ra + i];
+    mask_lower(ka, ta);
+    mask_lower(kb, tb);
+    C rs[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      C a;
+      a.x = 0;
+      a.y = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a = cfma(ta[4 * i + j], xJ0[j], a);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a = cfma(tb[4 * i + j], xJ1[j], a);
+      rs[i] = a;
+    }
+    // column sums: every sub-block of a full tile, the sub-blocks strictly
+    // above the diagonal of a diagonal one (masked entries are zero)
+    C xa[4], xbb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      xa[i] = csel(fa || strict, xI[i], czero<C>());
+      xbb[i] = csel(fb || strict, xI[i], czero<C>());
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        c0[j] = cfmaconj(ta[4 * i + j], xa[i], c0[j]);
+        c1[j] = cfmaconj(tb[4 * i + j], xbb[i], c1[j]);
+      }
+    const C v = rowsum_scatter(rs, cb);
+    if (!(cb & 1)) rp[32 * strip_row_slot(ns, I, s) + 4 * ra + (cb >> 1)] = v;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    c0[j] = cadd(c0[j], shfl_xor_c(c0[j], 8));
+    c0[j] = cadd(c0[j], shfl_xor_c(c0[j], 16));
+    c0[j] = cadd(c0[j], shfl_xor_c(c0[j], 32));
+    c1[j] = cadd(c1[j], shfl_xor_c(c1[j], 8));
+    c1[j] = cadd(c1[j], shfl_xor_c(c1[j], 16));
+    c1[j] = cadd(c1[j], shfl_xor_c(c1[j], 32));
+  }
+  if (ra < 4) {
+    part[d1.z + 4 * cb + ra] = sel4(c0[0], c0[1], c0[2], c0[3], ra);
+    if (two) part[d1.w + 4 * cb + ra] = sel4(c1[0], c1[1], c1[2], c1[3], ra);
+  }
 }
 
 // Half a wave per (block, tile row I): y_loc rows of I = column sums of the
@@ -389,6 +523,68 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
     rd[k] = make_int4((int)(cpo[b] + colbase(I)), (int)(rpo[b] + row_slot(nt, I, I)),
                       nseg | (nrw << 16), (int)(loff[b] + 32 * I));
   }
+  // FP32: units (block, strip, chunk), most tiles first: {entry offset of
+  // tile (0, J0) lo, hi, x offset of the block, row-sum base of the block},
+  // {J0 | nt << 16, Ia | Ib << 16, column-sum slot of J0, of J1 (0 without
+  // J1)}; rows: the column sums of tile column I (one slot per chunk of its
+  // strip) and the row sums of tile row I (one slot per strip s >= I / 2)
+  std::vector<int4> sud, srd;
+  if (fp32) {
+    struct Unit { int tiles; int4 d0, d1; };
+    std::vector<Unit> su;
+    std::vector<int64_t> scpo(nblk), srpo(nblk);
+    std::vector<std::vector<int32_t>> cbase(nblk);
+    int64_t sp = 0;
+    for (int b = 0; b < nblk; ++b) {
+      const int nt = (sizes[b] + 31) / 32;
+      if (nt > 0x7fff) throw DpgError(-1, "HermSet: block too large for strip descriptors");
+      std::vector<int32_t> &cbv = cbase[b];
+      cbv.assign(nt + 1, 0);
+      for (int J = 0; J < nt; ++J) cbv[J + 1] = cbv[J] + strip_chunks(nt, J / 2);
+      scpo[b] = sp;
+      sp += 32LL * cbv[nt];
+      srpo[b] = sp;
+      sp += 32 * strip_row_slots(nt);
+    }
+    snpart = sp;
+    if (snpart >= (1LL << 31)) throw DpgError(-1, "HermSet: partials beyond 32-bit offsets");
+    for (int b = 0; b < nblk; ++b) {
+      const int nt = (sizes[b] + 31) / 32;
+      for (int st = 0; 2 * st < nt; ++st) {
+        const int J0 = 2 * st, J1 = J0 + 1, rws = strip_rows(nt, st);
+        const bool two = J1 < nt;
+        const int64_t tile = eoff[b] + tile_entry(0, J0);
+        for (int c = 0; c * kChunk < rws; ++c) {
+          const int Ia = c * kChunk, Ib = std::min(rws, Ia + kChunk);
+          Unit u;
+          u.tiles = 0;
+          for (int I = Ia; I < Ib; ++I) u.tiles += (I <= J0) + (two && I <= J1);
+          u.d0 = make_int4((int)(uint32_t)(tile & 0xffffffff), (int)(tile >> 32), (int)loff[b],
+                           (int)srpo[b]);
+          u.d1 = make_int4(J0 | (nt << 16), Ia | (Ib << 16),
+                           (int)(scpo[b] + 32LL * (cbase[b][J0] + c)),
+                           two ? (int)(scpo[b] + 32LL * (cbase[b][J1] + c)) : 0);
+          su.push_back(u);
+        }
+      }
+    }
+    std::stable_sort(su.begin(), su.end(),
+                     [](const Unit &a, const Unit &c) { return a.tiles > c.tiles; });
+    snunits = (int64_t)su.size();
+    sud.resize(2 * su.size());
+    for (size_t k = 0; k < su.size(); ++k) {
+      sud[2 * k] = su[k].d0;
+      sud[2 * k + 1] = su[k].d1;
+    }
+    srd.resize(rw.size());
+    for (size_t k = 0; k < rw.size(); ++k) {
+      const int b = rw[k].x, I = rw[k].y, nt = (sizes[b] + 31) / 32, ns = (nt + 1) / 2;
+      const int nseg = strip_chunks(nt, I / 2), nrw = ns - I / 2;
+      srd[k] = make_int4((int)(scpo[b] + 32LL * cbase[b][I]),
+                         (int)(srpo[b] + 32 * strip_row_slot(ns, I, I / 2)), nseg | (nrw << 16),
+                         (int)(loff[b] + 32 * I));
+    }
+  }
   tile_off_h = toff;
   ent_off_h = eoff;
   loc_off_h = loff;
@@ -422,8 +618,10 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
     yl64.alloc(nloc, bud);
   }
   if (fp32) {
+    sunits.upload(sud, bud, s);
+    srowd.upload(srd, bud, s);
     t32.alloc(nent, bud);
-    p32.alloc(npart, bud);
+    p32.alloc(snpart, bud);
     xl32.alloc(nloc, bud);
     yl32.alloc(nloc, bud);
   }
@@ -467,13 +665,17 @@ void herm_apply(HermSet &H, const cplx_t<T> *x, cplx_t<T> *y, const cplx_t<T> *r
   {
     ProfScope ps(H.prof, sizeof(T) == 8 ? DPG_K_APPLY64 : DPG_K_APPLY32,
                  (double)H.packed_entries() * sizeof(cplx_t<T>), s);
-    hipLaunchKernelGGL((k_units<T>), dim3(cdiv(H.nunits, 4)), dim3(256), 0, s, tiles, H.units.p,
-                       H.nunits, xl, part);
+    if constexpr (sizeof(T) == 8)
+      hipLaunchKernelGGL((k_units<T>), dim3(cdiv(H.nunits, 4)), dim3(256), 0, s, tiles,
+                         H.units.p, H.nunits, xl, part);
+    else
+      hipLaunchKernelGGL((k_strips<T>), dim3(cdiv(H.snunits, 4)), dim3(256), 0, s, tiles,
+                         H.sunits.p, H.snunits, xl, part);
     LAUNCH_OK();
   }
   ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
-  hipLaunchKernelGGL((k_rows<T>), dim3(cdiv(H.nrows, 8)), dim3(256), 0, s, H.rowd.p, H.nrows,
-                     part, yl);
+  hipLaunchKernelGGL((k_rows<T>), dim3(cdiv(H.nrows, 8)), dim3(256), 0, s,
+                     sizeof(T) == 8 ? H.rowd.p : H.srowd.p, H.nrows, part, yl);
   LAUNCH_OK();
   const dim3 g(cdiv(H.nvec, 256));
   switch (mode) {

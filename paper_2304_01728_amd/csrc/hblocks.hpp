@@ -13,10 +13,13 @@
 //
 // Apply (four kernels, deterministic):
 //  1. gather:  x_loc[b] = R_b x, zero-padded to 32 nt_b entries;
-//  2. columns: one wave per (block, tile column J, segment of two tile rows)
-//     loads both tiles before any arithmetic, writes A_IJ x_J (row sums, one
-//     32-vector per tile, laid out tile row by tile row) and
+//  2. columns: FP64: one wave per (block, tile column J, segment of two tile
+//     rows) loads both tiles before any arithmetic, writes A_IJ x_J (row
+//     sums, one 32-vector per tile, laid out tile row by tile row) and
 //     sum_{I<J} A_IJ^H x_I over the segment (one 32-vector per segment);
+//     FP32: one wave per (block, pair of tile columns J0, J1, chunk of tile
+//     rows) writes A_I,J0 x_J0 + A_I,J1 x_J1 per row I (one 32-vector per
+//     two tiles) and the column sums of both columns over the chunk;
 //  3. rows:    half a wave per (block, tile row I) adds the column partials
 //     of column I and the row partials of row I (contiguous) into y_loc[b];
 //  4. scatter: one thread per vector entry adds y_loc of every block holding
@@ -59,6 +62,9 @@ struct HermSet {
   DevBuf<int2> rows;         // (block, I)
   DevBuf<int4> rowd;         // per (block, I): column-partial base, row-partial base,
                              // segment count | (row-partial count << 16), local offset
+  // the same for the FP32 apply by column pairs (strips); partials in p32
+  DevBuf<int4> sunits, srowd;
+  int64_t snunits = 0, snpart = 0;
   DevBuf<int4> tdesc;        // (block, I, J, 0) per stored tile (packing)
   DevBuf<int32_t> red_ptr;   // CSR over vector entries
   DevBuf<int32_t> red_ent;   // offsets into the local vectors

@@ -72,7 +72,7 @@ KERNEL_CLASSES = ["gram", "bmat", "load", "potrf", "trsm", "gemm", "macro_asm", 
 KERNEL_SYMBOLS = {"gram": "k_gram", "bmat": "k_bmat", "load": "k_load", "potrf": "k_potrf",
                   "trsm": "k_trsm", "gemm": "k_gemm", "macro_asm": "k_macro_assemble",
                   "patch_gather": "k_patch_gather", "apply64": "k_units<double>",
-                  "apply32": "k_units<float>", "reduce": "k_reduce",
+                  "apply32": "k_strips<float>", "reduce": "k_reduce",
                   "applyb64": "k_rows_mfma64", "applyb32": "k_rows_mfma"}
 
 
