@@ -141,8 +141,12 @@ void dpg_default_options(dpg_options *opt);
 /* Builds the mesh topology (canonical numbering, element maps, macro sets,
  * vertex patches, prolongation maps) for an n^3 mesh of order p >= 1 with
  * test enrichment dp >= 1 and angular frequency omega > 0, and uploads it.
- * loads[0..nrhs-1] are the right-hand sides assembled by dpg_assemble.
- * mat may be NULL.  On success *out owns the context. */
+ * The problem is the one of Sec. 2 (eq. helmholtz: time-harmonic acoustics
+ * in first-order form with an impedance condition on Gamma, the ultraweak
+ * DPG formulation with the test order raised by dp); the levels, macro grids
+ * and patches are those of the solver of Sec. 3.  loads[0..nrhs-1] are the
+ * right-hand sides assembled by dpg_assemble.  mat may be NULL.  On success
+ * *out owns the context. */
 int dpg_setup(const dpg_mesh *mesh, int p, int dp, double omega, const dpg_material *mat,
               const dpg_load *loads, int nrhs, const dpg_options *opt, dpg_ctx **out);
 
@@ -173,8 +177,16 @@ int dpg_assemble(dpg_ctx *ctx);
 int dpg_build_hierarchy(dpg_ctx *ctx);
 
 /* Replaces the assembled loads by new right-hand sides for the same operator
- * (runs the load part of dpg_assemble).  Output: the condensed trace loads,
- * n_trace x nrhs, if s_out is not NULL. */
+ * (the loads l_K of Sec. 2 condensed onto the traces as in Sec. 1.2:
+ * s = b_t - K_tf K_ff^-1 b_f with b = W^H (L^-1 l)).  Cost: the element
+ * chain of dpg_assemble (Gram and B, both Cholesky factors, the forward
+ * solves and products, with the new load columns beside B) is run again,
+ * since only the condensed matrices are kept, not the factors of G.  Over
+ * every element when some load has plane-wave or u0_qp data; when all loads
+ * are Gaussian point sources only over the elements whose box comes within
+ * 8 sigma of a source (the others get zero loads).  A change of nrhs
+ * re-plans the element stage (small uploads and one stream sync).  Output:
+ * the condensed trace loads, n_trace x nrhs, if s_out is not NULL. */
 int dpg_load_rhs(dpg_ctx *ctx, const dpg_load *loads, int nrhs, double *s_out);
 
 /* Frees what only dpg_assemble and dpg_build_hierarchy use: the element and
@@ -248,7 +260,9 @@ int dpg_solve_noalloc(dpg_ctx *ctx, const double *rhs, int nrhs, double tol, dou
                       int32_t *iters_out, double *relres_out);
 
 /* Field coefficients of the element-interior unknowns for trace solutions x
- * (n_trace x nrhs): x_f = K_ff^-1 (b_f - K_ft x_t) per element, output
+ * (n_trace x nrhs): the back-substitution of the static condensation
+ * (Sec. 1.2: the field unknowns are eliminated element by element and
+ * recovered from the traces), x_f = K_ff^-1 (b_f - K_ft x_t) per element, output
  * [nrhs][n^3][4 p^3] in the order (p, u_x, u_y, u_z), each a Legendre
  * tensor product with x-degree fastest.  Requires the assembled loads. */
 int dpg_get_fields(dpg_ctx *ctx, const double *x, int nrhs, double *fields_out);
