@@ -325,8 +325,13 @@ def cpu_baseline(w, N_cpu=4):
     with the host BLAS threads.  value = n_trace x PCG iterations / time of
     the solve phase, the definition the GPU line uses, for the faster of the
     two runs; job_value counts the whole job."""
+    from paper_2304_01728_amd import workloads as W
     one = cpu_oracle_job(w, N_cpu, 1)
     allc = cpu_oracle_job(w, N_cpu, None)
+    # the smallest workload (4^3, p = 2, omega = 2 pi, V(1,1), tol 1e-10) at its own size
+    w4 = W.plane_wave_4()
+    small = {"workload": w4.name, "one_core": cpu_oracle_job(w4, w4.N, 1),
+             "all_cores": cpu_oracle_job(w4, w4.N, None)}
     # threaded BLAS on the oracle's many small matrices can be slower than one
     # core: the faster of the two settings is the baseline, both are reported
     best = allc if allc["value"] >= one["value"] else one
@@ -340,7 +345,7 @@ def cpu_baseline(w, N_cpu=4):
                        % (w.tol, N_cpu, w.p, allc["omega"], w.nu_pre, w.nu_post,
                           allc["n_trace"], allc["iterations"])),
             "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
-            "all_cores": allc, "one_core": one}
+            "all_cores": allc, "one_core": one, "plane_wave_4": small}
 
 
 def serving_stream(n_req, seed, max_active, load_factor):
@@ -350,58 +355,61 @@ def serving_stream(n_req, seed, max_active, load_factor):
     load_factor x the measured single-request capacity, 1-16 sources per
     request, mixed precision, tol 1e-8.  The hierarchies that fit the HBM
     budget are built before the clock starts (a server keeps them resident);
-    operators admitted later are built on arrival and counted in latency."""
+    operators admitted later are built on arrival and counted in latency.
+    The capacity is measured on the warm server itself: one 8-source request
+    per resident operator, alone, through the same batch path (the second of
+    two runs; the first captures the batch's graphs).  Returns the result
+    as a dict."""
     import torch
-    from paper_2304_01728_amd import dpgmg as D
     from paper_2304_01728_amd import serving as S
     torch.cuda.set_device(0)
     free, total = torch.cuda.mem_get_info(0)
     budget = int(0.85 * free)
     ops = S.draw_pool(seed=seed)
-    # service time of one 8-source request per operator, each alone on the GPU
-    probe = np.random.default_rng(seed + 2)
-    service = []
-    for op in ops:
-        print(f"[serving] calibrate op {op.key}: N={op.N} p={op.p} omega={op.omega:.2f}",
-              file=sys.stderr, flush=True)
-        ctx = op.build(batch_slots=1)
-        cen = probe.uniform(0.1, 0.9, size=(8, 3))
-        src = np.column_stack([cen, np.full(8, 0.02), np.ones(8), np.zeros(8)])
-        ld = [dict(dir=(0.0, 0.0, 1.0), amp=0.0, sources=src)]
-        for rep in range(2):   # the first run captures the graphs of the batch
-            t0 = time.perf_counter()
-            D.dpg_load_rhs(ctx, ld, want=False)
-            k = D.dpg_batch_add(ctx, None, load_col=0, tol=op.tol)
-            while not D.dpg_batch_step(ctx, 100):
-                pass
-            D.dpg_batch_take(ctx, k)
-            t = time.perf_counter() - t0
-        service.append(t)
-        ctx.close()
-    capacity = 1.0 / float(np.mean(service))
-    rate = load_factor * capacity
-    reqs = S.draw_requests(ops, n_req, rate, seed=seed)
     srv = S.Server(ops, budget_bytes=budget, max_active=max_active)
-    # warm the resident set in pool order while it fits
-    warm = []
-    for op in ops:
-        if sum(r.nbytes for r in srv.resident.values()) + srv.estimate(op) > budget:
-            break
-        r = S.Request(-1 - op.key, op.key, np.array([[0.5, 0.5, 0.5, 0.02, 1.0, 0.0]]))
-        srv.submit(r)
-        r.done.wait()
-        warm.append(op.key)
-    builds0, evict0 = srv.builds, srv.evictions
-    print(f"[serving] capacity {capacity:.2f} req/s, rate {rate:.2f} req/s, {n_req} requests, "
-          f"warm operators {warm}", file=sys.stderr, flush=True)
     try:
+        # warm the resident set in pool order while it fits
+        warm = []
+        for op in ops:
+            if sum(r.nbytes for r in srv.resident.values()) + srv.estimate(op) > budget:
+                break
+            print(f"[serving] build op {op.key}: N={op.N} p={op.p} omega={op.omega:.2f}",
+                  file=sys.stderr, flush=True)
+            r = S.Request(-1 - op.key, op.key, np.array([[0.5, 0.5, 0.5, 0.02, 1.0, 0.0]]))
+            srv.submit(r)
+            r.done.wait()
+            if r.error is not None:
+                raise RuntimeError(f"operator {op.key}: {r.error}")
+            warm.append(op.key)
+        # service time of one 8-source request per operator, alone on the server
+        probe = np.random.default_rng(seed + 2)
+        service = []
+        for key in warm:
+            cen = probe.uniform(0.1, 0.9, size=(8, 3))
+            src = np.column_stack([cen, np.full(8, 0.02), np.ones(8), np.zeros(8)])
+            for rep in range(2):
+                r = S.Request(-100 - key, key, src)
+                t0 = time.perf_counter()
+                srv.submit(r)
+                r.done.wait()
+                t = time.perf_counter() - t0
+                if r.error is not None:
+                    raise RuntimeError(f"operator {key}: {r.error}")
+            service.append(t)
+        capacity = 1.0 / float(np.mean(service))
+        rate = load_factor * capacity
+        reqs = S.draw_requests(ops, n_req, rate, seed=seed)
+        builds0, evict0 = srv.builds, srv.evictions
+        print(f"[serving] capacity {capacity:.2f} req/s, rate {rate:.2f} req/s, {n_req} requests, "
+              f"warm operators {warm}", file=sys.stderr, flush=True)
         wall, lat = S.run_stream(srv, reqs)
+        builds, evictions = srv.builds - builds0, srv.evictions - evict0
     finally:
         srv.close()
     batches = [r.batch for r in reqs]
-    out = {
+    return {
         "metric": "solves/s", "value": n_req / wall, "unit": "solves/s", "n_gpus": 1,
-        "higher_is_better": True, "dtype": "mixed (FP32 V-cycle, FP64 outer CG)",
+        "higher_is_better": True, "dtype": "f64+f32",
         "data": "synthetic",
         "latency_ms": {"p50": 1e3 * S.percentile(lat, 50), "p99": 1e3 * S.percentile(lat, 99),
                        "mean": 1e3 * float(np.mean(lat)), "max": 1e3 * float(np.max(lat))},
@@ -412,8 +420,8 @@ def serving_stream(n_req, seed, max_active, load_factor):
         "batch_note": ("batch = most columns a request's operator batch ran while the request "
                        "was in it; joined_running_batch = requests admitted into a block solve "
                        "already part-way through"),
-        "builds_during_stream": srv.builds - builds0,
-        "evictions_during_stream": srv.evictions - evict0,
+        "builds_during_stream": builds,
+        "evictions_during_stream": evictions,
         "hbm_budget_GB": budget / 1e9,
         "config": {"workload": "serving stream: 8 layered-medium operators, N 8-32, p 2-4, "
                                "Poisson arrivals, 1-16 Gaussian sources per request",
@@ -422,7 +430,6 @@ def serving_stream(n_req, seed, max_active, load_factor):
                                  for o in ops],
                    "seed": seed, "max_active": max_active, "tol": 1e-8},
     }
-    print(json.dumps(out))
 
 
 def fp64_twin(w, x_mixed):
@@ -501,6 +508,9 @@ def main():
                     help="run the layered-medium request stream through the serving loop; "
                          "report solves/s and p50/p99 latency")
     ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--serving-requests", type=int, default=100,
+                    help="requests of the serving stream the default run reports beside the "
+                         "solver line (0: none)")
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--max-active", type=int, default=4)
     ap.add_argument("--load-factor", type=float, default=0.7)
@@ -522,7 +532,8 @@ def main():
         p_robustness(args.workload)
         return
     if args.serving:
-        serving_stream(args.requests, args.seed, args.max_active, args.load_factor)
+        print(json.dumps(serving_stream(args.requests, args.seed, args.max_active,
+                                        args.load_factor)), flush=True)
         return
 
     import torch
@@ -641,6 +652,10 @@ def main():
             "speedup_mixed": tw["time_to_tol_ms"] / (1e3 * solve_s),
             "mixed_rel_error_vs_fp64": tw["mixed_rel_error_vs_fp64"],
             "fp64": tw}
+    if args.serving_requests > 0:
+        print("[bench] serving stream", file=sys.stderr, flush=True)
+        out["serving"] = serving_stream(args.serving_requests, args.seed, args.max_active,
+                                        args.load_factor)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)

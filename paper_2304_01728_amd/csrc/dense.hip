@@ -3,7 +3,9 @@
 // The rank-k updates share one tile routine: a workgroup of 256 threads
 // stages 64x16 slices of op(A) and 16x64 slices of op(B) in LDS and its four
 // waves accumulate the 64x64 complex output tile on the FP64 matrix cores
-// (v_mfma_f64_16x16x4f64).  The FP64 matrix and vector peaks of MI355X are
+// (v_mfma_f64_16x16x4f64), three real products per complex one.  The tile
+// kernels run two waves per SIMD: the three accumulator sets and the
+// prefetched slice take 184-192 registers, which at three waves (168) spilled.  The FP64 matrix and vector peaks of MI355X are
 // equal (78.6 TFLOP/s); the matrix cores win because they reuse each operand
 // sixteen times inside the instruction, where vector FMAs would need one LDS
 // read per two complex multiply-adds.
@@ -23,6 +25,8 @@ namespace dpg {
 namespace {
 
 constexpr int TM = 64, TN = 64, TK = 16, NT = 256, NB = 64, NBO = 128;
+// entries of a k-slice of op(A) (and of op(B)) per thread
+constexpr int QS = TM * TK / NT;
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 struct GemmSmem {
@@ -72,7 +76,7 @@ __device__ __forceinline__ void xcd_remap(int &bx, int &by) {
   }
 }
 
-// One k-slice of op(A) (64 x 16) and op(B) (16 x 64), four entries of each per
+// One k-slice of op(A) (64 x 16) and op(B) (16 x 64), QS = 4 entries of each per
 // thread.  Every load is issued (entries outside m x k and k x n read the
 // nearest entry inside, which exists because the tile is not empty), and the
 // returned mask marks the entries inside; store_slice writes zeros for the
@@ -82,11 +86,11 @@ __device__ __forceinline__ void xcd_remap(int &bx, int &by) {
 template <int OPA, int OPB>
 __device__ __forceinline__ unsigned load_slice(int m, int n, int k, int k0, int r0, int c0,
                                                const double2 *A, int lda, const double2 *B,
-                                               int ldb, double2 ra[4], double2 rb[4]) {
+                                               int ldb, double2 ra[QS], double2 rb[QS]) {
   const int tid = threadIdx.x;
   unsigned ok = 0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < QS; ++q) {
     const int e = tid + NT * q;
     int rr, kk;
     if (OPA == OP_N) { rr = e % TM; kk = e / TM; } else { kk = e % TK; rr = e / TK; }
@@ -95,23 +99,23 @@ __device__ __forceinline__ unsigned load_slice(int m, int n, int k, int k0, int 
     ra[q] = ld_op<OPA == OP_C ? OP_T : OPA>(A, lda, min(r, m - 1), min(kg, k - 1));
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < QS; ++q) {
     const int e = tid + NT * q;
     int kk, cc;
     if (OPB == OP_N) { kk = e % TK; cc = e / TK; } else { cc = e % TN; kk = e / TN; }
     const int c = c0 + cc, kg = k0 + kk;
-    ok |= (unsigned)(c < n && kg < k) << (4 + q);
+    ok |= (unsigned)(c < n && kg < k) << (QS + q);
     rb[q] = ld_op<OPB == OP_C ? OP_T : OPB>(B, ldb, min(kg, k - 1), min(c, n - 1));
   }
   return ok;
 }
 
 template <int OPA, int OPB>
-__device__ __forceinline__ void store_slice(const double2 ra[4], const double2 rb[4], unsigned ok,
+__device__ __forceinline__ void store_slice(const double2 ra[QS], const double2 rb[QS], unsigned ok,
                                             GemmSmem &sm) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < QS; ++q) {
     const int e = tid + NT * q;
     int rr, kk;
     if (OPA == OP_N) { rr = e % TM; kk = e / TM; } else { kk = e % TK; rr = e / TK; }
@@ -119,12 +123,12 @@ __device__ __forceinline__ void store_slice(const double2 ra[4], const double2 r
     sm.As[rr][kk] = ((ok >> q) & 1) ? v : mk(0.0, 0.0);
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < QS; ++q) {
     const int e = tid + NT * q;
     int kk, cc;
     if (OPB == OP_N) { kk = e % TK; cc = e / TK; } else { cc = e % TN; kk = e / TN; }
     const double2 v = OPB == OP_C ? cconj(rb[q]) : rb[q];
-    sm.Bs[kk][cc] = ((ok >> (4 + q)) & 1) ? v : mk(0.0, 0.0);
+    sm.Bs[kk][cc] = ((ok >> (QS + q)) & 1) ? v : mk(0.0, 0.0);
   }
 }
 
@@ -142,23 +146,30 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int 
   // FP64 matrix cores: v_mfma_f64_16x16x4f64 computes D(16x16) += A(16x4) B(4x16)
   // with A[i][k] in lane i + 16k, B[k][j] in lane j + 16k and D[i][j] in
   // lane j + 16 (i % 4), element i / 4.  Wave w owns the 32x32 sub-tile at
-  // (32 (w / 2), 32 (w % 2)) as 2x2 blocks; a complex product takes four real
-  // MFMAs (re*re - im*im, re*im + im*re), issued term by term so that two
-  // updates of one accumulator are never adjacent.
+  // (32 (w / 2), 32 (w % 2)) as 2x2 blocks.  A complex product takes three
+  // real MFMAs (the three-multiplication form): P1 = sum a_re b_re,
+  // P2 = sum a_im b_im, P3 = sum (a_re + a_im)(b_re + b_im); then
+  // re = P1 - P2 and im = P3 - P1 - P2.  The real part is as accurate as with
+  // four products; the imaginary part's error bound grows from
+  // 2 u sum |a||b| to about 4 u sum |a||b|, still a normwise bound of the same
+  // order, which is what the factorisations and products here need.  The
+  // three products are issued term by term so that two updates of one
+  // accumulator are never adjacent.
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = 32 * (wave >> 1), wc = 32 * (wave & 1);
   const int li = lane & 15, lk = lane >> 4;
-  v4d acc_re[2][2], acc_im[2][2];
+  v4d acc_p1[2][2], acc_p2[2][2], acc_p3[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      acc_re[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-      acc_im[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      acc_p1[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      acc_p2[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      acc_p3[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
     }
   // The next k-slice is fetched into registers while the current one is
   // multiplied from LDS, so global latency hides behind the matrix cores.
-  double2 ra[4], rb[4];
+  double2 ra[QS], rb[QS];
   unsigned ok = 0;
   if (k_begin < k) ok = load_slice<OPA, OPB>(m, n, k, k_begin, r0, c0, A, lda, B, ldb, ra, rb);
 #pragma unroll 1
@@ -173,26 +184,26 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int 
       for (int i = 0; i < 2; ++i) a[i] = sm.As[wr + 16 * i + li][ks + lk];
 #pragma unroll
       for (int j = 0; j < 2; ++j) b[j] = sm.Bs[ks + lk][wc + 16 * j + li];
+      double sa[2], sb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) sa[i] = a[i].x + a[i].y;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) sb[j] = b[j].x + b[j].y;
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc_re[i][j], 0, 0, 0);
+          acc_p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc_p1[i][j], 0, 0, 0);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].y, acc_im[i][j], 0, 0, 0);
+          acc_p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].y, acc_p2[i][j], 0, 0, 0);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[i].y, b[j].y, acc_re[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].x, acc_im[i][j], 0, 0, 0);
+          acc_p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[i], sb[j], acc_p3[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -218,7 +229,8 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int 
       for (int e = 0; e < 4; ++e) {
         const int r = r0 + wr + 16 * i + lk + 4 * e, c = c0 + wc + 16 * j + li;
         if (r < m && c < n && (!lower_only || c <= r)) {
-          double2 v = cmul(alpha, mk(acc_re[i][j][e], acc_im[i][j][e]));
+          const double p1 = acc_p1[i][j][e], p2 = acc_p2[i][j][e];
+          double2 v = cmul(alpha, mk(p1 - p2, acc_p3[i][j][e] - p1 - p2));
           if (use_beta) v = cfma(beta, cv[j][e], v);
           C[r + (int64_t)c * ldc] = v;
           if (mirror) C[c + (int64_t)r * ldc] = cconj(v);
@@ -614,7 +626,7 @@ __global__ __launch_bounds__(NTB, 2) void k_potrf_diag(double2 *base, const Potr
 
 // Panel below the diagonal block: X = A_panel L_kk^-H as a product with the
 // stored inverse, one 64-row tile per workgroup, in place.
-__global__ __launch_bounds__(NT, 3) void k_potrf_panel(double2 *base, const PotrfItem *items,
+__global__ __launch_bounds__(NT, 2) void k_potrf_panel(double2 *base, const PotrfItem *items,
                                                     const int *info, int k0, int kend,
                                                     const double2 *work, int wslots) {
   __shared__ GemmSmem sm;
@@ -634,7 +646,7 @@ __global__ __launch_bounds__(NT, 3) void k_potrf_panel(double2 *base, const Potr
 
 // Update C[r, c] -= sum_{k in [k_lo, k_hi)} A[r, k] conj(A[c, k]) for
 // c in [c_lo, c_hi), r >= c (lower triangle only).
-__global__ __launch_bounds__(NT, 3) void k_potrf_update(double2 *base, const PotrfItem *items,
+__global__ __launch_bounds__(NT, 2) void k_potrf_update(double2 *base, const PotrfItem *items,
                                                      const int *info, int k_lo, int k_hi,
                                                      int c_lo, int c_hi, int tiles_c) {
   // tiles_c > 0: grid of tiles_c tile columns; tiles_c = 0: the lower
@@ -680,7 +692,7 @@ __global__ __launch_bounds__(NTD) void k_trsm_inv(const double2 *lbase, const Tr
 
 // Rows [k0, k0+kb) of B: X_k = L_kk^-1 B_k, one 64-column tile per workgroup,
 // in place.
-__global__ __launch_bounds__(NT, 3) void k_trsm_solve(double2 *bbase, const TrsmItem *items, int k0,
+__global__ __launch_bounds__(NT, 2) void k_trsm_solve(double2 *bbase, const TrsmItem *items, int k0,
                                                    int kend, int tri, const double2 *work,
                                                    int wslots) {
   __shared__ GemmSmem sm;
@@ -700,7 +712,7 @@ __global__ __launch_bounds__(NT, 3) void k_trsm_solve(double2 *bbase, const Trsm
 
 // B[r, c] -= sum_{k in [k_lo, k_hi)} L[r, k] X[k, c] for r in [r_lo, r_hi),
 // one 64x64 tile per workgroup.
-__global__ __launch_bounds__(NT, 3) void k_trsm_update(const double2 *lbase, double2 *bbase,
+__global__ __launch_bounds__(NT, 2) void k_trsm_update(const double2 *lbase, double2 *bbase,
                                                     const TrsmItem *items, int k_lo, int k_hi,
                                                     int r_lo, int r_hi, int tri, int tiles_c) {
   __shared__ GemmSmem sm;
@@ -723,7 +735,7 @@ __global__ __launch_bounds__(NT, 3) void k_trsm_update(const double2 *lbase, dou
 // ---- GEMM ----------------------------------------------------------------------------
 
 template <int OPA, int OPB>
-__global__ __launch_bounds__(NT, 3) void k_gemm(double2 alpha, const double2 *abase,
+__global__ __launch_bounds__(NT, 2) void k_gemm(double2 alpha, const double2 *abase,
                                              const double2 *bbase, double2 beta, double2 *cbase,
                                              const GemmItem *items, int tiles_n, int mode) {
   __shared__ GemmSmem sm;
