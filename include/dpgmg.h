@@ -318,19 +318,27 @@ int64_t dpg_export(const dpg_ctx *ctx, int what, int level, void *out, int64_t c
 
 /* Kernel timing.  dpg_profile(ctx, 1) resets the counters and brackets every
  * later kernel launch of the context with HIP events on its stream;
- * dpg_profile(ctx, 0) stops.  dpg_kernel_stats returns, for one kernel class,
- * the launches timed so far, their summed duration and their summed
+ * dpg_profile(ctx, 0) stops.  While profiling is on, the setup runs on the
+ * context's stream alone (no overlap of its four setup streams), so that each
+ * launch's events time that launch.  dpg_kernel_stats returns, for one kernel
+ * class, the launches timed so far, their summed duration and their summed
  * algorithmic work: bytes for the single-column block-apply kernels (packed
  * Hermitian blocks, each read once), flops for the dense kernels (LAPACK
  * counts) and for the multi-column block applies (8 n^2 nr real flops per
  * block of order n applied to nr columns).  Classes follow the kernel
- * symbols. */
+ * symbols; DPG_K_POTRF and DPG_K_TRSM time whole Cholesky and forward-solve
+ * routines (several kernels each), and DPG_K_POTRF_DIAG ... DPG_K_TRSM_UPDATE
+ * their kernels one by one, each launch with its share of the routine's
+ * LAPACK count split by the steps of the blocked algorithm (diagonal block,
+ * panel, updates; solves with the diagonal-block inverses, updates). */
 enum {
   DPG_K_GRAM = 0, DPG_K_BMAT = 1, DPG_K_LOAD = 2, DPG_K_POTRF = 3, DPG_K_TRSM = 4,
   DPG_K_GEMM = 5, DPG_K_MACRO_ASM = 6, DPG_K_PATCH_GATHER = 7, DPG_K_APPLY64 = 8,
   DPG_K_APPLY32 = 9, DPG_K_REDUCE = 10, DPG_K_CONDENSE = 11, DPG_K_EXPAND = 12,
   DPG_K_TRANSFER = 13, DPG_K_CG = 14, DPG_K_OTHER = 15, DPG_K_APPLYB64 = 16,
-  DPG_K_APPLYB32 = 17, DPG_K_NCLASS = 18
+  DPG_K_APPLYB32 = 17, DPG_K_POTRF_DIAG = 18, DPG_K_POTRF_PANEL = 19,
+  DPG_K_POTRF_UPDATE = 20, DPG_K_TRSM_INV = 21, DPG_K_TRSM_SOLVE = 22,
+  DPG_K_TRSM_UPDATE = 23, DPG_K_NCLASS = 24
 };
 typedef struct {
   int64_t launches;

@@ -295,8 +295,10 @@ void element_stage(dpg_ctx *c, int l, bool write_matrices, const IndicatorArgs *
   }
   const double *kap = fine ? c->kappa.p : f.kappa.p, *Zel = fine ? c->Zel.p : f.Zel.p;
   ElemGeom g{f.N, c->side / f.N, c->omega, 1.0, {c->org[0], c->org[1], c->org[2]}, elist};
-  const int NS = P.ns;
+  // one stream while kernels are profiled, so that each launch's events time it alone
+  const int NS = c->prof.on ? 1 : P.ns;
   const hipStream_t xs[4] = {c->stream, c->aux, c->paux[0], c->paux[1]};
+  const DenseProf dG{&c->prof, nullptr, nt, nullptr, mp}, dK{&c->prof, nullptr, nf, nullptr, mp - nf};
   const hipEvent_t xj[4] = {nullptr, c->ev_join, c->ev_pjoin[0], c->ev_pjoin[1]};
   for (int k = 1; k < NS; ++k) stream_wait(c->stream, xs[k], c->ev_fork);
   for (int e0 = 0, k = 0; e0 < total; e0 += C, ++k) {
@@ -319,11 +321,11 @@ void element_stage(dpg_ctx *c, int l, bool write_matrices, const IndicatorArgs *
     }
     {
       ProfScope ps(&c->prof, DPG_K_POTRF, cnt * f_potrf(nt), s);
-      potrf_batched(G, P.pG.p, cnt, P.info.p + e0, nt, wk, s);
+      potrf_batched(G, P.pG.p, cnt, P.info.p + e0, nt, wk, s, &dG);
     }
     {
       ProfScope ps(&c->prof, DPG_K_TRSM, cnt * f_trsm(nt, mp), s);
-      trsm_batched(G, BL, P.tG.p, cnt, nt, mp, false, wk, true, s);
+      trsm_batched(G, BL, P.tG.p, cnt, nt, mp, false, wk, true, s, &dG);
     }
     {
       ProfScope ps(&c->prof, DPG_K_GEMM, cnt * f_herk(mp, nt), s);
@@ -331,11 +333,11 @@ void element_stage(dpg_ctx *c, int l, bool write_matrices, const IndicatorArgs *
     }
     {
       ProfScope ps(&c->prof, DPG_K_POTRF, cnt * f_potrf(nf), s);
-      potrf_batched(K, P.pK.p, cnt, P.info.p + nel + e0, nf, wk, s);
+      potrf_batched(K, P.pK.p, cnt, P.info.p + nel + e0, nf, wk, s, &dK);
     }
     {
       ProfScope ps(&c->prof, DPG_K_TRSM, cnt * f_trsm(nf, mp - nf), s);
-      trsm_batched(K, K, P.tK.p, cnt, nf, mp - nf, false, wk, true, s);
+      trsm_batched(K, K, P.tK.p, cnt, nf, mp - nf, false, wk, true, s, &dK);
     }
     if (ind) {
       const int q = ind->nr;
@@ -504,10 +506,12 @@ void build_macro_level(dpg_ctx *c, int l) {
   MacroPlan &P = f.mp;
   const int ntr = f.ntr_c, nBf = f.nBf, nI = f.nI, nT = nBf + nI, nblk = f.nblk, CB = P.CB;
   const bool two = nblk > CB;
-  if (two) stream_wait(c->stream, c->aux, c->ev_fork);
+  const bool one_stream = c->prof.on;   // profiled launches are timed alone
+  const DenseProf dI{&c->prof, nullptr, nI, nullptr, nBf}, dL{&c->prof, nullptr, nI, nullptr, nI};
+  if (two && !one_stream) stream_wait(c->stream, c->aux, c->ev_fork);
   for (int b0 = 0, k = 0; b0 < nblk; b0 += CB, ++k) {
     const int cnt = std::min(CB, nblk - b0), u = two ? (k & 1) : 0;
-    const hipStream_t s = u ? c->aux : c->stream;
+    const hipStream_t s = u && !one_stream ? c->aux : c->stream;
     double2 *T = c->mT[u].p, *Linv = c->mLinv[u].p, *X = c->mX[u].p, *wk = c->mwk[u].p;
     if (f.order) {
       // order level: the blocks are the element matrices themselves (nothing
@@ -520,11 +524,11 @@ void build_macro_level(dpg_ctx *c, int l) {
     }
     {
       ProfScope ps(&c->prof, DPG_K_POTRF, cnt * f_potrf(nI), s);
-      potrf_batched(T, P.pII.p, cnt, P.info.p + b0, nI, wk, s);
+      potrf_batched(T, P.pII.p, cnt, P.info.p + b0, nI, wk, s, &dI);
     }
     {
       ProfScope ps(&c->prof, DPG_K_TRSM, cnt * f_trsm(nI, nBf), s);
-      trsm_batched(T, T, P.tIB.p, cnt, nI, nBf, false, wk, true, s);
+      trsm_batched(T, T, P.tIB.p, cnt, nI, nBf, false, wk, true, s, &dI);
     }
     {
       ProfScope ps(&c->prof, DPG_K_GEMM, cnt * f_herk(nBf, nI), s);
@@ -536,7 +540,7 @@ void build_macro_level(dpg_ctx *c, int l) {
     }
     {
       ProfScope ps(&c->prof, DPG_K_TRSM, cnt * f_trsm(nI, nI), s);
-      trsm_batched(T, Linv, P.tLi.p, cnt, nI, nI, true, wk, true, s);
+      trsm_batched(T, Linv, P.tLi.p, cnt, nI, nI, true, wk, true, s, &dL);
     }
     {
       ProfScope ps(&c->prof, DPG_K_GEMM, cnt * f_herk(nI, nI), s);
@@ -561,7 +565,7 @@ void build_macro_level(dpg_ctx *c, int l) {
                    P.gA.p, cnt, ntr, ntr, s);
     }
   }
-  if (two) stream_wait(c->aux, c->stream, c->ev_join);
+  if (two && !one_stream) stream_wait(c->aux, c->stream, c->ev_join);
   const hipStream_t s = c->stream;
   if (c->opt.precision == DPG_MIXED && l < c->L && !f.order) {
     launch_to32(f.Tinv.n, f.Tinv.p, f.Tinv32.p, s);
@@ -655,6 +659,7 @@ void plan_patches(dpg_ctx *c, int l) {
       }
       B.off.upload(off, bd, s);
       B.nn.upload(nn, bd, s);
+      B.hn = nn;
       B.pi.upload(pi, bd, s);
       B.ti.upload(ti, bd, s);
       B.gi.upload(gi, bd, s);
@@ -700,6 +705,7 @@ void build_patches(dpg_ctx *c, int l, int half, hipStream_t s) {
   double2 *S = c->pS[half].p, *X = c->pX[half].p, *wk = c->pwk[half].p;
   for (PatchBatch &B : P.batches) {
     if (B.half != half) continue;
+    const DenseProf dp{&c->prof, B.hn.data(), 0, B.hn.data(), 0};
     {
       ProfScope ps(&c->prof, DPG_K_PATCH_GATHER, 0, s);
       launch_patch_gather(mfull(f), f.nBf, f.mc.Nc, f.patch_ptr.p, f.patch_slot.p, B.v0, B.cnt,
@@ -707,7 +713,7 @@ void build_patches(dpg_ctx *c, int l, int half, hipStream_t s) {
     }
     {
       ProfScope ps(&c->prof, DPG_K_POTRF, B.fp, s);
-      potrf_batched(S, B.pi.p, B.cnt, P.info.p + B.v0, B.nmax, wk, s);
+      potrf_batched(S, B.pi.p, B.cnt, P.info.p + B.v0, B.nmax, wk, s, &dp);
     }
     {
       ProfScope ps(&c->prof, DPG_K_OTHER, 0, s);
@@ -715,7 +721,7 @@ void build_patches(dpg_ctx *c, int l, int half, hipStream_t s) {
     }
     {
       ProfScope ps(&c->prof, DPG_K_TRSM, B.ft, s);
-      trsm_batched(S, X, B.ti.p, B.cnt, B.nmax, B.nmax, true, wk, true, s);
+      trsm_batched(S, X, B.ti.p, B.cnt, B.nmax, B.nmax, true, wk, true, s, &dp);
     }
     {
       ProfScope ps(&c->prof, DPG_K_GEMM, B.fg, s);
@@ -756,6 +762,7 @@ void smooth_recompute(dpg_ctx *c, int l, const double2 *x, double2 *y, const dou
   herm_gather(H, x, H.xl64.p, s);
   for (PatchBatch &B : P.batches) {
     double2 *S = c->pS[B.half].p, *X = c->pX[B.half].p, *wk = c->pwk[B.half].p;
+    const DenseProf dp{&c->prof, B.hn.data(), 0, B.hn.data(), 0};
     {
       PROF(DPG_K_PATCH_GATHER, 0);
       launch_patch_gather_tiles(f.Mset.t64.p, f.Mset.ent_off.p, f.mpidx.p, f.nBf, f.mc.Nc,
@@ -764,7 +771,7 @@ void smooth_recompute(dpg_ctx *c, int l, const double2 *x, double2 *y, const dou
     }
     {
       PROF(DPG_K_POTRF, B.fp);
-      potrf_batched(S, B.pi.p, B.cnt, P.info.p + B.v0, B.nmax, wk, s);
+      potrf_batched(S, B.pi.p, B.cnt, P.info.p + B.v0, B.nmax, wk, s, &dp);
     }
     {
       PROF(DPG_K_OTHER, 0);
@@ -772,7 +779,7 @@ void smooth_recompute(dpg_ctx *c, int l, const double2 *x, double2 *y, const dou
     }
     {
       PROF(DPG_K_TRSM, B.ft);
-      trsm_batched(S, X, B.ti.p, B.cnt, B.nmax, B.nmax, true, wk, true, s);
+      trsm_batched(S, X, B.ti.p, B.cnt, B.nmax, B.nmax, true, wk, true, s, &dp);
     }
     PROF(DPG_K_GEMM, 0);
     gemm_batched(OP_N, OP_N, mk(1, 0), X, H.xl64.p, mk(0, 0), c->ptmp.p, B.gy.p, B.cnt, B.nmax, 1,
@@ -811,9 +818,10 @@ void build_coarsest(dpg_ctx *c) {
   const int n0 = (int)z.num.n;
   launch_assemble_dense(z.E.p, z.ntr, z.edofs.p, z.nel, n0, c->T0.p, s);
   HIP_OK(hipMemcpyAsync(c->zF.p, c->T0.p, (size_t)n0 * n0 * 16, hipMemcpyDeviceToDevice, s));
-  potrf_batched(c->zF.p, c->zpi.p, 1, c->zinfo.p, n0, c->zwk.p, s);
+  const DenseProf dz{&c->prof, nullptr, n0, nullptr, n0};
+  potrf_batched(c->zF.p, c->zpi.p, 1, c->zinfo.p, n0, c->zwk.p, s, &dz);
   launch_identity(c->zoff.p, c->znn.p, 1, n0, c->zLi.p, s);
-  trsm_batched(c->zF.p, c->zLi.p, c->zti.p, 1, n0, n0, true, c->zwk.p, true, s);
+  trsm_batched(c->zF.p, c->zLi.p, c->zti.p, 1, n0, n0, true, c->zwk.p, true, s, &dz);
   gemm_batched(OP_C, OP_N, mk(1, 0), c->zLi.p, c->zLi.p, mk(0, 0), c->zTi.p, c->zgi.p, 1, n0, n0,
                s, GEMM_UPPER_LOWTRI);
   c->T0set.pack(c->zTi.p, c->zoff.p, c->zld.p, nullptr, nullptr, s);
@@ -850,17 +858,21 @@ void build_hierarchy(dpg_ctx *c) {
     }
     build_coarsest(c);
   } else {
-    for (int k = 0; k < NX; ++k) stream_wait(c->stream, xs[k], c->ev_fork);
+    // while kernels are profiled, every part runs on the main stream (each
+    // launch's events then time it alone)
+    if (c->prof.on)
+      for (int k = 0; k < NX; ++k) xs[k] = c->stream;
+    for (int k = 0; k < NX && !c->prof.on; ++k) stream_wait(c->stream, xs[k], c->ev_fork);
     for (int l = c->L; l >= 1; --l) {
       build_macro_level(c, l);
       for (int k = 0; k < NX; ++k) {
-        stream_wait(c->stream, xs[k], c->ev_level[l]);
+        if (!c->prof.on) stream_wait(c->stream, xs[k], c->ev_level[l]);
         build_patches(c, l, k, xs[k]);
       }
     }
     build_coarsest(c);
     for (int l = c->L; l >= 1; --l) build_patches(c, l, NX, c->stream);
-    for (int k = 0; k < NX; ++k) stream_wait(xs[k], c->stream, xj[k]);
+    for (int k = 0; k < NX && !c->prof.on; ++k) stream_wait(xs[k], c->stream, xj[k]);
   }
   for (int l = c->L; l >= 1; --l) {
     if (!c->lv[l].order)   // an order level factors no interior block

@@ -59,6 +59,7 @@ struct PatchBatch {
   double fp = 0, ft = 0, fg = 0;
   DevBuf<int64_t> off;
   DevBuf<int32_t> nn;
+  std::vector<int32_t> hn;           // the orders nn on the host (kernel statistics)
   DevBuf<PotrfItem> pi;
   DevBuf<TrsmItem> ti;
   DevBuf<GemmItem> gi;

@@ -17,6 +17,7 @@
 // the 64x64 diagonal block and its inverse in LDS; the panel itself is then a
 // small product with that inverse on the matrix cores, and the update inside
 // the 128-wide block a rank-64 product.
+#include <algorithm>
 #include <cmath>
 
 #include "dense.hpp"
@@ -775,25 +776,60 @@ int64_t dense_work_size(int nitems, int nmax) {
   return (int64_t)std::max(nitems, 0) * cdiv(std::max(nmax, 1), NB) * NB * NB;
 }
 
+// Algorithmic flops of the launches of one routine call (DenseProf): sums
+// over the items of the blocked algorithm's step counts.
+namespace {
+template <typename F> double over_items(const DenseProf *dp, int nitems, F f) {
+  double t = 0.0;
+  for (int i = 0; i < nitems; ++i) t += f(dp->order(i), dp->cols(i));
+  return t;
+}
+const DenseProf *prof_on(const DenseProf *dp) { return dp && dp->on() ? dp : nullptr; }
+Prof *prof_of(const DenseProf *dp) { return dp ? dp->prof : nullptr; }
+}  // namespace
+
 void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *info_dev, int nmax,
-                   double2 *work, hipStream_t s) {
+                   double2 *work, hipStream_t s, const DenseProf *dp) {
   if (nitems <= 0 || nmax <= 0) return;
   const int kmax = nmax;
   const int wslots = (int)cdiv(nmax, NB);
+  const DenseProf *pf = prof_on(dp);
   HIP_OK(hipMemsetAsync(info_dev, 0, nitems * sizeof(int), s));
   for (int K0 = 0; K0 < kmax; K0 += NBO) {
     const int K1 = std::min(K0 + NBO, kmax);
     for (int k0 = K0; k0 < K1; k0 += NB) {
       const int kb = std::min(NB, K1 - k0);
-      hipLaunchKernelGGL(k_potrf_diag, dim3(nitems), dim3(NTB), 0, s, base, items_dev, info_dev, k0,
-                         K1, work, wslots);
+      {
+        const double w = pf ? over_items(pf, nitems, [&](int n, int) {
+          const double b = std::max(0, std::min(NB, std::min(K1, n) - k0));
+          return 4.0 / 3.0 * b * b * b;
+        }) : 0.0;
+        ProfScope ps(prof_of(dp), DPG_K_POTRF_DIAG, w, s);
+        hipLaunchKernelGGL(k_potrf_diag, dim3(nitems), dim3(NTB), 0, s, base, items_dev, info_dev,
+                           k0, K1, work, wslots);
+      }
       const int rows = nmax - k0 - kb;
       if (rows <= 0) continue;
-      hipLaunchKernelGGL(k_potrf_panel, dim3(cdiv(rows, TM), nitems), dim3(NT), 0, s, base,
-                         items_dev, info_dev, k0, K1, (const double2 *)work, wslots);
+      {
+        const double w = pf ? over_items(pf, nitems, [&](int n, int) {
+          const int b = std::max(0, std::min(NB, std::min(K1, n) - k0));
+          const double m = b > 0 ? std::max(0, n - (k0 + b)) : 0;
+          return 4.0 * m * b * b;
+        }) : 0.0;
+        ProfScope ps(prof_of(dp), DPG_K_POTRF_PANEL, w, s);
+        hipLaunchKernelGGL(k_potrf_panel, dim3(cdiv(rows, TM), nitems), dim3(NT), 0, s, base,
+                           items_dev, info_dev, k0, K1, (const double2 *)work, wslots);
+      }
       // update of the rest of this block column only
       const int c_lo = k0 + kb, c_hi = K1;
       if (c_lo < c_hi) {
+        const double w = pf ? over_items(pf, nitems, [&](int n, int) {
+          const double kw = std::max(0, std::min(k0 + kb, n) - k0);
+          double macs = 0.0;
+          for (int c = c_lo; c < std::min(c_hi, n); ++c) macs += kw * (n - c);
+          return 8.0 * macs;
+        }) : 0.0;
+        ProfScope ps(prof_of(dp), DPG_K_POTRF_UPDATE, w, s);
         const int tr = (int)cdiv(nmax - c_lo, TM), tc = (int)cdiv(c_hi - c_lo, TN);
         hipLaunchKernelGGL(k_potrf_update, dim3(tr * tc, nitems), dim3(NT), 0, s, base,
                            items_dev, info_dev, k0, k0 + kb, c_lo, c_hi, tc);
@@ -801,6 +837,11 @@ void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *i
     }
     // block update of the trailing matrix
     if (K1 < nmax) {
+      const double w = pf ? over_items(pf, nitems, [&](int n, int) {
+        const double kw = std::max(0, std::min(K1, n) - K0), t = std::max(0, n - K1);
+        return 8.0 * kw * t * (t + 1) / 2;
+      }) : 0.0;
+      ProfScope ps(prof_of(dp), DPG_K_POTRF_UPDATE, w, s);
       const int t = (int)cdiv(nmax - K1, TM);
       hipLaunchKernelGGL(k_potrf_update, dim3(t * (t + 1) / 2, nitems), dim3(NT), 0, s, base,
                          items_dev, info_dev, K0, K1, K1, nmax, 0);
@@ -811,29 +852,61 @@ void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *i
 
 void trsm_batched(const double2 *lbase, double2 *bbase, const TrsmItem *items_dev, int nitems,
                   int max_n, int max_cols, bool identity_rhs, double2 *work, bool inverses_ready,
-                  hipStream_t s) {
+                  hipStream_t s, const DenseProf *dp) {
   if (nitems <= 0 || max_cols <= 0 || max_n <= 0) return;
   const int tri = identity_rhs ? 1 : 0;
   const int wslots = (int)cdiv(max_n, NB);
-  if (!inverses_ready)
+  const DenseProf *pf = prof_on(dp);
+  if (!inverses_ready) {
+    ProfScope ps(prof_of(dp), DPG_K_TRSM_INV, 0.0, s);   // no algorithmic flops of its own
     hipLaunchKernelGGL(k_trsm_inv, dim3(wslots, nitems), dim3(NTD), 0, s, lbase, items_dev, work,
                        wslots);
+  }
+  // multiply-adds of an update of rows [r_lo, r_hi) by inner indices
+  // [k_lo, k_hi) for an item of order n with nc columns (identity right-hand
+  // side: column c has nonzeros in rows >= c only)
+  auto upd = [&](int n, int nc, int k_lo, int k_hi, int r_lo, int r_hi) {
+    const double m = std::max(0, std::min(r_hi, n) - r_lo);
+    const int ke = std::min(k_hi, n);
+    const double kw = std::max(0, ke - k_lo);
+    if (m <= 0 || kw <= 0) return 0.0;
+    if (!tri) return 8.0 * m * kw * nc;
+    return 8.0 * m * ((double)k_lo * kw + kw * (kw + 1) / 2);
+  };
   for (int K0 = 0; K0 < max_n; K0 += NBO) {
     const int K1 = std::min(K0 + NBO, max_n);
     for (int k0 = K0; k0 < K1; k0 += NB) {
       const int kb = std::min(NB, K1 - k0);
       const int cols = tri ? std::min(max_cols, k0 + kb) : max_cols;
-      hipLaunchKernelGGL(k_trsm_solve, dim3(cdiv(cols, TN), nitems), dim3(NT), 0, s, bbase,
-                         items_dev, k0, K1, tri, (const double2 *)work, wslots);
+      {
+        const double w = pf ? over_items(pf, nitems, [&](int n, int nc) {
+          const double b = std::max(0, std::min(NB, std::min(K1, n) - k0));
+          if (b <= 0) return 0.0;
+          // identity right-hand side: full solves for the columns left of the
+          // block, triangular ones inside it
+          return tri ? 4.0 * k0 * b * b + 4.0 / 3.0 * b * b * b : 4.0 * b * b * nc;
+        }) : 0.0;
+        ProfScope ps(prof_of(dp), DPG_K_TRSM_SOLVE, w, s);
+        hipLaunchKernelGGL(k_trsm_solve, dim3(cdiv(cols, TN), nitems), dim3(NT), 0, s, bbase,
+                           items_dev, k0, K1, tri, (const double2 *)work, wslots);
+      }
       // rows of this block row below the solved ones
       const int r_lo = k0 + kb, r_hi = K1;
       if (r_lo < r_hi) {
+        const double w = pf ? over_items(pf, nitems, [&](int n, int nc) {
+          return upd(n, nc, k0, k0 + kb, r_lo, r_hi);
+        }) : 0.0;
+        ProfScope ps(prof_of(dp), DPG_K_TRSM_UPDATE, w, s);
         const int tc = (int)cdiv(cols, TN);
         hipLaunchKernelGGL(k_trsm_update, dim3(cdiv(r_hi - r_lo, TM) * tc, nitems), dim3(NT), 0,
                            s, lbase, bbase, items_dev, k0, k0 + kb, r_lo, r_hi, tri, tc);
       }
     }
     if (K1 < max_n) {
+      const double w = pf ? over_items(pf, nitems, [&](int n, int nc) {
+        return upd(n, nc, K0, K1, K1, max_n);
+      }) : 0.0;
+      ProfScope ps(prof_of(dp), DPG_K_TRSM_UPDATE, w, s);
       const int cols = tri ? std::min(max_cols, K1) : max_cols;
       const int tc = (int)cdiv(cols, TN);
       hipLaunchKernelGGL(k_trsm_update, dim3(cdiv(max_n - K1, TM) * tc, nitems), dim3(NT), 0, s,

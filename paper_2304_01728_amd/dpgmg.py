@@ -67,13 +67,17 @@ class dpg_kstat(C.Structure):
 
 KERNEL_CLASSES = ["gram", "bmat", "load", "potrf", "trsm", "gemm", "macro_asm", "patch_gather",
                   "apply64", "apply32", "reduce", "condense", "expand", "transfer", "cg", "other",
-                  "applyb64", "applyb32"]
+                  "applyb64", "applyb32", "potrf_diag", "potrf_panel", "potrf_update",
+                  "trsm_inv", "trsm_solve", "trsm_update"]
 # kernel symbols behind each class (for matching a rocprofv3 trace)
 KERNEL_SYMBOLS = {"gram": "k_gram", "bmat": "k_bmat", "load": "k_load", "potrf": "k_potrf",
                   "trsm": "k_trsm", "gemm": "k_gemm", "macro_asm": "k_macro_assemble",
                   "patch_gather": "k_patch_gather", "apply64": "k_units<double>",
                   "apply32": "k_strips<float>", "reduce": "k_reduce",
-                  "applyb64": "k_rows_mfma64", "applyb32": "k_rows_mfma"}
+                  "applyb64": "k_rows_mfma64", "applyb32": "k_rows_mfma",
+                  "potrf_diag": "k_potrf_diag", "potrf_panel": "k_potrf_panel",
+                  "potrf_update": "k_potrf_update", "trsm_inv": "k_trsm_inv",
+                  "trsm_solve": "k_trsm_solve", "trsm_update": "k_trsm_update"}
 
 
 class DPGError(RuntimeError):
