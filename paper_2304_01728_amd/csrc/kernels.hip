@@ -247,6 +247,11 @@ __global__ __launch_bounds__(256) void k_csr(int64_t nrows, const int64_t *__res
   y[i] = add ? cadd(y[i], acc) : acc;
 }
 
+// One workgroup per (block, 64 boundary slots): wave w sums the interior
+// unknowns i = w, w + 4, ... for its 64 slots (coalesced reads of one column
+// of W^H per step), and the four partial sums are added in a fixed order.
+// Seven or more workgroups per block keep the GPU busy on the coarse levels,
+// which have few blocks.
 template <typename T>
 __global__ __launch_bounds__(256) void k_condense_local(const cplx_t<T> *__restrict__ WH, int nI,
                                                         int nBf, const int32_t *__restrict__ blkI,
@@ -254,17 +259,28 @@ __global__ __launch_bounds__(256) void k_condense_local(const cplx_t<T> *__restr
                                                         cplx_t<T> *__restrict__ c) {
   using C = cplx_t<T>;
   __shared__ C rI[kMaxI];
-  const int b = blockIdx.x;
+  __shared__ C part[4][64];
+  const int b = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sl = blockIdx.y * 64 + lane;
   for (int i = threadIdx.x; i < nI; i += 256) rI[i] = rc[blkI[(int64_t)b * nI + i]];
   __syncthreads();
   const C *W = WH + (int64_t)b * nBf * nI;
-  for (int sl = threadIdx.x; sl < nBf; sl += 256) {
-    C acc;
-    acc.x = 0;
-    acc.y = 0;
-    for (int i = 0; i < nI; ++i) acc = cfma(W[sl + (int64_t)i * nBf], rI[i], acc);
-    c[(int64_t)b * nBf + sl] = acc;
+  C a0, a1;
+  a0.x = a0.y = 0;
+  a1.x = a1.y = 0;
+  if (sl < nBf) {
+    int i = wave;
+    for (; i + 4 < nI; i += 8) {
+      a0 = cfma(W[sl + (int64_t)i * nBf], rI[i], a0);
+      a1 = cfma(W[sl + (int64_t)(i + 4) * nBf], rI[i + 4], a1);
+    }
+    if (i < nI) a0 = cfma(W[sl + (int64_t)i * nBf], rI[i], a0);
   }
+  part[wave][lane] = cadd(a0, a1);
+  __syncthreads();
+  if (wave == 0 && sl < nBf)
+    c[(int64_t)b * nBf + sl] = cadd(cadd(part[0][lane], part[1][lane]),
+                                    cadd(part[2][lane], part[3][lane]));
 }
 
 template <typename T>
@@ -633,7 +649,8 @@ template <typename T>
 void launch_condense_local(const cplx_t<T> *WH, int nI, int nBf, const int32_t *blkI, int nblk,
                            const cplx_t<T> *rc, cplx_t<T> *c, hipStream_t s) {
   if (nI > kMaxI || nBf > kMaxB) throw DpgError(-1, "macro block too large");
-  hipLaunchKernelGGL((k_condense_local<T>), dim3(nblk), dim3(256), 0, s, WH, nI, nBf, blkI, rc, c);
+  hipLaunchKernelGGL((k_condense_local<T>), dim3(nblk, cdiv(nBf, 64)), dim3(256), 0, s, WH, nI,
+                     nBf, blkI, rc, c);
   LAUNCH_OK();
 }
 
