@@ -75,8 +75,10 @@ enum { DPG_DEVICE_PTRS = 1,                 /* dpg_options.flags              */
                                                 patch blocks from the macro
                                                 blocks (Sec. 5 and Sec. 6: a
                                                 GPU code that recomputes the
-                                                patches); FP64, one column at a
-                                                time (no batches)              */
+                                                patches, amortised over several
+                                                loads); FP64; a block solve or
+                                                batch refactors each patch once
+                                                per step for all its columns   */
 
 /* Uniform mesh of the cube [origin, origin + side]^3 into n^3 equal boxes;
  * element e = i + n (j + n k). */

@@ -673,6 +673,18 @@ void plan_patches(dpg_ctx *c, int l) {
         }
         B.gy.upload(gy, bd, s);
         B.gz.upload(gz, bd, s);
+        // nr columns, local vectors column by column (leading dimension nloc)
+        const int64_t nloc = f.Sset.nloc;
+        std::vector<GemmItem> gyc((size_t)kMaxCols * cnt), gzc((size_t)kMaxCols * cnt);
+        for (int q = 1; q <= kMaxCols; ++q)
+          for (int i = 0; i < cnt; ++i) {
+            const int n = nn[i];
+            const int64_t lo = f.Sset.loc_off_h[v0 + i];
+            gyc[(size_t)(q - 1) * cnt + i] = {off[i], lo, lo, n, q, n, n, (int)nloc, (int)nloc};
+            gzc[(size_t)(q - 1) * cnt + i] = {off[i], lo, lo, n, q, n, n, (int)nloc, (int)nloc};
+          }
+        B.gyc.upload(gyc, bd, s);
+        B.gzc.upload(gzc, bd, s);
       }
       B.t0 = f.Sset.tile_off_h[v0];
       B.t1 = (v0 + cnt < np) ? f.Sset.tile_off_h[v0 + cnt] : f.Sset.ntiles;
@@ -788,6 +800,50 @@ void smooth_recompute(dpg_ctx *c, int l, const double2 *x, double2 *y, const dou
                  1, s);
   }
   herm_scatter(H, H.yl64.p, y, r, mode, theta, s);
+}
+
+// The same for nr interleaved columns (x, y, r: block vectors of the level):
+// every patch block is gathered and factored once per smoothing step for all
+// nr columns, and its inverse factor multiplies an n x nr panel (the local
+// vectors stored column by column), so the refactorisation is amortised over
+// the right-hand sides of a block solve.
+void smooth_recompute_cols(dpg_ctx *c, int l, const double2 *x, double2 *y, const double2 *r,
+                           int mode, double theta, int nr) {
+  LevelData &f = c->lv[l];
+  PatchPlan &P = f.pp;
+  HermSet &H = f.Sset;
+  const hipStream_t s = c->stream;
+  if (nr < 1 || nr > kMaxCols || nr > f.Sb.cap) throw DpgError(DPG_EINVAL, "bad column count");
+  double2 *xl = f.Sb.xl64.p, *yl = f.Sb.yl64.p;
+  herm_gather_cols(H, x, xl, nr, s);
+  for (PatchBatch &B : P.batches) {
+    double2 *S = c->pS[B.half].p, *X = c->pX[B.half].p, *wk = c->pwk[B.half].p;
+    const DenseProf dp{&c->prof, B.hn.data(), 0, B.hn.data(), 0};
+    {
+      PROF(DPG_K_PATCH_GATHER, 0);
+      launch_patch_gather_tiles(f.Mset.t64.p, f.Mset.ent_off.p, f.mpidx.p, f.nBf, f.mc.Nc,
+                                f.patch_ptr.p, f.patch_slot.p, B.v0, B.cnt, B.nmax, B.off.p, S,
+                                s);
+    }
+    {
+      PROF(DPG_K_POTRF, B.fp);
+      potrf_batched(S, B.pi.p, B.cnt, P.info.p + B.v0, B.nmax, wk, s, &dp);
+    }
+    {
+      PROF(DPG_K_OTHER, 0);
+      launch_identity(B.off.p, B.nn.p, B.cnt, B.nmax, X, s);
+    }
+    {
+      PROF(DPG_K_TRSM, B.ft);
+      trsm_batched(S, X, B.ti.p, B.cnt, B.nmax, B.nmax, true, wk, true, s, &dp);
+    }
+    PROF(DPG_K_GEMM, 0);
+    const GemmItem *gy = B.gyc.p + (int64_t)(nr - 1) * B.cnt;
+    const GemmItem *gz = B.gzc.p + (int64_t)(nr - 1) * B.cnt;
+    gemm_batched(OP_N, OP_N, mk(1, 0), X, xl, mk(0, 0), c->ptmp.p, gy, B.cnt, B.nmax, nr, s);
+    gemm_batched(OP_C, OP_N, mk(1, 0), X, c->ptmp.p, mk(0, 0), yl, gz, B.cnt, B.nmax, nr, s);
+  }
+  herm_scatter_cols(H, yl, y, r, mode, theta, nr, s);
 }
 
 void plan_coarsest(dpg_ctx *c) {
@@ -1191,7 +1247,10 @@ void ensure_block(dpg_ctx *c, int nr) {
     }
     if (!mixed || l == c->L) f.bc64.alloc(ncb * nr, bd);
     f.Mb.ensure(f.Mset, nr, f.Mset.t64.p != nullptr, f.Mset.t32.p != nullptr, bd);
-    f.Sb.ensure(f.Sset, nr, f.Sset.t64.p != nullptr, f.Sset.t32.p != nullptr, bd);
+    const bool rec = c->opt.flags & DPG_RECOMPUTE_PATCHES;   // local vectors of the
+                                                             // recomputed smoother
+    f.Sb.ensure(f.Sset, nr, f.Sset.t64.p != nullptr || rec, f.Sset.t32.p != nullptr, bd);
+    if (rec) grow(c->ptmp, f.Sset.nloc * nr, bd);
     f.bcap = nr;
   }
   c->T0b.ensure(c->T0set, nr, c->T0set.t64.p != nullptr, c->T0set.t32.p != nullptr, bd);
@@ -1209,6 +1268,21 @@ void ensure_block(dpg_ctx *c, int nr) {
   c->bcap = nr;
 }
 
+// The smoother's patch sum on level l for nr columns: stored inverses, or
+// inverses recomputed in the application (FP64).
+template <typename T>
+void smooth_apply_blk(dpg_ctx *c, int l, const cplx_t<T> *x, cplx_t<T> *y, const cplx_t<T> *r,
+                      int mode, T theta, int nr) {
+  LevelData &f = c->lv[l];
+  if constexpr (sizeof(T) == 8) {
+    if (c->opt.flags & DPG_RECOMPUTE_PATCHES) {
+      smooth_recompute_cols(c, l, x, y, r, mode, theta, nr);
+      return;
+    }
+  }
+  herm_apply_blk<T>(f.Sset, f.Sb, x, y, r, mode, theta, nr, c->stream);
+}
+
 template <typename T> void vcycle_blk(dpg_ctx *c, int l, int nr) {
   using B = LB<T>;
   using BB = LBB<T>;
@@ -1219,10 +1293,10 @@ template <typename T> void vcycle_blk(dpg_ctx *c, int l, int nr) {
   if (c->opt.nu_pre == 0) launch_zero(f.nM * nr, x, s);
   for (int k = 0; k < c->opt.nu_pre; ++k) {
     if (k == 0) {
-      herm_apply_blk<T>(f.Sset, f.Sb, r, x, nullptr, RED_SET_SCALED, th, nr, s);
+      smooth_apply_blk<T>(c, l, r, x, nullptr, RED_SET_SCALED, th, nr);
     } else {
       herm_apply_blk<T>(f.Mset, f.Mb, x, res, r, RED_RESID, (T)0, nr, s);
-      herm_apply_blk<T>(f.Sset, f.Sb, res, x, nullptr, RED_AXPY, th, nr, s);
+      smooth_apply_blk<T>(c, l, res, x, nullptr, RED_AXPY, th, nr);
     }
   }
   herm_apply_blk<T>(f.Mset, f.Mb, x, res, r, RED_RESID, (T)0, nr, s);
@@ -1248,7 +1322,7 @@ template <typename T> void vcycle_blk(dpg_ctx *c, int l, int nr) {
   }
   for (int k = 0; k < c->opt.nu_post; ++k) {
     herm_apply_blk<T>(f.Mset, f.Mb, x, res, r, RED_RESID, (T)0, nr, s);
-    herm_apply_blk<T>(f.Sset, f.Sb, res, x, nullptr, RED_AXPY, th, nr, s);
+    smooth_apply_blk<T>(c, l, res, x, nullptr, RED_AXPY, th, nr);
   }
 }
 
@@ -1284,13 +1358,12 @@ void batch_close(dpg_ctx *c) {
   S.gw = 0;
   S.open = false;
   S.max = S.w = 0;
+  S.done.clear();   // finished slots not taken (dpg_solve's block path takes none)
 }
 
 void batch_open(dpg_ctx *c, int max_slots) {
   if (max_slots < 1 || max_slots > kMaxCols)
     throw DpgError(DPG_EINVAL, "a batch holds 1 to 32 columns");
-  if (c->opt.flags & DPG_RECOMPUTE_PATCHES)
-    throw DpgError(DPG_EINVAL, "recomputed patch inverses solve one column at a time");
   batch_close(c);
   ensure_block(c, max_slots);
   BatchSession &S = c->bs;
@@ -1949,7 +2022,7 @@ int dpg_solve(dpg_ctx *c, const double *rhs, int nrhs, double tol, double *x_out
     const int64_t nT = top.num.n;
     const bool dev = c->opt.flags & DPG_DEVICE_PTRS;
     int status = DPG_OK;
-    if (nrhs > 1 && !(c->opt.flags & (DPG_COLUMNWISE | DPG_RECOMPUTE_PATCHES))) {
+    if (nrhs > 1 && !(c->opt.flags & DPG_COLUMNWISE)) {
       if (c->bs.open) throw DpgError(DPG_ESTATE, "a batch is open (dpg_batch_close first)");
       for (int k0 = 0; k0 < nrhs; k0 += kMaxCols) {
         const int nr = std::min(kMaxCols, nrhs - k0);

@@ -329,6 +329,39 @@ __global__ __launch_bounds__(256) void k_scatter_blk(int64_t nvec, int nr,
   else y[e] = cscale(acc, theta);
 }
 
+// Local vectors column by column ([nr][nloc]).
+__global__ __launch_bounds__(256) void k_gather_cols(int64_t nloc, int nr,
+                                                     const int32_t *__restrict__ gidx,
+                                                     const double2 *__restrict__ x,
+                                                     double2 *__restrict__ xl) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nloc * nr) return;
+  const int64_t i = e % nloc;
+  const int k = (int)(e / nloc);
+  const int32_t g = gidx[i];
+  xl[e] = g >= 0 ? x[(int64_t)g * nr + k] : czero<double2>();
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_scatter_cols(int64_t nvec, int64_t nloc, int nr,
+                                                      const int32_t *__restrict__ red_ptr,
+                                                      const int32_t *__restrict__ red_ent,
+                                                      const double2 *__restrict__ yl,
+                                                      const double2 *__restrict__ r,
+                                                      double2 *__restrict__ y, double theta) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nvec * nr) return;
+  const int64_t d = e / nr;
+  const int k = (int)(e % nr);
+  double2 acc = czero<double2>();
+  for (int32_t j = red_ptr[d]; j < red_ptr[d + 1]; ++j)
+    acc = cadd(acc, yl[(int64_t)k * nloc + red_ent[j]]);
+  if (MODE == RED_SET) y[e] = acc;
+  else if (MODE == RED_RESID) y[e] = csub(r[e], acc);
+  else if (MODE == RED_AXPY) y[e] = cadd(y[e], cscale(acc, theta));
+  else y[e] = cscale(acc, theta);
+}
+
 // ---- transfers and condensation ----------------------------------------------------------
 
 template <typename T>
@@ -680,6 +713,35 @@ void herm_apply_blk(HermSet &H, HermBlockBufs &W, const cplx_t<T> *X, cplx_t<T> 
       break;
     default:
       hipLaunchKernelGGL((k_scatter_blk<T, RED_SET_SCALED>), g, dim3(256), 0, s, H.nvec, nr, H.red_ptr.p, H.red_ent.p, yl, R, Y, theta);
+  }
+  LAUNCH_OK();
+}
+
+void herm_gather_cols(const HermSet &H, const double2 *X, double2 *xl, int nr, hipStream_t s) {
+  if (nr < 1 || nr > kMaxCols) throw DpgError(-1, "column gather: bad column count");
+  ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
+  hipLaunchKernelGGL(k_gather_cols, dim3(cdiv(H.nloc * nr, 256)), dim3(256), 0, s, H.nloc, nr,
+                     H.gidx.p, X, xl);
+  LAUNCH_OK();
+}
+
+void herm_scatter_cols(const HermSet &H, const double2 *yl, double2 *Y, const double2 *R,
+                       int mode, double theta, int nr, hipStream_t s) {
+  if (nr < 1 || nr > kMaxCols) throw DpgError(-1, "column scatter: bad column count");
+  ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
+  const dim3 g(cdiv(H.nvec * nr, 256));
+  switch (mode) {
+    case RED_SET:
+      hipLaunchKernelGGL((k_scatter_cols<RED_SET>), g, dim3(256), 0, s, H.nvec, H.nloc, nr, H.red_ptr.p, H.red_ent.p, yl, R, Y, theta);
+      break;
+    case RED_RESID:
+      hipLaunchKernelGGL((k_scatter_cols<RED_RESID>), g, dim3(256), 0, s, H.nvec, H.nloc, nr, H.red_ptr.p, H.red_ent.p, yl, R, Y, theta);
+      break;
+    case RED_AXPY:
+      hipLaunchKernelGGL((k_scatter_cols<RED_AXPY>), g, dim3(256), 0, s, H.nvec, H.nloc, nr, H.red_ptr.p, H.red_ent.p, yl, R, Y, theta);
+      break;
+    default:
+      hipLaunchKernelGGL((k_scatter_cols<RED_SET_SCALED>), g, dim3(256), 0, s, H.nvec, H.nloc, nr, H.red_ptr.p, H.red_ent.p, yl, R, Y, theta);
   }
   LAUNCH_OK();
 }

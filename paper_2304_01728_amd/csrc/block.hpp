@@ -28,6 +28,17 @@ template <typename T>
 void herm_apply_blk(HermSet &H, HermBlockBufs &W, const cplx_t<T> *X, cplx_t<T> *Y,
                     const cplx_t<T> *R, int mode, T theta, int nr, hipStream_t s);
 
+// The local vectors of a block set for nr columns stored column by column
+// ([nr][nloc]: column k at k * nloc), so that the slice of one block is an
+// n x nr column-major panel with leading dimension nloc (the smoother with
+// recomputed patch inverses multiplies it with dense GEMMs).  FP64.
+// xl <- R X (gather from the interleaved block vector X);
+void herm_gather_cols(const HermSet &H, const double2 *X, double2 *xl, int nr, hipStream_t s);
+// Y <- epilogue(sum_b R_b^T yl_b) into the interleaved block vector Y (modes
+// as herm_apply).
+void herm_scatter_cols(const HermSet &H, const double2 *yl, double2 *Y, const double2 *R,
+                       int mode, double theta, int nr, hipStream_t s);
+
 // y[i, k] (+)= sum_j val[j] x[col[j], k] over CSR rows.
 template <typename T>
 void launch_csr_blk(int64_t nrows, const int64_t *ptr, const int32_t *col, const T *val,

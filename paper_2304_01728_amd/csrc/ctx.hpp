@@ -64,6 +64,8 @@ struct PatchBatch {
   DevBuf<TrsmItem> ti;
   DevBuf<GemmItem> gi;
   DevBuf<GemmItem> gy, gz;           // recomputed inverses: t = X x_v, y_v = X^H t
+  DevBuf<GemmItem> gyc, gzc;         // the same for nr = 1 .. kMaxCols columns stored
+                                     // column by column: items (nr - 1) cnt + i
 };
 struct PatchPlan {
   bool ready = false;

@@ -776,6 +776,14 @@ int64_t dense_work_size(int nitems, int nmax) {
   return (int64_t)std::max(nitems, 0) * cdiv(std::max(nmax, 1), NB) * NB * NB;
 }
 
+// info <- 0 for every item: a kernel rather than a memset node, since the
+// Cholesky may run inside a captured HIP graph (the smoother with recomputed
+// patch inverses).
+__global__ __launch_bounds__(256) void k_zero_info(int *info, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) info[i] = 0;
+}
+
 // Algorithmic flops of the launches of one routine call (DenseProf): sums
 // over the items of the blocked algorithm's step counts.
 namespace {
@@ -794,7 +802,7 @@ void potrf_batched(double2 *base, const PotrfItem *items_dev, int nitems, int *i
   const int kmax = nmax;
   const int wslots = (int)cdiv(nmax, NB);
   const DenseProf *pf = prof_on(dp);
-  HIP_OK(hipMemsetAsync(info_dev, 0, nitems * sizeof(int), s));
+  hipLaunchKernelGGL(k_zero_info, dim3(cdiv(nitems, 256)), dim3(256), 0, s, info_dev, nitems);
   for (int K0 = 0; K0 < kmax; K0 += NBO) {
     const int K1 = std::min(K0 + NBO, kmax);
     for (int k0 = K0; k0 < K1; k0 += NB) {

@@ -139,3 +139,26 @@ def test_point_source_load_update_visits_nearby_elements_only():
     fo = dpg.recover_fields(rec, pr.edofs, x.T)
     assert rel(f, fo.transpose(2, 0, 1)) <= 1e-10
     ctx.close()
+
+
+def test_batch_after_a_block_solve_starts_with_no_finished_slots():
+    """dpg_solve's block path runs its columns through a batch and takes none
+    of them; a batch opened afterwards must not report those columns as
+    finished (regression)."""
+    D = _D()
+    loads, _ = _sources(13, 3, 0.08)
+    ctx = _ctx(D, 4, 2, 2 * np.pi, loads)
+    x, it, rr, code = D.dpg_solve(ctx, nrhs=3, tol=1e-10)
+    assert code == D.DPG_OK
+    D.dpg_batch_open(ctx, 4)
+    k = D.dpg_batch_add(ctx, None, load_col=1, tol=1e-10)
+    assert D.dpg_batch_step(ctx, 2) == []
+    done = []
+    while not done:
+        done = D.dpg_batch_step(ctx, 100)
+    assert done == [k]
+    xb, itb, rrb, codeb = D.dpg_batch_take(ctx, k)
+    assert codeb == D.DPG_OK and abs(int(itb) - int(it[1])) <= 1
+    assert _relerr(xb, x[1]) <= 1e-10
+    D.dpg_batch_close(ctx)
+    ctx.close()

@@ -66,14 +66,63 @@ def test_recomputed_patches_match_oracle_and_stored(N, p, omega, seed, nu):
         ctx.close()
 
 
-def test_recompute_rejects_mixed_precision_and_batches():
+def test_recompute_rejects_mixed_precision():
     D = _D()
     opt = D.dpg_default_options(precision=D.DPG_MIXED, flags=D.DPG_RECOMPUTE_PATCHES)
     with pytest.raises(D.DPGError) as e:
         D.dpg_setup(4, 2, 2 * np.pi, [dict(dir=(1, 0, 0), amp=1.0)], options=opt)
     assert e.value.code == D.DPG_EINVAL
-    ctx = _ctx(D, 4, 2, 2 * np.pi, (1.0, 0.0, 0.0), (1, 1), D.DPG_RECOMPUTE_PATCHES)
-    with pytest.raises(D.DPGError) as e:
-        D.dpg_batch_open(ctx, 2)
-    assert e.value.code == D.DPG_EINVAL
-    ctx.close()
+
+
+def test_recomputed_patches_block_solve_and_batch():
+    """Several right-hand sides with recomputed inverses: one refactorisation
+    per smoothing step serves every column of the block (the amortisation over
+    loads).  Each column matches the oracle within 1e-10 (tol 1e-12) with
+    iterations +-1, and the same block solved with stored inverses; a batch
+    whose second column joins late gives that column's solve alone."""
+    D = _D()
+    N, p, omega, nu = 4, 3, 4 * np.pi, (2, 2)
+    cen = workloads.source_centres(11, 3)
+    loads = [dict(dir=(0, 0, 1), amp=0.0, sources=[[*c0, 0.1, 1.0, 0.3]]) for c0 in cen]
+    loads.append(dict(dir=workloads.plane_wave_direction(4), amp=1.0))
+    ctxs = {}
+    for name, flags in (("rec", D.DPG_RECOMPUTE_PATCHES), ("sto", 0)):
+        opt = D.dpg_default_options(nu_pre=nu[0], nu_post=nu[1], flags=flags)
+        print(f"[recompute-block] N={N} p={p} {name} nrhs={len(loads)}", flush=True)
+        ctx = D.dpg_setup(N, p, omega, loads, options=opt)
+        D.dpg_assemble(ctx)
+        D.dpg_build_hierarchy(ctx)
+        ctxs[name] = ctx
+    xr, itr, rrr, cr = D.dpg_solve(ctxs["rec"], nrhs=len(loads), tol=1e-12)
+    xs, its, _, cs = D.dpg_solve(ctxs["sto"], nrhs=len(loads), tol=1e-12)
+    assert cr == D.DPG_OK and cs == D.DPG_OK
+    oracle_loads = [dict(f=dpg.gaussian_sources([c0], 0.1, [1.0 + 0.3j])) for c0 in cen]
+    oracle_loads.append(dict(u0=dpg.plane_wave_u0(omega, workloads.plane_wave_direction(4))))
+    pr = dpg.Problem(N, p, omega, oracle_loads)
+    S, s, _ = pr.condensed()
+    rhs = dpg.assemble_vector(pr.edofs, s, pr.num.n)
+    H = multigrid.Hierarchy(N, p, S, nu_pre=nu[0], nu_post=nu[1])
+    for k in range(len(loads)):
+        xo, ito, _ = H.solve(rhs[:, k], 1e-12)
+        assert np.linalg.norm(xr[k] - xo) <= 1e-10 * np.linalg.norm(xo), k
+        assert abs(int(itr[k]) - ito) <= 1, (k, itr[k], ito)
+        assert np.linalg.norm(xr[k] - xs[k]) <= 1e-10 * np.linalg.norm(xs[k]), k
+        assert abs(int(itr[k]) - int(its[k])) <= 1
+    # continuous batching on the recomputing context: column 1 joins after
+    # two iterations of column 0 and equals its solve alone
+    ctx = ctxs["rec"]
+    alone, ita, _, _ = D.dpg_solve(ctx, rhs=rhs[:, 1][None, :], tol=1e-10)
+    D.dpg_batch_open(ctx, 4)
+    k0 = D.dpg_batch_add(ctx, rhs[:, 0], tol=1e-10)
+    D.dpg_batch_step(ctx, 2)
+    k1 = D.dpg_batch_add(ctx, rhs[:, 1], tol=1e-10)
+    got = {}
+    while len(got) < 2:
+        for k in D.dpg_batch_step(ctx, 100):
+            got[k] = D.dpg_batch_take(ctx, k)
+    D.dpg_batch_close(ctx)
+    x1, it1, rel1, code1 = got[k1]
+    assert code1 == D.DPG_OK and abs(int(it1) - int(ita[0])) <= 1
+    assert np.linalg.norm(x1 - alone[0]) <= 1e-8 * np.linalg.norm(alone[0])
+    for c in ctxs.values():
+        c.close()
