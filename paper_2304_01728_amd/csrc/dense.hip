@@ -19,6 +19,7 @@
 // the 128-wide block a rank-64 product.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "dense.hpp"
 
@@ -168,16 +169,25 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int 
       acc_p2[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
       acc_p3[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
     }
+  // 16x16 blocks whose results are never stored take no matrix-core work:
+  // those outside m x n (the ragged last tile row or column of sizes such as
+  // 451 = 7 x 64 + 3) and, with lower_only, those strictly above the
+  // diagonal.  The mask is uniform over the wave; a wave with every block
+  // active runs the unguarded loop.
+  unsigned act = 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int br = r0 + wr + 16 * i, bc = c0 + wc + 16 * j;
+      const bool on = br < m && bc < n && !(lower_only && bc > br + 15);
+      act |= (unsigned)on << (2 * i + j);
+    }
+  act = __builtin_amdgcn_readfirstlane(act);
   // The next k-slice is fetched into registers while the current one is
   // multiplied from LDS, so global latency hides behind the matrix cores.
-  double2 ra[QS], rb[QS];
-  unsigned ok = 0;
-  if (k_begin < k) ok = load_slice<OPA, OPB>(m, n, k, k_begin, r0, c0, A, lda, B, ldb, ra, rb);
-#pragma unroll 1
-  for (int k0 = k_begin; k0 < k; k0 += TK) {
-    store_slice<OPA, OPB>(ra, rb, ok, sm);
-    __syncthreads();
-    if (k0 + TK < k) ok = load_slice<OPA, OPB>(m, n, k, k0 + TK, r0, c0, A, lda, B, ldb, ra, rb);
+  auto mma_slice = [&](auto guarded) {
+    constexpr bool G = decltype(guarded)::value;
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 4) {
       double2 a[2], b[2];
@@ -194,18 +204,31 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, int k_begin, int 
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc_p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc_p1[i][j], 0, 0, 0);
+          if (!G || (act >> (2 * i + j) & 1))
+            acc_p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc_p1[i][j], 0, 0, 0);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc_p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].y, acc_p2[i][j], 0, 0, 0);
+          if (!G || (act >> (2 * i + j) & 1))
+            acc_p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].y, acc_p2[i][j], 0, 0, 0);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc_p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[i], sb[j], acc_p3[i][j], 0, 0, 0);
+          if (!G || (act >> (2 * i + j) & 1))
+            acc_p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[i], sb[j], acc_p3[i][j], 0, 0, 0);
     }
+  };
+  double2 ra[QS], rb[QS];
+  unsigned ok = 0;
+  if (k_begin < k) ok = load_slice<OPA, OPB>(m, n, k, k_begin, r0, c0, A, lda, B, ldb, ra, rb);
+#pragma unroll 1
+  for (int k0 = k_begin; k0 < k; k0 += TK) {
+    store_slice<OPA, OPB>(ra, rb, ok, sm);
+    __syncthreads();
+    if (k0 + TK < k) ok = load_slice<OPA, OPB>(m, n, k, k0 + TK, r0, c0, A, lda, B, ldb, ra, rb);
+    if (act) mma_slice(std::true_type{});
     __syncthreads();
   }
   // The C entries of a row block (eight per lane) are loaded together, from
