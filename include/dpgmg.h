@@ -180,24 +180,30 @@ int dpg_build_hierarchy(dpg_ctx *ctx);
 
 /* Replaces the assembled loads by new right-hand sides for the same operator
  * (the loads l_K of Sec. 2 condensed onto the traces as in Sec. 1.2:
- * s = b_t - K_tf K_ff^-1 b_f with b = W^H (L^-1 l)).  Cost: the element
- * chain of dpg_assemble (Gram and B, both Cholesky factors, the forward
- * solves and products, with the new load columns beside B) is run again,
- * since only the condensed matrices are kept, not the factors of G.  Over
- * every element when some load has plane-wave or u0_qp data; when all loads
- * are Gaussian point sources only over the elements whose box comes within
- * 8 sigma of a source (the others get zero loads).  A change of nrhs
- * re-plans the element stage (small uploads and one stream sync).  Output:
- * the condensed trace loads, n_trace x nrhs, if s_out is not NULL. */
+ * s = b_t - K_tf K_ff^-1 b_f with b = W^H (L^-1 l)).  Elements with equal
+ * wave speed and the same faces on Gamma have equal G and B, so s is one
+ * linear map of the element's load vector l per such class (and so are the
+ * field-recovery data): the first call (or dpg_release_setup) forms these
+ * maps by the element chain with identity loads on one element of each class
+ * (up to 512 classes), and every update is then the load integrals of the
+ * elements and one matrix product per element.  Over every element when some
+ * load has plane-wave or u0_qp data; when all loads are Gaussian point
+ * sources only over the elements whose box comes within 8 sigma of a source
+ * (the others get zero loads).  With more classes (a wave speed that varies
+ * from element to element) every update runs the element chain of
+ * dpg_assemble again on those elements.  Output: the condensed trace loads,
+ * n_trace x nrhs, if s_out is not NULL. */
 int dpg_load_rhs(dpg_ctx *ctx, const dpg_load *loads, int nrhs, double *s_out);
 
 /* Frees what only dpg_assemble and dpg_build_hierarchy use: the element and
  * coarse element matrices, the full condensed macro blocks, the dense
- * coarsest operator and the setup work areas.  Solves, dpg_load_rhs and
- * dpg_get_fields keep working; dpg_assemble, dpg_build_hierarchy and the
- * exports of the freed matrices return DPG_ESTATE afterwards.  For callers
- * that keep many hierarchies resident (a solve server).  Requires a built
- * hierarchy (DPG_ESTATE otherwise). */
+ * coarsest operator and the setup work areas (the element-stage ones too
+ * once the load maps of dpg_load_rhs exist; they are formed here if not
+ * yet).  Solves, dpg_load_rhs, dpg_get_fields and dpg_error_indicator keep
+ * working; dpg_assemble, dpg_build_hierarchy and the exports of the freed
+ * matrices return DPG_ESTATE afterwards.  For callers that keep many
+ * hierarchies resident (a solve server).  Requires a built hierarchy
+ * (DPG_ESTATE otherwise). */
 int dpg_release_setup(dpg_ctx *ctx);
 
 /* Solves T x = rhs for nrhs right-hand sides (rhs: n_trace x nrhs trace

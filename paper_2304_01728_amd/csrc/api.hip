@@ -3,7 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-
+#include <map>
 #include <mutex>
 
 #include "ctx.hpp"
@@ -394,6 +394,163 @@ void element_stage(dpg_ctx *c, int l, bool write_matrices, const IndicatorArgs *
   check_infos(P.info.p + nel, total, c->stream, elist ? "listed element (field block)" : "element field block");
 }
 
+// ---- load updates by element-class maps ---------------------------------------------
+
+// More classes than this (a wave speed varying from element to element) keep
+// the load updates on the element chain.
+constexpr int kMaxLoadClasses = 512;
+
+// Classes of the finest elements by (wave speed, faces on Gamma) and one
+// representative element of each; false when there are too many.
+bool classify_elements(const dpg_ctx *c, std::vector<int32_t> &cls, std::vector<int32_t> &rep) {
+  const int N = c->N;
+  std::map<std::pair<double, int>, int32_t> id;
+  cls.assign((size_t)N * N * N, 0);
+  rep.clear();
+  for (int k = 0; k < N; ++k)
+    for (int j = 0; j < N; ++j)
+      for (int i = 0; i < N; ++i) {
+        const int e = i + N * (j + N * k);
+        const int mask = (i == 0) | (i == N - 1) << 1 | (j == 0) << 2 | (j == N - 1) << 3 |
+                         (k == 0) << 4 | (k == N - 1) << 5;
+        const auto key = std::make_pair(c->c_h[e], mask);
+        auto it = id.find(key);
+        if (it == id.end()) {
+          if ((int)rep.size() >= kMaxLoadClasses) return false;
+          it = id.emplace(key, (int32_t)rep.size()).first;
+          rep.push_back(e);
+        }
+        cls[e] = it->second;
+      }
+  return true;
+}
+
+// The class maps: the element chain on one element per class with the n_test
+// identity columns as loads, W = L^-1 [B | I], K = W^H W, the field block of
+// K factored and condensed; T_c and F_c are then blocks of the condensed K.
+void build_load_maps(dpg_ctx *c) {
+  LoadMaps &M = c->lm;
+  std::vector<int32_t> rep;
+  if (!classify_elements(c, M.cls_h, rep)) {
+    M.state = -1;
+    M.cls_h.clear();
+    return;
+  }
+  const hipStream_t s = c->stream;
+  Budget *bd = &c->bud;
+  const int nt = c->n_test, nf = c->n_field, ntr = c->n_tr, m = c->m, mp = m + nt;
+  const int nc = (int)rep.size();
+  DevBuf<double2> G, BL, K, wk;
+  DevBuf<int> info;
+  DevBuf<int32_t> rl;
+  DevBuf<int64_t> idoff;
+  DevBuf<int32_t> idn;
+  DevBuf<PotrfItem> pG, pK;
+  DevBuf<TrsmItem> tG, tK;
+  DevBuf<GemmItem> gK, gS;
+  G.alloc((int64_t)nc * nt * nt, bd);
+  BL.alloc((int64_t)nc * nt * mp, bd);
+  K.alloc((int64_t)nc * mp * mp, bd);
+  wk.alloc(dense_work_size(nc, nt), bd);
+  info.alloc(2LL * nc, bd);
+  std::vector<PotrfItem> hpG(nc), hpK(nc);
+  std::vector<TrsmItem> htG(nc), htK(nc);
+  std::vector<GemmItem> hgK(nc), hgS(nc);
+  std::vector<int64_t> hoff(nc);
+  std::vector<int32_t> hn(nc, nt);
+  for (int i = 0; i < nc; ++i) {
+    const int64_t oG = (int64_t)i * nt * nt, oB = (int64_t)i * nt * mp, oK = (int64_t)i * mp * mp;
+    hpG[i] = {oG, nt, nt};
+    htG[i] = {oG, oB, nt, mp, nt, nt};
+    hgK[i] = {oB, oB, oK, mp, mp, nt, nt, nt, mp};
+    hpK[i] = {oK, nf, mp};
+    htK[i] = {oK, oK + (int64_t)nf * mp, nf, mp - nf, mp, mp};
+    hgS[i] = {oK + (int64_t)nf * mp, oK + (int64_t)nf * mp, oK + nf + (int64_t)nf * mp,
+              mp - nf, mp - nf, nf, mp, mp, mp};
+    hoff[i] = oB + (int64_t)m * nt;   // the identity load columns of item i
+  }
+  rl.upload(rep, bd, s);
+  pG.upload(hpG, bd, s);
+  pK.upload(hpK, bd, s);
+  tG.upload(htG, bd, s);
+  tK.upload(htK, bd, s);
+  gK.upload(hgK, bd, s);
+  gS.upload(hgS, bd, s);
+  idoff.upload(hoff, bd, s);
+  idn.upload(hn, bd, s);
+  LevelData &f = c->lv[c->L];
+  ElemGeom g{f.N, c->side / f.N, c->omega, 1.0, {c->org[0], c->org[1], c->org[2]}, rl.p};
+  launch_gram(c->tables.p, c->testd.p, nt, g, c->kappa.p, 0, nc, G.p, s);
+  launch_bmat(c->tables.p, c->testd.p, c->triald.p, nt, m, g, c->kappa.p, c->Zel.p, 0, nc, BL.p,
+              (int64_t)nt * mp, s);
+  launch_identity(idoff.p, idn.p, nc, nt, BL.p, s);
+  potrf_batched(G.p, pG.p, nc, info.p, nt, wk.p, s);
+  trsm_batched(G.p, BL.p, tG.p, nc, nt, mp, false, wk.p, true, s);
+  gemm_batched(OP_C, OP_N, mk(1, 0), BL.p, BL.p, mk(0, 0), K.p, gK.p, nc, mp, mp, s, GEMM_HERM);
+  potrf_batched(K.p, pK.p, nc, info.p + nc, nf, wk.p, s);
+  trsm_batched(K.p, K.p, tK.p, nc, nf, mp - nf, false, wk.p, true, s);
+  gemm_batched(OP_C, OP_N, mk(-1, 0), K.p, K.p, mk(1, 0), K.p, gS.p, nc, mp - nf, mp - nf, s,
+               GEMM_HERM);
+  M.T.alloc((int64_t)nc * ntr * nt, bd);
+  launch_copy_sub(K.p, (int64_t)mp * mp, mp, nf, m, ntr, nt, M.T.p, (int64_t)ntr * nt, ntr, nc, s);
+  if (c->keep_recovery) {
+    M.F.alloc((int64_t)nc * nf * nt, bd);
+    launch_copy_sub(K.p, (int64_t)mp * mp, mp, 0, m, nf, nt, M.F.p, (int64_t)nf * nt, nf, nc, s);
+  }
+  check_infos(info.p, 2LL * nc, s, "element class (load maps)");
+  M.nclass = nc;
+  M.state = 1;
+}
+
+// Condensed loads (and field-recovery data) of the listed finest elements
+// (every element when list is empty and all is set) by the class maps:
+// l_e from the load kernel, then s_e = T_c l_e and Yb_e = F_c l_e, in chunks
+// of about 1 GB of load vectors.  s_elem (and rec_Yb) must be zero outside
+// the list.
+void load_by_maps(dpg_ctx *c, const std::vector<int32_t> &list, const int32_t *list_dev,
+                  bool all) {
+  LoadMaps &M = c->lm;
+  LevelData &f = c->lv[c->L];
+  const hipStream_t s = c->stream;
+  Budget *bd = &c->bud;
+  const int nt = c->n_test, nf = c->n_field, ntr = c->n_tr, nr = c->nrhs, nel = f.nel;
+  const int total = all ? nel : (int)list.size();
+  if (total > 0) {
+    const int64_t per = (int64_t)nt * nr;
+    const int C = (int)std::max<int64_t>(1, std::min<int64_t>(total, 62500000LL / per));
+    grow(M.lbuf, (int64_t)C * per, bd);
+    const bool rec = c->keep_recovery && M.F.p;
+    std::vector<GemmItem> it((size_t)total * (rec ? 2 : 1));
+    for (int k = 0; k < total; ++k) {
+      const int e = all ? k : list[k];
+      const int64_t cl = M.cls_h[e], lo = (int64_t)(k % C) * per;
+      it[k] = {cl * ntr * nt, lo, (int64_t)e * ntr, ntr, nr, nt, ntr, nt, nel * ntr};
+      if (rec) it[(size_t)total + k] = {cl * nf * nt, lo, (int64_t)e * nf * nr, nf, nr, nt, nf, nt, nf};
+    }
+    M.items.upload(it, bd, s);
+    ElemGeom g{f.N, c->side / f.N, c->omega, 1.0, {c->org[0], c->org[1], c->org[2]},
+               all ? nullptr : list_dev};
+    for (int e0 = 0; e0 < total; e0 += C) {
+      const int cnt = std::min(C, total - e0);
+      {
+        ProfScope ps(&c->prof, DPG_K_LOAD, 0, s);
+        launch_load(c->tables.p, nt, 0, g, c->Zel.p, c->ld.p, c->src.p, c->u0q.p, nr, e0, cnt,
+                    M.lbuf.p, per, s);
+      }
+      ProfScope ps(&c->prof, DPG_K_GEMM, 8.0 * cnt * (double)(ntr + (rec ? nf : 0)) * nt * nr, s);
+      gemm_batched(OP_N, OP_N, mk(1, 0), M.T.p, M.lbuf.p, mk(0, 0), c->s_elem.p, M.items.p + e0,
+                   cnt, ntr, nr, s);
+      if (rec)
+        gemm_batched(OP_N, OP_N, mk(1, 0), M.F.p, M.lbuf.p, mk(0, 0), c->rec_Yb.p,
+                     M.items.p + total + e0, cnt, nf, nr, s);
+    }
+    HIP_OK(hipStreamSynchronize(s));   // the host item list and M.items may be reused next
+  }
+  for (int r = 0; r < nr; ++r)
+    launch_assemble_vec(f.num.n, c->asm_ptr.p, c->asm_ent.p, c->s_elem.p + (int64_t)r * nel * ntr,
+                        0, c->s_asm.p + (int64_t)r * f.num.n, s);
+}
+
 // ---- hierarchy -------------------------------------------------------------------------
 
 // The full (nBf x nBf) macro blocks of a level: its element matrices on an
@@ -664,15 +821,6 @@ void plan_patches(dpg_ctx *c, int l) {
       B.ti.upload(ti, bd, s);
       B.gi.upload(gi, bd, s);
       if (rec) {   // t_v = X_v x_v, y_v = X_v^H t_v on the local vectors of the patch set
-        std::vector<GemmItem> gy(cnt), gz(cnt);
-        for (int i = 0; i < cnt; ++i) {
-          const int n = nn[i];
-          const int64_t lo = f.Sset.loc_off_h[v0 + i];
-          gy[i] = {off[i], lo, lo, n, 1, n, n, n, n};
-          gz[i] = {off[i], lo, lo, n, 1, n, n, n, n};
-        }
-        B.gy.upload(gy, bd, s);
-        B.gz.upload(gz, bd, s);
         // nr columns, local vectors column by column (leading dimension nloc)
         const int64_t nloc = f.Sset.nloc;
         std::vector<GemmItem> gyc((size_t)kMaxCols * cnt), gzc((size_t)kMaxCols * cnt);
@@ -760,61 +908,25 @@ void check_patches(dpg_ctx *c, int l) {
 }
 
 // The smoother of level l with its patch inverses recomputed from the macro
-// blocks (DPG_RECOMPUTE_PATCHES; none is stored): y <- epilogue(sum_v R_v^T
-// S_v^-1 R_v x) batch by batch -- gather S_v from the packed macro-block
-// tiles the matvec streams anyway, S_v = L L^H, X = L^-1, then S_v^-1 x_v =
-// X^H (X x_v).  The same operator as the stored inverses, rounded
-// differently; HBM traffic and memory traded for matrix-core work.
-void smooth_recompute(dpg_ctx *c, int l, const double2 *x, double2 *y, const double2 *r, int mode,
-                      double theta) {
+// blocks (DPG_RECOMPUTE_PATCHES; none is stored), for nr interleaved columns
+// (x, y, r: vectors of the level, nr = 1 the single-column ones):
+// y <- epilogue(sum_v R_v^T S_v^-1 R_v x) batch by batch -- gather S_v from
+// the packed macro-block tiles the matvec streams anyway, S_v = L L^H,
+// X = L^-1, then S_v^-1 x_v = X^H (X x_v).  Every patch block is gathered and
+// factored once per smoothing step for all nr columns, and X multiplies an
+// n x nr panel (the local vectors stored column by column), so the
+// refactorisation is amortised over the right-hand sides of a block solve.
+// The same operator as the stored inverses, rounded differently; HBM traffic
+// and memory traded for matrix-core work.
+void smooth_recompute(dpg_ctx *c, int l, const double2 *x, double2 *y, const double2 *r,
+                      int mode, double theta, int nr) {
   LevelData &f = c->lv[l];
   PatchPlan &P = f.pp;
   HermSet &H = f.Sset;
   const hipStream_t s = c->stream;
-  herm_gather(H, x, H.xl64.p, s);
-  for (PatchBatch &B : P.batches) {
-    double2 *S = c->pS[B.half].p, *X = c->pX[B.half].p, *wk = c->pwk[B.half].p;
-    const DenseProf dp{&c->prof, B.hn.data(), 0, B.hn.data(), 0};
-    {
-      PROF(DPG_K_PATCH_GATHER, 0);
-      launch_patch_gather_tiles(f.Mset.t64.p, f.Mset.ent_off.p, f.mpidx.p, f.nBf, f.mc.Nc,
-                                f.patch_ptr.p, f.patch_slot.p, B.v0, B.cnt, B.nmax, B.off.p, S,
-                                s);
-    }
-    {
-      PROF(DPG_K_POTRF, B.fp);
-      potrf_batched(S, B.pi.p, B.cnt, P.info.p + B.v0, B.nmax, wk, s, &dp);
-    }
-    {
-      PROF(DPG_K_OTHER, 0);
-      launch_identity(B.off.p, B.nn.p, B.cnt, B.nmax, X, s);
-    }
-    {
-      PROF(DPG_K_TRSM, B.ft);
-      trsm_batched(S, X, B.ti.p, B.cnt, B.nmax, B.nmax, true, wk, true, s, &dp);
-    }
-    PROF(DPG_K_GEMM, 0);
-    gemm_batched(OP_N, OP_N, mk(1, 0), X, H.xl64.p, mk(0, 0), c->ptmp.p, B.gy.p, B.cnt, B.nmax, 1,
-                 s);
-    gemm_batched(OP_C, OP_N, mk(1, 0), X, c->ptmp.p, mk(0, 0), H.yl64.p, B.gz.p, B.cnt, B.nmax,
-                 1, s);
-  }
-  herm_scatter(H, H.yl64.p, y, r, mode, theta, s);
-}
-
-// The same for nr interleaved columns (x, y, r: block vectors of the level):
-// every patch block is gathered and factored once per smoothing step for all
-// nr columns, and its inverse factor multiplies an n x nr panel (the local
-// vectors stored column by column), so the refactorisation is amortised over
-// the right-hand sides of a block solve.
-void smooth_recompute_cols(dpg_ctx *c, int l, const double2 *x, double2 *y, const double2 *r,
-                           int mode, double theta, int nr) {
-  LevelData &f = c->lv[l];
-  PatchPlan &P = f.pp;
-  HermSet &H = f.Sset;
-  const hipStream_t s = c->stream;
-  if (nr < 1 || nr > kMaxCols || nr > f.Sb.cap) throw DpgError(DPG_EINVAL, "bad column count");
-  double2 *xl = f.Sb.xl64.p, *yl = f.Sb.yl64.p;
+  if (nr < 1 || nr > kMaxCols || (nr > 1 && nr > f.Sb.cap))
+    throw DpgError(DPG_EINVAL, "bad column count");
+  double2 *xl = nr == 1 ? H.xl64.p : f.Sb.xl64.p, *yl = nr == 1 ? H.yl64.p : f.Sb.yl64.p;
   herm_gather_cols(H, x, xl, nr, s);
   for (PatchBatch &B : P.batches) {
     double2 *S = c->pS[B.half].p, *X = c->pX[B.half].p, *wk = c->pwk[B.half].p;
@@ -972,7 +1084,7 @@ template <typename T>
 void smooth_apply(dpg_ctx *c, int l, const cplx_t<T> *x, cplx_t<T> *y, int mode, T theta) {
   if constexpr (sizeof(T) == 8) {
     if (c->opt.flags & DPG_RECOMPUTE_PATCHES) {
-      smooth_recompute(c, l, x, y, nullptr, mode, theta);
+      smooth_recompute(c, l, x, y, nullptr, mode, theta, 1);
       return;
     }
   }
@@ -1276,7 +1388,7 @@ void smooth_apply_blk(dpg_ctx *c, int l, const cplx_t<T> *x, cplx_t<T> *y, const
   LevelData &f = c->lv[l];
   if constexpr (sizeof(T) == 8) {
     if (c->opt.flags & DPG_RECOMPUTE_PATCHES) {
-      smooth_recompute_cols(c, l, x, y, r, mode, theta, nr);
+      smooth_recompute(c, l, x, y, r, mode, theta, nr);
       return;
     }
   }
@@ -1968,6 +2080,23 @@ int dpg_release_setup(dpg_ctx *c) {
     c->zTi.release();
     c->zwk.release();
     c->T0.release();
+    // load updates go through the class maps from now on, so the element-stage
+    // work areas can go too (a later element pass, the error indicator,
+    // plans and allocates them again)
+    if (c->lm.state == 0) build_load_maps(c);
+    if (c->lm.state == 1) {
+      ElemPlan &P = c->ep;
+      for (int k = 0; k < 4; ++k) {
+        P.G[k].release();
+        P.BL[k].release();
+        P.K[k].release();
+        P.wk[k].release();
+        P.X[k].release();
+      }
+      P.mp = -1;
+      P.nel = -1;
+      P.gR_nr = 0;
+    }
     c->released = true;
     return DPG_OK;
   });
@@ -1985,7 +2114,21 @@ int dpg_load_rhs(dpg_ctx *c, const dpg_load *loads, int nrhs, double *s_out) {
     if (c->keep_recovery)
       c->rec_Yb.ensure((int64_t)top.nel * c->n_field * c->nrhs, &c->bud);
     std::vector<int32_t> list;
-    if (source_elements(c, list)) {
+    const bool everywhere = source_elements(c, list);
+    if (c->lm.state == 0) build_load_maps(c);
+    if (c->lm.state == 1) {
+      // the class maps: the load kernel and one product per element
+      const hipStream_t s = c->stream;
+      if (!everywhere) {
+        launch_zero(c->s_elem.n, c->s_elem.p, s);
+        if (c->keep_recovery) launch_zero(c->rec_Yb.n, c->rec_Yb.p, s);
+        grow(c->elist, std::max<int64_t>(1, (int64_t)list.size()), &c->bud);
+        if (!list.empty())
+          HIP_OK(hipMemcpyAsync(c->elist.p, list.data(), list.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, s));
+      }
+      load_by_maps(c, list, c->elist.p, everywhere);
+    } else if (everywhere) {
       element_stage(c, c->L, false);
     } else {
       // point sources only: the elements near a source carry the whole load

@@ -35,6 +35,21 @@ struct ElemPlan {
   int gR_nr = 0, gR_C = 0;
 };
 
+// Load updates by maps per element class.  Elements with equal wave speed and
+// the same faces on Gamma have equal G and B (translated boxes), so one linear
+// map T_c takes an element's load vector l (over the test functions) to its
+// condensed trace load s = K_tl - K_tf K_ff^-1 K_fl, and F_c to its
+// field-recovery data L_f^-1 K_fl; both are formed once by the element chain
+// with identity load columns on one element of each class.
+struct LoadMaps {
+  int state = 0;                     // 0 not built, 1 built, -1 not used (too many classes)
+  int nclass = 0;
+  std::vector<int32_t> cls_h;        // class of every finest element
+  DevBuf<double2> T, F;              // [nclass] n_tr x n_test, n_field x n_test (column-major)
+  DevBuf<double2> lbuf;              // load vectors of a chunk of elements [C][nr][n_test]
+  DevBuf<GemmItem> items;            // per update: s_e = T_c l_e, then Yb_e = F_c l_e
+};
+
 // Macro condensation and Galerkin step of one level (workspaces shared by
 // all levels: the levels run one after the other on one stream).
 struct MacroPlan {
@@ -63,9 +78,9 @@ struct PatchBatch {
   DevBuf<PotrfItem> pi;
   DevBuf<TrsmItem> ti;
   DevBuf<GemmItem> gi;
-  DevBuf<GemmItem> gy, gz;           // recomputed inverses: t = X x_v, y_v = X^H t
-  DevBuf<GemmItem> gyc, gzc;         // the same for nr = 1 .. kMaxCols columns stored
-                                     // column by column: items (nr - 1) cnt + i
+  DevBuf<GemmItem> gyc, gzc;         // recomputed inverses, t = X x_v and y_v = X^H t for
+                                     // nr = 1 .. kMaxCols columns stored column by
+                                     // column: items (nr - 1) cnt + i
 };
 struct PatchPlan {
   bool ready = false;
@@ -189,6 +204,7 @@ struct dpg_ctx {
   dpg::DevBuf<int32_t> asm_ptr, asm_ent;
   dpg::DevBuf<double2> rec_L, rec_Y, rec_Yb;  // [nel][nf^2], [nel][nf n_tr], [nel][nrhs nf]
   dpg::DevBuf<int32_t> elist;        // elements of a point-source load update
+  dpg::LoadMaps lm;                  // load updates without the element chain
   // coarsest mesh
   dpg::DevBuf<double2> T0;
   dpg::HermSet T0set;

@@ -694,34 +694,6 @@ void herm_apply(HermSet &H, const cplx_t<T> *x, cplx_t<T> *y, const cplx_t<T> *r
   LAUNCH_OK();
 }
 
-void herm_gather(HermSet &H, const double2 *x, double2 *xl, hipStream_t s) {
-  ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
-  hipLaunchKernelGGL((k_gather_x<double>), dim3(cdiv(H.nloc, 256)), dim3(256), 0, s, H.nloc,
-                     H.gidx.p, x, xl);
-  LAUNCH_OK();
-}
-
-void herm_scatter(HermSet &H, const double2 *yl, double2 *y, const double2 *r, int mode,
-                  double theta, hipStream_t s) {
-  ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
-  const dim3 g(cdiv(H.nvec, 256));
-  using T = double;
-  switch (mode) {
-    case RED_SET:
-      hipLaunchKernelGGL((k_scatter<T, RED_SET>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
-      break;
-    case RED_RESID:
-      hipLaunchKernelGGL((k_scatter<T, RED_RESID>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
-      break;
-    case RED_AXPY:
-      hipLaunchKernelGGL((k_scatter<T, RED_AXPY>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
-      break;
-    default:
-      hipLaunchKernelGGL((k_scatter<T, RED_SET_SCALED>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
-  }
-  LAUNCH_OK();
-}
-
 template void herm_apply<double>(HermSet &, const double2 *, double2 *, const double2 *, int,
                                  double, hipStream_t);
 template void herm_apply<float>(HermSet &, const float2 *, float2 *, const float2 *, int, float,

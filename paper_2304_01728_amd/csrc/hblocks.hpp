@@ -89,13 +89,6 @@ struct HermSet {
             int64_t ntile_count = -1);
 };
 
-// The first and last phases of herm_apply alone (FP64), for a caller that
-// applies the blocks itself: xl = the local vectors R_b x (block b at
-// loc_off_h[b], 32-padded with zeros); y <- epilogue(sum_b R_b^T yl_b).
-void herm_gather(HermSet &H, const double2 *x, double2 *xl, hipStream_t s);
-void herm_scatter(HermSet &H, const double2 *yl, double2 *y, const double2 *r, int mode,
-                  double theta, hipStream_t s);
-
 // y <- epilogue(sum_b R_b^T A_b R_b x): RED_SET y = Ax; RED_RESID y = r - Ax;
 // RED_AXPY y += theta Ax; RED_SET_SCALED y = theta Ax.
 template <typename T>
