@@ -1081,14 +1081,16 @@ template <> struct LB<float> {
 
 // The smoother's patch sum on level l: stored inverses, or recomputed ones.
 template <typename T>
-void smooth_apply(dpg_ctx *c, int l, const cplx_t<T> *x, cplx_t<T> *y, int mode, T theta) {
+void smooth_apply(dpg_ctx *c, int l, const cplx_t<T> *x, cplx_t<T> *y, int mode, T theta,
+                  bool gathered = false, HermSet *fwd = nullptr) {
   if constexpr (sizeof(T) == 8) {
     if (c->opt.flags & DPG_RECOMPUTE_PATCHES) {
+      if (gathered || fwd) throw DpgError(-1, "recomputed patches take no forwarded vectors");
       smooth_recompute(c, l, x, y, nullptr, mode, theta, 1);
       return;
     }
   }
-  herm_apply<T>(c->lv[l].Sset, x, y, nullptr, mode, theta, c->stream);
+  herm_apply<T>(c->lv[l].Sset, x, y, nullptr, mode, theta, c->stream, gathered, fwd);
 }
 
 // Condensation of the macro-grid interior unknowns of level g (Sec. 3): the
@@ -1132,16 +1134,21 @@ template <typename T> void vcycle(dpg_ctx *c, int l) {
   const hipStream_t s = c->stream;
   const T th = (T)c->opt.theta;
   auto r = B::r(f), x = B::x(f), res = B::res(f), rc = B::rc(f), ec = B::ec(f);
+  // With stored patch inverses every smoother application forwards the new x
+  // to the residual's block set and every residual forwards r - Mx to the
+  // smoother's (the scatter writes their local vectors), so neither gathers.
+  const bool fw = sizeof(T) == 4 || !(c->opt.flags & DPG_RECOMPUTE_PATCHES);
+  HermSet *toM = fw ? &f.Mset : nullptr, *toS = fw ? &f.Sset : nullptr;
   if (c->opt.nu_pre == 0) launch_zero(f.nM, x, s);
   for (int k = 0; k < c->opt.nu_pre; ++k) {
     if (k == 0) {
-      smooth_apply<T>(c, l, r, x, RED_SET_SCALED, th);
+      smooth_apply<T>(c, l, r, x, RED_SET_SCALED, th, false, toM);
     } else {
-      herm_apply<T>(f.Mset, x, res, r, RED_RESID, (T)0, s);
-      smooth_apply<T>(c, l, res, x, RED_AXPY, th);
+      herm_apply<T>(f.Mset, x, res, r, RED_RESID, (T)0, s, fw, toS);
+      smooth_apply<T>(c, l, res, x, RED_AXPY, th, fw, toM);
     }
   }
-  herm_apply<T>(f.Mset, x, res, r, RED_RESID, (T)0, s);
+  herm_apply<T>(f.Mset, x, res, r, RED_RESID, (T)0, s, fw && c->opt.nu_pre > 0);
   LevelData &g = c->lv[l - 1];
   {
     PROF(DPG_K_TRANSFER, 0);
@@ -1163,8 +1170,8 @@ template <typename T> void vcycle(dpg_ctx *c, int l) {
     launch_csr<T>(f.nM, f.Pptr.p, f.Pcol.p, B::Pv(f), ec, x, 1, s);
   }
   for (int k = 0; k < c->opt.nu_post; ++k) {
-    herm_apply<T>(f.Mset, x, res, r, RED_RESID, (T)0, s);
-    smooth_apply<T>(c, l, res, x, RED_AXPY, th);
+    herm_apply<T>(f.Mset, x, res, r, RED_RESID, (T)0, s, fw && k > 0, toS);
+    smooth_apply<T>(c, l, res, x, RED_AXPY, th, fw, k + 1 < c->opt.nu_post ? toM : nullptr);
   }
 }
 

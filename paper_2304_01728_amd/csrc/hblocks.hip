@@ -3,6 +3,7 @@
 #include <numeric>
 
 #include "hblocks.hpp"
+#include "kernels.hpp"
 
 namespace dpg {
 namespace {
@@ -399,12 +400,18 @@ __global__ __launch_bounds__(256) void k_rows(const int4 *__restrict__ rowd, int
   yl[d.w + r] = acc[0];
 }
 
-template <typename T, int MODE>
+// With FWD the result of entry d is also written to every local row of the
+// next block set that holds d (its reduction list), which is then applied
+// without its own gather: the same values the gather would read.
+template <typename T, int MODE, bool FWD>
 __global__ __launch_bounds__(256) void k_scatter(int64_t nvec, const int32_t *__restrict__ red_ptr,
                                                  const int32_t *__restrict__ red_ent,
                                                  const cplx_t<T> *__restrict__ yl,
                                                  const cplx_t<T> *__restrict__ r,
-                                                 cplx_t<T> *__restrict__ y, T theta) {
+                                                 cplx_t<T> *__restrict__ y, T theta,
+                                                 const int32_t *__restrict__ fwd_ptr,
+                                                 const int32_t *__restrict__ fwd_ent,
+                                                 cplx_t<T> *__restrict__ fwd_xl) {
   using C = cplx_t<T>;
   const int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (d >= nvec) return;
@@ -412,10 +419,14 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t nvec, const int32_t *__
   acc.x = 0;
   acc.y = 0;
   for (int32_t k = red_ptr[d]; k < red_ptr[d + 1]; ++k) acc = cadd(acc, yl[red_ent[k]]);
-  if (MODE == RED_SET) y[d] = acc;
-  else if (MODE == RED_RESID) y[d] = csub(r[d], acc);
-  else if (MODE == RED_AXPY) y[d] = cadd(y[d], cscale(acc, theta));
-  else y[d] = cscale(acc, theta);
+  C out;
+  if (MODE == RED_SET) out = acc;
+  else if (MODE == RED_RESID) out = csub(r[d], acc);
+  else if (MODE == RED_AXPY) out = cadd(y[d], cscale(acc, theta));
+  else out = cscale(acc, theta);
+  y[d] = out;
+  if (FWD)
+    for (int32_t k = fwd_ptr[d]; k < fwd_ptr[d + 1]; ++k) fwd_xl[fwd_ent[k]] = out;
 }
 
 __global__ __launch_bounds__(256) void k_pack(const int4 *__restrict__ tdesc, int64_t tile0,
@@ -616,6 +627,7 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
     p64.alloc(npart, bud);
     xl64.alloc(nloc, bud);
     yl64.alloc(nloc, bud);
+    launch_zero(nloc, xl64.p, s);
   }
   if (fp32) {
     sunits.upload(sud, bud, s);
@@ -624,6 +636,7 @@ void HermSet::build(const std::vector<int32_t> &sizes, const std::vector<int32_t
     p32.alloc(snpart, bud);
     xl32.alloc(nloc, bud);
     yl32.alloc(nloc, bud);
+    launch_zero(nloc, xl32.p, s);
   }
   HIP_OK(hipStreamSynchronize(s));
 }
@@ -639,24 +652,43 @@ void HermSet::pack(const double2 *src, const int64_t *src_off_dev, const int32_t
   LAUNCH_OK();
 }
 
+template <typename T, int MODE>
+void launch_scatter(const HermSet &H, const cplx_t<T> *yl, const cplx_t<T> *r, cplx_t<T> *y,
+                    T theta, HermSet *fwd, cplx_t<T> *fxl, hipStream_t s) {
+  const dim3 g(cdiv(H.nvec, 256));
+  if (fwd)
+    hipLaunchKernelGGL((k_scatter<T, MODE, true>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p,
+                       H.red_ent.p, yl, r, y, theta, fwd->red_ptr.p, fwd->red_ent.p, fxl);
+  else
+    hipLaunchKernelGGL((k_scatter<T, MODE, false>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p,
+                       H.red_ent.p, yl, r, y, theta, nullptr, nullptr, nullptr);
+}
+
+template <typename T> cplx_t<T> *local_x(HermSet &H) {
+  if constexpr (sizeof(T) == 8) return H.xl64.p;
+  else return H.xl32.p;
+}
+
 template <typename T>
 void herm_apply(HermSet &H, const cplx_t<T> *x, cplx_t<T> *y, const cplx_t<T> *r, int mode,
-                T theta, hipStream_t s) {
+                T theta, hipStream_t s, bool gathered, HermSet *fwd) {
   const cplx_t<T> *tiles;
   cplx_t<T> *part, *xl, *yl;
   if constexpr (sizeof(T) == 8) {
     tiles = H.t64.p;
     part = H.p64.p;
-    xl = H.xl64.p;
     yl = H.yl64.p;
   } else {
     tiles = H.t32.p;
     part = H.p32.p;
-    xl = H.xl32.p;
     yl = H.yl32.p;
   }
+  xl = local_x<T>(H);
   if (!tiles || !part) throw DpgError(-6, "block set has no tiles of this precision");
-  {
+  cplx_t<T> *fxl = fwd ? local_x<T>(*fwd) : nullptr;
+  if (fwd && (!fxl || fwd->nvec != H.nvec))
+    throw DpgError(-1, "forwarded block set does not match this one");
+  if (!gathered) {
     ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
     hipLaunchKernelGGL((k_gather_x<T>), dim3(cdiv(H.nloc, 256)), dim3(256), 0, s, H.nloc,
                        H.gidx.p, x, xl);
@@ -677,26 +709,18 @@ void herm_apply(HermSet &H, const cplx_t<T> *x, cplx_t<T> *y, const cplx_t<T> *r
   hipLaunchKernelGGL((k_rows<T>), dim3(cdiv(H.nrows, 8)), dim3(256), 0, s,
                      sizeof(T) == 8 ? H.rowd.p : H.srowd.p, H.nrows, part, yl);
   LAUNCH_OK();
-  const dim3 g(cdiv(H.nvec, 256));
   switch (mode) {
-    case RED_SET:
-      hipLaunchKernelGGL((k_scatter<T, RED_SET>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
-      break;
-    case RED_RESID:
-      hipLaunchKernelGGL((k_scatter<T, RED_RESID>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
-      break;
-    case RED_AXPY:
-      hipLaunchKernelGGL((k_scatter<T, RED_AXPY>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
-      break;
-    default:
-      hipLaunchKernelGGL((k_scatter<T, RED_SET_SCALED>), g, dim3(256), 0, s, H.nvec, H.red_ptr.p, H.red_ent.p, yl, r, y, theta);
+    case RED_SET: launch_scatter<T, RED_SET>(H, yl, r, y, theta, fwd, fxl, s); break;
+    case RED_RESID: launch_scatter<T, RED_RESID>(H, yl, r, y, theta, fwd, fxl, s); break;
+    case RED_AXPY: launch_scatter<T, RED_AXPY>(H, yl, r, y, theta, fwd, fxl, s); break;
+    default: launch_scatter<T, RED_SET_SCALED>(H, yl, r, y, theta, fwd, fxl, s);
   }
   LAUNCH_OK();
 }
 
 template void herm_apply<double>(HermSet &, const double2 *, double2 *, const double2 *, int,
-                                 double, hipStream_t);
+                                 double, hipStream_t, bool, HermSet *);
 template void herm_apply<float>(HermSet &, const float2 *, float2 *, const float2 *, int, float,
-                                hipStream_t);
+                                hipStream_t, bool, HermSet *);
 
 }  // namespace dpg

@@ -23,7 +23,10 @@
 //  3. rows:    half a wave per (block, tile row I) adds the column partials
 //     of column I and the row partials of row I (contiguous) into y_loc[b];
 //  4. scatter: one thread per vector entry adds y_loc of every block holding
-//     it, in a fixed order, and applies the epilogue.
+//     it, in a fixed order, and applies the epilogue; it can also write the
+//     result into the local vector of the set applied next (the smoother
+//     after a residual, the residual after a smoother), whose gather is
+//     then left out.
 #pragma once
 #include "common.hpp"
 
@@ -91,8 +94,13 @@ struct HermSet {
 
 // y <- epilogue(sum_b R_b^T A_b R_b x): RED_SET y = Ax; RED_RESID y = r - Ax;
 // RED_AXPY y += theta Ax; RED_SET_SCALED y = theta Ax.
+// gathered: the local vector of H already holds R_b x (a previous
+// application forwarded x to H), so x is not read.  fwd: a block set on the
+// same vector whose local vector receives the new y (its padding rows stay
+// zero: they are zeroed at build and never written by a forward), for an
+// application of fwd to y that follows with gathered = true.
 template <typename T>
 void herm_apply(HermSet &H, const cplx_t<T> *x, cplx_t<T> *y, const cplx_t<T> *r, int mode,
-                T theta, hipStream_t s);
+                T theta, hipStream_t s, bool gathered = false, HermSet *fwd = nullptr);
 
 }  // namespace dpg
