@@ -1245,7 +1245,7 @@ int solve_one(dpg_ctx *c, const double2 *sv, double tol, double2 *xout, int32_t 
     // convergence check: (A) matvec, alpha, x and r; (B) V-cycle, beta, p.
     // Without per-kernel profiling they are captured once per solve as HIP
     // graphs and replayed (B in two versions: z and z_old swap every
-    // iteration), which removes the launch gaps between the ~130 kernels.
+    // iteration), which removes the launch gaps between the ~105 kernels.
     auto part_a = [&]() {
       herm_apply<double>(top.Mset, c->pv.p, c->q.p, nullptr, RED_SET, 1.0, s);
       PROF(DPG_K_CG, 0);

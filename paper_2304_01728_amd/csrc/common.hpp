@@ -108,9 +108,6 @@ template <typename T> struct DevBuf {
     alloc((int64_t)h.size(), b);
     if (n) HIP_OK(hipMemcpyAsync(p, h.data(), n * sizeof(T), hipMemcpyHostToDevice, s));
   }
-  void zero(hipStream_t s) {
-    if (n) HIP_OK(hipMemsetAsync(p, 0, n * sizeof(T), s));
-  }
   std::vector<T> download(hipStream_t s) const {
     std::vector<T> h(n);
     if (n) {
