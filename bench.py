@@ -583,7 +583,7 @@ def main():
                     help="requests of the serving stream the default run reports beside the "
                          "solver line (0: none)")
     ap.add_argument("--seed", type=int, default=4)
-    ap.add_argument("--max-active", type=int, default=4)
+    ap.add_argument("--max-active", type=int, default=8)
     ap.add_argument("--load-factor", type=float, default=0.7)
     args = ap.parse_args()
     if args.gpus != 1:

@@ -100,7 +100,7 @@ class Server:
     max_batch: column slots of each operator's batch.  step_iters: block PCG
     iterations between two looks at the queue (admissions happen there)."""
 
-    def __init__(self, operators, budget_bytes, max_active=4, max_batch=8, step_iters=1):
+    def __init__(self, operators, budget_bytes, max_active=8, max_batch=8, step_iters=1):
         self.ops = {op.key: op for op in operators}
         self.budget = budget_bytes
         self.max_batch = max_batch
