@@ -1365,14 +1365,16 @@ void ensure_block(dpg_ctx *c, int nr) {
       f.bec64.alloc(nc * nr, bd);
     }
     if (!mixed || l == c->L) f.bc64.alloc(ncb * nr, bd);
-    f.Mb.ensure(f.Mset, nr, f.Mset.t64.p != nullptr, f.Mset.t32.p != nullptr, bd);
+    f.Mb.ensure(f.Mset, nr, f.Mset.t64.p != nullptr, f.Mset.t32.p != nullptr, bd, c->stream);
     const bool rec = c->opt.flags & DPG_RECOMPUTE_PATCHES;   // local vectors of the
                                                              // recomputed smoother
-    f.Sb.ensure(f.Sset, nr, f.Sset.t64.p != nullptr || rec, f.Sset.t32.p != nullptr, bd);
+    f.Sb.ensure(f.Sset, nr, f.Sset.t64.p != nullptr || rec, f.Sset.t32.p != nullptr, bd,
+                c->stream);
     if (rec) grow(c->ptmp, f.Sset.nloc * nr, bd);
     f.bcap = nr;
   }
-  c->T0b.ensure(c->T0set, nr, c->T0set.t64.p != nullptr, c->T0set.t32.p != nullptr, bd);
+  c->T0b.ensure(c->T0set, nr, c->T0set.t64.p != nullptr, c->T0set.t32.p != nullptr, bd,
+                c->stream);
   LevelData &top = c->lv[c->L];
   const int64_t nM = top.nM, nT = top.num.n;
   for (auto *v : {&c->bb, &c->bx, &c->br, &c->bz, &c->bzo, &c->bp, &c->bq}) v->alloc(nM * nr, bd);
@@ -1391,15 +1393,17 @@ void ensure_block(dpg_ctx *c, int nr) {
 // inverses recomputed in the application (FP64).
 template <typename T>
 void smooth_apply_blk(dpg_ctx *c, int l, const cplx_t<T> *x, cplx_t<T> *y, const cplx_t<T> *r,
-                      int mode, T theta, int nr) {
+                      int mode, T theta, int nr, bool gathered = false, bool fwd = false) {
   LevelData &f = c->lv[l];
   if constexpr (sizeof(T) == 8) {
     if (c->opt.flags & DPG_RECOMPUTE_PATCHES) {
+      if (gathered || fwd) throw DpgError(-1, "recomputed patches take no forwarded vectors");
       smooth_recompute(c, l, x, y, r, mode, theta, nr);
       return;
     }
   }
-  herm_apply_blk<T>(f.Sset, f.Sb, x, y, r, mode, theta, nr, c->stream);
+  herm_apply_blk<T>(f.Sset, f.Sb, x, y, r, mode, theta, nr, c->stream, gathered,
+                    fwd ? &f.Mset : nullptr, fwd ? &f.Mb : nullptr);
 }
 
 template <typename T> void vcycle_blk(dpg_ctx *c, int l, int nr) {
@@ -1409,16 +1413,20 @@ template <typename T> void vcycle_blk(dpg_ctx *c, int l, int nr) {
   const hipStream_t s = c->stream;
   const T th = (T)c->opt.theta;
   auto r = BB::r(f), x = BB::x(f), res = BB::res(f), rc = BB::rc(f), ec = BB::ec(f);
+  // forwarding between the smoother and the residual as in vcycle
+  const bool fw = sizeof(T) == 4 || !(c->opt.flags & DPG_RECOMPUTE_PATCHES);
+  HermSet *toS = fw ? &f.Sset : nullptr;
+  HermBlockBufs *bS = fw ? &f.Sb : nullptr;
   if (c->opt.nu_pre == 0) launch_zero(f.nM * nr, x, s);
   for (int k = 0; k < c->opt.nu_pre; ++k) {
     if (k == 0) {
-      smooth_apply_blk<T>(c, l, r, x, nullptr, RED_SET_SCALED, th, nr);
+      smooth_apply_blk<T>(c, l, r, x, nullptr, RED_SET_SCALED, th, nr, false, fw);
     } else {
-      herm_apply_blk<T>(f.Mset, f.Mb, x, res, r, RED_RESID, (T)0, nr, s);
-      smooth_apply_blk<T>(c, l, res, x, nullptr, RED_AXPY, th, nr);
+      herm_apply_blk<T>(f.Mset, f.Mb, x, res, r, RED_RESID, (T)0, nr, s, fw, toS, bS);
+      smooth_apply_blk<T>(c, l, res, x, nullptr, RED_AXPY, th, nr, fw, fw);
     }
   }
-  herm_apply_blk<T>(f.Mset, f.Mb, x, res, r, RED_RESID, (T)0, nr, s);
+  herm_apply_blk<T>(f.Mset, f.Mb, x, res, r, RED_RESID, (T)0, nr, s, fw && c->opt.nu_pre > 0);
   LevelData &g = c->lv[l - 1];
   {
     PROF(DPG_K_TRANSFER, 0);
@@ -1440,8 +1448,8 @@ template <typename T> void vcycle_blk(dpg_ctx *c, int l, int nr) {
     launch_csr_blk<T>(f.nM, f.Pptr.p, f.Pcol.p, B::Pv(f), ec, x, 1, nr, s);
   }
   for (int k = 0; k < c->opt.nu_post; ++k) {
-    herm_apply_blk<T>(f.Mset, f.Mb, x, res, r, RED_RESID, (T)0, nr, s);
-    smooth_apply_blk<T>(c, l, res, x, nullptr, RED_AXPY, th, nr);
+    herm_apply_blk<T>(f.Mset, f.Mb, x, res, r, RED_RESID, (T)0, nr, s, fw && k > 0, toS, bS);
+    smooth_apply_blk<T>(c, l, res, x, nullptr, RED_AXPY, th, nr, fw, fw && k + 1 < c->opt.nu_post);
   }
 }
 

@@ -2,6 +2,7 @@
 #include <algorithm>
 
 #include "block.hpp"
+#include "kernels.hpp"
 
 namespace dpg {
 namespace {
@@ -308,13 +309,18 @@ __global__ __launch_bounds__(64) void k_rows_mfma64(const double2 *__restrict__ 
     }
 }
 
-template <typename T, int MODE>
+// With FWD the result (d, k) also goes to the local rows of the next block
+// set that hold d (its reduction lists), in that set's block buffers.
+template <typename T, int MODE, bool FWD>
 __global__ __launch_bounds__(256) void k_scatter_blk(int64_t nvec, int nr,
                                                      const int32_t *__restrict__ red_ptr,
                                                      const int32_t *__restrict__ red_ent,
                                                      const cplx_t<T> *__restrict__ yl,
                                                      const cplx_t<T> *__restrict__ r,
-                                                     cplx_t<T> *__restrict__ y, T theta) {
+                                                     cplx_t<T> *__restrict__ y, T theta,
+                                                     const int32_t *__restrict__ fwd_ptr,
+                                                     const int32_t *__restrict__ fwd_ent,
+                                                     cplx_t<T> *__restrict__ fwd_xl) {
   using C = cplx_t<T>;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= nvec * nr) return;
@@ -323,10 +329,14 @@ __global__ __launch_bounds__(256) void k_scatter_blk(int64_t nvec, int nr,
   C acc = czero<C>();
   for (int32_t j = red_ptr[d]; j < red_ptr[d + 1]; ++j)
     acc = cadd(acc, yl[(int64_t)red_ent[j] * nr + k]);
-  if (MODE == RED_SET) y[e] = acc;
-  else if (MODE == RED_RESID) y[e] = csub(r[e], acc);
-  else if (MODE == RED_AXPY) y[e] = cadd(y[e], cscale(acc, theta));
-  else y[e] = cscale(acc, theta);
+  C out;
+  if (MODE == RED_SET) out = acc;
+  else if (MODE == RED_RESID) out = csub(r[e], acc);
+  else if (MODE == RED_AXPY) out = cadd(y[e], cscale(acc, theta));
+  else out = cscale(acc, theta);
+  y[e] = out;
+  if (FWD)
+    for (int32_t j = fwd_ptr[d]; j < fwd_ptr[d + 1]; ++j) fwd_xl[(int64_t)fwd_ent[j] * nr + k] = out;
 }
 
 // Local vectors column by column ([nr][nloc]).
@@ -644,26 +654,52 @@ __global__ __launch_bounds__(256) void k_update_p_blk(int64_t n, int nr, double2
 
 }  // namespace
 
-void HermBlockBufs::ensure(const HermSet &H, int nr, bool fp64, bool fp32, Budget *bud) {
+void HermBlockBufs::ensure(const HermSet &H, int nr, bool fp64, bool fp32, Budget *bud,
+                           hipStream_t s) {
   if (nr <= cap) return;
   if (fp64) {
     xl64.alloc(H.nloc * nr, bud);
     yl64.alloc(H.nloc * nr, bud);
+    launch_zero(H.nloc * nr, xl64.p, s);
   }
   if (fp32) {
     xl32.alloc(H.nloc * nr, bud);
     yl32.alloc(H.nloc * nr, bud);
+    launch_zero(H.nloc * nr, xl32.p, s);
   }
   cap = nr;
 }
 
+template <typename T, int MODE>
+void launch_scatter_blk(const HermSet &H, int nr, const cplx_t<T> *yl, const cplx_t<T> *R,
+                        cplx_t<T> *Y, T theta, const HermSet *fwd, cplx_t<T> *fxl,
+                        hipStream_t s) {
+  const dim3 g(cdiv(H.nvec * nr, 256));
+  if (fwd)
+    hipLaunchKernelGGL((k_scatter_blk<T, MODE, true>), g, dim3(256), 0, s, H.nvec, nr,
+                       H.red_ptr.p, H.red_ent.p, yl, R, Y, theta, fwd->red_ptr.p,
+                       fwd->red_ent.p, fxl);
+  else
+    hipLaunchKernelGGL((k_scatter_blk<T, MODE, false>), g, dim3(256), 0, s, H.nvec, nr,
+                       H.red_ptr.p, H.red_ent.p, yl, R, Y, theta, nullptr, nullptr, nullptr);
+}
+
 template <typename T>
 void herm_apply_blk(HermSet &H, HermBlockBufs &W, const cplx_t<T> *X, cplx_t<T> *Y,
-                    const cplx_t<T> *R, int mode, T theta, int nr, hipStream_t s) {
+                    const cplx_t<T> *R, int mode, T theta, int nr, hipStream_t s, bool gathered,
+                    HermSet *fwd, HermBlockBufs *fwd_bufs) {
   if (nr < 1 || nr > kMaxCols || nr > W.cap) throw DpgError(-1, "block apply: bad column count");
   if (nr == 1) {   // one column: the HBM-bound single-vector apply (same layout)
-    herm_apply<T>(H, X, Y, R, mode, theta, s);
+    herm_apply<T>(H, X, Y, R, mode, theta, s, gathered, fwd);
     return;
+  }
+  cplx_t<T> *fxl = nullptr;
+  if (fwd) {
+    if (!fwd_bufs || fwd->nvec != H.nvec || nr > fwd_bufs->cap)
+      throw DpgError(-1, "forwarded block set does not match this one");
+    if constexpr (sizeof(T) == 8) fxl = fwd_bufs->xl64.p;
+    else fxl = fwd_bufs->xl32.p;
+    if (!fxl) throw DpgError(-1, "forwarded block set has no local vectors of this precision");
   }
   const cplx_t<T> *tiles;
   cplx_t<T> *xl, *yl;
@@ -677,7 +713,7 @@ void herm_apply_blk(HermSet &H, HermBlockBufs &W, const cplx_t<T> *X, cplx_t<T> 
     yl = W.yl32.p;
   }
   if (!tiles || !xl) throw DpgError(-6, "block set has no tiles of this precision");
-  {
+  if (!gathered) {
     ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
     hipLaunchKernelGGL((k_gather_blk<T>), dim3(cdiv(H.nloc * nr, 256)), dim3(256), 0, s, H.nloc,
                        nr, H.gidx.p, X, xl);
@@ -700,19 +736,11 @@ void herm_apply_blk(HermSet &H, HermBlockBufs &W, const cplx_t<T> *X, cplx_t<T> 
     LAUNCH_OK();
   }
   ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
-  const dim3 g(cdiv(H.nvec * nr, 256));
   switch (mode) {
-    case RED_SET:
-      hipLaunchKernelGGL((k_scatter_blk<T, RED_SET>), g, dim3(256), 0, s, H.nvec, nr, H.red_ptr.p, H.red_ent.p, yl, R, Y, theta);
-      break;
-    case RED_RESID:
-      hipLaunchKernelGGL((k_scatter_blk<T, RED_RESID>), g, dim3(256), 0, s, H.nvec, nr, H.red_ptr.p, H.red_ent.p, yl, R, Y, theta);
-      break;
-    case RED_AXPY:
-      hipLaunchKernelGGL((k_scatter_blk<T, RED_AXPY>), g, dim3(256), 0, s, H.nvec, nr, H.red_ptr.p, H.red_ent.p, yl, R, Y, theta);
-      break;
-    default:
-      hipLaunchKernelGGL((k_scatter_blk<T, RED_SET_SCALED>), g, dim3(256), 0, s, H.nvec, nr, H.red_ptr.p, H.red_ent.p, yl, R, Y, theta);
+    case RED_SET: launch_scatter_blk<T, RED_SET>(H, nr, yl, R, Y, theta, fwd, fxl, s); break;
+    case RED_RESID: launch_scatter_blk<T, RED_RESID>(H, nr, yl, R, Y, theta, fwd, fxl, s); break;
+    case RED_AXPY: launch_scatter_blk<T, RED_AXPY>(H, nr, yl, R, Y, theta, fwd, fxl, s); break;
+    default: launch_scatter_blk<T, RED_SET_SCALED>(H, nr, yl, R, Y, theta, fwd, fxl, s);
   }
   LAUNCH_OK();
 }
@@ -861,9 +889,11 @@ void cgb_update_p(int64_t n, int nr, double2 *p, const double2 *z, const double 
 }
 
 template void herm_apply_blk<double>(HermSet &, HermBlockBufs &, const double2 *, double2 *,
-                                     const double2 *, int, double, int, hipStream_t);
+                                     const double2 *, int, double, int, hipStream_t, bool,
+                                     HermSet *, HermBlockBufs *);
 template void herm_apply_blk<float>(HermSet &, HermBlockBufs &, const float2 *, float2 *,
-                                    const float2 *, int, float, int, hipStream_t);
+                                    const float2 *, int, float, int, hipStream_t, bool,
+                                    HermSet *, HermBlockBufs *);
 template void launch_csr_blk<double>(int64_t, const int64_t *, const int32_t *, const double *,
                                      const double2 *, double2 *, int, int, hipStream_t);
 template void launch_csr_blk<float>(int64_t, const int64_t *, const int32_t *, const float *,

@@ -20,13 +20,24 @@ struct HermBlockBufs {
   int cap = 0;
   DevBuf<double2> xl64, yl64;
   DevBuf<float2> xl32, yl32;
-  void ensure(const HermSet &H, int nr, bool fp64, bool fp32, Budget *bud);
+  // local vectors zeroed when allocated: a forward (below) writes only the
+  // rows a vector entry maps to
+  void ensure(const HermSet &H, int nr, bool fp64, bool fp32, Budget *bud, hipStream_t s);
 };
 
 // Y <- epilogue(sum_b R_b^T A_b R_b X) for nr columns (modes as herm_apply).
+// gathered: W already holds the local rows of X (a previous application
+// forwarded them).  fwd, fwd_bufs: a block set on the same vector and its
+// buffers, whose local vectors receive the new Y for an application of fwd
+// to Y that follows with gathered = true.  Rows of a block past its size
+// may hold stale finite values from another width; they meet only the zero
+// padding of the tiles.  One column goes through herm_apply (the single-
+// vector local vectors of the sets).
 template <typename T>
 void herm_apply_blk(HermSet &H, HermBlockBufs &W, const cplx_t<T> *X, cplx_t<T> *Y,
-                    const cplx_t<T> *R, int mode, T theta, int nr, hipStream_t s);
+                    const cplx_t<T> *R, int mode, T theta, int nr, hipStream_t s,
+                    bool gathered = false, HermSet *fwd = nullptr,
+                    HermBlockBufs *fwd_bufs = nullptr);
 
 // The local vectors of a block set for nr columns stored column by column
 // ([nr][nloc]: column k at k * nloc), so that the slice of one block is an
