@@ -336,7 +336,8 @@ __global__ __launch_bounds__(256) void k_scatter_blk(int64_t nvec, int nr,
   else out = cscale(acc, theta);
   y[e] = out;
   if (FWD)
-    for (int32_t j = fwd_ptr[d]; j < fwd_ptr[d + 1]; ++j) fwd_xl[(int64_t)fwd_ent[j] * nr + k] = out;
+    for (int32_t j = fwd_ptr[d]; j < fwd_ptr[d + 1]; ++j)
+      fwd_xl[(int64_t)fwd_ent[j] * nr + k] = out;
 }
 
 // Local vectors column by column ([nr][nloc]).
