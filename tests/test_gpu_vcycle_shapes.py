@@ -6,7 +6,9 @@ local vectors are filled by the scatter of the application before them.
 
 Bar: FP64 within 1e-10 of the oracle's solution (tol 1e-12) with iteration
 counts +-1; mixed precision (tol 1e-10) within 1e-8 of the FP64 oracle, its
-iteration count within 2 of the oracle's at that tolerance.
+iteration count within 2 of the oracle's at that tolerance.  The block path
+(three explicit right-hand sides in one solve, the same chains on block
+buffers) is held to the same bar column by column.
 """
 import numpy as np
 import pytest
@@ -35,12 +37,18 @@ def problem():
     return d, S, rhs, {}
 
 
-def _oracle(problem, nu, tol):
-    """The oracle's solution and iteration count for V(nu) at tol (cached)."""
-    _, S, rhs, cache = problem
+def _hierarchy(problem, nu):
+    """The oracle's hierarchy for V(nu) and its solutions so far (cached)."""
+    _, S, _, cache = problem
     if nu not in cache:
         cache[nu] = (multigrid.Hierarchy(N, P, S, nu_pre=nu[0], nu_post=nu[1]), {})
-    H, sols = cache[nu]
+    return cache[nu]
+
+
+def _oracle(problem, nu, tol):
+    """The oracle's solution and iteration count for V(nu) at tol (cached)."""
+    rhs = problem[2]
+    H, sols = _hierarchy(problem, nu)
     if tol not in sols:
         sols[tol] = H.solve(rhs, tol)
     return sols[tol]
@@ -71,5 +79,34 @@ def test_vcycle_shape_matches_oracle(problem, nu, precision):
             assert code == D.DPG_OK
             assert np.linalg.norm(x[0] - xo) <= 1e-8 * np.linalg.norm(xo)
             assert abs(int(it[0]) - ito) <= 2, (it[0], ito)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("nu,precision", [((1, 3), "fp64"), ((0, 1), "mixed"), ((3, 0), "fp64"),
+                                          ((1, 3), "mixed")])
+def test_block_vcycle_shape_matches_oracle(problem, nu, precision):
+    D = _D()
+    d, _, rhs, _ = problem
+    opt = D.dpg_default_options(nu_pre=nu[0], nu_post=nu[1],
+                                precision=D.DPG_MIXED if precision == "mixed" else D.DPG_FP64)
+    print(f"[vcycle block] N={N} p={P} nu={nu} {precision}", flush=True)
+    ctx = D.dpg_setup(N, P, OMEGA, [dict(dir=d, amp=1.0)], options=opt)
+    try:
+        D.dpg_assemble(ctx)
+        D.dpg_build_hierarchy(ctx)
+        rng = np.random.default_rng(17)
+        n = rhs.shape[0]
+        B = np.stack([rhs, (rng.standard_normal(n) + 1j * rng.standard_normal(n)),
+                      (0.5 - 2j) * rhs + (rng.standard_normal(n) + 1j * rng.standard_normal(n))])
+        H = _hierarchy(problem, nu)[0]
+        tol, bar = (1e-12, 1e-10) if precision == "fp64" else (1e-10, 1e-8)
+        x, it, rr, code = D.dpg_solve(ctx, rhs=B, nrhs=3, tol=tol)
+        assert code == D.DPG_OK
+        for k in range(3):
+            xo, _, _ = H.solve(B[k], 1e-12)
+            _, ito, _ = H.solve(B[k], tol)
+            assert np.linalg.norm(x[k] - xo) <= bar * np.linalg.norm(xo), k
+            assert abs(int(it[k]) - ito) <= (1 if precision == "fp64" else 2), (k, it[k], ito)
     finally:
         ctx.close()
