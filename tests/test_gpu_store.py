@@ -96,3 +96,35 @@ def test_store_rejects_wave_speed_varying_inside_a_coarse_element():
     c = np.repeat([1.0, 2.0], 32)       # z < 1/2 and z > 1/2
     ctx = D.dpg_setup(4, 2, 2 * np.pi, [dict(dir=(1, 0, 0), amp=1.0)], c=c, options=opt)
     ctx.close()
+
+
+def test_store_mixed_precision_block_solve_matches_oracle():
+    """Stored coarse operators with the FP32 V-cycle and three right-hand
+    sides in one block solve: each column within 1e-8 of the oracle's store
+    hierarchy solution (tol 1e-10), iterations within 2."""
+    D = _D()
+    N, p, omega, nu = 8, 2, 4 * np.pi, (2, 2)
+    d = workloads.plane_wave_direction(5)
+    opt = D.dpg_default_options(nu_pre=nu[0], nu_post=nu[1], flags=D.DPG_STORE_COARSE,
+                                precision=D.DPG_MIXED)
+    print(f"[store mixed block] N={N} p={p}", flush=True)
+    ctx = D.dpg_setup(N, p, omega, [dict(dir=d, amp=1.0)], options=opt)
+    try:
+        D.dpg_assemble(ctx)
+        D.dpg_build_hierarchy(ctx)
+        pr = dpg.Problem(N, p, omega, [dict(u0=dpg.plane_wave_u0(omega, d))])
+        S, s, _ = pr.condensed()
+        rhs = dpg.assemble_vector(pr.edofs, s, pr.num.n)[:, 0]
+        H = multigrid.Hierarchy(N, p, S, nu_pre=nu[0], nu_post=nu[1], coarse=_store(p, omega))
+        rng = np.random.default_rng(3)
+        n = rhs.shape[0]
+        B = np.stack([rhs, rng.standard_normal(n) + 1j * rng.standard_normal(n), (1 + 1j) * rhs])
+        x, it, rr, code = D.dpg_solve(ctx, rhs=B, nrhs=3, tol=1e-10)
+        assert code == D.DPG_OK
+        for k in range(3):
+            xo, _, _ = H.solve(B[k], 1e-12)
+            _, ito, _ = H.solve(B[k], 1e-10)
+            assert np.linalg.norm(x[k] - xo) <= 1e-8 * np.linalg.norm(xo), k
+            assert abs(int(it[k]) - ito) <= 2, (k, it[k], ito)
+    finally:
+        ctx.close()
