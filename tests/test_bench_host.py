@@ -80,3 +80,19 @@ def test_more_than_one_gpu_is_refused():
                          capture_output=True, text=True, timeout=120)
     assert res.returncode == 2
     assert "one GPU" in res.stderr and res.stdout == ""
+
+
+def test_serving_child_failure_is_loud(monkeypatch):
+    """The serving leg runs bench.py --serving in a child process; a child
+    that fails (here a stand-in interpreter that exits with status 3) raises
+    instead of leaving the leg out of the line."""
+    import subprocess as sp
+    real = sp.run
+
+    def fake(cmd, **kw):
+        assert cmd[2:4] == ["--serving", "--requests"] and cmd[4] == "5"
+        return real([sys.executable, "-c", "import sys; sys.exit(3)"], **kw)
+
+    monkeypatch.setattr(sp, "run", fake)
+    with pytest.raises(RuntimeError, match="status 3"):
+        bench.serving_child(5, 4, 8, 0.7)
