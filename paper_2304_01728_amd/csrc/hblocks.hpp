@@ -61,7 +61,7 @@ struct HermSet {
   DevBuf<int32_t> bn;
   DevBuf<int64_t> ent_off, cp_off, rp_off, loc_off;
   DevBuf<int32_t> gidx;      // [nloc] vector index of each padded local row, -1 = padding
-  DevBuf<int4> units;        // two int4 descriptors per (block, J, tile-row pair), longest first
+  DevBuf<int4> units;        // two int4 descriptors per (block, J, tile-row pair), block order
   DevBuf<int2> rows;         // (block, I)
   DevBuf<int4> rowd;         // per (block, I): column-partial base, row-partial base,
                              // segment count | (row-partial count << 16), local offset
