@@ -212,7 +212,10 @@ __global__ __launch_bounds__(256) void k_units(const cplx_t<T> *__restrict__ til
   using C = cplx_t<T>;
   __shared__ C xs[4][kSeg * 32];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t wv = (int64_t)blockIdx.x * 4 + wave;
+  // workgroup g runs on XCD g % 8: each XCD takes a contiguous range of
+  // units (the grid is a multiple of 8; workgroups past the end exit)
+  const int64_t per = gridDim.x / 8, wg = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int64_t wv = wg * 4 + wave;
   if (wv >= nunits) return;
   const int lane = threadIdx.x & 63, ra = lane >> 3, cb = lane & 7;
   const int4 d0 = units[2 * wv], d1 = units[2 * wv + 1];
@@ -271,7 +274,10 @@ __global__ __launch_bounds__(256) void k_strips(const cplx_t<T> *__restrict__ ti
                                                cplx_t<T> *__restrict__ part) {
   using C = cplx_t<T>;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t wv = (int64_t)blockIdx.x * 4 + wave;
+  // workgroup g runs on XCD g % 8: each XCD takes a contiguous range of
+  // units (the grid is a multiple of 8; workgroups past the end exit)
+  const int64_t per = gridDim.x / 8, wg = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int64_t wv = wg * 4 + wave;
   if (wv >= nunits) return;
   const int lane = threadIdx.x & 63, ra = lane >> 3, cb = lane & 7;
   const int4 d0 = units[2 * wv], d1 = units[2 * wv + 1];
@@ -693,11 +699,11 @@ void herm_apply(HermSet &H, const cplx_t<T> *x, cplx_t<T> *y, const cplx_t<T> *r
     ProfScope ps(H.prof, sizeof(T) == 8 ? DPG_K_APPLY64 : DPG_K_APPLY32,
                  (double)H.packed_entries() * sizeof(cplx_t<T>), s);
     if constexpr (sizeof(T) == 8)
-      hipLaunchKernelGGL((k_units<T>), dim3(cdiv(H.nunits, 4)), dim3(256), 0, s, tiles,
-                         H.units.p, H.nunits, xl, part);
+      hipLaunchKernelGGL((k_units<T>), dim3(8 * cdiv(cdiv(H.nunits, 4), 8)), dim3(256), 0, s,
+                         tiles, H.units.p, H.nunits, xl, part);
     else
-      hipLaunchKernelGGL((k_strips<T>), dim3(cdiv(H.snunits, 4)), dim3(256), 0, s, tiles,
-                         H.sunits.p, H.snunits, xl, part);
+      hipLaunchKernelGGL((k_strips<T>), dim3(8 * cdiv(cdiv(H.snunits, 4), 8)), dim3(256), 0, s,
+                         tiles, H.sunits.p, H.snunits, xl, part);
     LAUNCH_OK();
   }
   ProfScope ps(H.prof, DPG_K_REDUCE, 0.0, s);
